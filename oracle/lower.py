@@ -1,0 +1,184 @@
+"""Dual-upscaling lower bound (Section 3.5, Algorithm 5, lazy c-transform of Section 4).
+
+Given coarse dual potentials f~ on the coarse grid:
+
+1. upscale f~ to the fine grid by multilinear interpolation, f^ = R(f~);
+2. g = (f^)^c, i.e. g_j = min_i C_ij - f^_i            (first c-transform)
+3. f = g^c,     i.e. f_i = min_j C_ij - g_j            (second c-transform)
+4. lower bound = (<f, mu> + <g, nu>)^(1/p).
+
+(f, g) is an admissible pair for C, so <f, mu> + <g, nu> <= L_C(mu, nu)
+(the proposition of Section 3.5), for any choice of f^.
+
+Two tracks:
+
+* ``*_o64``: every step in float64 - the mathematical definition.
+* ``*_o32``: the float32 reading used by the GPU path.  f^ is rounded once to
+  float32; each candidate C_ij - phi_i is one float32 subtraction of the
+  float32 cost (exact for p = 2, correctly rounded sqrt for p = 1); the min is
+  exact and ties go to the lowest flat index.  The sums <f, mu>, <g, nu> are
+  float64.  Because float32 rounding can make (f, g) slightly infeasible, the
+  emitted value subtracts a feasibility shift s (``feasibility_shift``), which
+  also keeps it at or below the float64 value.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .grid import coords, cost32, cost64
+
+
+# ----------------------------------------------------------------------------
+# Interpolation R of the coarse potential (Section 3.5; multilinear, as in the
+# paper's experiments).  Reading: coarse potentials live at the block centres
+# k*K + (k-1)/2; fine pixels outside the hull of the centres take the value of
+# the nearest edge (clamped, no extrapolation).  The interpolation is the
+# nested linear interpolation lerp(a, b, w) = a + w * (b - a), the last axis
+# innermost, each operation rounded separately in float64.
+# ----------------------------------------------------------------------------
+
+def _axis_weights(N: int, k: int):
+    """Per fine coordinate x: (K0, K1, w) with x = centre(K0) + w * k (clamped)."""
+    n = N // k
+    x = np.arange(N, dtype=np.int64)
+    t = 2 * x - (k - 1)          # position relative to centre 0, in units of 1/(2k)
+    den = 2 * k
+    K0 = np.floor_divide(t, den)
+    r = t - den * K0
+    w = r.astype(np.float64) / float(den)
+    K1 = K0 + 1
+    low = t <= 0
+    high = K0 >= n - 1
+    K0 = np.where(low, 0, np.where(high, n - 1, K0))
+    K1 = np.where(low, 0, np.where(high, n - 1, K1))
+    w = np.where(low | high, 0.0, w)
+    return K0, K1, w
+
+
+def upscale_potential(ftil: np.ndarray, N: int, d: int, k: int) -> np.ndarray:
+    n = N // k
+    F = np.asarray(ftil, dtype=np.float64).reshape((n,) * d)
+    X = coords(N, d)
+    K0, K1, W = _axis_weights(N, k)
+
+    def rec(axis, idx):
+        if axis == d:
+            return F[tuple(idx)]
+        xa = X[:, axis]
+        lo = rec(axis + 1, idx + [K0[xa]])
+        hi = rec(axis + 1, idx + [K1[xa]])
+        return lo + W[xa] * (hi - lo)
+
+    return rec(0, [])
+
+
+# ----------------------------------------------------------------------------
+# Lazy c-transform psi_j = min_i C_ij - phi_i (Section 4, eq. of the lazy
+# c-transform).  The cost is symmetric, so one routine serves both steps.
+# ----------------------------------------------------------------------------
+
+def _chunks(P: int):
+    step = max(1, (1 << 22) // P)
+    for s in range(0, P, step):
+        yield s, min(P, s + step)
+
+
+def ctransform_o64(phi: np.ndarray, N: int, d: int, p: int, targets=None):
+    """FP64 c-transform.  Returns (psi, argmin) for all targets (or the given ones)."""
+    X = coords(N, d)
+    phi = np.asarray(phi, dtype=np.float64)
+    tg = np.arange(len(X)) if targets is None else np.asarray(targets)
+    psi = np.empty(len(tg))
+    arg = np.empty(len(tg), dtype=np.int64)
+    for s, e in _chunks(len(X)):
+        if s >= len(tg):
+            break
+        J = tg[s:e]
+        t = cost64(X, X[J], p) - phi[:, None]
+        arg[s:e] = np.argmin(t, axis=0)
+        psi[s:e] = t[arg[s:e], np.arange(len(J))]
+    return psi, arg
+
+
+def ctransform_o32(phi32: np.ndarray, N: int, d: int, p: int, targets=None):
+    """FP32-faithful c-transform: min_i RN32(RN32(C_ij) - phi_i), lowest index on ties."""
+    X = coords(N, d)
+    phi32 = np.asarray(phi32, dtype=np.float32)
+    tg = np.arange(len(X)) if targets is None else np.asarray(targets)
+    psi = np.empty(len(tg), dtype=np.float32)
+    arg = np.empty(len(tg), dtype=np.int64)
+    for s, e in _chunks(len(X)):
+        if s >= len(tg):
+            break
+        J = tg[s:e]
+        t = cost32(X, X[J], p) - phi32[:, None]       # float32 - float32 -> float32
+        assert t.dtype == np.float32
+        arg[s:e] = np.argmin(t, axis=0)
+        psi[s:e] = t[arg[s:e], np.arange(len(J))]
+    return psi, arg
+
+
+def fsum_dot(x, w) -> float:
+    """sum_i x_i * w_i in float64: products rounded once, then an exactly rounded sum."""
+    x = np.asarray(x, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    return math.fsum((x * w).tolist())
+
+
+# ----------------------------------------------------------------------------
+# Bound assembly
+# ----------------------------------------------------------------------------
+
+def lower_bound_o64(mu, nu, ftil, k: int, p: int):
+    """Algorithm 5 in float64: returns f^, g, f, S = <f,mu> + <g,nu>, lower bound."""
+    d, N = mu.ndim, mu.shape[0]
+    fhat = upscale_potential(ftil, N, d, k)
+    g, ig = ctransform_o64(fhat, N, d, p)
+    f, jf = ctransform_o64(g, N, d, p)
+    S = fsum_dot(f, mu.reshape(-1)) + fsum_dot(g, nu.reshape(-1))
+    return {"fhat": fhat, "g": g, "f": f, "argmin_g": ig, "argmin_f": jf,
+            "S": S, "lower": max(S, 0.0) ** (1.0 / p)}
+
+
+U32 = 2.0 ** -24
+
+
+def feasibility_shift(F_hat: float, G: float, Fo: float, p: int, P: int) -> float:
+    """Shift s such that (f32 - s, g32) is admissible for the exact costs and
+    <f32 - s, mu> + <g32, nu> <= the float64 value of Algorithm 5.
+
+    Inputs: F_hat = max|f^32|, G = max|g32|, Fo = max|f32|, P = number of
+    pixels.  Derivation (first order in u = 2^-24, the rest absorbed by the
+    factor 1 + 2^-10): the c-transform is 1-Lipschitz in the sup norm and each
+    candidate carries one float32 rounding of a value whose magnitude at the
+    arg-min is |g| (resp. |f|), plus the rounding of f^ (u |f^|) and, for p = 1,
+    of the cost (u * C with C <= |f| + |g| at the arg-min):
+        |g32 - g64| <= e_g = (u + u_p)(G + F)
+        |f32 - f64| <= e_f = u Fo + u_p (Fo + G) + e_g
+    and the float64 sums of P terms are off by at most P 2^-52 (Fo + G).
+    The same e_f bounds the infeasibility f32_i + g32_j - C_ij."""
+    u = U32
+    up = u if p == 1 else 0.0
+    F = F_hat * (1.0 + 2.0 * u)
+    e_g = (u + up) * (G + F)
+    e_f = u * Fo + up * (Fo + G) + e_g
+    return (e_f + e_g) * (1.0 + 2.0 ** -10) + 2.0 ** -52 * P * (Fo + G)
+
+
+def lower_bound_o32(mu, nu, ftil, k: int, p: int):
+    """Algorithm 5 in the float32 reading, with the float64 sums and shift."""
+    d, N = mu.ndim, mu.shape[0]
+    P = N ** d
+    fhat64 = upscale_potential(ftil, N, d, k)
+    fhat32 = fhat64.astype(np.float32)
+    g32, ig = ctransform_o32(fhat32, N, d, p)
+    f32, jf = ctransform_o32(g32, N, d, p)
+    S32 = fsum_dot(f32, mu.reshape(-1)) + fsum_dot(g32, nu.reshape(-1))
+    s = feasibility_shift(float(np.abs(fhat32).max()), float(np.abs(g32).max()),
+                          float(np.abs(f32).max()), p, P)
+    S_emit = S32 - s
+    return {"fhat32": fhat32, "g32": g32, "f32": f32, "argmin_g": ig, "argmin_f": jf,
+            "S32": S32, "shift": s, "S_emit": S_emit,
+            "lower": max(S_emit, 0.0) ** (1.0 / p), "clipped": S_emit <= 0.0}

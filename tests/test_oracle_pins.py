@@ -1,0 +1,478 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: brute force
+on tiny inputs, closed forms, textbook or library routines, exact LPs, and the
+paper's theorems (bracketing, admissibility, couplings, the total-variation
+bound).  None of these tests touches the GPU library.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import closed, coarse, grid, lower, lp, upper
+from oracle import grad as ograd
+
+
+def pair(N, d, fam_a, fam_b, seed):
+    return si.family(fam_a, N, d, si.rng(seed)), si.family(fam_b, N, d, si.rng(seed + 1))
+
+
+# ---------------------------------------------------------------- grid / cost
+
+def test_flat_index_is_c_order():
+    for N, d in [(5, 2), (4, 3)]:
+        X = grid.coords(N, d)
+        for i in range(N ** d):
+            assert tuple(X[i]) == np.unravel_index(i, (N,) * d)
+
+
+def test_cost_p2_is_exact_integer_in_float32():
+    X = grid.coords(512, 2)[::4099]
+    c32 = grid.cost32(X, X, 2).astype(np.int64)
+    ref = ((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)
+    assert np.array_equal(c32, ref) and ref.max() < 2 ** 24
+
+
+def test_cost_p1_float32_sqrt_equals_rounded_double_sqrt():
+    # sqrt rounded to float32 directly equals float32(sqrt in float64): double
+    # rounding is innocuous for sqrt when 53 >= 2*24 + 2.
+    n = np.arange(0, 2 * 511 ** 2 + 1, dtype=np.int64)
+    a = np.sqrt(n.astype(np.float32))
+    b = np.sqrt(n.astype(np.float64)).astype(np.float32)
+    assert np.array_equal(a, b)
+
+
+def test_cmax():
+    X = grid.coords(7, 3)
+    assert grid.cmax(7, 3, 2) == grid.cost64(X, X, 2).max()
+    assert grid.cmax(7, 3, 1) == pytest.approx(grid.cost64(X, X, 1).max(), rel=1e-15)
+
+
+# ---------------------------------------------------------------- coarsening
+
+def test_sumpool_brute_force_and_mass():
+    m = si.white_noise(8, 2, si.rng(3))
+    k = 4
+    out = coarse.sumpool(m, k)
+    ref = np.zeros(4)
+    for x in range(8):
+        for y in range(8):
+            ref[(x // k) * 2 + (y // k)] += m[x, y]
+    assert np.allclose(out, ref, rtol=16 * 2.0 ** -53, atol=0)  # 16 terms per block
+    m3 = si.white_noise(6, 3, si.rng(4))
+    assert math.isclose(coarse.sumpool(m3, 3).sum(), 1.0, rel_tol=1e-15)
+
+
+def test_centres_are_block_means():
+    N, d, k = 12, 2, 3
+    X = grid.coords(N, d).astype(float)
+    blk = coarse.block_of(N, d, k)
+    c = coarse.centres(N, d, k)
+    for b in range(len(c)):
+        assert np.array_equal(c[b], X[blk == b].mean(0))
+
+
+def test_centre_cost_closed_form():
+    N, d, k = 12, 3, 4
+    n = N // k
+    K = grid.coords(n, d)
+    for p in (1, 2):
+        ref = (k * k * ((K[:, None] - K[None]) ** 2).sum(-1)) ** (p / 2.0)
+        assert np.allclose(coarse.centre_cost(N, d, k, p), ref, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("N,d,k", [(8, 2, 2), (4, 3, 2)])
+@pytest.mark.parametrize("p", [1, 2])
+def test_cbar_brute_force(N, d, k, p):
+    mu = si.white_noise(N, d, si.rng(10))
+    nu = si.gmm(N, d, si.rng(11))
+    X = grid.coords(N, d)
+    blk = coarse.block_of(N, d, k)
+    Q = (N // k) ** d
+    S = np.zeros((Q, Q))
+    mm, nn = np.zeros(Q), np.zeros(Q)
+    muf, nuf = mu.reshape(-1), nu.reshape(-1)
+    for i in range(len(X)):
+        mm[blk[i]] += muf[i]
+        nn[blk[i]] += nuf[i]
+        for j in range(len(X)):
+            r = math.sqrt(sum((int(X[i, a]) - int(X[j, a])) ** 2 for a in range(d)))
+            S[blk[i], blk[j]] += r ** p * muf[i] * nuf[j]
+    ref = S / np.outer(mm, nn)
+    assert np.allclose(coarse.cbar(mu, nu, k, p), ref, rtol=1e-13, atol=0)
+
+
+def test_cbar_p2_moment_form():
+    # For p = 2 the weighted block cost separates into centroid distance plus
+    # the two within-block variances.
+    N, d, k = 16, 2, 4
+    mu, nu = pair(N, d, "grf", "cauchy", 20)
+    X = grid.coords(N, d).astype(float)
+    blk = coarse.block_of(N, d, k)
+    Q = (N // k) ** d
+
+    def moments(m):
+        m = m.reshape(-1)
+        w = np.bincount(blk, m, Q)
+        cen = np.stack([np.bincount(blk, m * X[:, a], Q) for a in range(d)], 1) / w[:, None]
+        var = np.bincount(blk, m * ((X - cen[blk]) ** 2).sum(1), Q) / w
+        return cen, var
+
+    cm, vm = moments(mu)
+    cn, vn = moments(nu)
+    ref = ((cm[:, None] - cn[None]) ** 2).sum(-1) + vm[:, None] + vn[None]
+    assert np.allclose(coarse.cbar(mu, nu, k, 2), ref, rtol=1e-12, atol=0)
+
+
+def test_cmin_closed_form():
+    N, d, k = 12, 2, 3
+    n = N // k
+    K = grid.coords(n, d)
+    gap = np.maximum(0, k * np.abs(K[:, None] - K[None]) - (k - 1))
+    for p in (1, 2):
+        ref = ((gap ** 2).sum(-1)) ** (p / 2.0)
+        assert np.allclose(coarse.cmin(N, d, k, p), ref, rtol=1e-15, atol=0)
+
+
+# ---------------------------------------------------------------- LP
+
+def test_lp_matches_assignment_brute_force():
+    g = si.rng(30)
+    n = 5
+    C = g.uniform(0, 10, (n, n))
+    a = np.full(n, 1.0 / n)
+    r, c, v, f, gg, obj = lp.solve_ot(a, a, C)
+    best = min(sum(C[i, s[i]] for i in range(n)) for s in itertools.permutations(range(n))) / n
+    assert obj == pytest.approx(best, rel=1e-12)
+    cert = lp.certify(r, c, v, f, gg, a, a, C)
+    assert cert["dual_viol"] <= 1e-12 and cert["slack_on_support"] <= 1e-12
+    assert cert["dual"] == pytest.approx(obj, rel=1e-12)
+
+
+def test_northwest_corner_is_basic_coupling():
+    g = si.rng(31)
+    a = g.dirichlet(np.ones(7))
+    b = g.dirichlet(np.ones(9))
+    r, c, v = lp.northwest_corner(a, b)
+    assert len(v) <= 7 + 9 - 1 and v.min() > 0
+    assert np.allclose(np.bincount(r, v, 7), a, atol=1e-15)
+    assert np.allclose(np.bincount(c, v, 9), b, atol=1e-15)
+
+
+# ---------------------------------------------------------------- interpolation
+
+def test_upscale_constant_and_centres():
+    N, d, k = 15, 2, 3                      # odd k: block centres are pixels
+    n = N // k
+    ft = si.rng(40).standard_normal(n ** d)
+    fh = lower.upscale_potential(ft, N, d, k).reshape(N, N)
+    for K in range(n):
+        for L in range(n):
+            assert fh[k * K + 1, k * L + 1] == ft[K * n + L]
+    assert np.all(lower.upscale_potential(np.full(n * n, 2.5), N, d, k) == 2.5)
+
+
+def test_upscale_matches_np_interp_along_one_axis():
+    N, k = 16, 4
+    n = N // k
+    prof = si.rng(41).standard_normal(n)
+    ft = np.repeat(prof, n)                     # varies along axis 0 only
+    fh = lower.upscale_potential(ft, N, 2, k).reshape(N, N)
+    xc = np.arange(n) * k + (k - 1) / 2
+    ref = np.interp(np.arange(N), xc, prof)     # np.interp clamps at both ends
+    assert np.allclose(fh[:, 5], ref, rtol=0, atol=1e-14)
+
+
+def test_upscale_bilinear_of_product_is_product():
+    N, k = 16, 4
+    n = N // k
+    u = si.rng(42).standard_normal(n)
+    v = si.rng(43).standard_normal(n)
+    ft = np.outer(u, v).reshape(-1)
+    fh = lower.upscale_potential(ft, N, 2, k).reshape(N, N)
+    xc = np.arange(n) * k + (k - 1) / 2
+    ref = np.outer(np.interp(np.arange(N), xc, u), np.interp(np.arange(N), xc, v))
+    assert np.allclose(fh, ref, rtol=0, atol=1e-13)
+
+
+def test_upscale_affine_is_exact_in_3d_interior():
+    N, d, k = 8, 3, 2
+    c = coarse.centres(N, d, k)
+    beta = np.array([0.5, -1.25, 2.0])
+    ft = 3.0 + c @ beta
+    fh = lower.upscale_potential(ft, N, d, k)
+    X = grid.coords(N, d).astype(float)
+    inside = np.all((X >= c.min(0)) & (X <= c.max(0)), axis=1)
+    assert np.allclose(fh[inside], 3.0 + X[inside] @ beta, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- c-transform
+
+@pytest.mark.parametrize("N,d,p", [(4, 2, 2), (4, 2, 1), (3, 3, 2), (3, 3, 1)])
+def test_ctransform_brute_force(N, d, p):
+    X = grid.coords(N, d)
+    P = len(X)
+    phi = si.rng(50 + p).standard_normal(P) * 3
+    phi32 = phi.astype(np.float32)
+    g64, i64 = lower.ctransform_o64(phi, N, d, p)
+    g32, i32 = lower.ctransform_o32(phi32, N, d, p)
+    for j in range(P):
+        vals64, vals32 = [], []
+        for i in range(P):
+            d2 = sum((int(X[i, a]) - int(X[j, a])) ** 2 for a in range(d))
+            c = math.sqrt(d2) if p == 1 else float(d2)
+            vals64.append(c - phi[i])
+            vals32.append(np.float32(np.float32(c) - phi32[i]))
+        assert g64[j] == min(vals64) and i64[j] == int(np.argmin(vals64))
+        assert g32[j] == min(vals32) and i32[j] == int(np.argmin(vals32))
+
+
+def test_ctransform_zero_potential():
+    for p in (1, 2):
+        g, _ = lower.ctransform_o32(np.zeros(64, np.float32), 8, 2, p)
+        assert np.all(g == 0)
+
+
+def test_ctransform_of_linear_potential_p2():
+    # phi_i = -2<x_i, t>: min_x |x - y|^2 + 2<x, t> = 2<y, t> - |t|^2, attained
+    # at x = y - t whenever that point is on the grid.
+    N, d = 12, 2
+    t = np.array([2, -3])
+    X = grid.coords(N, d)
+    phi = (-2.0 * (X @ t)).astype(np.float32)
+    g, arg = lower.ctransform_o32(phi, N, d, 2)
+    inside = np.all((X - t >= 0) & (X - t < N), axis=1)
+    assert np.array_equal(g[inside], (2.0 * (X[inside] @ t) - t @ t).astype(np.float32))
+
+
+def test_ctransform_of_distance_potential_p1():
+    # phi_i = -|x_i - z|: min_x |x - y| + |x - z| = |y - z| (triangle inequality).
+    N, d = 10, 2
+    X = grid.coords(N, d)
+    z = np.array([3, 7])
+    phi = -np.sqrt(((X - z) ** 2).sum(1))
+    g, _ = lower.ctransform_o64(phi, N, d, 1)
+    assert np.allclose(g, np.sqrt(((X - z) ** 2).sum(1)), rtol=0, atol=1e-12)
+
+
+def test_ctransform_tie_goes_to_lowest_index():
+    N, d = 6, 2
+    X = grid.coords(N, d)
+    j, i1, i2 = 14, 3, 29
+    c = grid.cost32(X, X[[j]], 2)[:, 0]
+    phi = np.zeros(N * N, np.float32)
+    phi[i1] = c[i1] + 100
+    phi[i2] = c[i2] + 100
+    g, arg = lower.ctransform_o32(phi, N, d, 2, targets=[j])
+    assert g[0] == -100 and arg[0] == i1
+
+
+def test_double_ctransform_properties():
+    N, d, p = 8, 2, 2
+    fhat = si.rng(60).standard_normal(N * N) * 20
+    g, _ = lower.ctransform_o64(fhat, N, d, p)
+    f, _ = lower.ctransform_o64(g, N, d, p)
+    assert np.all(f >= fhat - 1e-12)                  # f = fhat^cc >= fhat
+    g2, _ = lower.ctransform_o64(f, N, d, p)
+    assert np.allclose(g2, g, rtol=0, atol=1e-12)     # f^ccc = f^c
+
+
+# ---------------------------------------------------------------- lower bound
+
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("fams,seed", [(("gmm", "gmm"), 70), (("white_noise", "shapes"), 72),
+                                       (("cauchy", "grf"), 74)])
+def test_lower_bound_brackets_exact(p, fams, seed):
+    N, d, k = 16, 2, 4
+    mu, nu = pair(N, d, *fams, seed)
+    W = lp.wasserstein_exact(mu, nu, p)
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
+    L64 = lower.lower_bound_o64(mu, nu, ft, k, p)
+    L32 = lower.lower_bound_o32(mu, nu, ft, k, p)
+    assert L64["lower"] <= W * (1 + 1e-12)
+    assert L32["S_emit"] <= L64["S"]
+    U = upper.upper_bound_o64(mu, nu, r, c, v, k, p)
+    assert U["upper"] >= W * (1 - 1e-12)
+
+
+def test_lower_bound_is_exact_at_k1():
+    # k = 1: the coarse problem is the fine one; the optimal dual gives L_C.
+    N, d, p = 8, 2, 2
+    mu, nu = pair(N, d, "gmm", "grf", 80)
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, 1, p)
+    L = lower.lower_bound_o64(mu, nu, ft, 1, p)
+    assert L["S"] == pytest.approx(obj, rel=1e-10)
+    U = upper.upper_bound_o64(mu, nu, r, c, v, 1, p)
+    assert U["plan_cost"] == pytest.approx(obj, rel=1e-12)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_feasibility_shift_gives_admissible_pair(p):
+    N, d, k = 16, 2, 4
+    for seed in (90, 92):
+        mu, nu = pair(N, d, "grf", "cauchy", seed)
+        *_, ft, gt, _ = upper.coarse_record_lp(mu, nu, k, p)
+        ft = ft + 1e4 * (seed - 91)            # large offsets stress float32 rounding
+        L32 = lower.lower_bound_o32(mu, nu, ft, k, p)
+        L64 = lower.lower_bound_o64(mu, nu, ft, k, p)
+        X = grid.coords(N, d)
+        C = grid.cost64(X, X, p)
+        f = L32["f32"].astype(np.float64) - L32["shift"]
+        g = L32["g32"].astype(np.float64)
+        assert (f[:, None] + g[None, :] - C).max() <= 0.0
+        # the derived per-transform error bounds hold
+        u, up = 2.0 ** -24, (2.0 ** -24 if p == 1 else 0.0)
+        F = np.abs(L32["fhat32"]).max() * (1 + 2 * u)
+        G = np.abs(L32["g32"]).max()
+        Fo = np.abs(L32["f32"]).max()
+        e_g = (u + up) * (G + F)
+        assert np.abs(L32["g32"] - L64["g"]).max() <= e_g
+        assert np.abs(L32["f32"] - L64["f"]).max() <= u * Fo + up * (Fo + G) + e_g
+        assert L32["S_emit"] <= L64["S"]
+
+
+# ---------------------------------------------------------------- upper bound
+
+def test_upper_bound_plan_properties_and_identity():
+    N, d, k, p = 16, 2, 4, 2
+    mu, nu = pair(N, d, "gmm", "shapes", 100)
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
+    U = upper.upper_bound_o64(mu, nu, r, c, v, k, p)
+    I, J, V = upper.upscale_plan(r, c, v, N, d, k)
+    Q = (N // k) ** d
+    assert len(V) <= k ** (2 * d) * (2 * Q - 1)
+    assert math.isclose(V.sum(), 1.0, rel_tol=1e-14)
+    fitted = U["a"][I] * V * U["b"][J]
+    P = N ** d
+    assert np.abs(np.bincount(I, fitted, P) - mu.reshape(-1)).sum() < 1e-12
+    assert np.abs(np.bincount(J, fitted, P) - nu.reshape(-1)).sum() < 1e-12
+    # uniform kernel: the fitted plan is the quantization coupling, whose cost is <pi~, C-bar>
+    Cb = coarse.cbar(mu, nu, k, p)
+    assert U["plan_cost"] == pytest.approx(float((Cb[r, c] * v).sum()), rel=1e-12)
+    assert U["plan_cost"] == pytest.approx(upper.quantization_coupling_cost(mu, nu, r, c, v, k, p), rel=1e-12)
+    assert U["iters"] == 1
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_tv_terms_bounded_and_upper_bound_valid_when_not_converged(p):
+    N, d, k = 16, 2, 4
+    mu, nu = pair(N, d, "grf", "gmm", 110)
+    W = lp.wasserstein_exact(mu, nu, p)
+    g = si.rng(111)
+    mt = coarse.sumpool(mu, k) * np.exp(0.3 * g.standard_normal(16))
+    nt = coarse.sumpool(nu, k)
+    r, c, v = lp.northwest_corner(mt / mt.sum(), nt)       # a coupling of the wrong marginals
+    U = upper.upper_bound_o64(mu, nu, r, c, v, k, p, xi=1e-12, max_iter=1)
+    assert U["residual"] > 1e-3 and U["tv_mu"] + U["tv_nu"] > 0
+    rad = math.sqrt(d) * (N - 1) / 2.0
+    assert U["tv_mu"] + U["tv_nu"] <= 2 ** (2 - 2 / p) * U["residual"] ** (1 / p) * rad
+    assert U["upper"] >= W
+
+
+def test_ordering_of_the_four_bounds():
+    N, d, k, p = 16, 2, 4, 2
+    mu, nu = pair(N, d, "gmm", "gmm", 120)
+    W = lp.wasserstein_exact(mu, nu, p)
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
+    lo_min = upper.min_cost_lower(mu, nu, k, p)
+    up_wc = upper.weighted_cost_upper(mu, nu, k, p)
+    up_pu = upper.upper_bound_o64(mu, nu, r, c, v, k, p)["upper"]
+    assert lo_min <= W <= up_wc * (1 + 1e-12)
+    assert up_wc <= up_pu * (1 + 1e-12)
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_closed_forms_match_exact_lp(p):
+    N, d = 12, 2
+    mu, nu = si.translated_pair(N, d, (2, -3), si.rng(130))
+    assert lp.wasserstein_exact(mu, nu, p) == pytest.approx(math.sqrt(13), rel=1e-9)
+    a, b = si.axis_constant_pair(N, d, si.rng(131))
+    assert lp.wasserstein_exact(a, b, p) == pytest.approx(closed.axis_constant_w(a, b, p), rel=1e-9)
+    m1, m2, x, y = si.dirac_pair(N, d, si.rng(132))
+    assert lp.wasserstein_exact(m1, m2, p) == pytest.approx(float(np.linalg.norm(x - y)), rel=1e-12)
+
+
+def test_w1d_against_scipy():
+    import scipy.stats
+    g = si.rng(140)
+    a, b = g.dirichlet(np.ones(30)), g.dirichlet(np.ones(30))
+    x = np.arange(30)
+    assert closed.w1d(a, b, 1) == pytest.approx(scipy.stats.wasserstein_distance(x, x, a, b), rel=1e-12)
+
+
+def test_identical_measures():
+    N, d, k, p = 16, 2, 4, 2
+    mu = si.grf(N, d, si.rng(150))
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, mu, k, p)
+    L = lower.lower_bound_o32(mu, mu, ft, k, p)
+    assert L["lower"] == 0.0 and L["clipped"]
+    U = upper.upper_bound_o64(mu, mu, r, c, v, k, p)
+    assert U["upper"] >= 0.0
+
+
+# ---------------------------------------------------------------- gradients
+
+def _mass_preserving_direction(m, g, block_k=None):
+    v = g.uniform(-1, 1, m.shape)
+    if block_k is None:
+        v -= (m * v).sum() / m.sum()
+    else:
+        # remove the mu-weighted mean inside every block: block masses unchanged
+        d, N = m.ndim, m.shape[0]
+        blk = coarse.block_of(N, d, block_k).reshape(m.shape)
+        Q = (N // block_k) ** d
+        mw = np.bincount(blk.reshape(-1), (m * v).reshape(-1), Q)
+        ms = np.bincount(blk.reshape(-1), m.reshape(-1), Q)
+        v -= (mw / ms)[blk]
+    return v / np.abs(v).max()
+
+
+def test_lower_bound_gradient_matches_full_pipeline_fd():
+    N, d, k, p = 16, 2, 4, 2
+    mu, nu = pair(N, d, "gmm", "grf", 160)
+    g = si.rng(161)
+    _, _, _, ft, _, _ = upper.coarse_record_lp(mu, nu, k, p)
+    L = lower.lower_bound_o64(mu, nu, ft, k, p)
+    gm, gn = ograd.lower_grad(L["f"], L["g"], L["S"], p)
+    v = _mass_preserving_direction(mu, g, block_k=k)
+    h = 1e-4
+
+    def full(m):  # re-solves the coarse problem: block masses unchanged -> same solution
+        _, _, _, f2, _, _ = upper.coarse_record_lp(m, nu, k, p)
+        return lower.lower_bound_o64(m, nu, f2, k, p)["lower"]
+
+    fd = (full(mu * (1 + h * v)) - full(mu * (1 - h * v))) / (2 * h)
+    assert fd == pytest.approx(float((gm * (mu * v).reshape(-1)).sum()), rel=1e-6)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_upper_bound_gradient_matches_fd(p):
+    N, d, k = 16, 2, 4
+    mu, nu = pair(N, d, "gmm", "gmm", 170 + p)
+    r, c, v, *_ = upper.coarse_record_lp(mu, nu, k, p)
+    # a perturbed coupling makes the fitting take several iterations
+    v = v * np.exp(0.2 * si.rng(172).standard_normal(len(v)))
+    U = upper.upper_bound_o64(mu, nu, r, c, v, k, p)
+    T = U["iters"]
+    assert T >= 2
+    gm, gn, val = ograd.upper_grad(mu, nu, r, c, v, k, p, T)
+    assert val == pytest.approx(U["plan_cost"] ** (1 / p), rel=1e-12)
+    g = si.rng(173)
+    h = 1e-4
+
+    def W(m, n):
+        U2 = upper.upper_bound_o64(m, n, r, c, v, k, p, xi=-1.0, max_iter=T)
+        return U2["plan_cost"] ** (1 / p)
+
+    for _ in range(2):
+        vm, vn = _mass_preserving_direction(mu, g), _mass_preserving_direction(nu, g)
+        fd = (W(mu * (1 + h * vm), nu * (1 + h * vn)) - W(mu * (1 - h * vm), nu * (1 - h * vn))) / (2 * h)
+        an = float((gm * (mu * vm).reshape(-1)).sum() + (gn * (nu * vn).reshape(-1)).sum())
+        assert fd == pytest.approx(an, rel=1e-6, abs=1e-9)
