@@ -12,16 +12,7 @@ import scipy.optimize
 import scipy.sparse as sp
 
 
-def solve_ot(a: np.ndarray, b: np.ndarray, C: np.ndarray):
-    """Exact OT between a (length n) and b (length m) for cost C (n x m).
-
-    Returns (rows, cols, vals, f, g, obj): the positive entries of an optimal
-    plan, optimal dual potentials and the optimal value.  The last column
-    constraint is redundant and is dropped (its potential is fixed to 0); b
-    is rescaled to the mass of a so the system is consistent to the last bit.
-    """
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
+def _solve_ot_positive(a, b, C):
     n, m = C.shape
     b = b * (a.sum() / b.sum())
     rows_r = np.repeat(np.arange(n), m)
@@ -45,6 +36,37 @@ def solve_ot(a: np.ndarray, b: np.ndarray, C: np.ndarray):
     g = np.concatenate([y[n:], [0.0]])
     r, c = np.nonzero(x > 0)
     return r, c, x[r, c], f, g, float(res.fun)
+
+
+def solve_ot(a: np.ndarray, b: np.ndarray, C: np.ndarray):
+    """Exact OT between a (length n) and b (length m) for cost C (n x m).
+
+    Returns (rows, cols, vals, f, g, obj): the positive entries of an optimal
+    plan, optimal dual potentials and the optimal value.
+
+    Points of zero mass carry no mass in any coupling, so they are left out of
+    the LP; their potentials are completed by c-transforms of the solved ones
+    (f_k = min_l C_kl - g_l, then g_l = min_k C_kl - f_k), which keeps
+    f_k + g_l <= C_kl everywhere.  In the reduced LP the last column
+    constraint is redundant and is dropped (its potential is fixed to 0); b is
+    rescaled to the mass of a so the system is consistent to the last bit.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    ia = np.nonzero(a > 0)[0]
+    ib = np.nonzero(b > 0)[0]
+    r, c, v, fr, gr, obj = _solve_ot_positive(a[ia], b[ib], C[np.ix_(ia, ib)])
+    f = np.full(len(a), np.nan)
+    g = np.full(len(b), np.nan)
+    f[ia] = fr
+    g[ib] = gr
+    za = np.setdiff1d(np.arange(len(a)), ia)
+    zb = np.setdiff1d(np.arange(len(b)), ib)
+    if len(za):
+        f[za] = (C[np.ix_(za, ib)] - gr[None, :]).min(1)
+    if len(zb):
+        g[zb] = (C[:, zb] - f[:, None]).min(0)
+    return ia[r], ib[c], v, f, g, obj
 
 
 def wasserstein_exact(mu: np.ndarray, nu: np.ndarray, p: int) -> float:
