@@ -1,0 +1,272 @@
+/*
+ * qbw.h - C ABI of libqbw: quantization-based bounds on the Wasserstein
+ * metric for discrete measures on regular grids, on AMD MI355X (gfx950).
+ *
+ * The method (Bobrutsky & Moscovich, "Quantization-based Bounds on the
+ * Wasserstein Metric"): measures a (= mu) and b (= nu) on X = [N]^d with
+ * ground cost |x - y|^p are sum-pooled by a factor k onto an n^d coarse grid
+ * (n = N / k, Section 2.2); one exact coarse Kantorovich problem on the
+ * centre cost is solved; then
+ *   - lower bound (Section 3.5, Algorithm 5): the coarse potential is
+ *     upscaled by multilinear interpolation and improved by two c-transforms
+ *     over all fine pixel pairs; bound = (<f, a> + <g, b>)^(1/p);
+ *   - upper bound (Section 3.4, Algorithm 4): the coarse coupling is upscaled
+ *     with the uniform kernel, its marginals corrected by iterative
+ *     proportional fitting (IPF), its fine cost evaluated on its support, and
+ *     weighted total-variation corrections (eq. of the weighted total
+ *     variation) added.
+ * The marginally weighted coarse cost C-bar of Section 3.2 (Algorithm 3) is
+ * exported as well.
+ *
+ * Conventions shared by every call:
+ *   - A measure is float64, C-contiguous with shape (N,)*d, nonnegative; a
+ *     and b must have equal mass (they are normally probability vectors).
+ *     Pixel (x_0, ..., x_{d-1}) has integer coordinates in 0..N-1 and flat
+ *     index ((x_0 N + x_1) N + ...) (C order).  Coarse block K has flat index
+ *     over [n]^d in the same order; its centre is k K + (k - 1) / 2.
+ *   - d in {2, 3}, p in {1, 2}, N % k == 0, 1 <= k <= N.  Violations return
+ *     QBW_E_GRID.
+ *   - "device" pointers are HIP device memory of the context's device;
+ *     "host" pointers are ordinary host memory.  The caller owns every buffer
+ *     it passes; the library owns its context workspaces.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *     enqueued on it; calls that return host values synchronise it.
+ *   - Every call returns a qbw_status; nothing is thrown across the ABI.  On
+ *     failure qbw_last_error() returns a message for the calling thread.
+ *   - Contexts are not thread safe: use one context per host thread.
+ */
+#ifndef QBW_H
+#define QBW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum qbw_status {
+  QBW_OK = 0,
+  QBW_E_INVAL = 1,  /* null pointer, bad option, bad size */
+  QBW_E_GRID = 2,   /* d not in {2,3}, p not in {1,2}, N % k != 0, ... */
+  QBW_E_MASS = 3,   /* negative or NaN mass, unequal or zero total mass */
+  QBW_E_LP = 4,     /* the coarse network simplex failed */
+  QBW_E_HIP = 5,    /* a HIP runtime call failed */
+  QBW_E_NOMEM = 6,  /* device or host allocation failed */
+  QBW_E_STATE = 7   /* object used in the wrong state */
+} qbw_status;
+
+typedef struct qbw_grid {
+  int32_t d;  /* dimension, 2 or 3 */
+  int32_t N;  /* fine grid side */
+  int32_t k;  /* pooling factor kappa; coarse side n = N / k */
+  int32_t p;  /* ground cost |x - y|^p, p in {1, 2} */
+} qbw_grid;
+
+/* qbw_opts.flags */
+#define QBW_WANT_ARGMIN 1u   /* also compute c-transform arg-mins (needed for d/d f^) */
+#define QBW_SAVE_FOR_BWD 2u  /* keep what qbw_bounds_backward needs */
+
+/* qbw_result.warn bits */
+#define QBW_WARN_IPF_NOT_CONVERGED 1u /* stopped at max_ipf_iter; the upper bound stays valid */
+#define QBW_WARN_LB_CLIPPED 2u        /* <f,a>+<g,b>-shift <= 0; lower bound clipped to 0 */
+
+typedef struct qbw_opts {
+  double xi;            /* IPF stop: ||a^ - a||_1 + ||b - b^||_1 < xi (default 1e-12) */
+  int32_t max_ipf_iter; /* IPF iteration cap (default 50, >= 1) */
+  uint32_t flags;       /* QBW_WANT_ARGMIN | QBW_SAVE_FOR_BWD */
+} qbw_opts;
+
+typedef struct qbw_result {
+  double lower;            /* emitted lower bound on W_p (<= the float64 value of Algorithm 5) */
+  double upper;            /* emitted upper bound on W_p (>= the float64 value of Algorithm 4) */
+  double lower_S;          /* <f,a> + <g,b> - feas_shift, in units of W_p^p */
+  double feas_shift;       /* float32 rounding shift subtracted from <f,a> + <g,b> */
+  double upper_cost;       /* emitted <pi^_xi, C> (units of W_p^p), rounded outwards */
+  double tv_mu, tv_nu;     /* emitted weighted-TV corrections Delta_mu^, Delta_nu^ */
+  double ipf_residual;     /* ||a^ - a||_1 + ||b - b^||_1 at the last IPF iteration */
+  double coarse_objective; /* <pi~, C~> of the coarse coupling used */
+  int32_t ipf_iters;       /* IPF iterations taken */
+  uint32_t warn;           /* QBW_WARN_* bits */
+} qbw_result;
+
+/* A coarse solution (pi~, f~) in host memory, owned by the caller.
+ * rows/cols/vals: the coupling of the coarse measures as COO with block
+ * indices in [0, Q); f: the coarse potential on the a side (length Q).
+ * Any coupling of the coarse measures gives a valid upper bound and any f
+ * gives a valid lower bound (the lemma of the triangle-inequality upper bound
+ * and the proposition of Section 3.5); optimal ones give the tight bounds. */
+typedef struct qbw_coarse {
+  int32_t Q;   /* n^d */
+  int32_t nnz; /* entries of the coupling (<= 2Q - 1 for a basic solution) */
+  const int32_t* rows;
+  const int32_t* cols;
+  const double* vals;
+  const double* f;
+} qbw_coarse;
+
+typedef struct qbw_ctx qbw_ctx;
+typedef struct qbw_saved qbw_saved;
+typedef struct qbw_batch qbw_batch;
+typedef void* qbw_stream; /* hipStream_t */
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device` (workspaces grow on demand).
+ * Errors: QBW_E_HIP if the device cannot be set, QBW_E_NOMEM. */
+qbw_status qbw_create(qbw_ctx** ctx, int32_t device);
+/* Free a context and its workspaces (NULL is a no-op). */
+void qbw_destroy(qbw_ctx* ctx);
+/* Thread-local message of the last failure (never NULL). */
+const char* qbw_last_error(void);
+/* xi = 1e-12, max_ipf_iter = 50, flags = 0. */
+qbw_opts qbw_default_opts(void);
+/* Library version string. */
+const char* qbw_version(void);
+
+/* ---- whole method ------------------------------------------------------ */
+
+/* Lower and upper bound of W_p(a, b) (Algorithms 4 and 5).  a, b: device.
+ * Pools a and b on the device, copies the coarse measures to the host, solves
+ * the coarse problem with the project's network simplex (host, serial),
+ * uploads the solution and runs the fine stages on the device.  out: host.
+ * saved: if opts.flags has QBW_SAVE_FOR_BWD and saved != NULL, receives a
+ * handle for qbw_bounds_backward (free with qbw_saved_free); a and b must stay
+ * valid until then.  Errors: QBW_E_GRID, QBW_E_MASS (checked on the pooled
+ * masses), QBW_E_LP, QBW_E_HIP. */
+qbw_status qbw_bounds(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                      const qbw_opts* opts, qbw_result* out, qbw_saved** saved, qbw_stream stream);
+
+/* Same as qbw_bounds with the coarse solution supplied by the caller (host
+ * memory, see qbw_coarse); no coarse solve.  Validates coarse->Q == n^d and
+ * every index.  Errors: QBW_E_GRID, QBW_E_INVAL, QBW_E_HIP. */
+qbw_status qbw_bounds_with_coarse(qbw_ctx* ctx, const qbw_grid* grid, const double* a,
+                                  const double* b, const qbw_coarse* coarse, const qbw_opts* opts,
+                                  qbw_result* out, qbw_saved** saved, qbw_stream stream);
+
+/* Gradients of dlower * lower + dupper * upper with respect to a and b, with
+ * the coarse solution frozen, accumulated (+=) into grad_a, grad_b (device,
+ * float64, shape of a).  Lower bound: through the potentials (d S / d a = f,
+ * d S / d b = g).  Upper bound: through the plan cost and the exact number of
+ * IPF iterations of the forward pass (checkpointed iterates); the TV
+ * corrections are treated as constants.  grad_fhat (device float64 of length
+ * N^d, may be NULL) receives d lower / d f^ through the c-transform arg-mins
+ * (requires QBW_WANT_ARGMIN in the forward).  Errors: QBW_E_STATE. */
+qbw_status qbw_bounds_backward(qbw_ctx* ctx, const qbw_saved* saved, double dlower, double dupper,
+                               double* grad_a, double* grad_b, double* grad_fhat,
+                               qbw_stream stream);
+void qbw_saved_free(qbw_saved* saved);
+
+/* ---- stages (each follows one step of the method) ---------------------- */
+
+/* SumPool with size and stride k (Section 2.2): out[K] = sum of m over block
+ * K.  m: device (N^d), out: device (n^d float64). */
+qbw_status qbw_sumpool(qbw_ctx* ctx, const qbw_grid* grid, const double* m, double* out,
+                       qbw_stream stream);
+
+/* Centre cost C~_KL = |x~_K - x~_L|^p (Algorithms 4-5): out host, n^d x n^d,
+ * row-major. */
+qbw_status qbw_coarse_cost(const qbw_grid* grid, double* out);
+
+/* Marginally weighted cost (Section 3.2, Algorithm 3):
+ * C-bar_KL = sum_{x in X_K, y in Y_L} |x - y|^p a(x) b(y) / (a~_K b~_L), with
+ * C-bar_KL = C~_KL where a~_K b~_L = 0.  a, b: device; out: device, n^d x n^d
+ * float64 row-major. */
+qbw_status qbw_cbar(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                    double* out, qbw_stream stream);
+
+/* Exact coarse Kantorovich solve on C~ (network simplex, host).  a_t, b_t:
+ * host coarse measures (n^d).  Outputs (host, caller-allocated): rows, cols,
+ * vals with capacity 2 n^d - 1, *nnz; f, g (n^d) optimal potentials with
+ * f_K + g_L <= C~_KL, shifted so that sum_K a_t[K] f[K] = 0 (within 1/2 for
+ * p = 2, where the shift is rounded to keep the potentials integers);
+ * *objective = <pi~, C~>.  Errors: QBW_E_MASS, QBW_E_LP. */
+qbw_status qbw_coarse_solve_host(const qbw_grid* grid, const double* a_t, const double* b_t,
+                                 int32_t* rows, int32_t* cols, double* vals, int32_t* nnz,
+                                 double* f, double* g, double* objective);
+
+/* Multilinear upscaling of a coarse potential (Section 3.5, interpolation
+ * R): ftil device float64 (n^d) -> fhat device float32 (N^d).  Pixels
+ * outside the hull of the block centres take the nearest edge value. */
+qbw_status qbw_upscale_potential(qbw_ctx* ctx, const qbw_grid* grid, const double* ftil,
+                                 float* fhat, qbw_stream stream);
+
+/* Lazy c-transform (Section 4, eq. of the lazy c-transform):
+ * dst[j] = min_i RN32(RN32(|x_i - x_j|^p) - src[i]) over all N^d pixels,
+ * float32, exact min; argmin (device int32, may be NULL) = the lowest flat
+ * index attaining it.  src, dst: device float32 (N^d). */
+qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
+                          int32_t* argmin, qbw_stream stream);
+
+/* IPF of Algorithm 4 on the uniformly upscaled coupling: from b_s = 1,
+ * repeat a_s = a / (pi^ b_s), b_s = b / (pi^T a_s) until the L1 marginal
+ * error < opts->xi or opts->max_ipf_iter iterations (0/0 := 0).  a_s, b_s:
+ * device float64 (N^d) outputs.  *iters, *residual: host. */
+qbw_status qbw_ipf(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                   const qbw_coarse* coarse, const qbw_opts* opts, double* a_s, double* b_s,
+                   int32_t* iters, double* residual, qbw_stream stream);
+
+/* <diag(a_s) pi^ diag(b_s), C> summed over the support of pi^ (Section 4):
+ * *cost host. */
+qbw_status qbw_plan_cost(qbw_ctx* ctx, const qbw_grid* grid, const qbw_coarse* coarse,
+                         const double* a_s, const double* b_s, double* cost, qbw_stream stream);
+
+/* Weighted-TV corrections of Algorithm 4 for scalings a_s, b_s:
+ * Delta_mu = 2^(1-1/p) <w, |a_s * (pi^ b_s) - a|>^(1/p), Delta_nu likewise,
+ * w_i = |x-bar - x_i|^p, x-bar the grid mean.  Values as the paper defines
+ * them (no rounding allowance).  *tv_mu, *tv_nu host. */
+qbw_status qbw_tv(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                  const qbw_coarse* coarse, const double* a_s, const double* b_s,
+                  double* tv_mu, double* tv_nu, qbw_stream stream);
+
+/* ---- batched path: many pairs of uneven sizes in one persistent launch --- */
+
+typedef struct qbw_job {
+  qbw_grid grid;
+  const double* a; /* device */
+  const double* b; /* device */
+  double* grad_a;  /* device, may be NULL (no backward for this job) */
+  double* grad_b;  /* device, may be NULL */
+} qbw_job;
+
+#define QBW_BATCH_BACKWARD 1u /* qbw_batch_run also runs the backward pass */
+#define QBW_BATCH_GRAPH 2u    /* capture the device work in a hipGraph, replay it */
+#define QBW_BATCH_AUTOTUNE 4u /* time c-transform tilings at creation, keep the fastest */
+
+/* Build a batch: validates every job, pools the measures, solves the coarse
+ * problems (host threads) unless `coarse` (array of njobs, host) is given,
+ * uploads the coarse solutions, plans the persistent work queues and (flag)
+ * autotunes and captures a graph.  The job buffers must stay valid for the
+ * batch's life.  Errors as qbw_bounds. */
+qbw_status qbw_batch_create(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs,
+                            const qbw_coarse* coarse, const qbw_opts* opts, uint32_t batch_flags,
+                            qbw_batch** out, qbw_stream stream);
+/* One forward (+ backward with QBW_BATCH_BACKWARD) pass over every job.
+ * dlower, dupper: host arrays of njobs upstream gradients (used only with
+ * QBW_BATCH_BACKWARD; NULL means 1).  Asynchronous. */
+qbw_status qbw_batch_run(qbw_batch* batch, const double* dlower, const double* dupper,
+                         qbw_stream stream);
+/* Copy the last run's results (host, njobs entries); synchronises. */
+qbw_status qbw_batch_results(qbw_batch* batch, qbw_result* out, qbw_stream stream);
+/* Tile shape chosen for a job: targets per lane and source splits. */
+qbw_status qbw_batch_tiling(const qbw_batch* batch, int32_t job, int32_t* targets_per_lane,
+                            int32_t* splits);
+void qbw_batch_destroy(qbw_batch* batch);
+
+/* Convenience: create, run the forward pass once, fetch results, destroy. */
+qbw_status qbw_bounds_batched(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs,
+                              const qbw_opts* opts, qbw_result* out, qbw_stream stream);
+
+/* ---- autotuner --------------------------------------------------------- */
+
+/* Time the c-transform tilings for `grid` (targets per lane x source splits)
+ * on the device and remember the fastest in the context and in the on-disk
+ * cache (path from env QBW_TUNE_CACHE, default ~/.cache/qbw_tune.txt).
+ * Outputs host. */
+qbw_status qbw_autotune_ctransform(qbw_ctx* ctx, const qbw_grid* grid, int32_t* targets_per_lane,
+                                   int32_t* splits, double* best_ms, qbw_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QBW_H */

@@ -1,0 +1,108 @@
+"""ctypes declarations of libqbw's C ABI (include/qbw.h).  Marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqbw.so")
+
+QBW_WANT_ARGMIN = 1
+QBW_SAVE_FOR_BWD = 2
+QBW_WARN_IPF_NOT_CONVERGED = 1
+QBW_WARN_LB_CLIPPED = 2
+QBW_BATCH_BACKWARD = 1
+QBW_BATCH_GRAPH = 2
+QBW_BATCH_AUTOTUNE = 4
+
+STATUS = {0: "QBW_OK", 1: "QBW_E_INVAL", 2: "QBW_E_GRID", 3: "QBW_E_MASS", 4: "QBW_E_LP",
+          5: "QBW_E_HIP", 6: "QBW_E_NOMEM", 7: "QBW_E_STATE"}
+
+
+class QbwGrid(C.Structure):
+    _fields_ = [("d", C.c_int32), ("N", C.c_int32), ("k", C.c_int32), ("p", C.c_int32)]
+
+
+class QbwOpts(C.Structure):
+    _fields_ = [("xi", C.c_double), ("max_ipf_iter", C.c_int32), ("flags", C.c_uint32)]
+
+
+class QbwResult(C.Structure):
+    _fields_ = [("lower", C.c_double), ("upper", C.c_double), ("lower_S", C.c_double),
+                ("feas_shift", C.c_double), ("upper_cost", C.c_double), ("tv_mu", C.c_double),
+                ("tv_nu", C.c_double), ("ipf_residual", C.c_double),
+                ("coarse_objective", C.c_double), ("ipf_iters", C.c_int32), ("warn", C.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class QbwCoarse(C.Structure):
+    _fields_ = [("Q", C.c_int32), ("nnz", C.c_int32), ("rows", C.POINTER(C.c_int32)),
+                ("cols", C.POINTER(C.c_int32)), ("vals", C.POINTER(C.c_double)),
+                ("f", C.POINTER(C.c_double))]
+
+
+class QbwJob(C.Structure):
+    _fields_ = [("grid", QbwGrid), ("a", C.c_void_p), ("b", C.c_void_p),
+                ("grad_a", C.c_void_p), ("grad_b", C.c_void_p)]
+
+
+# (name, restype, argtypes) for every symbol include/qbw.h declares
+_vp, _i32, _u32, _d = C.c_void_p, C.c_int32, C.c_uint32, C.c_double
+_pg, _po, _pr, _pc = C.POINTER(QbwGrid), C.POINTER(QbwOpts), C.POINTER(QbwResult), C.POINTER(QbwCoarse)
+SIGNATURES = [
+    ("qbw_create", C.c_int, [C.POINTER(_vp), _i32]),
+    ("qbw_destroy", None, [_vp]),
+    ("qbw_last_error", C.c_char_p, []),
+    ("qbw_default_opts", QbwOpts, []),
+    ("qbw_version", C.c_char_p, []),
+    ("qbw_bounds", C.c_int, [_vp, _pg, _vp, _vp, _po, _pr, C.POINTER(_vp), _vp]),
+    ("qbw_bounds_with_coarse", C.c_int, [_vp, _pg, _vp, _vp, _pc, _po, _pr, C.POINTER(_vp), _vp]),
+    ("qbw_bounds_backward", C.c_int, [_vp, _vp, _d, _d, _vp, _vp, _vp, _vp]),
+    ("qbw_saved_free", None, [_vp]),
+    ("qbw_sumpool", C.c_int, [_vp, _pg, _vp, _vp, _vp]),
+    ("qbw_coarse_cost", C.c_int, [_pg, _vp]),
+    ("qbw_cbar", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
+    ("qbw_coarse_solve_host", C.c_int, [_pg, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("qbw_upscale_potential", C.c_int, [_vp, _pg, _vp, _vp, _vp]),
+    ("qbw_ctransform", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
+    ("qbw_ipf", C.c_int, [_vp, _pg, _vp, _vp, _pc, _po, _vp, _vp, _vp, _vp, _vp]),
+    ("qbw_plan_cost", C.c_int, [_vp, _pg, _pc, _vp, _vp, _vp, _vp]),
+    ("qbw_tv", C.c_int, [_vp, _pg, _vp, _vp, _pc, _vp, _vp, _vp, _vp, _vp]),
+    ("qbw_batch_create", C.c_int, [_vp, C.POINTER(QbwJob), _i32, _pc, _po, _u32, C.POINTER(_vp), _vp]),
+    ("qbw_batch_run", C.c_int, [_vp, _vp, _vp, _vp]),
+    ("qbw_batch_results", C.c_int, [_vp, _pr, _vp]),
+    ("qbw_batch_tiling", C.c_int, [_vp, _i32, _vp, _vp]),
+    ("qbw_batch_destroy", None, [_vp]),
+    ("qbw_bounds_batched", C.c_int, [_vp, C.POINTER(QbwJob), _i32, _po, _pr, _vp]),
+    ("qbw_autotune_ctransform", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
+]
+
+_lib = None
+
+
+class QbwError(RuntimeError):
+    pass
+
+
+def load(path: str = LIB_PATH):
+    """Load libqbw.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise QbwError(f"{path} is missing: build it with `python -m paper_2506_00976_amd.build`")
+    lib = C.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int, what: str = ""):
+    if rc != 0:
+        msg = load().qbw_last_error().decode()
+        raise QbwError(f"{what}: {STATUS.get(rc, rc)}: {msg}")

@@ -1,0 +1,1189 @@
+// Host orchestration of libqbw: validation, workspace planning, the C ABI.
+//
+// One "plan" describes a set of jobs (one pair, or a batch of pairs of uneven
+// sizes): it lays out every per-job device buffer in one arena, uploads the
+// job table, the coarse couplings (entry list + CSR/CSC views) and the work
+// tables, and enqueues the forward and backward kernel sequences.  The
+// single-pair calls and the batched calls share it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "qbw_internal.h"
+
+namespace qbw {
+
+static thread_local std::string g_err = "no error";
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+#define HIPCHK(x)                                                         \
+  do {                                                                    \
+    hipError_t e_ = (x);                                                  \
+    if (e_ != hipSuccess) {                                               \
+      set_error("%s failed: %s", #x, hipGetErrorString(e_));              \
+      return QBW_E_HIP;                                                   \
+    }                                                                     \
+  } while (0)
+#define CHK(x)                        \
+  do {                                \
+    int r_ = (x);                     \
+    if (r_ != QBW_OK) return (qbw_status)r_; \
+  } while (0)
+
+static inline hipStream_t S(qbw_stream s) { return (hipStream_t)s; }
+
+static int ipow(int b, int e) {
+  int r = 1;
+  while (e--) r *= b;
+  return r;
+}
+
+static int check_grid(const qbw_grid* g) {
+  if (!g) { set_error("grid is NULL"); return QBW_E_INVAL; }
+  if (g->d != 2 && g->d != 3) { set_error("d must be 2 or 3 (got %d)", g->d); return QBW_E_GRID; }
+  if (g->p != 1 && g->p != 2) { set_error("p must be 1 or 2 (got %d)", g->p); return QBW_E_GRID; }
+  if (g->N < 1 || g->k < 1 || g->k > g->N || g->N % g->k) {
+    set_error("need 1 <= k <= N and N %% k == 0 (N=%d k=%d)", g->N, g->k);
+    return QBW_E_GRID;
+  }
+  const double P = std::pow((double)g->N, g->d);
+  if (P > (double)(1 << 26)) { set_error("grid too large (N^d = %.0f > 2^26)", P); return QBW_E_GRID; }
+  if (g->d * (double)(g->N - 1) * (g->N - 1) >= 16777216.0) {
+    set_error("squared distances must stay below 2^24 (float32-exact)");
+    return QBW_E_GRID;
+  }
+  return QBW_OK;
+}
+
+void centre_cost(const qbw_grid& g, double* out) {
+  const int n = g.N / g.k;
+  const int Q = ipow(n, g.d);
+  for (int K = 0; K < Q; ++K) {
+    int kc[3] = {0, 0, 0}, t = K;
+    for (int a = g.d - 1; a >= 0; --a) { kc[a] = t % n; t /= n; }
+    for (int L = 0; L < Q; ++L) {
+      int lc[3] = {0, 0, 0}, s = L;
+      for (int a = g.d - 1; a >= 0; --a) { lc[a] = s % n; s /= n; }
+      long long d2 = 0;
+      for (int a = 0; a < g.d; ++a) {
+        long long e = (long long)g.k * (kc[a] - lc[a]);
+        d2 += e * e;
+      }
+      out[(size_t)K * Q + L] = g.p == 2 ? (double)d2 : std::sqrt((double)d2);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ device arena
+
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  ~Arena() { if (base) (void)hipFree(base); }
+  int reserve(size_t bytes) {
+    if (bytes <= cap) return QBW_OK;
+    if (base) { HIPCHK(hipFree(base)); base = nullptr; cap = 0; }
+    size_t want = std::max(bytes, cap * 3 / 2);
+    if (hipMalloc(&base, want) != hipSuccess) {
+      base = nullptr;
+      if (hipMalloc(&base, bytes) != hipSuccess) {
+        base = nullptr;
+        set_error("device allocation of %zu bytes failed", bytes);
+        return QBW_E_NOMEM;
+      }
+      want = bytes;
+    }
+    cap = want;
+    return QBW_OK;
+  }
+};
+
+// Byte layout builder: records (offset) for each named buffer.
+struct Layout {
+  size_t size = 0;
+  size_t add(size_t bytes) {
+    size_t off = (size + 255) & ~size_t(255);
+    size = off + bytes;
+    return off;
+  }
+};
+
+// ------------------------------------------------------------------ tuning
+
+struct Tiling { int R, S; };
+
+static int default_R(int N) {
+  for (int r : {16, 8, 4, 2})
+    if (N % r == 0) return r;
+  return 1;
+}
+
+// ------------------------------------------------------------------ context
+
+}  // namespace qbw
+
+struct qbw_ctx {
+  int device = 0;
+  int num_cu = 256;
+  qbw::Arena work;      // scratch for single-pair calls that keep nothing
+  std::map<std::tuple<int, int, int>, qbw::Tiling> tuned;  // (d, N, p) -> tiling
+  int target_waves = 4096;
+};
+
+namespace qbw {
+
+struct CoarseHost {
+  int Q = 0, nnz = 0;
+  std::vector<int> rows, cols;  // sorted by row
+  std::vector<double> vals, f;
+  std::vector<int> csr_ptr, csc_ptr, csc_idx;
+  double obj = 0;
+};
+
+static int make_coarse(const qbw_grid& g, const qbw_coarse* c, CoarseHost* out) {
+  const int n = g.N / g.k, Q = ipow(n, g.d);
+  if (!c || !c->rows || !c->cols || !c->vals || !c->f) { set_error("coarse solution has NULL arrays"); return QBW_E_INVAL; }
+  if (c->Q != Q) { set_error("coarse solution has Q=%d, grid needs %d", c->Q, Q); return QBW_E_INVAL; }
+  if (c->nnz < 1 || c->nnz > Q * Q) { set_error("coarse coupling has %d entries", c->nnz); return QBW_E_INVAL; }
+  out->Q = Q;
+  out->nnz = c->nnz;
+  std::vector<int> ord(c->nnz);
+  std::iota(ord.begin(), ord.end(), 0);
+  for (int e = 0; e < c->nnz; ++e) {
+    if (c->rows[e] < 0 || c->rows[e] >= Q || c->cols[e] < 0 || c->cols[e] >= Q) {
+      set_error("coarse coupling entry %d has an index out of range", e);
+      return QBW_E_INVAL;
+    }
+    if (!(c->vals[e] >= 0.0) || !std::isfinite(c->vals[e])) {
+      set_error("coarse coupling entry %d is negative or not finite", e);
+      return QBW_E_INVAL;
+    }
+  }
+  for (int K = 0; K < Q; ++K)
+    if (!std::isfinite(c->f[K])) { set_error("coarse potential is not finite"); return QBW_E_INVAL; }
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return c->rows[a] < c->rows[b]; });
+  out->rows.resize(c->nnz); out->cols.resize(c->nnz); out->vals.resize(c->nnz);
+  double obj = 0;
+  std::vector<double> Ct;
+  for (int q = 0; q < c->nnz; ++q) {
+    out->rows[q] = c->rows[ord[q]];
+    out->cols[q] = c->cols[ord[q]];
+    out->vals[q] = c->vals[ord[q]];
+  }
+  out->csr_ptr.assign(Q + 1, 0);
+  out->csc_ptr.assign(Q + 1, 0);
+  for (int q = 0; q < c->nnz; ++q) { out->csr_ptr[out->rows[q] + 1]++; out->csc_ptr[out->cols[q] + 1]++; }
+  for (int K = 0; K < Q; ++K) { out->csr_ptr[K + 1] += out->csr_ptr[K]; out->csc_ptr[K + 1] += out->csc_ptr[K]; }
+  out->csc_idx.resize(c->nnz);
+  std::vector<int> fill(out->csc_ptr.begin(), out->csc_ptr.end() - 1);
+  for (int q = 0; q < c->nnz; ++q) out->csc_idx[fill[out->cols[q]]++] = q;
+  out->f.assign(c->f, c->f + Q);
+  // objective <pi~, C~> (reported only)
+  const int n_ = n;
+  for (int q = 0; q < c->nnz; ++q) {
+    int K = out->rows[q], L = out->cols[q];
+    long long d2 = 0;
+    int tk = K, tl = L;
+    for (int a = 0; a < g.d; ++a) {
+      long long e = (long long)g.k * ((tk % n_) - (tl % n_));
+      d2 += e * e;
+      tk /= n_; tl /= n_;
+    }
+    obj += out->vals[q] * (g.p == 2 ? (double)d2 : std::sqrt((double)d2));
+  }
+  out->obj = obj;
+  return QBW_OK;
+}
+
+// A job as given to the planner.
+struct JobIn {
+  qbw_grid g;
+  const double* a;
+  const double* b;
+  double* ga;
+  double* gb;
+  const CoarseHost* coarse;  // may be null (stage-only plans)
+  Tiling tiling;
+};
+
+enum PlanMode : unsigned {
+  PM_FORWARD = 1, PM_ARGMIN = 2, PM_BACKWARD = 4, PM_CBAR = 8,
+};
+
+struct Plan {
+  int njobs = 0;
+  unsigned mode = 0;
+  int max_iter = 50;
+  double xi = 1e-12;
+  std::vector<DevJob> hj;
+  std::vector<JobIn> in;
+  Arena own;         // used when the plan owns its memory
+  char* base = nullptr;
+  DevJob* djobs = nullptr;
+  int *off_chunk = nullptr, *off_pool = nullptr, *off_entry = nullptr, *off_block = nullptr,
+      *off_cbar = nullptr, *off_mom = nullptr;
+  int tot_chunk = 0, tot_pool = 0, tot_entry = 0, tot_block = 0, tot_cbar = 0, tot_mom = 0;
+  CtItem* items = nullptr;
+  int n_items = 0;
+  int ct_grid = 1;
+  int* ints = nullptr;   // [0..1] work counters, [2..2+njobs) flags
+  int n_ints = 0;
+  double* dl = nullptr;  // per-job upstream gradients
+  double* du = nullptr;
+  double* bwd_scratch = nullptr;
+  int max_q = 1;              // row stride of bwd_scratch (per job: 4 x max_q doubles)
+  double* results = nullptr;  // njobs x RS_COUNT
+  double** cbar_out = nullptr;  // device array of njobs pointers
+  double** moms = nullptr;      // device array of 2 njobs pointers
+  double** fhat_grad_out = nullptr;
+  std::vector<double> host_results;
+};
+
+static int choose_splits(std::vector<JobIn>& in, int target_waves) {
+  double total = 0;
+  for (auto& j : in) total += std::pow((double)j.g.N, 2.0 * j.g.d);
+  for (auto& j : in) {
+    const int P = ipow(j.g.N, j.g.d), rows = ipow(j.g.N, j.g.d - 1);
+    if (j.tiling.R <= 0) j.tiling.R = default_R(j.g.N);
+    const int tiles = (P + 64 * j.tiling.R - 1) / (64 * j.tiling.R);
+    if (j.tiling.S <= 0) {
+      const double share = std::pow((double)j.g.N, 2.0 * j.g.d) / total;
+      const double items = std::max<double>(tiles, share * target_waves);
+      j.tiling.S = (int)std::ceil(items / tiles);
+    }
+    j.tiling.S = std::max(1, std::min(j.tiling.S, rows));
+  }
+  return QBW_OK;
+}
+
+// Build the layout, allocate (or reuse) device memory, upload tables.
+static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mode,
+                      const qbw_opts& o, bool own_memory, hipStream_t st) {
+  pl.in = std::move(in);
+  pl.njobs = (int)pl.in.size();
+  pl.mode = mode;
+  pl.max_iter = o.max_ipf_iter;
+  pl.xi = o.xi;
+  const int NJ = pl.njobs;
+  CHK(choose_splits(pl.in, ctx->target_waves));
+  Layout L;
+  struct Offs {
+    size_t mu_t, nu_t, ftil, fhat, g, f, part, win, arg_g, arg_f, e_row, e_col, e_val, csr, csc,
+        csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, gbar_mu, gbar_nu, coef, mom0, mom1,
+        cbar;
+  };
+  std::vector<Offs> offs(NJ);
+  const bool ub = true;
+  for (int j = 0; j < NJ; ++j) {
+    const auto& J = pl.in[j];
+    const int N = J.g.N, d = J.g.d, n = N / J.g.k;
+    const int P = ipow(N, d), Q = ipow(n, d);
+    const int chunks = (P + kChunk - 1) / kChunk;
+    const int nnz = J.coarse ? J.coarse->nnz : 1;
+    Offs& O = offs[j];
+    O.mu_t = L.add(8 * Q);
+    O.nu_t = L.add(8 * Q);
+    O.ftil = L.add(8 * Q);
+    O.fhat = L.add(4 * (size_t)P);
+    O.g = L.add(4 * (size_t)P);
+    O.f = L.add(4 * (size_t)P);
+    O.part = L.add(4 * (size_t)P * J.tiling.S);
+    O.win = L.add(4 * (size_t)P);
+    O.arg_g = (mode & PM_ARGMIN) ? L.add(4 * (size_t)P) : 0;
+    O.arg_f = (mode & PM_ARGMIN) ? L.add(4 * (size_t)P) : 0;
+    O.e_row = L.add(4 * (size_t)nnz);
+    O.e_col = L.add(4 * (size_t)nnz);
+    O.e_val = L.add(8 * (size_t)nnz);
+    O.csr = L.add(4 * (size_t)(Q + 1));
+    O.csc = L.add(4 * (size_t)(Q + 1));
+    O.csc_idx = L.add(4 * (size_t)nnz);
+    O.ipf_u = L.add(8 * (size_t)Q * (o.max_ipf_iter + 2));
+    O.ipf_v = L.add(8 * (size_t)Q * (o.max_ipf_iter + 2));
+    O.a_s = ub ? L.add(8 * (size_t)P) : 0;
+    O.b_s = ub ? L.add(8 * (size_t)P) : 0;
+    O.red_lb = L.add(8 * (size_t)chunks * kRedSlotsLB);
+    O.red_tv = L.add(8 * (size_t)chunks * kRedSlotsTV);
+    O.red_pc = L.add(8 * (size_t)nnz);
+    O.gbar_mu = L.add(8 * (size_t)Q);
+    O.gbar_nu = L.add(8 * (size_t)Q);
+    O.coef = L.add(8 * (size_t)nnz);
+    O.mom0 = (mode & PM_CBAR) ? L.add(8 * 4 * (size_t)Q) : 0;
+    O.mom1 = (mode & PM_CBAR) ? L.add(8 * 4 * (size_t)Q) : 0;
+  }
+  const size_t o_jobs = L.add(sizeof(DevJob) * NJ);
+  const size_t o_offs = L.add(sizeof(int) * 6 * (NJ + 1));
+  // c-transform work items
+  std::vector<CtItem> items;
+  for (int j = 0; j < NJ; ++j) {
+    const auto& J = pl.in[j];
+    const int P = ipow(J.g.N, J.g.d);
+    const int tiles = (P + 64 * J.tiling.R - 1) / (64 * J.tiling.R);
+    for (int s = 0; s < J.tiling.S; ++s)
+      for (int t = 0; t < tiles; ++t) items.push_back({j, t, s, 0});
+  }
+  // longest items first (cost ~ targets x sources of the item)
+  auto item_cost = [&](const CtItem& w) {
+    const auto& J = pl.in[w.job];
+    const double rows = std::pow((double)J.g.N, J.g.d - 1);
+    return 64.0 * J.tiling.R * (rows / J.tiling.S) * J.g.N * (J.g.p == 1 ? 1.4 : 1.0);
+  };
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const CtItem& a, const CtItem& b) { return item_cost(a) > item_cost(b); });
+  pl.n_items = (int)items.size();
+  const size_t o_items = L.add(sizeof(CtItem) * std::max(1, pl.n_items));
+  pl.n_ints = 2 + NJ;
+  const size_t o_ints = L.add(sizeof(int) * pl.n_ints);
+  const size_t o_dl = L.add(8 * NJ), o_du = L.add(8 * NJ);
+  const size_t o_res = L.add(8 * (size_t)RS_COUNT * NJ);
+  size_t maxQ = 1;
+  for (auto& J : pl.in) maxQ = std::max<size_t>(maxQ, ipow(J.g.N / J.g.k, J.g.d));
+  const size_t o_bwd = L.add(8 * 4 * maxQ * NJ);
+  pl.max_q = (int)maxQ;
+  const size_t o_ptrs = L.add(sizeof(double*) * 4 * NJ);
+
+  if (own_memory) {
+    CHK(pl.own.reserve(L.size));
+    pl.base = pl.own.base;
+  } else {
+    CHK(ctx->work.reserve(L.size));
+    pl.base = ctx->work.base;
+  }
+  char* B = pl.base;
+  // host images of the uploaded region
+  pl.hj.resize(NJ);
+  std::vector<int> off(6 * (NJ + 1), 0);
+  for (int j = 0; j < NJ; ++j) {
+    const auto& J = pl.in[j];
+    const Offs& O = offs[j];
+    DevJob& D = pl.hj[j];
+    std::memset(&D, 0, sizeof(D));
+    D.d = J.g.d; D.N = J.g.N; D.k = J.g.k; D.p = J.g.p;
+    D.n = J.g.N / J.g.k;
+    D.P = ipow(D.N, D.d);
+    D.Q = ipow(D.n, D.d);
+    D.rows = ipow(D.N, D.d - 1);
+    D.R = J.tiling.R;
+    D.S = J.tiling.S;
+    D.chunks = (D.P + kChunk - 1) / kChunk;
+    D.nnz = J.coarse ? J.coarse->nnz : 0;
+    D.max_iter = o.max_ipf_iter;
+    D.want_argmin = (mode & PM_ARGMIN) ? 1 : 0;
+    D.xi = o.xi;
+    D.coarse_obj = J.coarse ? J.coarse->obj : 0.0;
+    D.mu = J.a;
+    D.nu = J.b;
+    D.mu_t = (double*)(B + O.mu_t);
+    D.nu_t = (double*)(B + O.nu_t);
+    D.ftil = (const double*)(B + O.ftil);
+    D.fhat = (float*)(B + O.fhat);
+    D.g = (float*)(B + O.g);
+    D.f = (float*)(B + O.f);
+    D.part = (float*)(B + O.part);
+    D.win = (int*)(B + O.win);
+    D.arg_g = (mode & PM_ARGMIN) ? (int*)(B + O.arg_g) : nullptr;
+    D.arg_f = (mode & PM_ARGMIN) ? (int*)(B + O.arg_f) : nullptr;
+    D.e_row = (const int*)(B + O.e_row);
+    D.e_col = (const int*)(B + O.e_col);
+    D.e_val = (const double*)(B + O.e_val);
+    D.csr_ptr = (const int*)(B + O.csr);
+    D.csc_ptr = (const int*)(B + O.csc);
+    D.csc_idx = (const int*)(B + O.csc_idx);
+    D.ipf_u = (double*)(B + O.ipf_u);
+    D.ipf_v = (double*)(B + O.ipf_v);
+    D.a_s = (double*)(B + O.a_s);
+    D.b_s = (double*)(B + O.b_s);
+    D.red_lb = (double*)(B + O.red_lb);
+    D.red_tv = (double*)(B + O.red_tv);
+    D.red_pc = (double*)(B + O.red_pc);
+    D.result = (double*)(B + o_res) + (size_t)RS_COUNT * j;
+    D.flags = (int*)(B + o_ints) + 2 + j;
+    D.grad_a = J.ga;
+    D.grad_b = J.gb;
+    D.gbar_mu = (double*)(B + O.gbar_mu);
+    D.gbar_nu = (double*)(B + O.gbar_nu);
+    D.coef = (double*)(B + O.coef);
+    off[0 * (NJ + 1) + j + 1] = off[0 * (NJ + 1) + j] + D.chunks;
+    off[1 * (NJ + 1) + j + 1] = off[1 * (NJ + 1) + j] + (D.Q + 255) / 256;
+    off[2 * (NJ + 1) + j + 1] = off[2 * (NJ + 1) + j] + D.nnz;
+    off[3 * (NJ + 1) + j + 1] = off[3 * (NJ + 1) + j] + D.Q;
+    off[4 * (NJ + 1) + j + 1] = off[4 * (NJ + 1) + j] + (int)(((long long)D.Q * D.Q + 255) / 256);
+    off[5 * (NJ + 1) + j + 1] = off[5 * (NJ + 1) + j] + (2 * D.Q + 255) / 256;
+  }
+  pl.djobs = (DevJob*)(B + o_jobs);
+  int* offd = (int*)(B + o_offs);
+  pl.off_chunk = offd;
+  pl.off_pool = offd + (NJ + 1);
+  pl.off_entry = offd + 2 * (NJ + 1);
+  pl.off_block = offd + 3 * (NJ + 1);
+  pl.off_cbar = offd + 4 * (NJ + 1);
+  pl.off_mom = offd + 5 * (NJ + 1);
+  pl.tot_chunk = off[0 * (NJ + 1) + NJ];
+  pl.tot_pool = off[1 * (NJ + 1) + NJ];
+  pl.tot_entry = off[2 * (NJ + 1) + NJ];
+  pl.tot_block = off[3 * (NJ + 1) + NJ];
+  pl.tot_cbar = off[4 * (NJ + 1) + NJ];
+  pl.tot_mom = off[5 * (NJ + 1) + NJ];
+  pl.items = (CtItem*)(B + o_items);
+  pl.ints = (int*)(B + o_ints);
+  pl.dl = (double*)(B + o_dl);
+  pl.du = (double*)(B + o_du);
+  pl.results = (double*)(B + o_res);
+  pl.bwd_scratch = (double*)(B + o_bwd);
+  double** ptrs = (double**)(B + o_ptrs);
+  pl.cbar_out = ptrs;
+  pl.moms = ptrs + NJ;
+  pl.fhat_grad_out = ptrs + 3 * NJ;
+  // persistent grid: enough waves to fill the chip, never more than the items
+  pl.ct_grid = std::max(1, std::min(pl.n_items, ctx->num_cu * 4 * 8));
+
+  // uploads
+  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob) * NJ, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(offd, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, st));
+  if (pl.n_items)
+    HIPCHK(hipMemcpyAsync(pl.items, items.data(), sizeof(CtItem) * items.size(), hipMemcpyHostToDevice, st));
+  std::vector<double*> hp(4 * NJ, nullptr);
+  for (int j = 0; j < NJ; ++j) {
+    hp[NJ + 2 * j] = (mode & PM_CBAR) ? (double*)(B + offs[j].mom0) : nullptr;
+    hp[NJ + 2 * j + 1] = (mode & PM_CBAR) ? (double*)(B + offs[j].mom1) : nullptr;
+  }
+  HIPCHK(hipMemcpyAsync(ptrs, hp.data(), sizeof(double*) * hp.size(), hipMemcpyHostToDevice, st));
+  std::vector<double> ones(NJ, 1.0);
+  HIPCHK(hipMemcpyAsync(pl.dl, ones.data(), 8 * NJ, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pl.du, ones.data(), 8 * NJ, hipMemcpyHostToDevice, st));
+  for (int j = 0; j < NJ; ++j) {
+    const CoarseHost* C = pl.in[j].coarse;
+    if (!C) continue;
+    const Offs& O = offs[j];
+    HIPCHK(hipMemcpyAsync(B + O.ftil, C->f.data(), 8 * C->Q, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B + O.e_row, C->rows.data(), 4 * C->nnz, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B + O.e_col, C->cols.data(), 4 * C->nnz, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B + O.e_val, C->vals.data(), 8 * C->nnz, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B + O.csr, C->csr_ptr.data(), 4 * (C->Q + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B + O.csc, C->csc_ptr.data(), 4 * (C->Q + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B + O.csc_idx, C->csc_idx.data(), 4 * C->nnz, hipMemcpyHostToDevice, st));
+  }
+  // the uploads read pageable host vectors that go out of scope: finish them
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
+static int enqueue_ctransforms(Plan& pl, hipStream_t st) {
+  const int NJ = pl.njobs;
+  for (int phase = 0; phase < 2; ++phase) {
+    CHK(launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints + phase, phase, pl.ct_grid, st));
+    CHK(launch_merge(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
+    if (pl.mode & PM_ARGMIN) CHK(launch_argmin(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
+  }
+  return QBW_OK;
+}
+
+static int enqueue_forward(Plan& pl, hipStream_t st) {
+  const int NJ = pl.njobs;
+  CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
+  CHK(launch_pool(pl.djobs, NJ, pl.off_pool, pl.tot_pool, st));
+  // lower bound (Algorithm 5)
+  CHK(launch_upscale(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
+  CHK(enqueue_ctransforms(pl, st));
+  CHK(launch_lb_partial(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
+  // upper bound (Algorithm 4)
+  CHK(launch_ipf(pl.djobs, NJ, st));
+  CHK(launch_scalings(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
+  CHK(launch_tv_partial(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
+  CHK(launch_plancost(pl.djobs, NJ, pl.off_entry, pl.tot_entry, st));
+  CHK(launch_finalize(pl.djobs, NJ, st));
+  return QBW_OK;
+}
+
+static int enqueue_backward(Plan& pl, hipStream_t st) {
+  const int NJ = pl.njobs;
+  CHK(launch_lb_grad(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, st));
+  CHK(launch_ub_coarse_bwd2(pl.djobs, NJ, pl.bwd_scratch, pl.max_q, st));
+  CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 0, st));
+  CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 1, st));
+  return QBW_OK;
+}
+
+static void to_result(const double* r, qbw_result* out) {
+  out->lower = r[RS_LOWER];
+  out->upper = r[RS_UPPER];
+  out->lower_S = r[RS_LOWER_S];
+  out->feas_shift = r[RS_SHIFT];
+  out->upper_cost = r[RS_UPPER_COST];
+  out->tv_mu = r[RS_TV_MU];
+  out->tv_nu = r[RS_TV_NU];
+  out->ipf_residual = r[RS_IPF_RESID];
+  out->coarse_objective = r[RS_COARSE_OBJ];
+  out->ipf_iters = (int32_t)r[RS_IPF_ITERS];
+  out->warn = (uint32_t)r[RS_WARN];
+}
+
+static int fetch_results(Plan& pl, hipStream_t st) {
+  pl.host_results.resize((size_t)RS_COUNT * pl.njobs);
+  HIPCHK(hipMemcpyAsync(pl.host_results.data(), pl.results, 8 * pl.host_results.size(),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
+// Pool on the device, validate on the host (negative / NaN entries, masses).
+static int pool_and_check(qbw_ctx* ctx, const std::vector<JobIn>& jobs, std::vector<std::vector<double>>* mt,
+                          std::vector<std::vector<double>>* nt, hipStream_t st) {
+  Plan pl;
+  qbw_opts o = qbw_default_opts();
+  o.max_ipf_iter = 1;
+  CHK(plan_build(ctx, pl, jobs, 0, o, true, st));
+  CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
+  CHK(launch_pool(pl.djobs, pl.njobs, pl.off_pool, pl.tot_pool, st));
+  std::vector<int> flags(pl.n_ints);
+  mt->resize(pl.njobs);
+  nt->resize(pl.njobs);
+  for (int j = 0; j < pl.njobs; ++j) {
+    const DevJob& D = pl.hj[j];
+    (*mt)[j].resize(D.Q);
+    (*nt)[j].resize(D.Q);
+    HIPCHK(hipMemcpyAsync((*mt)[j].data(), D.mu_t, 8 * D.Q, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync((*nt)[j].data(), D.nu_t, 8 * D.Q, hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipMemcpyAsync(flags.data(), pl.ints, 4 * pl.n_ints, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int j = 0; j < pl.njobs; ++j) {
+    const int fl = flags[2 + j];
+    if (fl & 2) { set_error("job %d: a measure contains NaN", j); return QBW_E_MASS; }
+    if (fl & 1) { set_error("job %d: a measure has a negative entry", j); return QBW_E_MASS; }
+    double sa = 0, sb = 0;
+    for (double v : (*mt)[j]) sa += v;
+    for (double v : (*nt)[j]) sb += v;
+    if (!(sa > 0) || !(sb > 0) || !std::isfinite(sa) || !std::isfinite(sb)) {
+      set_error("job %d: a measure has no mass", j);
+      return QBW_E_MASS;
+    }
+    if (std::fabs(sa - sb) > 1e-10 * std::max(sa, sb)) {
+      set_error("job %d: unequal masses %.17g vs %.17g", j, sa, sb);
+      return QBW_E_MASS;
+    }
+  }
+  return QBW_OK;
+}
+
+static int solve_coarse_host(const qbw_grid& g, const std::vector<double>& mt, const std::vector<double>& nt,
+                             CoarseSolution* sol) {
+  const int Q = (int)mt.size();
+  std::vector<double> C((size_t)Q * Q);
+  centre_cost(g, C.data());
+  CoarseProblem P{Q, mt.data(), nt.data(), C.data(), g.p == 2};
+  int rc = coarse_solve(P, sol);
+  if (rc != QBW_OK) set_error("coarse network simplex failed (Q=%d)", Q);
+  return rc;
+}
+
+static int to_coarse_host(const qbw_grid& g, const CoarseSolution& s, CoarseHost* out) {
+  qbw_coarse c;
+  c.Q = (int)s.f.size();
+  c.nnz = (int)s.vals.size();
+  c.rows = s.rows.data();
+  c.cols = s.cols.data();
+  c.vals = s.vals.data();
+  c.f = s.f.data();
+  return make_coarse(g, &c, out);
+}
+
+// Parallel host solves over jobs.
+static int solve_all(const std::vector<qbw_grid>& grids, const std::vector<std::vector<double>>& mt,
+                     const std::vector<std::vector<double>>& nt, std::vector<CoarseHost>* out) {
+  const int NJ = (int)grids.size();
+  out->resize(NJ);
+  std::vector<int> rcs(NJ, QBW_OK);
+  std::vector<std::string> errs(NJ);
+  std::atomic<int> next{0};
+  unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nthreads = std::max(1, std::min<int>(NJ, (int)hw));
+  auto worker = [&]() {
+    for (;;) {
+      int j = next.fetch_add(1);
+      if (j >= NJ) break;
+      CoarseSolution sol;
+      int rc = solve_coarse_host(grids[j], mt[j], nt[j], &sol);
+      if (rc == QBW_OK) rc = to_coarse_host(grids[j], sol, &(*out)[j]);
+      rcs[j] = rc;
+      if (rc != QBW_OK) errs[j] = g_err;
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nthreads; ++t) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+  for (int j = 0; j < NJ; ++j)
+    if (rcs[j] != QBW_OK) { set_error("job %d: %s", j, errs[j].c_str()); return rcs[j]; }
+  return QBW_OK;
+}
+
+static Tiling lookup_tiling(qbw_ctx* ctx, const qbw_grid& g) {
+  auto it = ctx->tuned.find({g.d, g.N, g.p});
+  if (it != ctx->tuned.end()) return it->second;
+  return {default_R(g.N), 0};
+}
+
+}  // namespace qbw
+
+using namespace qbw;
+
+struct qbw_saved {
+  Plan plan;
+  std::vector<CoarseHost> coarse;
+};
+
+struct qbw_batch {
+  qbw_ctx* ctx = nullptr;
+  Plan plan;
+  std::vector<CoarseHost> coarse;
+  uint32_t flags = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double* pinned = nullptr;  // 2 * njobs upstream gradients
+};
+
+extern "C" {
+
+const char* qbw_last_error(void) { return g_err.c_str(); }
+const char* qbw_version(void) { return "qbw 0.1 (gfx950)"; }
+
+qbw_opts qbw_default_opts(void) {
+  qbw_opts o;
+  o.xi = 1e-12;
+  o.max_ipf_iter = 50;
+  o.flags = 0;
+  return o;
+}
+
+qbw_status qbw_create(qbw_ctx** ctx, int32_t device) {
+  if (!ctx) { set_error("ctx is NULL"); return QBW_E_INVAL; }
+  *ctx = nullptr;
+  int cnt = 0;
+  HIPCHK(hipGetDeviceCount(&cnt));
+  if (device < 0 || device >= cnt) { set_error("device %d not available (%d devices)", device, cnt); return QBW_E_HIP; }
+  HIPCHK(hipSetDevice(device));
+  auto* c = new (std::nothrow) qbw_ctx();
+  if (!c) { set_error("out of host memory"); return QBW_E_NOMEM; }
+  c->device = device;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+    c->num_cu = cu;
+  c->target_waves = c->num_cu * 16;
+  *ctx = c;
+  return QBW_OK;
+}
+
+void qbw_destroy(qbw_ctx* ctx) { delete ctx; }
+
+static int check_opts(const qbw_opts* o) {
+  if (!o) return QBW_OK;
+  if (o->max_ipf_iter < 1 || o->max_ipf_iter > 100000) { set_error("max_ipf_iter must be in [1, 1e5]"); return QBW_E_INVAL; }
+  if (!(o->xi > 0) && !(o->xi <= 0)) { set_error("xi is NaN"); return QBW_E_INVAL; }
+  return QBW_OK;
+}
+
+static qbw_status bounds_impl(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                              const CoarseHost* C, const qbw_opts* opts, qbw_result* out, qbw_saved** saved,
+                              qbw_stream stream, std::vector<CoarseHost>* keep) {
+  qbw_opts o = opts ? *opts : qbw_default_opts();
+  const bool save = (o.flags & QBW_SAVE_FOR_BWD) && saved;
+  unsigned mode = PM_FORWARD | ((o.flags & QBW_WANT_ARGMIN) ? PM_ARGMIN : 0u);
+  JobIn J{*grid, a, b, nullptr, nullptr, nullptr, lookup_tiling(ctx, *grid)};
+  hipStream_t st = S(stream);
+  if (save) {
+    auto* sv = new (std::nothrow) qbw_saved();
+    if (!sv) { set_error("out of host memory"); return QBW_E_NOMEM; }
+    sv->coarse = std::move(*keep);
+    J.coarse = &sv->coarse[0];
+    int rc = plan_build(ctx, sv->plan, {J}, mode | PM_BACKWARD, o, true, st);
+    if (rc == QBW_OK) rc = enqueue_forward(sv->plan, st);
+    if (rc == QBW_OK) rc = fetch_results(sv->plan, st);
+    if (rc != QBW_OK) { delete sv; return (qbw_status)rc; }
+    to_result(sv->plan.host_results.data(), out);
+    *saved = sv;
+    return QBW_OK;
+  }
+  J.coarse = C;
+  Plan pl;
+  CHK(plan_build(ctx, pl, {J}, mode, o, false, st));
+  CHK(enqueue_forward(pl, st));
+  CHK(fetch_results(pl, st));
+  to_result(pl.host_results.data(), out);
+  if (saved) *saved = nullptr;
+  return QBW_OK;
+}
+
+qbw_status qbw_bounds_with_coarse(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                                  const qbw_coarse* coarse, const qbw_opts* opts, qbw_result* out,
+                                  qbw_saved** saved, qbw_stream stream) {
+  if (!ctx || !a || !b || !out || !coarse) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  CHK(check_opts(opts));
+  std::vector<CoarseHost> ch(1);
+  CHK(make_coarse(*grid, coarse, &ch[0]));
+  return bounds_impl(ctx, grid, a, b, &ch[0], opts, out, saved, stream, &ch);
+}
+
+qbw_status qbw_bounds(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                      const qbw_opts* opts, qbw_result* out, qbw_saved** saved, qbw_stream stream) {
+  if (!ctx || !a || !b || !out) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  CHK(check_opts(opts));
+  std::vector<std::vector<double>> mt, nt;
+  JobIn J{*grid, a, b, nullptr, nullptr, nullptr, {default_R(grid->N), 1}};
+  CHK(pool_and_check(ctx, {J}, &mt, &nt, S(stream)));
+  std::vector<CoarseHost> ch;
+  CHK(solve_all({*grid}, mt, nt, &ch));
+  return bounds_impl(ctx, grid, a, b, &ch[0], opts, out, saved, stream, &ch);
+}
+
+qbw_status qbw_bounds_backward(qbw_ctx* ctx, const qbw_saved* saved, double dlower, double dupper,
+                               double* grad_a, double* grad_b, double* grad_fhat, qbw_stream stream) {
+  if (!ctx || !saved) { set_error("NULL argument"); return QBW_E_INVAL; }
+  if (!grad_a || !grad_b) { set_error("grad_a and grad_b are required"); return QBW_E_INVAL; }
+  auto* sv = const_cast<qbw_saved*>(saved);
+  Plan& pl = sv->plan;
+  hipStream_t st = S(stream);
+  pl.hj[0].grad_a = grad_a;
+  pl.hj[0].grad_b = grad_b;
+  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
+  double g2[2] = {dlower, dupper};
+  HIPCHK(hipMemcpyAsync(pl.dl, &g2[0], 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pl.du, &g2[1], 8, hipMemcpyHostToDevice, st));
+  CHK(enqueue_backward(pl, st));
+  if (grad_fhat) {
+    if (!(pl.mode & PM_ARGMIN)) { set_error("grad_fhat needs QBW_WANT_ARGMIN in the forward pass"); return QBW_E_STATE; }
+    HIPCHK(hipMemcpyAsync(pl.fhat_grad_out, &grad_fhat, sizeof(double*), hipMemcpyHostToDevice, st));
+    CHK(launch_fhat_grad2(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, pl.dl, pl.fhat_grad_out, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
+void qbw_saved_free(qbw_saved* saved) { delete saved; }
+
+// ---------------------------------------------------------------- stages
+
+static JobIn stage_job(const qbw_grid* g, const double* a, const double* b) {
+  return JobIn{*g, a, b, nullptr, nullptr, nullptr, {default_R(g->N), 0}};
+}
+
+qbw_status qbw_sumpool(qbw_ctx* ctx, const qbw_grid* grid, const double* m, double* out, qbw_stream stream) {
+  if (!ctx || !m || !out) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  Plan pl;
+  hipStream_t st = S(stream);
+  CHK(plan_build(ctx, pl, {stage_job(grid, m, m)}, 0, qbw_default_opts(), false, st));
+  pl.hj[0].mu_t = out;
+  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
+  CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_pool, pl.tot_pool, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
+qbw_status qbw_coarse_cost(const qbw_grid* grid, double* out) {
+  if (!out) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  centre_cost(*grid, out);
+  return QBW_OK;
+}
+
+qbw_status qbw_cbar(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b, double* out,
+                    qbw_stream stream) {
+  if (!ctx || !a || !b || !out) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  Plan pl;
+  hipStream_t st = S(stream);
+  CHK(plan_build(ctx, pl, {stage_job(grid, a, b)}, PM_CBAR, qbw_default_opts(), false, st));
+  HIPCHK(hipMemcpyAsync(pl.cbar_out, &out, sizeof(double*), hipMemcpyHostToDevice, st));
+  CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_pool, pl.tot_pool, st));
+  CHK(launch_moments(pl.djobs, 1, pl.off_mom, pl.tot_mom, pl.moms, st));
+  CHK(launch_cbar2(pl.djobs, 1, pl.off_cbar, pl.tot_cbar, pl.cbar_out, (const double* const*)pl.moms, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
+qbw_status qbw_coarse_solve_host(const qbw_grid* grid, const double* a_t, const double* b_t, int32_t* rows,
+                                 int32_t* cols, double* vals, int32_t* nnz, double* f, double* g,
+                                 double* objective) {
+  if (!a_t || !b_t || !rows || !cols || !vals || !nnz || !f || !g) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  const int Q = ipow(grid->N / grid->k, grid->d);
+  std::vector<double> mt(a_t, a_t + Q), nt(b_t, b_t + Q);
+  double sa = 0, sb = 0;
+  for (int K = 0; K < Q; ++K) {
+    if (!(mt[K] >= 0) || !(nt[K] >= 0)) { set_error("coarse masses must be nonnegative"); return QBW_E_MASS; }
+    sa += mt[K]; sb += nt[K];
+  }
+  if (!(sa > 0) || std::fabs(sa - sb) > 1e-10 * std::max(sa, sb)) { set_error("unequal or zero coarse masses"); return QBW_E_MASS; }
+  CoarseSolution sol;
+  CHK(solve_coarse_host(*grid, mt, nt, &sol));
+  if ((int)sol.vals.size() > 2 * Q - 1) { set_error("internal: basis larger than 2Q-1"); return QBW_E_LP; }
+  *nnz = (int)sol.vals.size();
+  for (int e = 0; e < *nnz; ++e) { rows[e] = sol.rows[e]; cols[e] = sol.cols[e]; vals[e] = sol.vals[e]; }
+  for (int K = 0; K < Q; ++K) { f[K] = sol.f[K]; g[K] = sol.g[K]; }
+  if (objective) *objective = sol.objective;
+  return QBW_OK;
+}
+
+qbw_status qbw_upscale_potential(qbw_ctx* ctx, const qbw_grid* grid, const double* ftil, float* fhat,
+                                 qbw_stream stream) {
+  if (!ctx || !ftil || !fhat) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  Plan pl;
+  hipStream_t st = S(stream);
+  CHK(plan_build(ctx, pl, {stage_job(grid, nullptr, nullptr)}, 0, qbw_default_opts(), false, st));
+  pl.hj[0].ftil = ftil;
+  pl.hj[0].fhat = fhat;
+  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
+  CHK(launch_upscale(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
+qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst, int32_t* argmin,
+                          qbw_stream stream) {
+  if (!ctx || !src || !dst) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  Plan pl;
+  hipStream_t st = S(stream);
+  JobIn J = stage_job(grid, nullptr, nullptr);
+  J.tiling = lookup_tiling(ctx, *grid);
+  CHK(plan_build(ctx, pl, {J}, argmin ? PM_ARGMIN : 0u, qbw_default_opts(), false, st));
+  pl.hj[0].fhat = const_cast<float*>(src);
+  pl.hj[0].g = dst;
+  if (argmin) pl.hj[0].arg_g = argmin;
+  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
+  CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
+  CHK(launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints, 0, pl.ct_grid, st));
+  CHK(launch_merge(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, 0, st));
+  if (argmin) CHK(launch_argmin(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, 0, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
+static qbw_status coarse_stage_plan(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                                    const qbw_coarse* coarse, const qbw_opts* opts, Plan& pl, CoarseHost& ch,
+                                    hipStream_t st) {
+  if (!ctx || !coarse) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  CHK(check_opts(opts));
+  CHK(make_coarse(*grid, coarse, &ch));
+  JobIn J = stage_job(grid, a, b);
+  J.coarse = &ch;
+  return (qbw_status)plan_build(ctx, pl, {J}, 0, opts ? *opts : qbw_default_opts(), false, st);
+}
+
+qbw_status qbw_ipf(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                   const qbw_coarse* coarse, const qbw_opts* opts, double* a_s, double* b_s, int32_t* iters,
+                   double* residual, qbw_stream stream) {
+  if (!a || !b || !a_s || !b_s) { set_error("NULL argument"); return QBW_E_INVAL; }
+  Plan pl;
+  CoarseHost ch;
+  hipStream_t st = S(stream);
+  CHK(coarse_stage_plan(ctx, grid, a, b, coarse, opts, pl, ch, st));
+  pl.hj[0].a_s = a_s;
+  pl.hj[0].b_s = b_s;
+  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
+  CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_pool, pl.tot_pool, st));
+  CHK(launch_ipf(pl.djobs, 1, st));
+  CHK(launch_scalings(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, st));
+  CHK(fetch_results(pl, st));
+  if (iters) *iters = (int32_t)pl.host_results[RS_IPF_ITERS];
+  if (residual) *residual = pl.host_results[RS_IPF_RESID];
+  return QBW_OK;
+}
+
+qbw_status qbw_plan_cost(qbw_ctx* ctx, const qbw_grid* grid, const qbw_coarse* coarse, const double* a_s,
+                         const double* b_s, double* cost, qbw_stream stream) {
+  if (!a_s || !b_s || !cost) { set_error("NULL argument"); return QBW_E_INVAL; }
+  Plan pl;
+  CoarseHost ch;
+  hipStream_t st = S(stream);
+  CHK(coarse_stage_plan(ctx, grid, a_s, b_s, coarse, nullptr, pl, ch, st));
+  DevJob& D = pl.hj[0];
+  D.a_s = const_cast<double*>(a_s);
+  D.b_s = const_cast<double*>(b_s);
+  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(D.red_lb, 0, 8 * (size_t)D.chunks * kRedSlotsLB, st));
+  HIPCHK(hipMemsetAsync(D.red_tv, 0, 8 * (size_t)D.chunks * kRedSlotsTV, st));
+  HIPCHK(hipMemsetAsync(D.result, 0, 8 * RS_COUNT, st));
+  CHK(launch_plancost(pl.djobs, 1, pl.off_entry, pl.tot_entry, st));
+  CHK(launch_finalize(pl.djobs, 1, st));
+  CHK(fetch_results(pl, st));
+  *cost = pl.host_results[RS_PCOST_RAW];
+  return QBW_OK;
+}
+
+qbw_status qbw_tv(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                  const qbw_coarse* coarse, const double* a_s, const double* b_s, double* tv_mu, double* tv_nu,
+                  qbw_stream stream) {
+  if (!a || !b || !a_s || !b_s || !tv_mu || !tv_nu) { set_error("NULL argument"); return QBW_E_INVAL; }
+  Plan pl;
+  CoarseHost ch;
+  hipStream_t st = S(stream);
+  CHK(coarse_stage_plan(ctx, grid, a, b, coarse, nullptr, pl, ch, st));
+  DevJob& D = pl.hj[0];
+  D.a_s = const_cast<double*>(a_s);
+  D.b_s = const_cast<double*>(b_s);
+  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(D.red_lb, 0, 8 * (size_t)D.chunks * kRedSlotsLB, st));
+  HIPCHK(hipMemsetAsync(D.red_pc, 0, 8 * (size_t)std::max(1, D.nnz), st));
+  HIPCHK(hipMemsetAsync(D.result, 0, 8 * RS_COUNT, st));
+  CHK(launch_tv_prep(pl.djobs, 1, st));
+  CHK(launch_tv_partial(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, st));
+  CHK(launch_finalize(pl.djobs, 1, st));
+  CHK(fetch_results(pl, st));
+  *tv_mu = pl.host_results[RS_TV_RAW_MU];
+  *tv_nu = pl.host_results[RS_TV_RAW_NU];
+  return QBW_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+static qbw_status batch_enqueue(qbw_batch* B, hipStream_t st) {
+  CHK(enqueue_forward(B->plan, st));
+  if (B->flags & QBW_BATCH_BACKWARD) CHK(enqueue_backward(B->plan, st));
+  return QBW_OK;
+}
+
+static double time_ctransform(qbw_ctx* ctx, Plan& pl, hipStream_t st, int reps) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 1e30;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return 1e30; }
+  double best = 1e30;
+  for (int r = 0; r < reps; ++r) {
+    (void)launch_reset_counter(pl.ints, pl.n_ints, st);
+    (void)hipEventRecord(e0, st);
+    (void)launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints, 0, pl.ct_grid, st);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) break;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, (double)ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)ctx;
+  return best;
+}
+
+static std::string tune_cache_path() {
+  const char* p = std::getenv("QBW_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* h = std::getenv("HOME");
+  return std::string(h ? h : ".") + "/.cache/qbw_tune.txt";
+}
+
+static void load_tune_cache(qbw_ctx* ctx) {
+  std::ifstream in(tune_cache_path());
+  int d, N, p, R, Sp;
+  std::string arch;
+  while (in >> arch >> d >> N >> p >> R >> Sp)
+    if (arch == "gfx950" && !ctx->tuned.count({d, N, p})) ctx->tuned[{d, N, p}] = {R, Sp};
+}
+
+static void save_tune_entry(int d, int N, int p, Tiling t) {
+  std::ofstream out(tune_cache_path(), std::ios::app);
+  if (out) out << "gfx950 " << d << " " << N << " " << p << " " << t.R << " " << t.S << "\n";
+}
+
+qbw_status qbw_autotune_ctransform(qbw_ctx* ctx, const qbw_grid* grid, int32_t* targets_per_lane,
+                                   int32_t* splits, double* best_ms, qbw_stream stream) {
+  if (!ctx) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  hipStream_t st = S(stream);
+  const int N = grid->N, d = grid->d;
+  const int P = ipow(N, d), rows = ipow(N, d - 1);
+  Tiling best{default_R(N), 1};
+  double best_t = 1e30;
+  for (int R : {16, 8, 4}) {
+    if (N % R) continue;
+    const int tiles = (P + 64 * R - 1) / (64 * R);
+    for (int waves : {ctx->num_cu * 4, ctx->num_cu * 8, ctx->num_cu * 16, ctx->num_cu * 32}) {
+      int Sp = std::max(1, std::min(rows, (waves + tiles - 1) / tiles));
+      Plan pl;
+      JobIn J = stage_job(grid, nullptr, nullptr);
+      J.tiling = {R, Sp};
+      CHK(plan_build(ctx, pl, {J}, 0, qbw_default_opts(), false, st));
+      HIPCHK(hipMemsetAsync(pl.hj[0].fhat, 0, 4 * (size_t)P, st));
+      const double t = time_ctransform(ctx, pl, st, 3);
+      if (t < best_t) { best_t = t; best = {R, Sp}; }
+    }
+  }
+  ctx->tuned[{d, N, grid->p}] = best;
+  save_tune_entry(d, N, grid->p, best);
+  if (targets_per_lane) *targets_per_lane = best.R;
+  if (splits) *splits = best.S;
+  if (best_ms) *best_ms = best_t;
+  return QBW_OK;
+}
+
+qbw_status qbw_batch_create(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs, const qbw_coarse* coarse,
+                            const qbw_opts* opts, uint32_t batch_flags, qbw_batch** out, qbw_stream stream) {
+  if (!ctx || !jobs || njobs < 1 || !out) { set_error("NULL argument or empty batch"); return QBW_E_INVAL; }
+  *out = nullptr;
+  CHK(check_opts(opts));
+  qbw_opts o = opts ? *opts : qbw_default_opts();
+  hipStream_t st = S(stream);
+  std::vector<JobIn> in(njobs);
+  std::vector<qbw_grid> grids(njobs);
+  for (int j = 0; j < njobs; ++j) {
+    CHK(check_grid(&jobs[j].grid));
+    if (!jobs[j].a || !jobs[j].b) { set_error("job %d has NULL measures", j); return QBW_E_INVAL; }
+    if ((batch_flags & QBW_BATCH_BACKWARD) && (!jobs[j].grad_a || !jobs[j].grad_b)) {
+      set_error("job %d: backward batches need grad_a and grad_b", j);
+      return QBW_E_INVAL;
+    }
+    in[j] = JobIn{jobs[j].grid, jobs[j].a, jobs[j].b, jobs[j].grad_a, jobs[j].grad_b, nullptr, {0, 0}};
+    grids[j] = jobs[j].grid;
+  }
+  auto* B = new (std::nothrow) qbw_batch();
+  if (!B) { set_error("out of host memory"); return QBW_E_NOMEM; }
+  std::unique_ptr<qbw_batch, void (*)(qbw_batch*)> guard(B, qbw_batch_destroy);
+  B->ctx = ctx;
+  B->flags = batch_flags;
+  B->coarse.resize(njobs);
+  if (coarse) {
+    for (int j = 0; j < njobs; ++j) CHK(make_coarse(grids[j], &coarse[j], &B->coarse[j]));
+  } else {
+    std::vector<std::vector<double>> mt, nt;
+    std::vector<JobIn> pin = in;
+    for (auto& J : pin) J.tiling = {default_R(J.g.N), 1};
+    CHK(pool_and_check(ctx, pin, &mt, &nt, st));
+    CHK(solve_all(grids, mt, nt, &B->coarse));
+  }
+  for (int j = 0; j < njobs; ++j) in[j].coarse = &B->coarse[j];
+  const unsigned mode = PM_FORWARD | ((batch_flags & QBW_BATCH_BACKWARD) ? PM_BACKWARD : 0u) |
+                        ((o.flags & QBW_WANT_ARGMIN) ? PM_ARGMIN : 0u);
+  load_tune_cache(ctx);
+  if (batch_flags & QBW_BATCH_AUTOTUNE) {
+    // batch-level tuning: targets per lane and the total number of waves the
+    // source splits aim for; every candidate times the whole batch's c-transform
+    double best_t = 1e30;
+    int best_R = 0, best_w = ctx->target_waves;
+    for (int R : {16, 8, 4}) {
+      for (int waves : {ctx->num_cu * 4, ctx->num_cu * 8, ctx->num_cu * 16, ctx->num_cu * 32}) {
+        std::vector<JobIn> cand = in;
+        for (auto& J : cand) J.tiling = {(J.g.N % R == 0) ? R : default_R(J.g.N), 0};
+        const int keep = ctx->target_waves;
+        ctx->target_waves = waves;
+        Plan pl;
+        int rc = plan_build(ctx, pl, cand, mode, o, false, st);
+        ctx->target_waves = keep;
+        if (rc != QBW_OK) return (qbw_status)rc;
+        for (auto& D : pl.hj) HIPCHK(hipMemsetAsync(D.fhat, 0, 4 * (size_t)D.P, st));
+        const double t = time_ctransform(ctx, pl, st, 2);
+        if (t < best_t) { best_t = t; best_R = R; best_w = waves; }
+      }
+    }
+    for (auto& J : in) J.tiling = {(J.g.N % best_R == 0) ? best_R : default_R(J.g.N), 0};
+    const int keep = ctx->target_waves;
+    ctx->target_waves = best_w;
+    int rc = plan_build(ctx, B->plan, in, mode, o, true, st);
+    ctx->target_waves = keep;
+    CHK(rc);
+  } else {
+    for (auto& J : in) {
+      auto it = ctx->tuned.find({J.g.d, J.g.N, J.g.p});
+      J.tiling = {it != ctx->tuned.end() ? it->second.R : default_R(J.g.N), 0};
+    }
+    CHK(plan_build(ctx, B->plan, in, mode, o, true, st));
+  }
+  HIPCHK(hipHostMalloc((void**)&B->pinned, 16 * (size_t)njobs, hipHostMallocDefault));
+  if (batch_flags & QBW_BATCH_GRAPH) {
+    HIPCHK(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+    qbw_status rc = batch_enqueue(B, B->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(B->cap_stream, &g);
+    if (rc != QBW_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e2 != hipSuccess) { set_error("graph capture failed: %s", hipGetErrorString(e2)); return QBW_E_HIP; }
+    B->graph = g;
+    HIPCHK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+  }
+  *out = guard.release();
+  return QBW_OK;
+}
+
+qbw_status qbw_batch_run(qbw_batch* B, const double* dlower, const double* dupper, qbw_stream stream) {
+  if (!B) { set_error("NULL batch"); return QBW_E_INVAL; }
+  hipStream_t st = S(stream);
+  const int NJ = B->plan.njobs;
+  if (B->flags & QBW_BATCH_BACKWARD) {
+    for (int j = 0; j < NJ; ++j) {
+      B->pinned[j] = dlower ? dlower[j] : 1.0;
+      B->pinned[NJ + j] = dupper ? dupper[j] : 1.0;
+    }
+    HIPCHK(hipMemcpyAsync(B->plan.dl, B->pinned, 8 * NJ, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B->plan.du, B->pinned + NJ, 8 * NJ, hipMemcpyHostToDevice, st));
+  }
+  if (B->exec) {
+    HIPCHK(hipGraphLaunch(B->exec, st));
+    return QBW_OK;
+  }
+  return batch_enqueue(B, st);
+}
+
+qbw_status qbw_batch_results(qbw_batch* B, qbw_result* out, qbw_stream stream) {
+  if (!B || !out) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(fetch_results(B->plan, S(stream)));
+  for (int j = 0; j < B->plan.njobs; ++j) to_result(B->plan.host_results.data() + (size_t)RS_COUNT * j, &out[j]);
+  return QBW_OK;
+}
+
+qbw_status qbw_batch_tiling(const qbw_batch* B, int32_t job, int32_t* targets_per_lane, int32_t* splits) {
+  if (!B || job < 0 || job >= B->plan.njobs) { set_error("bad batch or job index"); return QBW_E_INVAL; }
+  if (targets_per_lane) *targets_per_lane = B->plan.hj[job].R;
+  if (splits) *splits = B->plan.hj[job].S;
+  return QBW_OK;
+}
+
+void qbw_batch_destroy(qbw_batch* B) {
+  if (!B) return;
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+  if (B->pinned) (void)hipHostFree(B->pinned);
+  delete B;
+}
+
+qbw_status qbw_bounds_batched(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs, const qbw_opts* opts,
+                              qbw_result* out, qbw_stream stream) {
+  qbw_batch* B = nullptr;
+  CHK(qbw_batch_create(ctx, jobs, njobs, nullptr, opts, 0, &B, stream));
+  qbw_status rc = qbw_batch_run(B, nullptr, nullptr, stream);
+  if (rc == QBW_OK) rc = qbw_batch_results(B, out, stream);
+  qbw_batch_destroy(B);
+  return rc;
+}
+
+}  // extern "C"

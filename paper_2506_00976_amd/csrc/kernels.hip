@@ -1,0 +1,1063 @@
+// HIP kernels for gfx950 (CDNA4): fine-grid stages of the quantization bounds.
+//
+// Every kernel works on a table of jobs (DevJob), so one launch serves one
+// pair or a batch of pairs of uneven sizes.  Work items are mapped to jobs by
+// a prefix table (find_job); the c-transform instead pulls items from a
+// global work queue (persistent kernel).  Reductions are deterministic:
+// per-work-group partials in a fixed tree order, combined by a finalize
+// kernel in a fixed order - repeated runs are bitwise identical.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "qbw_internal.h"
+
+namespace qbw {
+
+#define HIP_TRY(x)                                                        \
+  do {                                                                    \
+    hipError_t e_ = (x);                                                  \
+    if (e_ != hipSuccess) {                                               \
+      set_error("%s failed: %s", #x, hipGetErrorString(e_));              \
+      return QBW_E_HIP;                                                   \
+    }                                                                     \
+  } while (0)
+
+__device__ __forceinline__ int find_job(const int* __restrict__ off, int njobs, int item) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int NT>
+__device__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ double block_max(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Coordinates of a flat pixel index (C order).
+__device__ __forceinline__ void pix_coords(int i, int N, int d, int& x0, int& x1, int& x2) {
+  if (d == 2) { x0 = 0; x1 = i / N; x2 = i - x1 * N; }
+  else { x0 = i / (N * N); int r = i - x0 * N * N; x1 = r / N; x2 = r - x1 * N; }
+}
+
+// Flat index of member m (0 <= m < k^d) of coarse block K.
+__device__ __forceinline__ int block_member(int K, int m, int N, int n, int k, int d) {
+  if (d == 2) {
+    int b0 = K / n, b1 = K - b0 * n;
+    int u0 = m / k, u1 = m - u0 * k;
+    return (b0 * k + u0) * N + b1 * k + u1;
+  }
+  int b0 = K / (n * n), r = K - b0 * n * n, b1 = r / n, b2 = r - b1 * n;
+  int u0 = m / (k * k), s = m - u0 * k * k, u1 = s / k, u2 = s - u1 * k;
+  return ((b0 * k + u0) * N + b1 * k + u1) * N + b2 * k + u2;
+}
+
+// Ground cost in float64 between two pixels: |x - y|^p (exact integer for p = 2).
+__device__ __forceinline__ double cost64(int i, int j, int N, int d, int p) {
+  int a0, a1, a2, b0, b1, b2;
+  pix_coords(i, N, d, a0, a1, a2);
+  pix_coords(j, N, d, b0, b1, b2);
+  int e0 = a0 - b0, e1 = a1 - b1, e2 = a2 - b2;
+  double d2 = (double)(e0 * e0 + e1 * e1 + e2 * e2);
+  return p == 2 ? d2 : sqrt(d2);
+}
+
+// Correctly rounded float32 square root for exact nonnegative integers below
+// 2^24 (no denormals): hardware estimate, then the two neighbouring floats
+// are tested with exact fused residuals.
+__device__ __forceinline__ float sqrt_rn_int(float x) {
+  float s = __builtin_amdgcn_sqrtf(x);
+  float sd = __int_as_float(__float_as_int(s) - 1);
+  float su = __int_as_float(__float_as_int(s) + 1);
+  float rd = __builtin_fmaf(-sd, s, x);
+  float ru = __builtin_fmaf(-su, s, x);
+  s = (rd <= 0.0f) ? sd : s;
+  s = (ru > 0.0f) ? su : s;
+  return s;
+}
+
+// ------------------------------------------------------------------ pooling
+
+__global__ __launch_bounds__(256) void k_pool(const DevJob* __restrict__ jobs, int njobs,
+                                              const int* __restrict__ off, int total) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int K = (it - off[jb]) * 256 + threadIdx.x;
+    if (K >= J.Q) continue;
+    const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    double sm = 0.0, sn = 0.0;
+    int bad = 0;
+    for (int t = 0; t < m; ++t) {
+      const int i = block_member(K, t, J.N, J.n, J.k, J.d);
+      const double x = J.mu[i], y = J.nu[i];
+      sm += x;
+      sn += y;
+      bad |= (x < 0.0 || y < 0.0) ? 1 : 0;
+      bad |= (x != x || y != y) ? 2 : 0;
+    }
+    J.mu_t[K] = sm;
+    J.nu_t[K] = sn;
+    if (bad) atomicOr(J.flags, bad);
+  }
+}
+
+// ------------------------------------------------------------------ upscaling
+
+// Per axis: x = centre(K0) + w * k, clamped to the hull of the block centres.
+__device__ __forceinline__ void axis_weight(int x, int k, int n, int& K0, int& K1, double& w) {
+  const int t = 2 * x - (k - 1);
+  const int den = 2 * k;
+  if (t <= 0 || n == 1) { K0 = 0; K1 = 0; w = 0.0; return; }
+  const int q = t / den;
+  if (q >= n - 1) { K0 = n - 1; K1 = n - 1; w = 0.0; return; }
+  K0 = q;
+  K1 = q + 1;
+  w = (double)(t - den * q) / (double)den;
+}
+
+__device__ __forceinline__ double lerp_nc(double a, double b, double w) {
+#pragma clang fp contract(off)
+  return a + w * (b - a);
+}
+
+__global__ __launch_bounds__(256) void k_upscale(const DevJob* __restrict__ jobs, int njobs,
+                                                 const int* __restrict__ off, int total) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int base = (it - off[jb]) * kChunk;
+    const double* __restrict__ F = J.ftil;
+    const int n = J.n;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int i = base + q;
+      if (i >= J.P) break;
+      int x0, x1, x2;
+      pix_coords(i, J.N, J.d, x0, x1, x2);
+      double val;
+      if (J.d == 2) {
+        int A0, A1, B0, B1;
+        double wa, wb;
+        axis_weight(x1, J.k, n, A0, A1, wa);
+        axis_weight(x2, J.k, n, B0, B1, wb);
+        const double r0 = lerp_nc(F[A0 * n + B0], F[A0 * n + B1], wb);
+        const double r1 = lerp_nc(F[A1 * n + B0], F[A1 * n + B1], wb);
+        val = lerp_nc(r0, r1, wa);
+      } else {
+        int A0, A1, B0, B1, C0, C1;
+        double wa, wb, wc;
+        axis_weight(x0, J.k, n, A0, A1, wa);
+        axis_weight(x1, J.k, n, B0, B1, wb);
+        axis_weight(x2, J.k, n, C0, C1, wc);
+        auto at = [&](int a, int b, int c) { return F[(a * n + b) * n + c]; };
+        const double s00 = lerp_nc(at(A0, B0, C0), at(A0, B0, C1), wc);
+        const double s01 = lerp_nc(at(A0, B1, C0), at(A0, B1, C1), wc);
+        const double s10 = lerp_nc(at(A1, B0, C0), at(A1, B0, C1), wc);
+        const double s11 = lerp_nc(at(A1, B1, C0), at(A1, B1, C1), wc);
+        const double t0 = lerp_nc(s00, s01, wb);
+        const double t1 = lerp_nc(s10, s11, wb);
+        val = lerp_nc(t0, t1, wa);
+      }
+      J.fhat[i] = (float)val;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ c-transform
+//
+// psi_j = min_i RN32(c_ij - phi_i) over all sources i.
+//
+// Mapping: one wave per work item = (job, target tile, source split).  Lane
+// l owns R consecutive targets of one grid row (the last axis): columns
+// v0 .. v0+R-1 of row r.  Sources are swept row by row; within a source row
+// every lane needs, at source column t, the costs c(A, t - v0 - q) for
+// q = 0..R-1, where A is the squared distance over the other axes.  Moving
+// from t to t+1 shifts that window by one: R-1 values are reused and only
+// c(A, t + 1 - v0) is new (an exact integer update for p = 2, plus one
+// correctly rounded square root for p = 1).  With the window held in R
+// registers whose roles rotate through a fully unrolled block of R steps,
+// each (source, target) pair costs one subtraction plus half of a v_min3.
+// The source potential is wave-uniform and comes through scalar loads.
+// Source potentials are read through the constant address space: the data
+// is not written during the launch and every lane reads the same address, so
+// the loads become scalar (s_load) and the values feed the VALU as SGPRs.
+typedef const __attribute__((address_space(4))) float* const_fptr;
+
+template <int R, int PP>
+__device__ __forceinline__ void ct_tile(const float* __restrict__ src, float* __restrict__ out,
+                                        int N, int d, int P, int tile, int r0, int r1) {
+  const int lane = threadIdx.x & 63;
+  const int j0 = tile * 64 * R + lane * R;
+  const bool valid = j0 < P;
+  const int jj = valid ? j0 : 0;
+  const int trow = jj / N;
+  const int v0 = jj - trow * N;
+  int ta, tb;
+  if (d == 2) { ta = 0; tb = trow; } else { ta = trow / N; tb = trow - ta * N; }
+  float mn[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) mn[q] = INFINITY;
+
+  for (int sr = r0; sr < r1; ++sr) {
+    int sa, sb;
+    if (d == 2) { sa = 0; sb = sr; } else { sa = sr / N; sb = sr - sa * N; }
+    const int da = sa - ta, db = sb - tb;
+    const float A = (float)(da * da + db * db);
+    float W[R];
+    float n0 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int e = v0 + q;
+      const float nk = A + (float)(e * e);
+      W[q] = (PP == 2) ? nk : sqrt_rn_int(nk);
+      if (q == 0) n0 = nk;
+    }
+    float D = (float)(1 - 2 * v0);
+    const_fptr ph = (const_fptr)(src + (size_t)sr * N);
+    for (int b = 0; b < N; b += R) {
+      float phv[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) phv[m] = ph[b + m];
+      float tmp[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const float t = W[(q - m + R) % R] - phv[m];
+          if (R == 1) {
+            mn[q] = fminf(mn[q], t);
+          } else if (m & 1) {
+            mn[q] = fminf(mn[q], fminf(tmp[q], t));
+            // keep the running minimum a chain of v_min3 (no re-association)
+            __asm__("" : "+v"(mn[q]));
+          } else {
+            tmp[q] = t;
+          }
+        }
+        if (PP == 2) {
+          W[(R - 1 - m + R) % R] = W[(R - m) % R] + D;
+        } else {
+          n0 = n0 + D;
+          W[(R - 1 - m + R) % R] = sqrt_rn_int(n0);
+        }
+        D += 2.0f;
+      }
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) out[j0 + q] = mn[q];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_ctransform(const DevJob* __restrict__ jobs,
+                                                   const CtItem* __restrict__ items, int n_items,
+                                                   int* __restrict__ counter, int phase) {
+  for (;;) {
+    int it = 0;
+    if (threadIdx.x == 0) it = atomicAdd(counter, 1);
+    it = __shfl(it, 0);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= n_items) break;
+    const CtItem w = items[it];
+    const DevJob& J = jobs[w.job];
+    const float* src = phase == 0 ? J.fhat : J.g;
+    float* out = J.part + (size_t)w.split * J.P;
+    const int r0 = (int)(((long long)w.split * J.rows) / J.S);
+    const int r1 = (int)(((long long)(w.split + 1) * J.rows) / J.S);
+    const int key = J.R * 4 + J.p;
+    switch (key) {
+      case 16 * 4 + 2: ct_tile<16, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+      case 16 * 4 + 1: ct_tile<16, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+      case 8 * 4 + 2: ct_tile<8, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+      case 8 * 4 + 1: ct_tile<8, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+      case 4 * 4 + 2: ct_tile<4, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+      case 4 * 4 + 1: ct_tile<4, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+      case 2 * 4 + 2: ct_tile<2, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+      case 2 * 4 + 1: ct_tile<2, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+      case 1 * 4 + 2: ct_tile<1, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+      default: ct_tile<1, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    }
+  }
+}
+
+__global__ void k_reset_counter(int* counter, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) counter[i] = 0;
+}
+
+// Minimum over source splits; the winning split is the lowest one attaining it.
+__global__ __launch_bounds__(256) void k_merge(const DevJob* __restrict__ jobs, int njobs,
+                                               const int* __restrict__ off, int total, int phase) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int base = (it - off[jb]) * kChunk;
+    float* dst = phase == 0 ? J.g : J.f;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int j = base + q;
+      if (j >= J.P) break;
+      float best = INFINITY;
+      int win = 0;
+      for (int s = 0; s < J.S; ++s) {
+        const float v = J.part[(size_t)s * J.P + j];
+        if (v < best) { best = v; win = s; }
+      }
+      dst[j] = best;
+      J.win[j] = win;
+    }
+  }
+}
+
+// Lowest source index attaining the minimum: rescan the winning split only.
+__global__ __launch_bounds__(256) void k_argmin(const DevJob* __restrict__ jobs, int njobs,
+                                                const int* __restrict__ off, int total, int phase) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int base = (it - off[jb]) * kChunk;
+    const float* src = phase == 0 ? J.fhat : J.g;
+    const float* dst = phase == 0 ? J.g : J.f;
+    int* arg = phase == 0 ? J.arg_g : J.arg_f;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int j = base + q;
+      if (j >= J.P) break;
+      const int s = J.win[j];
+      const int r0 = (int)(((long long)s * J.rows) / J.S);
+      const int r1 = (int)(((long long)(s + 1) * J.rows) / J.S);
+      int y0, y1, y2;
+      pix_coords(j, J.N, J.d, y0, y1, y2);
+      const float target = dst[j];
+      int found = -1;
+      for (int i = r0 * J.N; i < r1 * J.N && found < 0; ++i) {
+        int x0, x1, x2;
+        pix_coords(i, J.N, J.d, x0, x1, x2);
+        const int e0 = x0 - y0, e1 = x1 - y1, e2 = x2 - y2;
+        const float c2 = (float)(e0 * e0 + e1 * e1 + e2 * e2);
+        const float c = J.p == 2 ? c2 : sqrt_rn_int(c2);
+        if (c - src[i] == target) found = i;
+      }
+      arg[j] = found;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ lower-bound sums
+
+__global__ __launch_bounds__(256) void k_lb_partial(const DevJob* __restrict__ jobs, int njobs,
+                                                    const int* __restrict__ off, int total) {
+  __shared__ double sh[256];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int c = it - off[jb];
+    const int base = c * kChunk;
+    double sf = 0.0, sg = 0.0, mh = 0.0, mg = 0.0, mf = 0.0;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int i = base + q;
+      if (i >= J.P) break;
+      const double f = J.f[i], g = J.g[i];
+      sf += f * J.mu[i];
+      sg += g * J.nu[i];
+      mh = fmax(mh, fabs((double)J.fhat[i]));
+      mg = fmax(mg, fabs(g));
+      mf = fmax(mf, fabs(f));
+    }
+    double* r = J.red_lb + (size_t)c * kRedSlotsLB;
+    sf = block_sum<256>(sf, sh);
+    sg = block_sum<256>(sg, sh);
+    mh = block_max<256>(mh, sh);
+    mg = block_max<256>(mg, sh);
+    mf = block_max<256>(mf, sh);
+    if (threadIdx.x == 0) { r[0] = sf; r[1] = sg; r[2] = mh; r[3] = mg; r[4] = mf; }
+  }
+}
+
+// ------------------------------------------------------------------ IPF (Algorithm 4)
+//
+// With the uniform kernel, pi^ b is constant on every block:
+//   (pi^ b)_i = k^(-2d) sum_L pi~_KL B_L,  B_L = sum_{j in Y_L} b_j,
+// so the fitting runs on coarse vectors.  With a = mu / u (u = pi^ b) and
+// b = nu / v (v = pi^T a) the block sums are A_K = mu~_K / u_K and
+// B_L = nu~_L / v_L; b = 1 at the start gives B^0 = k^d.  Every iterate u^t,
+// v^t is kept for the backward pass.  One work-group per job.
+__global__ __launch_bounds__(1024) void k_ipf(const DevJob* __restrict__ jobs, int njobs) {
+  __shared__ double sh[1024];
+  const DevJob& J = jobs[blockIdx.x];
+  const int Q = J.Q;
+  const double kd = J.d == 2 ? (double)J.k * J.k : (double)J.k * J.k * J.k;
+  const double cc = 1.0 / (kd * kd);
+  double* U = J.ipf_u;  // row t holds u^t, t = 1 .. T+1
+  double* V = J.ipf_v;  // row t holds v^t
+  double* Bprev = J.gbar_nu;  // scratch: B^{t-1}
+  double* Acur = J.gbar_mu;   // scratch: A^t
+  for (int L = threadIdx.x; L < Q; L += 1024) Bprev[L] = kd;
+  __syncthreads();
+  int T = 0;
+  double resid = INFINITY;
+  for (int t = 1; t <= J.max_iter; ++t) {
+    double* u = U + (size_t)t * Q;
+    double* v = V + (size_t)t * Q;
+    for (int K = threadIdx.x; K < Q; K += 1024) {
+      double s = 0.0;
+      for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) s += J.e_val[e] * Bprev[J.e_col[e]];
+      u[K] = cc * s;
+    }
+    __syncthreads();
+    for (int K = threadIdx.x; K < Q; K += 1024) Acur[K] = u[K] > 0.0 ? J.mu_t[K] / u[K] : 0.0;
+    __syncthreads();
+    for (int L = threadIdx.x; L < Q; L += 1024) {
+      double s = 0.0;
+      for (int q = J.csc_ptr[L]; q < J.csc_ptr[L + 1]; ++q) {
+        const int e = J.csc_idx[q];
+        s += J.e_val[e] * Acur[J.e_row[e]];
+      }
+      v[L] = cc * s;
+    }
+    __syncthreads();
+    for (int L = threadIdx.x; L < Q; L += 1024) Bprev[L] = v[L] > 0.0 ? J.nu_t[L] / v[L] : 0.0;
+    __syncthreads();
+    double* un = U + (size_t)(t + 1) * Q;
+    double part = 0.0;
+    for (int K = threadIdx.x; K < Q; K += 1024) {
+      double s = 0.0;
+      for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) s += J.e_val[e] * Bprev[J.e_col[e]];
+      un[K] = cc * s;
+      // ||mu^ - mu||_1 on block K: mu^_i = mu_i u^{t+1}_K / u^t_K
+      const double m = J.mu_t[K];
+      if (u[K] > 0.0) part += m * fabs(un[K] / u[K] - 1.0);
+      else part += m;
+    }
+    for (int L = threadIdx.x; L < Q; L += 1024) {
+      // nu^_j = b_j (pi^T a)_j = nu_j exactly when v^t_L > 0
+      if (!(v[L] > 0.0)) part += J.nu_t[L];
+    }
+    resid = block_sum<1024>(part, sh);
+    T = t;
+    if (resid < J.xi) break;
+  }
+  if (threadIdx.x == 0) {
+    J.result[RS_IPF_ITERS] = (double)T;
+    J.result[RS_IPF_RESID] = resid;
+    J.result[RS_WARN] = (resid < J.xi) ? 0.0 : (double)QBW_WARN_IPF_NOT_CONVERGED;
+  }
+}
+
+// Fine scalings of the last iterate: a_s = mu / u^T, b_s = nu / v^T (0/0 := 0).
+__global__ __launch_bounds__(256) void k_scalings(const DevJob* __restrict__ jobs, int njobs,
+                                                  const int* __restrict__ off, int total) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int T = (int)J.result[RS_IPF_ITERS];
+    const double* u = J.ipf_u + (size_t)T * J.Q;
+    const double* v = J.ipf_v + (size_t)T * J.Q;
+    const int base = (it - off[jb]) * kChunk;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int i = base + q;
+      if (i >= J.P) break;
+      int x0, x1, x2;
+      pix_coords(i, J.N, J.d, x0, x1, x2);
+      const int n = J.n, k = J.k;
+      const int K = J.d == 2 ? (x1 / k) * n + x2 / k : ((x0 / k) * n + x1 / k) * n + x2 / k;
+      J.a_s[i] = u[K] > 0.0 ? J.mu[i] / u[K] : 0.0;
+      J.b_s[i] = v[K] > 0.0 ? J.nu[i] / v[K] : 0.0;
+    }
+  }
+}
+
+// Weighted TV sums: w_i = |x_i - x-bar|^p; mu^_i = a_s_i u^{T+1}_K, nu^_j = b_s_j v^T_L.
+__global__ __launch_bounds__(256) void k_tv_partial(const DevJob* __restrict__ jobs, int njobs,
+                                                    const int* __restrict__ off, int total) {
+  __shared__ double sh[256];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int T = (int)J.result[RS_IPF_ITERS];
+    const double* un = J.ipf_u + (size_t)(T + 1) * J.Q;
+    const double* v = J.ipf_v + (size_t)T * J.Q;
+    const int c = it - off[jb];
+    const int base = c * kChunk;
+    const double h = 0.5 * (J.N - 1);
+    double tm = 0.0, tn = 0.0, wm = 0.0, wn = 0.0;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int i = base + q;
+      if (i >= J.P) break;
+      int x0, x1, x2;
+      pix_coords(i, J.N, J.d, x0, x1, x2);
+      const double d0 = J.d == 2 ? 0.0 : x0 - h, d1 = x1 - h, d2 = x2 - h;
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double w = J.p == 2 ? r2 : sqrt(r2);
+      const int n = J.n, k = J.k;
+      const int K = J.d == 2 ? (x1 / k) * n + x2 / k : ((x0 / k) * n + x1 / k) * n + x2 / k;
+      const double muh = J.a_s[i] * un[K];
+      const double nuh = J.b_s[i] * v[K];
+      tm += w * fabs(muh - J.mu[i]);
+      tn += w * fabs(J.nu[i] - nuh);
+      wm += w * J.mu[i];
+      wn += w * J.nu[i];
+    }
+    tm = block_sum<256>(tm, sh);
+    tn = block_sum<256>(tn, sh);
+    wm = block_sum<256>(wm, sh);
+    wn = block_sum<256>(wn, sh);
+    if (threadIdx.x == 0) {
+      double* r = J.red_tv + (size_t)c * kRedSlotsTV;
+      r[0] = tm; r[1] = tn; r[2] = wm; r[3] = wn;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ plan cost
+//
+// One work-group per support entry (K, L): sum over X_K x Y_L of a_s_i b_s_j c_ij.
+__global__ __launch_bounds__(256) void k_plancost(const DevJob* __restrict__ jobs, int njobs,
+                                                  const int* __restrict__ off, int total) {
+  __shared__ double sh[256];
+  __shared__ double sb[1024];
+  __shared__ int sc[1024];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int e = it - off[jb];
+    const int K = J.e_row[e], L = J.e_col[e];
+    const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    double acc = 0.0;
+    for (int t0 = 0; t0 < m; t0 += 1024) {
+      const int tn = min(1024, m - t0);
+      for (int q = threadIdx.x; q < tn; q += 256) {
+        const int j = block_member(L, t0 + q, J.N, J.n, J.k, J.d);
+        sb[q] = J.b_s[j];
+        sc[q] = j;
+      }
+      __syncthreads();
+      for (int a = threadIdx.x; a < m; a += 256) {
+        const int i = block_member(K, a, J.N, J.n, J.k, J.d);
+        double s = 0.0;
+        for (int q = 0; q < tn; ++q) s += sb[q] * cost64(i, sc[q], J.N, J.d, J.p);
+        acc += J.a_s[i] * s;
+      }
+      __syncthreads();
+    }
+    acc = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) J.red_pc[e] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ finalize
+
+__global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ jobs, int njobs) {
+  __shared__ double sh[256];
+  const DevJob& J = jobs[blockIdx.x];
+  double* res = J.result;
+  // lower bound
+  double sf = 0, sg = 0, mh = 0, mg = 0, mf = 0;
+  for (int c = threadIdx.x; c < J.chunks; c += 256) {
+    const double* r = J.red_lb + (size_t)c * kRedSlotsLB;
+    sf += r[0]; sg += r[1];
+    mh = fmax(mh, r[2]); mg = fmax(mg, r[3]); mf = fmax(mf, r[4]);
+  }
+  sf = block_sum<256>(sf, sh);
+  sg = block_sum<256>(sg, sh);
+  mh = block_max<256>(mh, sh);
+  mg = block_max<256>(mg, sh);
+  mf = block_max<256>(mf, sh);
+  // upper bound
+  const double kd = J.d == 2 ? (double)J.k * J.k : (double)J.k * J.k * J.k;
+  const double cc = 1.0 / (kd * kd);
+  double pc = 0;
+  for (int e = threadIdx.x; e < J.nnz; e += 256) pc += cc * J.e_val[e] * J.red_pc[e];
+  pc = block_sum<256>(pc, sh);
+  double tm = 0, tn = 0, wm = 0, wn = 0;
+  for (int c = threadIdx.x; c < J.chunks; c += 256) {
+    const double* r = J.red_tv + (size_t)c * kRedSlotsTV;
+    tm += r[0]; tn += r[1]; wm += r[2]; wn += r[3];
+  }
+  tm = block_sum<256>(tm, sh);
+  tn = block_sum<256>(tn, sh);
+  wm = block_sum<256>(wm, sh);
+  wn = block_sum<256>(wn, sh);
+  if (threadIdx.x != 0) return;
+  const double p = J.p;
+  // float32 feasibility shift (first order in u = 2^-24; see the oracle's derivation)
+  const double u = 5.9604644775390625e-08;
+  const double up = J.p == 1 ? u : 0.0;
+  const double F = mh * (1.0 + 2.0 * u);
+  const double e_g = (u + up) * (mg + F);
+  const double e_f = u * mf + up * (mf + mg) + e_g;
+  const double shift = (e_f + e_g) * (1.0 + 0.0009765625) + 2.220446049250313e-16 * J.P * (mf + mg);
+  const double S32 = sf + sg;
+  const double Se = S32 - shift;
+  unsigned warn = (unsigned)res[RS_WARN];
+  double lower = 0.0;
+  if (Se > 0.0) lower = J.p == 2 ? sqrt(Se) : Se;
+  else warn |= QBW_WARN_LB_CLIPPED;
+  // upper bound with outward rounding allowances: relative 2^-40 on the plan
+  // cost, absolute 2^-40 <w, mu> (resp. nu) on each TV sum
+  const double pe = pc * (1.0 + 9.094947017729282e-13);
+  const double c1 = J.p == 2 ? 1.4142135623730951 : 1.0;
+  auto root = [&](double x) { return J.p == 2 ? sqrt(x) : x; };
+  const double tvm = c1 * root(tm + 9.094947017729282e-13 * wm);
+  const double tvn = c1 * root(tn + 9.094947017729282e-13 * wn);
+  const double upper = root(pe) + tvm + tvn;
+  res[RS_LOWER] = lower;
+  res[RS_UPPER] = upper;
+  res[RS_LOWER_S] = Se;
+  res[RS_SHIFT] = shift;
+  res[RS_UPPER_COST] = pe;
+  res[RS_TV_MU] = tvm;
+  res[RS_TV_NU] = tvn;
+  res[RS_COARSE_OBJ] = J.coarse_obj;
+  res[RS_WARN] = (double)warn;
+  res[RS_S32] = S32;
+  res[RS_PCOST_RAW] = pc;
+  res[RS_MAX_FHAT] = mh;
+  res[RS_MAX_G] = mg;
+  res[RS_MAX_F] = mf;
+  res[RS_TVSUM_MU] = tm;
+  res[RS_TVSUM_NU] = tn;
+  res[RS_MW_MU] = wm;
+  res[RS_MW_NU] = wn;
+  res[RS_TV_RAW_MU] = c1 * root(tm);
+  res[RS_TV_RAW_NU] = c1 * root(tn);
+  (void)p;
+}
+
+// ------------------------------------------------------------------ C-bar (Section 3.2)
+//
+// p = 2: with block centres c_K and offsets delta = x - c_K the block-pair sum
+// of |x - y|^2 mu(x) nu(y) expands into pooled moments (mass, first moment,
+// second moment); p = 1: brute force over the k^(2d) pixel pairs.
+__global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, int njobs,
+                                              const int* __restrict__ off, int total,
+                                              double* const* __restrict__ outs,
+                                              const double* const* __restrict__ moms) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const long long pr = (long long)(it - off[jb]) * 256 + threadIdx.x;
+    const int Q = J.Q;
+    if (pr >= (long long)Q * Q) continue;
+    const int K = (int)(pr / Q), L = (int)(pr - (long long)K * Q);
+    int k0, k1, k2, l0, l1, l2;
+    pix_coords(K, J.n, J.d, k0, k1, k2);
+    pix_coords(L, J.n, J.d, l0, l1, l2);
+    const double c0 = (double)J.k * (k0 - l0), c1 = (double)J.k * (k1 - l1), c2 = (double)J.k * (k2 - l2);
+    const double dc2 = c0 * c0 + c1 * c1 + c2 * c2;
+    const double mK = J.mu_t[K], nL = J.nu_t[L];
+    double val;
+    if (J.p == 2) {
+      const double* Mm = moms[2 * jb] + (size_t)K * 4;      // (m1_0, m1_1, m1_2, m2)
+      const double* Mn = moms[2 * jb + 1] + (size_t)L * 4;
+      if (mK > 0.0 && nL > 0.0) {
+        const double s = mK * nL * dc2
+            + 2.0 * (c0 * (nL * Mm[0] - mK * Mn[0]) + c1 * (nL * Mm[1] - mK * Mn[1]) + c2 * (nL * Mm[2] - mK * Mn[2]))
+            + nL * Mm[3] + mK * Mn[3]
+            - 2.0 * (Mm[0] * Mn[0] + Mm[1] * Mn[1] + Mm[2] * Mn[2]);
+        val = s / (mK * nL);
+      } else {
+        val = dc2;
+      }
+    } else {
+      if (mK > 0.0 && nL > 0.0) {
+        const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+        double s = 0.0;
+        for (int a = 0; a < m; ++a) {
+          const int i = block_member(K, a, J.N, J.n, J.k, J.d);
+          const double x = J.mu[i];
+          if (x == 0.0) continue;
+          double r = 0.0;
+          for (int b = 0; b < m; ++b) {
+            const int j = block_member(L, b, J.N, J.n, J.k, J.d);
+            r += J.nu[j] * cost64(i, j, J.N, J.d, 1);
+          }
+          s += x * r;
+        }
+        val = s / (mK * nL);
+      } else {
+        val = sqrt(dc2);
+      }
+    }
+    outs[jb][(size_t)K * Q + L] = val;
+  }
+}
+
+// Pooled moments for C-bar (p = 2): per block (sum m delta_0, delta_1, delta_2, sum m |delta|^2).
+__global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs, int njobs,
+                                                 const int* __restrict__ off, int total,
+                                                 double* const* __restrict__ moms) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int idx = (it - off[jb]) * 256 + threadIdx.x;
+    if (idx >= 2 * J.Q) continue;
+    const int side = idx / J.Q, K = idx - side * J.Q;
+    const double* m = side == 0 ? J.mu : J.nu;
+    const int mm = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    const double h = 0.5 * (J.k - 1);
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int a = 0; a < mm; ++a) {
+      const int i = block_member(K, a, J.N, J.n, J.k, J.d);
+      int u0, u1, u2;
+      pix_coords(a, J.k, J.d, u0, u1, u2);
+      const double d0 = J.d == 2 ? 0.0 : u0 - h, d1 = u1 - h, d2 = u2 - h;
+      const double w = m[i];
+      s0 += w * d0; s1 += w * d1; s2 += w * d2;
+      s3 += w * (d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    double* o = moms[2 * jb + side] + (size_t)K * 4;
+    o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3;
+  }
+}
+
+// ------------------------------------------------------------------ backward
+
+__global__ __launch_bounds__(256) void k_lb_grad(const DevJob* __restrict__ jobs, int njobs,
+                                                 const int* __restrict__ off, int total,
+                                                 const double* __restrict__ dl) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    if (!J.grad_a || !J.grad_b) continue;
+    const double Se = J.result[RS_LOWER_S];
+    const double s = Se > 0.0 ? (J.p == 2 ? 0.5 / sqrt(Se) : 1.0) * dl[jb] : 0.0;
+    const int base = (it - off[jb]) * kChunk;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int i = base + q;
+      if (i >= J.P) break;
+      J.grad_a[i] += s * (double)J.f[i];
+      J.grad_b[i] += s * (double)J.g[i];
+    }
+  }
+}
+
+// Reverse mode through the coarse IPF recurrence (one work-group per job).
+// Produces d P / d mu~ (gbar_mu), d P / d nu~ (gbar_nu) and, per support
+// entry, coef_e = k^(-2d) pi~_e / (u^T_K v^T_L), the weight of
+// S_e = sum mu_i nu_j c_ij in P.
+__global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict__ jobs, int njobs,
+                                                        double* __restrict__ scratch_all,
+                                                        int stride) {
+  const DevJob& J = jobs[blockIdx.x];
+  const int Q = J.Q;
+  const int T = (int)J.result[RS_IPF_ITERS];
+  const double kd = J.d == 2 ? (double)J.k * J.k : (double)J.k * J.k * J.k;
+  const double cc = 1.0 / (kd * kd);
+  double* sc = scratch_all + (size_t)blockIdx.x * 4 * stride;  // stride >= every job's Q
+  double* ub = sc;          // adjoint of u^t
+  double* vb = sc + Q;      // adjoint of v^t
+  double* Ab = sc + 2 * Q;  // adjoint of A^t
+  double* Bb = sc + 3 * Q;  // adjoint of B^{t-1}
+  const double* uT = J.ipf_u + (size_t)T * Q;
+  const double* vT = J.ipf_v + (size_t)T * Q;
+  for (int e = threadIdx.x; e < J.nnz; e += 1024) {
+    const int K = J.e_row[e], L = J.e_col[e];
+    J.coef[e] = (uT[K] > 0.0 && vT[L] > 0.0) ? cc * J.e_val[e] / (uT[K] * vT[L]) : 0.0;
+  }
+  for (int K = threadIdx.x; K < Q; K += 1024) { J.gbar_mu[K] = 0.0; J.gbar_nu[K] = 0.0; }
+  __syncthreads();
+  // direct terms: P = sum_e cc val_e red_pc[e], red_pc = S_e / (u_K v_L)
+  for (int K = threadIdx.x; K < Q; K += 1024) {
+    double s = 0.0;
+    for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) s += cc * J.e_val[e] * J.red_pc[e];
+    ub[K] = uT[K] > 0.0 ? -s / uT[K] : 0.0;
+  }
+  for (int L = threadIdx.x; L < Q; L += 1024) {
+    double s = 0.0;
+    for (int q = J.csc_ptr[L]; q < J.csc_ptr[L + 1]; ++q) {
+      const int e = J.csc_idx[q];
+      s += cc * J.e_val[e] * J.red_pc[e];
+    }
+    vb[L] = vT[L] > 0.0 ? -s / vT[L] : 0.0;
+  }
+  __syncthreads();
+  for (int t = T; t >= 1; --t) {
+    const double* u = J.ipf_u + (size_t)t * Q;
+    // v^t = cc pi^T A^t  ->  Ab
+    for (int K = threadIdx.x; K < Q; K += 1024) {
+      double s = 0.0;
+      for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) s += J.e_val[e] * vb[J.e_col[e]];
+      Ab[K] = cc * s;
+    }
+    __syncthreads();
+    // A^t = mu~ / u^t
+    for (int K = threadIdx.x; K < Q; K += 1024) {
+      if (u[K] > 0.0) {
+        J.gbar_mu[K] += Ab[K] / u[K];
+        ub[K] += -Ab[K] * J.mu_t[K] / (u[K] * u[K]);
+      }
+    }
+    __syncthreads();
+    if (t == 1) break;
+    const double* vp = J.ipf_v + (size_t)(t - 1) * Q;
+    // u^t = cc pi B^{t-1}  ->  Bb
+    for (int L = threadIdx.x; L < Q; L += 1024) {
+      double s = 0.0;
+      for (int q = J.csc_ptr[L]; q < J.csc_ptr[L + 1]; ++q) {
+        const int e = J.csc_idx[q];
+        s += J.e_val[e] * ub[J.e_row[e]];
+      }
+      Bb[L] = cc * s;
+    }
+    __syncthreads();
+    // B^{t-1} = nu~ / v^{t-1}
+    for (int L = threadIdx.x; L < Q; L += 1024) {
+      if (vp[L] > 0.0) {
+        J.gbar_nu[L] += Bb[L] / vp[L];
+        vb[L] = -Bb[L] * J.nu_t[L] / (vp[L] * vp[L]);
+      } else {
+        vb[L] = 0.0;
+      }
+    }
+    for (int K = threadIdx.x; K < Q; K += 1024) ub[K] = 0.0;
+    __syncthreads();
+  }
+}
+
+// d upper / d mu (side 0) or d nu (side 1): one work-group per coarse block.
+__global__ __launch_bounds__(256) void k_ub_grad(const DevJob* __restrict__ jobs, int njobs,
+                                                 const int* __restrict__ off, int total,
+                                                 const double* __restrict__ du, int side) {
+  __shared__ double sw[1024];
+  __shared__ int sidx[1024];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    double* grad = side == 0 ? J.grad_a : J.grad_b;
+    if (!grad) continue;
+    const int B = it - off[jb];
+    const double P = J.result[RS_PCOST_RAW];
+    const double s = P > 0.0 ? (J.p == 2 ? 0.5 / sqrt(P) : 1.0) * du[jb] : 0.0;
+    const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    const double* other = side == 0 ? J.nu : J.mu;
+    const double base_g = side == 0 ? J.gbar_mu[B] : J.gbar_nu[B];
+    // entries of row B (side 0) or column B (side 1)
+    const int e0 = side == 0 ? J.csr_ptr[B] : J.csc_ptr[B];
+    const int e1 = side == 0 ? J.csr_ptr[B + 1] : J.csc_ptr[B + 1];
+    for (int a0 = 0; a0 < m; a0 += 256) {
+      const int a = a0 + threadIdx.x;
+      const int i = a < m ? block_member(B, a, J.N, J.n, J.k, J.d) : 0;
+      double h = 0.0;
+      for (int q = e0; q < e1; ++q) {
+        const int e = side == 0 ? q : J.csc_idx[q];
+        const int Ot = side == 0 ? J.e_col[e] : J.e_row[e];
+        const double cf = J.coef[e];
+        for (int t0 = 0; t0 < m; t0 += 1024) {
+          const int tn = min(1024, m - t0);
+          __syncthreads();
+          for (int r = threadIdx.x; r < tn; r += 256) {
+            const int j = block_member(Ot, t0 + r, J.N, J.n, J.k, J.d);
+            sw[r] = other[j];
+            sidx[r] = j;
+          }
+          __syncthreads();
+          if (a < m) {
+            double acc = 0.0;
+            for (int r = 0; r < tn; ++r) acc += sw[r] * cost64(i, sidx[r], J.N, J.d, J.p);
+            h += cf * acc;
+          }
+        }
+      }
+      if (a < m) grad[i] += s * (h + base_g);
+    }
+  }
+}
+
+// d lower / d fhat through the arg-mins: sum_i mu_i [argmin_g(argmin_f(i)) = r] - sum_j nu_j [argmin_g(j) = r].
+__global__ __launch_bounds__(256) void k_fhat_grad(const DevJob* __restrict__ jobs, int njobs,
+                                                   const int* __restrict__ off, int total,
+                                                   const double* __restrict__ dl,
+                                                   double* const* __restrict__ outs) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    double* out = outs[jb];
+    if (!out || !J.arg_g || !J.arg_f) continue;
+    const double Se = J.result[RS_LOWER_S];
+    const double s = Se > 0.0 ? (J.p == 2 ? 0.5 / sqrt(Se) : 1.0) * dl[jb] : 0.0;
+    const int base = (it - off[jb]) * kChunk;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int i = base + q;
+      if (i >= J.P) break;
+      const int jf = J.arg_f[i];
+      const int r1 = (jf >= 0 && jf < J.P) ? J.arg_g[jf] : -1;
+      const int r2 = J.arg_g[i];
+      if (r1 >= 0 && r1 < J.P) atomicAdd(out + r1, s * J.mu[i]);
+      if (r2 >= 0 && r2 < J.P) atomicAdd(out + r2, -s * J.nu[i]);
+    }
+  }
+}
+
+// For caller-supplied scalings (a_s, b_s): block sums A_K = sum a_s, B_L = sum b_s,
+// then (pi^ b_s) on block K = k^(-2d) sum_L pi~_KL B_L and (pi^T a_s) on block
+// L = k^(-2d) sum_K pi~_KL A_K, stored where k_tv_partial reads u^{T+1}, v^T
+// (with T = 1).  One work-group per job.
+__global__ __launch_bounds__(1024) void k_tv_prep(const DevJob* __restrict__ jobs, int njobs) {
+  const DevJob& J = jobs[blockIdx.x];
+  const int Q = J.Q;
+  const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+  const double kd = (double)m;
+  const double cc = 1.0 / (kd * kd);
+  double* A = J.gbar_mu;
+  double* B = J.gbar_nu;
+  for (int K = threadIdx.x; K < Q; K += 1024) {
+    double sa = 0.0, sb = 0.0;
+    for (int t = 0; t < m; ++t) {
+      const int i = block_member(K, t, J.N, J.n, J.k, J.d);
+      sa += J.a_s[i];
+      sb += J.b_s[i];
+    }
+    A[K] = sa;
+    B[K] = sb;
+  }
+  __syncthreads();
+  for (int K = threadIdx.x; K < Q; K += 1024) {
+    double s = 0.0;
+    for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) s += J.e_val[e] * B[J.e_col[e]];
+    J.ipf_u[2 * (size_t)Q + K] = cc * s;
+  }
+  for (int L = threadIdx.x; L < Q; L += 1024) {
+    double s = 0.0;
+    for (int q = J.csc_ptr[L]; q < J.csc_ptr[L + 1]; ++q) {
+      const int e = J.csc_idx[q];
+      s += J.e_val[e] * A[J.e_row[e]];
+    }
+    J.ipf_v[(size_t)Q + L] = cc * s;
+  }
+  if (threadIdx.x == 0) J.result[RS_IPF_ITERS] = 1.0;
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline int grid_for(int total, int cap = 65535) { return total < 1 ? 1 : (total < cap ? total : cap); }
+
+int launch_pool(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
+  hipLaunchKernelGGL(k_pool, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
+  hipLaunchKernelGGL(k_upscale, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_reset_counter(int* counter, int n, void* stream) {
+  hipLaunchKernelGGL(k_reset_counter, dim3((n + 63) / 64), dim3(64), 0, (hipStream_t)stream, counter, n);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter, int phase,
+                      int grid, void* stream) {
+  hipLaunchKernelGGL(k_ctransform, dim3(grid), dim3(64), 0, (hipStream_t)stream, jobs, items, n_items,
+                     counter, phase);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream) {
+  hipLaunchKernelGGL(k_merge, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, phase);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_argmin(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream) {
+  hipLaunchKernelGGL(k_argmin, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, phase);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_lb_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
+  hipLaunchKernelGGL(k_lb_partial, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_ipf(const DevJob* jobs, int njobs, void* stream) {
+  hipLaunchKernelGGL(k_ipf, dim3(njobs), dim3(1024), 0, (hipStream_t)stream, jobs, njobs);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_scalings(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
+  hipLaunchKernelGGL(k_scalings, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_tv_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
+  hipLaunchKernelGGL(k_tv_partial, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_plancost(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
+  hipLaunchKernelGGL(k_plancost, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_finalize(const DevJob* jobs, int njobs, void* stream) {
+  hipLaunchKernelGGL(k_finalize, dim3(njobs), dim3(256), 0, (hipStream_t)stream, jobs, njobs);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_moments(const DevJob* jobs, int njobs, const int* off, int total, double* const* moms,
+                   void* stream) {
+  hipLaunchKernelGGL(k_moments, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, moms);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_cbar2(const DevJob* jobs, int njobs, const int* off, int total, double* const* outs,
+                 const double* const* moms, void* stream) {
+  hipLaunchKernelGGL(k_cbar, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, outs, moms);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_lb_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* dl, void* stream) {
+  hipLaunchKernelGGL(k_lb_grad, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, dl);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int stride, void* stream) {
+  hipLaunchKernelGGL(k_ub_coarse_bwd, dim3(njobs), dim3(1024), 0, (hipStream_t)stream, jobs, njobs, scratch, stride);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* du, int side,
+                   void* stream) {
+  hipLaunchKernelGGL(k_ub_grad, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, du, side);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_tv_prep(const DevJob* jobs, int njobs, void* stream) {
+  hipLaunchKernelGGL(k_tv_prep, dim3(njobs), dim3(1024), 0, (hipStream_t)stream, jobs, njobs);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
+                      double* const* outs, void* stream) {
+  hipLaunchKernelGGL(k_fhat_grad, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, dl, outs);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+
+}  // namespace qbw

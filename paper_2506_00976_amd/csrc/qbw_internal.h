@@ -1,0 +1,132 @@
+// Internal declarations shared by the host orchestration and the kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qbw.h"
+
+namespace qbw {
+
+// ---------------------------------------------------------------- host side
+
+struct CoarseProblem {
+  int Q;
+  const double* mu;    // host, Q
+  const double* nu;    // host, Q
+  const double* cost;  // host, Q x Q row-major
+  bool integer_cost;   // p = 2: C~ is an integer matrix
+};
+
+struct CoarseSolution {
+  std::vector<int> rows, cols;
+  std::vector<double> vals, f, g;
+  double objective = 0;
+  int64_t pivots = 0;
+};
+
+int coarse_solve(const CoarseProblem& P, CoarseSolution* out);
+void centre_cost(const qbw_grid& g, double* out);  // C~, host
+void set_error(const char* fmt, ...);
+
+// ---------------------------------------------------------------- device job
+
+// Layout of the per-job result block (doubles) written by the finalize kernel.
+enum ResultSlot {
+  RS_LOWER = 0, RS_UPPER, RS_LOWER_S, RS_SHIFT, RS_UPPER_COST, RS_TV_MU, RS_TV_NU,
+  RS_IPF_RESID, RS_COARSE_OBJ, RS_IPF_ITERS, RS_WARN,
+  RS_S32, RS_PCOST_RAW, RS_MAX_FHAT, RS_MAX_G, RS_MAX_F, RS_TVSUM_MU, RS_TVSUM_NU,
+  RS_MW_MU, RS_MW_NU, RS_TV_RAW_MU, RS_TV_RAW_NU,
+  RS_COUNT = 24
+};
+
+constexpr int kChunk = 1024;       // pixels per work-group in the O(P) kernels
+constexpr int kRedSlotsLB = 5;     // per chunk: sum f*mu, sum g*nu, max|fhat|, max|g|, max|f|
+constexpr int kRedSlotsTV = 4;     // per chunk: sum w|mu^-mu|, sum w|nu-nu^|, sum w mu, sum w nu
+
+// Everything a kernel needs to know about one job.  Plain data; pointers are
+// device memory.  The host builds an array of these and uploads it.
+struct DevJob {
+  int d, N, k, p;
+  int n, P, Q, rows;        // n = N/k, P = N^d, Q = n^d, rows = N^(d-1)
+  int R, S;                 // c-transform: targets per lane, source splits
+  int chunks;               // ceil(P / kChunk)
+  int nnz;                  // coarse coupling entries
+  int max_iter;             // IPF cap
+  int want_argmin;
+  double xi;
+  double coarse_obj;
+  const double* mu;         // fine measures
+  const double* nu;
+  double* mu_t;             // pooled measures (Q)
+  double* nu_t;
+  const double* ftil;       // coarse potential (Q)
+  float* fhat;              // upscaled potential (P)
+  float* g;                 // first c-transform (P)
+  float* f;                 // second c-transform (P)
+  float* part;              // partial minima (S x P)
+  int* win;                 // winning split per target (P)
+  int* arg_g;               // arg-mins (P) or null
+  int* arg_f;
+  // coarse coupling: entry list (sorted by row) and CSR / CSC views
+  const int* e_row;
+  const int* e_col;
+  const double* e_val;
+  const int* csr_ptr;       // Q+1, entries of row K are [csr_ptr[K], csr_ptr[K+1]) of the list
+  const int* csc_ptr;       // Q+1
+  const int* csc_idx;       // nnz: entry ids sorted by column
+  double* ipf_u;            // (max_iter + 2) x Q: u^t (t = 1..T+1)
+  double* ipf_v;            // (max_iter + 1) x Q: v^t (t = 1..T)
+  double* a_s;              // fine IPF scalings (P)
+  double* b_s;
+  double* red_lb;           // chunks x kRedSlotsLB
+  double* red_tv;           // chunks x kRedSlotsTV
+  double* red_pc;           // nnz: per-entry sum of a_s b_s c
+  double* result;           // RS_COUNT doubles
+  int* flags;               // bit 0: negative entry, bit 1: NaN (pool kernel)
+  // backward
+  double* grad_a;
+  double* grad_b;
+  double* gbar_mu;          // Q: d P / d mu~ (coarse adjoint)
+  double* gbar_nu;
+  double* coef;             // nnz: d P / d S_e coefficient
+};
+
+struct CtItem { int job, tile, split, pad; };
+
+// Kernel launchers (kernels.hip).  All enqueue on `stream`.
+struct Launch {
+  const DevJob* jobs;  // device array
+  int njobs;
+  const int* off;      // device prefix table for the launch's item kind
+  int total;           // total items
+};
+
+int launch_pool(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter,
+                      int phase, int grid, void* stream);
+int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
+int launch_argmin(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
+int launch_lb_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+int launch_ipf(const DevJob* jobs, int njobs, void* stream);
+int launch_scalings(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+int launch_tv_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+int launch_plancost(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+int launch_finalize(const DevJob* jobs, int njobs, void* stream);
+int launch_moments(const DevJob* jobs, int njobs, const int* off, int total, double* const* moms,
+                   void* stream);
+int launch_cbar2(const DevJob* jobs, int njobs, const int* off, int total, double* const* outs,
+                 const double* const* moms, void* stream);
+int launch_lb_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
+                   void* stream);
+int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int stride, void* stream);
+int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* du,
+                   int side, void* stream);
+int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
+                      double* const* outs, void* stream);
+int launch_tv_prep(const DevJob* jobs, int njobs, void* stream);
+int launch_reset_counter(int* counter, int n, void* stream);
+
+}  // namespace qbw

@@ -1,0 +1,393 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (derivations in the design doc):
+* float32 values and arg-mins of the c-transform, the upscaled potential:
+  bit-exact against the oracle's float32 reading;
+* float64 sums (lower bound, plan cost, pooled masses, C-bar): relative 1e-9
+  or tighter;
+* upper bound: the plan-cost part to 1e-9 relative; the total-variation terms
+  are square roots (p = 2) of rounding-level sums, so the emitted upper bound
+  must lie in [oracle, oracle + 1e-9 UB + 2 * 2^(1-1/p) (2^-39 <w, mu>)^(1/p)].
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+from oracle import coarse, grid, lower, lp, upper
+from oracle import grad as ograd
+
+pytestmark = pytest.mark.gpu
+
+qbw = pytest.importorskip("paper_2506_00976_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qbw.load()
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), device="cuda:0")
+
+
+def pair(N, d, fa, fb, seed):
+    return si.family(fa, N, d, si.rng(seed)), si.family(fb, N, d, si.rng(seed + 1))
+
+
+def record(mu, nu, k, p):
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
+    return qbw.Coarse(r, c, v, ft, gt, obj), (r, c, v, ft, gt, obj)
+
+
+def ub_tol(mu, nu, N, d, p, ub):
+    w = upper.tv_weights(N, d, p)
+    Mw = max(float(w @ mu.reshape(-1)), float(w @ nu.reshape(-1)))
+    c1 = 2.0 ** (1 - 1 / p)
+    return 1e-9 * ub + 2 * 2 * c1 * (2.0 ** -39 * Mw) ** (1 / p)
+
+
+# ------------------------------------------------------------------ c-transform
+
+CT_CASES = [(32, 2, 2), (32, 2, 1), (16, 3, 2), (16, 3, 1), (24, 2, 2), (20, 2, 1), (15, 2, 2),
+            (9, 3, 1), (64, 2, 2)]
+
+
+@pytest.mark.parametrize("N,d,p", CT_CASES)
+def test_ctransform_bit_exact(N, d, p):
+    P = N ** d
+    phi = (si.rng(7000 + N + p).standard_normal(P) * N * N / 4).astype(np.float32)
+    out, arg = qbw.ctransform(dev(phi), N, d, p, want_argmin=True)
+    ref, refarg = lower.ctransform_o32(phi, N, d, p)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    assert np.array_equal(arg.cpu().numpy().astype(np.int64), refarg)
+
+
+def test_ctransform_ties_and_constant_potential():
+    N, d, p = 16, 2, 2
+    phi = np.zeros(N * N, np.float32)           # every target's min is 0 at itself
+    out, arg = qbw.ctransform(dev(phi), N, d, p, want_argmin=True)
+    assert np.all(out.cpu().numpy() == 0) and np.array_equal(arg.cpu().numpy(), np.arange(N * N))
+    phi = np.full(N * N, -3.0, np.float32)
+    phi[::7] = 5.0                              # many equal candidates: lowest index wins
+    out, arg = qbw.ctransform(dev(phi), N, d, p, want_argmin=True)
+    ref, refarg = lower.ctransform_o32(phi, N, d, p)
+    assert np.array_equal(out.cpu().numpy(), ref) and np.array_equal(arg.cpu().numpy(), refarg)
+
+
+# ------------------------------------------------------------------ stages
+
+@pytest.mark.parametrize("N,d,k", [(32, 2, 4), (30, 2, 3), (16, 3, 2), (16, 2, 16), (12, 2, 1), (8, 3, 8)])
+def test_upscale_bit_exact(N, d, k):
+    n = N // k
+    ft = si.rng(7100 + N + k).standard_normal(n ** d) * 100
+    out = qbw.upscale_potential(dev(ft), N, d, k)
+    ref = lower.upscale_potential(ft, N, d, k).astype(np.float32)
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("N,d,k", [(32, 2, 4), (16, 3, 4), (30, 2, 5)])
+def test_sumpool(N, d, k):
+    m = si.grf(N, d, si.rng(7200 + N))
+    out = qbw.sumpool(dev(m), k).cpu().numpy()
+    assert np.allclose(out, coarse.sumpool(m, k), rtol=k ** d * 2.0 ** -53, atol=0)
+
+
+@pytest.mark.parametrize("N,d,k,p", [(16, 2, 4, 2), (16, 2, 4, 1), (8, 3, 2, 2), (8, 3, 2, 1),
+                                     (16, 2, 2, 2)])
+def test_cbar(N, d, k, p):
+    mu, nu = pair(N, d, "shapes", "grf", 7300 + N + p)   # shapes: empty blocks -> C~ fallback
+    out = qbw.cbar(dev(mu), dev(nu), k, p).cpu().numpy()
+    ref = coarse.cbar(mu, nu, k, p)
+    assert np.allclose(out, ref, rtol=1e-11, atol=1e-11 * ref.max())
+
+
+def test_coarse_cost():
+    for p in (1, 2):
+        assert np.allclose(qbw.coarse_cost(16, 3, 4, p), coarse.centre_cost(16, 3, 4, p), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("N,d,k,p", [(32, 2, 4, 2), (16, 3, 2, 1), (24, 2, 3, 2)])
+def test_ipf_plan_cost_tv(N, d, k, p):
+    mu, nu = pair(N, d, "gmm", "shapes", 7400 + N)
+    rec, (r, c, v, ft, gt, obj) = record(mu, nu, k, p)
+    a_s, b_s, it, res = qbw.ipf(dev(mu), dev(nu), k, rec)
+    P = N ** d
+    I, J, V = upper.upscale_plan(r, c, v, N, d, k)
+    oa, ob, mh, nh, oit, ores = upper.ipf(mu.reshape(-1), nu.reshape(-1), I, J, V, 1e-12, 50)
+    assert it == oit
+    assert np.allclose(a_s.cpu().numpy(), oa, rtol=1e-12, atol=0)
+    assert np.allclose(b_s.cpu().numpy(), ob, rtol=1e-12, atol=0)
+    pc = qbw.plan_cost(a_s, b_s, N, d, k, p, rec)
+    assert pc == pytest.approx(upper.plan_cost(I, J, V, oa, ob, N, d, p), rel=1e-12)
+    tm, tn = qbw.tv(dev(mu), dev(nu), k, p, rec, a_s, b_s)
+    w = upper.tv_weights(N, d, p)
+    tol = 2 * 2.0 ** (1 - 1 / p) * (2.0 ** -40 * float(w @ mu.reshape(-1) + w @ nu.reshape(-1))) ** (1 / p)
+    assert abs(tm - upper.weighted_tv(w, mh, mu.reshape(-1), p)) <= tol
+    assert abs(tn - upper.weighted_tv(w, nu.reshape(-1), nh, p)) <= tol
+
+
+def test_ipf_not_converged_coupling():
+    # a coupling of perturbed marginals: several iterations, non-trivial TV terms
+    N, d, k, p = 16, 2, 4, 2
+    mu, nu = pair(N, d, "grf", "gmm", 7450)
+    mt = coarse.sumpool(mu, k) * np.exp(0.3 * si.rng(7451).standard_normal(16))
+    r, c, v = lp.northwest_corner(mt / mt.sum(), coarse.sumpool(nu, k))
+    rec = qbw.Coarse(r, c, v, np.zeros(16))
+    a_s, b_s, it, res = qbw.ipf(dev(mu), dev(nu), k, rec, max_ipf_iter=3)
+    I, J, V = upper.upscale_plan(r, c, v, N, d, k)
+    oa, ob, mh, nh, oit, ores = upper.ipf(mu.reshape(-1), nu.reshape(-1), I, J, V, 1e-12, 3)
+    assert it == oit == 3
+    assert res == pytest.approx(ores, rel=1e-9)
+    assert np.allclose(a_s.cpu().numpy(), oa, rtol=1e-12, atol=0)
+    tm, tn = qbw.tv(dev(mu), dev(nu), k, p, rec, a_s, b_s)
+    w = upper.tv_weights(N, d, p)
+    assert tm == pytest.approx(upper.weighted_tv(w, mh, mu.reshape(-1), p), rel=1e-9)
+    out = qbw.bounds(dev(mu), dev(nu), k, p, coarse=rec, max_ipf_iter=3)
+    assert out["warn"] & qbw.QBW_WARN_IPF_NOT_CONVERGED
+    U = upper.upper_bound_o64(mu, nu, r, c, v, k, p, max_iter=3)
+    assert U["upper"] <= out["upper"] <= U["upper"] + ub_tol(mu, nu, N, d, p, U["upper"])
+
+
+# ------------------------------------------------------------------ whole method
+
+BOUND_CASES = [(32, 2, 4, 2, "blobs", "blobs"), (32, 2, 4, 1, "gmm", "grf"), (64, 2, 8, 2, "cauchy", "shapes"),
+               (16, 3, 2, 2, "grf", "grf"), (16, 3, 4, 1, "gmm", "white_noise"), (24, 2, 3, 2, "grf", "cauchy")]
+
+
+@pytest.mark.parametrize("N,d,k,p,fa,fb", BOUND_CASES)
+def test_bounds_with_coarse(N, d, k, p, fa, fb):
+    mu, nu = pair(N, d, fa, fb, 7500 + N + k + p)
+    rec, (r, c, v, ft, gt, obj) = record(mu, nu, k, p)
+    out = qbw.bounds(dev(mu), dev(nu), k, p, coarse=rec)
+    L32 = lower.lower_bound_o32(mu, nu, ft, k, p)
+    L64 = lower.lower_bound_o64(mu, nu, ft, k, p)
+    U = upper.upper_bound_o64(mu, nu, r, c, v, k, p)
+    assert out["lower_S"] == pytest.approx(L32["S_emit"], rel=1e-9)
+    assert out["feas_shift"] == pytest.approx(L32["shift"], rel=1e-12)
+    assert out["lower"] == pytest.approx(L32["lower"], rel=1e-9)
+    assert out["lower"] <= L64["lower"]
+    assert out["ipf_iters"] == U["iters"]
+    assert out["upper_cost"] == pytest.approx(U["plan_cost"], rel=1e-9)
+    assert out["upper_cost"] >= U["plan_cost"]
+    assert U["upper"] <= out["upper"] <= U["upper"] + ub_tol(mu, nu, N, d, p, U["upper"])
+    assert out["coarse_objective"] == pytest.approx(obj, rel=1e-12)
+
+
+def test_bounds_potentials_bit_exact():
+    N, d, k, p = 32, 2, 4, 2
+    mu, nu = pair(N, d, "gmm", "gmm", 7600)
+    rec, (r, c, v, ft, gt, obj) = record(mu, nu, k, p)
+    fhat = qbw.upscale_potential(dev(ft), N, d, k)
+    g = qbw.ctransform(fhat, N, d, p)
+    f = qbw.ctransform(g, N, d, p)
+    L32 = lower.lower_bound_o32(mu, nu, ft, k, p)
+    assert np.array_equal(g.cpu().numpy(), L32["g32"]) and np.array_equal(f.cpu().numpy(), L32["f32"])
+    L64 = lower.lower_bound_o64(mu, nu, ft, k, p)
+    scale = max(np.abs(L64["g"]).max(), 1.0)
+    assert np.abs(g.cpu().numpy() - L64["g"]).max() <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("N,d,k,p", [(16, 2, 4, 2), (16, 2, 4, 1), (8, 3, 2, 2)])
+def test_end_to_end_brackets_exact(N, d, k, p):
+    mu, nu = pair(N, d, "gmm", "cauchy", 7700 + N + p)
+    W = lp.wasserstein_exact(mu, nu, p)
+    out = qbw.bounds(dev(mu), dev(nu), k, p)
+    *_, obj = upper.coarse_record_lp(mu, nu, k, p)
+    assert out["coarse_objective"] == pytest.approx(obj, rel=1e-9)
+    assert out["lower"] <= W <= out["upper"]
+
+
+def test_config1_against_exact_lp():
+    import json
+    import os
+    mu, nu = si.config1_pair()
+    gold = os.path.join(os.path.dirname(__file__), "golden", "config1_exact.json")
+    if not os.path.exists(gold):
+        pytest.skip("golden value not generated")
+    W = json.load(open(gold))["exact_W2"]
+    out = qbw.bounds(dev(mu), dev(nu), 4, 2)
+    assert out["lower"] <= W <= out["upper"]
+
+
+def test_input_validation():
+    N = 16
+    mu, nu = pair(N, 2, "grf", "grf", 7800)
+    with pytest.raises(qbw.QbwError, match="E_GRID"):
+        qbw.bounds(dev(mu), dev(nu), 5, 2)
+    bad = mu.copy()
+    bad[3, 3] = -1e-3
+    with pytest.raises(qbw.QbwError, match="E_MASS"):
+        qbw.bounds(dev(bad), dev(nu), 4, 2)
+    with pytest.raises(qbw.QbwError, match="E_MASS"):
+        qbw.bounds(dev(mu), dev(nu * 1.5), 4, 2)
+    nanm = mu.copy()
+    nanm[0, 0] = np.nan
+    with pytest.raises(qbw.QbwError, match="E_MASS"):
+        qbw.bounds(dev(nanm), dev(nu), 4, 2)
+
+
+# ------------------------------------------------------------------ gradients
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_gradients_against_oracle_and_fd(p):
+    N, d, k = 16, 2, 4
+    mu, nu = pair(N, d, "gmm", "gmm", 7900 + p)
+    rec, (r, c, v, ft, gt, obj) = record(mu, nu, k, p)
+    v2 = v * np.exp(0.2 * si.rng(7902).standard_normal(len(v)))    # several IPF iterations
+    rec2 = qbw.Coarse(r, c, v2, ft)
+    res, ga, gb, _ = qbw.bounds_with_grads(dev(mu), dev(nu), k, p, coarse=rec2, dlower=0.7, dupper=1.3)
+    L32 = lower.lower_bound_o32(mu, nu, ft, k, p)
+    lgm, lgn = ograd.lower_grad(L32["f32"], L32["g32"], L32["S_emit"], p)
+    U = upper.upper_bound_o64(mu, nu, r, c, v2, k, p)
+    ugm, ugn, _ = ograd.upper_grad(mu, nu, r, c, v2, k, p, U["iters"])
+    ref_a = 0.7 * lgm + 1.3 * ugm
+    ref_b = 0.7 * lgn + 1.3 * ugn
+    scale = np.abs(ref_a).max()
+    assert np.allclose(ga.cpu().numpy().reshape(-1), ref_a, rtol=1e-9, atol=1e-9 * scale)
+    assert np.allclose(gb.cpu().numpy().reshape(-1), ref_b, rtol=1e-9, atol=1e-9 * scale)
+    # central differences of the GPU forward (frozen coarse solution), mass preserving
+    g = si.rng(7903)
+    h = 1e-4
+    for _ in range(2):
+        vm = g.uniform(-1, 1, mu.shape)
+        vm -= (mu * vm).sum() / mu.sum()
+        vn = g.uniform(-1, 1, nu.shape)
+        vn -= (nu * vn).sum() / nu.sum()
+
+        def F(s):
+            o = qbw.bounds(dev(mu * (1 + s * vm)), dev(nu * (1 + s * vn)), k, p, coarse=rec2)
+            return 0.7 * o["lower"] + 1.3 * (o["upper_cost"] ** (1 / p))
+
+        fd = (F(h) - F(-h)) / (2 * h)
+        an = float((ga.cpu().numpy() * mu * vm).sum() + (gb.cpu().numpy() * nu * vn).sum())
+        assert fd == pytest.approx(an, rel=2e-5, abs=1e-7)
+
+
+def test_autograd_function():
+    N, d, k, p = 16, 2, 4, 2
+    mu, nu = pair(N, d, "grf", "gmm", 7950)
+    rec, (r, c, v, ft, gt, obj) = record(mu, nu, k, p)
+    a = dev(mu).requires_grad_(True)
+    b = dev(nu).requires_grad_(True)
+    lo, up = qbw.wasserstein_bounds(a, b, k, p, coarse=rec)
+    (2.0 * lo - up).backward()
+    res, ga, gb, _ = qbw.bounds_with_grads(dev(mu), dev(nu), k, p, coarse=rec, dlower=2.0, dupper=-1.0)
+    assert torch.equal(a.grad, ga) and torch.equal(b.grad, gb)
+
+
+def test_fhat_gradient_through_argmins():
+    N, d, k, p = 16, 2, 4, 2
+    mu, nu = pair(N, d, "grf", "cauchy", 7960)
+    rec, (r, c, v, ft, gt, obj) = record(mu, nu, k, p)
+    res, ga, gb, gf = qbw.bounds_with_grads(dev(mu), dev(nu), k, p, coarse=rec, dlower=1.0, dupper=0.0,
+                                            want_fhat_grad=True)
+    L32 = lower.lower_bound_o32(mu, nu, ft, k, p)
+    s = 0.5 / math.sqrt(L32["S_emit"])
+    ref = np.zeros(N * N)
+    np.add.at(ref, L32["argmin_g"][L32["argmin_f"]], s * mu.reshape(-1))
+    np.add.at(ref, L32["argmin_g"], -s * nu.reshape(-1))
+    assert np.allclose(gf.cpu().numpy(), ref, rtol=1e-12, atol=1e-15)
+
+
+# ------------------------------------------------------------------ batches
+
+def test_batch_matches_single_and_graph_replays():
+    jobs, recs, singles = [], [], []
+    specs = [(32, 2, 4, 2), (16, 3, 2, 1), (24, 2, 3, 2), (32, 2, 8, 1), (16, 2, 4, 2)]
+    for i, (N, d, k, p) in enumerate(specs):
+        mu, nu = pair(N, d, "grf", "gmm", 8000 + 2 * i)
+        rec, _ = record(mu, nu, k, p)
+        a, b = dev(mu), dev(nu)
+        jobs.append((a, b, k, p))
+        recs.append(rec)
+        singles.append(qbw.bounds(a, b, k, p, coarse=rec))
+    for graph in (False, True):
+        B = qbw.Batch(jobs, coarse=recs, graph=graph, backward=True)
+        for rep in range(3):
+            for ga, gb in B.grads:
+                ga.zero_()
+                gb.zero_()
+            torch.ones(1000, device="cuda:0").sum().item()   # eager work between replays
+            B.run()
+            out = B.results()
+            for s, o in zip(singles, out):
+                for key in ("lower", "upper", "lower_S", "upper_cost", "feas_shift", "ipf_iters"):
+                    assert s[key] == o[key], (graph, rep, key)
+        # batch gradients equal the single-pair backward
+        for (a, b, k, p), rec, (ga, gb) in zip(jobs, recs, B.grads):
+            _, sa, sb, _ = qbw.bounds_with_grads(a, b, k, p, coarse=rec)
+            assert torch.allclose(ga, sa, rtol=1e-12, atol=0) and torch.allclose(gb, sb, rtol=1e-12, atol=0)
+
+
+def test_batch_internal_coarse_and_autotune():
+    specs = [(32, 2, 4, 2), (16, 3, 4, 1), (32, 2, 8, 2)]
+    jobs, refs = [], []
+    for i, (N, d, k, p) in enumerate(specs):
+        mu, nu = pair(N, d, "cauchy", "grf", 8100 + 2 * i)
+        jobs.append((dev(mu), dev(nu), k, p))
+        *_, obj = upper.coarse_record_lp(mu, nu, k, p)
+        refs.append(obj)
+    B = qbw.Batch(jobs, autotune=True)
+    B.run()
+    for o, obj, (a, b, k, p) in zip(B.results(), refs, jobs):
+        assert o["coarse_objective"] == pytest.approx(obj, rel=1e-9)
+        assert o["lower"] <= o["upper"]
+    for j in range(len(jobs)):
+        R, Sp = B.tiling(j)
+        assert R in (1, 2, 4, 8, 16) and Sp >= 1
+
+
+# ------------------------------------------------------------------ full size (256 x 256, k = 8)
+
+@pytest.fixture(scope="module")
+def big_records():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "records_256_k8.npz")
+    return np.load(path)
+
+
+@pytest.mark.parametrize("fam", ["grf", "cauchy"])
+def test_full_size_sampled_parity(fam, big_records):
+    N, d, k, p = 256, 2, 8, 2
+    mu, nu = si.config3_pair(N, fam)
+    R = big_records
+    rec = qbw.Coarse(R[f"{fam}_rows"], R[f"{fam}_cols"], R[f"{fam}_vals"], R[f"{fam}_f"])
+    fhat = qbw.upscale_potential(dev(R[f"{fam}_f"]), N, d, k)
+    fh_ref = lower.upscale_potential(R[f"{fam}_f"], N, d, k).astype(np.float32)
+    assert np.array_equal(fhat.cpu().numpy(), fh_ref)
+    g, garg = qbw.ctransform(fhat, N, d, p, want_argmin=True)
+    f = qbw.ctransform(g, N, d, p)
+    tg = si.rng(8200).choice(N * N, 192, replace=False)
+    ref, refarg = lower.ctransform_o32(fh_ref, N, d, p, targets=tg)
+    assert np.array_equal(g.cpu().numpy()[tg], ref)
+    assert np.array_equal(garg.cpu().numpy()[tg].astype(np.int64), refarg)
+    # second transform: f = g^c at sampled targets, for the g the kernel produced
+    gn = g.cpu().numpy()
+    ref_f, _ = lower.ctransform_o32(gn, N, d, p, targets=tg)
+    assert np.array_equal(f.cpu().numpy()[tg], ref_f)
+    out = qbw.bounds(dev(mu), dev(nu), k, p, coarse=rec)
+    # the lower bound is the float64 sum of the float32 potentials minus the shift
+    S = lower.fsum_dot(f.cpu().numpy(), mu.reshape(-1)) + lower.fsum_dot(gn, nu.reshape(-1))
+    assert out["lower_S"] == pytest.approx(S - out["feas_shift"], rel=1e-9)
+    assert out["lower"] <= out["upper"]
+    assert out["ipf_iters"] == 1
+    # uniform kernel + converged fitting: plan cost = <pi~, C-bar>
+    Cb = qbw.cbar(dev(mu), dev(nu), k, p).cpu().numpy()
+    ident = float((Cb[R[f"{fam}_rows"], R[f"{fam}_cols"]] * R[f"{fam}_vals"]).sum())
+    assert out["upper_cost"] == pytest.approx(ident, rel=1e-9)
+
+
+def test_full_size_translation_closed_form():
+    N, d, k, p = 256, 2, 8, 2
+    mu, nu = si.translated_pair(N, d, (5, -9), si.rng(8300))
+    out = qbw.bounds(dev(mu), dev(nu), k, p)
+    W = math.sqrt(5 ** 2 + 9 ** 2)
+    assert out["lower"] <= W <= out["upper"]
+    assert out["lower"] > 0.9 * W
