@@ -1,0 +1,243 @@
+#!/usr/bin/env python
+"""Benchmark: bound pairs per second at 256x256, k = 8, p = 2 (lower + upper
+bound), batched forward + backward, on one MI355X.
+
+One step = one pass of the whole fine-grid path over a batch of B pairs:
+pooling, potential upscaling, both c-transforms, lower-bound sums and shift,
+IPF, plan cost, TV terms, finalisation, and the backward kernels of both
+bounds, replayed as one hipGraph.  The coarse Kantorovich problems are solved
+once before the timed region by the host network simplex (all host cores);
+their cost is reported separately as the end-to-end rate.
+
+Prints ONE JSON line (stdout); progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP32 vector peak of MI355X: 157.3 TFLOP/s = 256 CUs x 128 FMA lanes/clk x 2 flop x 2.4 GHz,
+# i.e. 78.6 T VALU lane-operations/s (measured: all-VGPR v_sub_f32 issues at ~100 lanes/clk/CU).
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
+INSTR_PER_PAIR = 1.5               # minimum per (source, target) pair: one v_sub_f32 + half a v_min3_f32
+PEAK_PAIRS = PEAK_LANE_OPS / INSTR_PER_PAIR
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2506_00976_amd", "csrc", "kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per c-transform launch from the committed counter summary,
+    only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "ctransform_traffic_256_k8.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def make_inputs(batch: int, N: int = 256):
+    import synth_inputs as si
+    pairs = []
+    for i in range(batch):
+        fam = "grf" if i % 2 == 0 else "cauchy"
+        pairs.append(si.config3_pair(N, fam, idx=i // 2))
+    return pairs
+
+
+def cpu_baseline(N: int, k: int, p: int, n_targets: int = 128):
+    """The oracle as it stands, on a bounded sample of one 256x256 pair: n_targets
+    targets of each c-transform (extrapolated to all 2 N^2 targets) plus the full
+    upper bound and its gradient; the lower-bound gradient is f, g themselves."""
+    import synth_inputs as si
+    from oracle import grad as og
+    from oracle import lower, upper
+    mu, nu = si.config3_pair(N, "grf")
+    r, c, v = None, None, None
+    path = os.path.join(ROOT, "tests", "golden", "records_256_k8.npz")
+    R = np.load(path)
+    r, c, v, ft = R["grf_rows"], R["grf_cols"], R["grf_vals"], R["grf_f"]
+    P = N * N
+    t0 = time.perf_counter()
+    fh = lower.upscale_potential(ft, N, 2, k).astype(np.float32)
+    tg = np.linspace(0, P - 1, n_targets).astype(np.int64)
+    g, _ = lower.ctransform_o32(fh, N, 2, p, targets=tg)
+    t_ct = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    U = upper.upper_bound_o64(mu, nu, r, c, v, k, p)
+    og.upper_grad(mu, nu, r, c, v, k, p, U["iters"])
+    t_ub = time.perf_counter() - t1
+    per_pair = t_ct / n_targets * 2 * P + t_ub
+    return {"value": 1.0 / per_pair, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"one 256x256 GRF pair, k=8: {n_targets} targets of the float32 c-transform "
+                      f"(x{2 * P // n_targets} to cover both transforms) + full upper bound and its "
+                      f"gradient; {t_ct + t_ub:.1f} s measured, {per_pair:.1f} s per bound pair",
+            "seconds_measured": t_ct + t_ub}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="only the timed steps (for rocprofv3 runs)")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch the kernels one by one instead of replaying a hipGraph")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain device copy of 1 GiB (calibrates FETCH_SIZE / WRITE_SIZE)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the method's "
+              "fine-grid path runs on a single MI355X here; see DESIGN.md for how it would shard.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2506_00976_amd as qbw
+
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 8, "copies": 3}))
+        return
+
+    N, d, k, p = 256, 2, 8, 2
+    B = args.batch
+    dev = torch.device("cuda:0")
+    qbw.load()
+    log(f"[bench] generating {B} pairs at {N}x{N}")
+    pairs = make_inputs(B, N)
+    A = [torch.tensor(a, device=dev) for a, _ in pairs]
+    Bm = [torch.tensor(b, device=dev) for _, b in pairs]
+    torch.cuda.synchronize()
+
+    # ---- coarse solutions: pool on the device, host network simplex on all cores
+    t0 = time.perf_counter()
+    mts = [qbw.sumpool(a, k).cpu().numpy() for a in A]
+    nts = [qbw.sumpool(b, k).cpu().numpy() for b in Bm]
+    workers = os.cpu_count() or 1
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        recs = list(ex.map(lambda t: qbw.coarse_solve(t[0], t[1], N, d, k, p), zip(mts, nts)))
+    t_coarse = time.perf_counter() - t0
+    log(f"[bench] coarse solves: {t_coarse:.2f} s for {B} pairs on {workers} threads")
+
+    grads = [(torch.zeros_like(a), torch.zeros_like(b)) for a, b in zip(A, Bm)]
+    jobs = [(a, b, k, p, ga, gb) for (a, b), (ga, gb) in zip(zip(A, Bm), grads)]
+    batch = qbw.Batch(jobs, coarse=recs, backward=True, graph=not args.eager)
+    for _ in range(args.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} graph steps (batch {B}, fwd+bwd)")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = B / (ms_step / 1e3)
+    res = batch.results()
+    if args.profile:
+        print(json.dumps({"profile_run": True, "ms_per_step": ms_step}))
+        return
+    log(f"[bench] {ms_step:.3f} ms/step -> {value:.1f} pairs/s")
+
+    # ---- the dominant kernel, timed live with HIP events on its stream
+    eager = qbw.Batch(jobs, coarse=recs, backward=True, graph=False)
+    eager.run()
+    torch.cuda.synchronize()
+    eager.set_timing(True)
+    reps = max(3, args.steps // 2)
+    for _ in range(reps):
+        eager.run()
+    mean_ms, launches = eager.ctransform_time()
+    eager.set_timing(False)
+    pairs_per_launch = eager.ctransform_pairs()
+    achieved = pairs_per_launch / (mean_ms / 1e3)
+    log(f"[bench] c-transform: {launches} launches, mean {mean_ms:.3f} ms, "
+        f"{achieved / 1e12:.2f} Tpair/s ({achieved / PEAK_PAIRS:.1%} of {PEAK_PAIRS / 1e12:.1f})")
+
+    # ---- plain single-pair path (one pair per call, no graph, same accuracy)
+    nplain = min(8, B)
+    for i in range(2):
+        qbw.bounds(A[i], Bm[i], k, p, coarse=recs[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nplain):
+        qbw.bounds(A[i], Bm[i], k, p, coarse=recs[i])
+    torch.cuda.synchronize()
+    plain_fwd = nplain / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    for i in range(nplain):
+        qbw.bounds_with_grads(A[i], Bm[i], k, p, coarse=recs[i])
+    torch.cuda.synchronize()
+    plain_fb = nplain / (time.perf_counter() - t0)
+    log(f"[bench] plain: fwd {plain_fwd:.1f} pairs/s, fwd+bwd {plain_fb:.1f} pairs/s")
+
+    # consistency of the timed results with the single-pair path
+    ref = qbw.bounds(A[0], Bm[0], k, p, coarse=recs[0])
+    assert ref["lower"] == res[0]["lower"] and ref["upper"] == res[0]["upper"], (ref, res[0])
+
+    out = {
+        "metric": "bound pairs/sec at 256^2 k=8 (lower+upper), batched fwd+bwd",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {B} pairs of 256x256 measures (GRF and Cauchy families), "
+                               "k=8, p=2, forward+backward of both bounds, coarse solutions pre-solved",
+                   "N": N, "d": d, "k": k, "p": p, "batch": B,
+                   "precision": "float32 c-transforms, float64 sums/IPF/plan cost"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_PAIRS / 1e12,
+                     "unit": "Tpair/s", "frac": achieved / PEAK_PAIRS, "traffic": read_traffic(),
+                     "kernel": "k_ctransform", "mean_launch_ms": mean_ms,
+                     "pairs_per_launch": pairs_per_launch},
+        "plain": {"fwd_pairs_per_s": plain_fwd, "fwd_bwd_pairs_per_s": plain_fb,
+                  "batched_over_plain_fwd_bwd": value / plain_fb},
+        "end_to_end": {"coarse_seconds": t_coarse, "host_threads": workers,
+                       "pairs_per_s_sequential": B / (t_coarse + ms_step / 1e3),
+                       "pairs_per_s_pipelined": B / max(t_coarse, ms_step / 1e3)},
+        "bounds_sample": {"lower": res[0]["lower"], "upper": res[0]["upper"]},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(N, k, p)
+        log(f"[bench] cpu oracle: {out['cpu_baseline']['value']:.3e} pairs/s")
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -252,6 +252,17 @@ qbw_status qbw_batch_tiling(const qbw_batch* batch, int32_t job, int32_t* target
                             int32_t* splits);
 void qbw_batch_destroy(qbw_batch* batch);
 
+/* Kernel timing for measurement: while enabled, eager (non-graph) runs record
+ * a pair of hipEvents on the run's stream around every c-transform launch.
+ * qbw_batch_ctransform_time synchronises on them and returns the mean launch
+ * duration (ms) and the number of launches recorded since the last call,
+ * then forgets them.  Graph runs record nothing.  Outputs host. */
+qbw_status qbw_batch_set_timing(qbw_batch* batch, int32_t enable);
+qbw_status qbw_batch_ctransform_time(qbw_batch* batch, double* mean_ms, int32_t* launches);
+/* Pair evaluations (sources x targets) one c-transform launch of the batch
+ * performs: sum over jobs of (N^d)^2. */
+qbw_status qbw_batch_ctransform_pairs(const qbw_batch* batch, double* pairs);
+
 /* Convenience: create, run the forward pass once, fetch results, destroy. */
 qbw_status qbw_bounds_batched(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs,
                               const qbw_opts* opts, qbw_result* out, qbw_stream stream);

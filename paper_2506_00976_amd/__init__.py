@@ -382,6 +382,21 @@ class Batch:
         check(load().qbw_batch_tiling(self.handle, j, C.byref(R), C.byref(Sp)), "qbw_batch_tiling")
         return R.value, Sp.value
 
+    def set_timing(self, enable: bool):
+        check(load().qbw_batch_set_timing(self.handle, int(bool(enable))), "qbw_batch_set_timing")
+
+    def ctransform_time(self):
+        """(mean c-transform launch duration in ms, launches) since the last call."""
+        ms, n = C.c_double(), C.c_int32()
+        check(load().qbw_batch_ctransform_time(self.handle, C.byref(ms), C.byref(n)),
+              "qbw_batch_ctransform_time")
+        return ms.value, n.value
+
+    def ctransform_pairs(self) -> float:
+        out = C.c_double()
+        check(load().qbw_batch_ctransform_pairs(self.handle, C.byref(out)), "qbw_batch_ctransform_pairs")
+        return out.value
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:

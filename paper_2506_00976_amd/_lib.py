@@ -75,6 +75,9 @@ SIGNATURES = [
     ("qbw_batch_results", C.c_int, [_vp, _pr, _vp]),
     ("qbw_batch_tiling", C.c_int, [_vp, _i32, _vp, _vp]),
     ("qbw_batch_destroy", None, [_vp]),
+    ("qbw_batch_set_timing", C.c_int, [_vp, _i32]),
+    ("qbw_batch_ctransform_time", C.c_int, [_vp, _vp, _vp]),
+    ("qbw_batch_ctransform_pairs", C.c_int, [_vp, _vp]),
     ("qbw_bounds_batched", C.c_int, [_vp, C.POINTER(QbwJob), _i32, _po, _pr, _vp]),
     ("qbw_autotune_ctransform", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
 ]

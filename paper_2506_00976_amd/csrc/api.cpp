@@ -245,8 +245,9 @@ struct Plan {
   char* base = nullptr;
   DevJob* djobs = nullptr;
   int *off_chunk = nullptr, *off_pool = nullptr, *off_entry = nullptr, *off_block = nullptr,
-      *off_cbar = nullptr, *off_mom = nullptr;
-  int tot_chunk = 0, tot_pool = 0, tot_entry = 0, tot_block = 0, tot_cbar = 0, tot_mom = 0;
+      *off_cbar = nullptr, *off_mom = nullptr, *off_pc1 = nullptr, *off_pc2 = nullptr;
+  int tot_chunk = 0, tot_pool = 0, tot_entry = 0, tot_block = 0, tot_cbar = 0, tot_mom = 0,
+      tot_pc1 = 0, tot_pc2 = 0;
   CtItem* items = nullptr;
   int n_items = 0;
   int ct_grid = 1;
@@ -258,9 +259,14 @@ struct Plan {
   int max_q = 1;              // row stride of bwd_scratch (per job: 4 x max_q doubles)
   double* results = nullptr;  // njobs x RS_COUNT
   double** cbar_out = nullptr;  // device array of njobs pointers
-  double** moms = nullptr;      // device array of 2 njobs pointers
   double** fhat_grad_out = nullptr;
   std::vector<double> host_results;
+  bool timing = false;                                  // event pairs around c-transforms
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  size_t ev_used = 0;
+  ~Plan() {
+    for (auto& e : ev_pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  }
 };
 
 static int choose_splits(std::vector<JobIn>& in, int target_waves) {
@@ -293,8 +299,8 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   Layout L;
   struct Offs {
     size_t mu_t, nu_t, ftil, fhat, g, f, part, win, arg_g, arg_f, e_row, e_col, e_val, csr, csc,
-        csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, gbar_mu, gbar_nu, coef, mom0, mom1,
-        cbar;
+        csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, gbar_mu, gbar_nu, coef, mom_mu, mom_nu,
+        mom_as, mom_bs;
   };
   std::vector<Offs> offs(NJ);
   const bool ub = true;
@@ -331,11 +337,14 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     O.gbar_mu = L.add(8 * (size_t)Q);
     O.gbar_nu = L.add(8 * (size_t)Q);
     O.coef = L.add(8 * (size_t)nnz);
-    O.mom0 = (mode & PM_CBAR) ? L.add(8 * 4 * (size_t)Q) : 0;
-    O.mom1 = (mode & PM_CBAR) ? L.add(8 * 4 * (size_t)Q) : 0;
+    O.mom_mu = L.add(8 * 5 * (size_t)Q);
+    O.mom_nu = L.add(8 * 5 * (size_t)Q);
+    O.mom_as = L.add(8 * 5 * (size_t)Q);
+    O.mom_bs = L.add(8 * 5 * (size_t)Q);
   }
   const size_t o_jobs = L.add(sizeof(DevJob) * NJ);
-  const size_t o_offs = L.add(sizeof(int) * 6 * (NJ + 1));
+  constexpr int kTables = 8;
+  const size_t o_offs = L.add(sizeof(int) * kTables * (NJ + 1));
   // c-transform work items
   std::vector<CtItem> items;
   for (int j = 0; j < NJ; ++j) {
@@ -375,7 +384,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   char* B = pl.base;
   // host images of the uploaded region
   pl.hj.resize(NJ);
-  std::vector<int> off(6 * (NJ + 1), 0);
+  std::vector<int> off(kTables * (NJ + 1), 0);
   for (int j = 0; j < NJ; ++j) {
     const auto& J = pl.in[j];
     const Offs& O = offs[j];
@@ -426,12 +435,18 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.gbar_mu = (double*)(B + O.gbar_mu);
     D.gbar_nu = (double*)(B + O.gbar_nu);
     D.coef = (double*)(B + O.coef);
+    D.mom_mu = (double*)(B + O.mom_mu);
+    D.mom_nu = (double*)(B + O.mom_nu);
+    D.mom_as = (double*)(B + O.mom_as);
+    D.mom_bs = (double*)(B + O.mom_bs);
     off[0 * (NJ + 1) + j + 1] = off[0 * (NJ + 1) + j] + D.chunks;
     off[1 * (NJ + 1) + j + 1] = off[1 * (NJ + 1) + j] + (D.Q + 255) / 256;
     off[2 * (NJ + 1) + j + 1] = off[2 * (NJ + 1) + j] + D.nnz;
     off[3 * (NJ + 1) + j + 1] = off[3 * (NJ + 1) + j] + D.Q;
     off[4 * (NJ + 1) + j + 1] = off[4 * (NJ + 1) + j] + (int)(((long long)D.Q * D.Q + 255) / 256);
     off[5 * (NJ + 1) + j + 1] = off[5 * (NJ + 1) + j] + (2 * D.Q + 255) / 256;
+    off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + (D.p == 1 ? D.nnz : 0);
+    off[7 * (NJ + 1) + j + 1] = off[7 * (NJ + 1) + j] + (D.p == 2 ? (D.nnz + 255) / 256 : 0);
   }
   pl.djobs = (DevJob*)(B + o_jobs);
   int* offd = (int*)(B + o_offs);
@@ -441,6 +456,10 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   pl.off_block = offd + 3 * (NJ + 1);
   pl.off_cbar = offd + 4 * (NJ + 1);
   pl.off_mom = offd + 5 * (NJ + 1);
+  pl.off_pc1 = offd + 6 * (NJ + 1);
+  pl.off_pc2 = offd + 7 * (NJ + 1);
+  pl.tot_pc1 = off[6 * (NJ + 1) + NJ];
+  pl.tot_pc2 = off[7 * (NJ + 1) + NJ];
   pl.tot_chunk = off[0 * (NJ + 1) + NJ];
   pl.tot_pool = off[1 * (NJ + 1) + NJ];
   pl.tot_entry = off[2 * (NJ + 1) + NJ];
@@ -455,7 +474,6 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   pl.bwd_scratch = (double*)(B + o_bwd);
   double** ptrs = (double**)(B + o_ptrs);
   pl.cbar_out = ptrs;
-  pl.moms = ptrs + NJ;
   pl.fhat_grad_out = ptrs + 3 * NJ;
   // persistent grid: enough waves to fill the chip, never more than the items
   pl.ct_grid = std::max(1, std::min(pl.n_items, ctx->num_cu * 4 * 8));
@@ -466,10 +484,6 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   if (pl.n_items)
     HIPCHK(hipMemcpyAsync(pl.items, items.data(), sizeof(CtItem) * items.size(), hipMemcpyHostToDevice, st));
   std::vector<double*> hp(4 * NJ, nullptr);
-  for (int j = 0; j < NJ; ++j) {
-    hp[NJ + 2 * j] = (mode & PM_CBAR) ? (double*)(B + offs[j].mom0) : nullptr;
-    hp[NJ + 2 * j + 1] = (mode & PM_CBAR) ? (double*)(B + offs[j].mom1) : nullptr;
-  }
   HIPCHK(hipMemcpyAsync(ptrs, hp.data(), sizeof(double*) * hp.size(), hipMemcpyHostToDevice, st));
   std::vector<double> ones(NJ, 1.0);
   HIPCHK(hipMemcpyAsync(pl.dl, ones.data(), 8 * NJ, hipMemcpyHostToDevice, st));
@@ -494,10 +508,32 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
 static int enqueue_ctransforms(Plan& pl, hipStream_t st) {
   const int NJ = pl.njobs;
   for (int phase = 0; phase < 2; ++phase) {
+    std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+    if (pl.timing) {
+      if (pl.ev_used == pl.ev_pool.size()) {
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        pl.ev_pool.push_back({a, b});
+      }
+      ev = &pl.ev_pool[pl.ev_used++];
+      HIPCHK(hipEventRecord(ev->first, st));
+    }
     CHK(launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints + phase, phase, pl.ct_grid, st));
+    if (ev) HIPCHK(hipEventRecord(ev->second, st));
     CHK(launch_merge(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
     if (pl.mode & PM_ARGMIN) CHK(launch_argmin(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
   }
+  return QBW_OK;
+}
+
+static int enqueue_plancost(Plan& pl, hipStream_t st) {
+  const int NJ = pl.njobs;
+  if (pl.tot_pc2) {
+    CHK(launch_moments(pl.djobs, NJ, pl.off_mom, pl.tot_mom, 1, st));
+    CHK(launch_plancost2(pl.djobs, NJ, pl.off_pc2, pl.tot_pc2, st));
+  }
+  if (pl.tot_pc1) CHK(launch_plancost(pl.djobs, NJ, pl.off_pc1, pl.tot_pc1, st));
   return QBW_OK;
 }
 
@@ -513,7 +549,7 @@ static int enqueue_forward(Plan& pl, hipStream_t st) {
   CHK(launch_ipf(pl.djobs, NJ, st));
   CHK(launch_scalings(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
   CHK(launch_tv_partial(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
-  CHK(launch_plancost(pl.djobs, NJ, pl.off_entry, pl.tot_entry, st));
+  CHK(enqueue_plancost(pl, st));
   CHK(launch_finalize(pl.djobs, NJ, st));
   return QBW_OK;
 }
@@ -521,6 +557,7 @@ static int enqueue_forward(Plan& pl, hipStream_t st) {
 static int enqueue_backward(Plan& pl, hipStream_t st) {
   const int NJ = pl.njobs;
   CHK(launch_lb_grad(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, st));
+  if (pl.tot_pc2) CHK(launch_moments(pl.djobs, NJ, pl.off_mom, pl.tot_mom, 0, st));
   CHK(launch_ub_coarse_bwd2(pl.djobs, NJ, pl.bwd_scratch, pl.max_q, st));
   CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 0, st));
   CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 1, st));
@@ -824,8 +861,8 @@ qbw_status qbw_cbar(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const d
   HIPCHK(hipMemcpyAsync(pl.cbar_out, &out, sizeof(double*), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
   CHK(launch_pool(pl.djobs, 1, pl.off_pool, pl.tot_pool, st));
-  CHK(launch_moments(pl.djobs, 1, pl.off_mom, pl.tot_mom, pl.moms, st));
-  CHK(launch_cbar2(pl.djobs, 1, pl.off_cbar, pl.tot_cbar, pl.cbar_out, (const double* const*)pl.moms, st));
+  CHK(launch_moments(pl.djobs, 1, pl.off_mom, pl.tot_mom, 0, st));
+  CHK(launch_cbar2(pl.djobs, 1, pl.off_cbar, pl.tot_cbar, pl.cbar_out, st));
   HIPCHK(hipStreamSynchronize(st));
   return QBW_OK;
 }
@@ -936,7 +973,7 @@ qbw_status qbw_plan_cost(qbw_ctx* ctx, const qbw_grid* grid, const qbw_coarse* c
   HIPCHK(hipMemsetAsync(D.red_lb, 0, 8 * (size_t)D.chunks * kRedSlotsLB, st));
   HIPCHK(hipMemsetAsync(D.red_tv, 0, 8 * (size_t)D.chunks * kRedSlotsTV, st));
   HIPCHK(hipMemsetAsync(D.result, 0, 8 * RS_COUNT, st));
-  CHK(launch_plancost(pl.djobs, 1, pl.off_entry, pl.tot_entry, st));
+  CHK(enqueue_plancost(pl, st));
   CHK(launch_finalize(pl.djobs, 1, st));
   CHK(fetch_results(pl, st));
   *cost = pl.host_results[RS_PCOST_RAW];
@@ -1157,6 +1194,37 @@ qbw_status qbw_batch_results(qbw_batch* B, qbw_result* out, qbw_stream stream) {
   if (!B || !out) { set_error("NULL argument"); return QBW_E_INVAL; }
   CHK(fetch_results(B->plan, S(stream)));
   for (int j = 0; j < B->plan.njobs; ++j) to_result(B->plan.host_results.data() + (size_t)RS_COUNT * j, &out[j]);
+  return QBW_OK;
+}
+
+qbw_status qbw_batch_set_timing(qbw_batch* B, int32_t enable) {
+  if (!B) { set_error("NULL batch"); return QBW_E_INVAL; }
+  B->plan.timing = enable != 0;
+  B->plan.ev_used = 0;
+  return QBW_OK;
+}
+
+qbw_status qbw_batch_ctransform_time(qbw_batch* B, double* mean_ms, int32_t* launches) {
+  if (!B || !mean_ms || !launches) { set_error("NULL argument"); return QBW_E_INVAL; }
+  Plan& pl = B->plan;
+  double tot = 0;
+  for (size_t i = 0; i < pl.ev_used; ++i) {
+    HIPCHK(hipEventSynchronize(pl.ev_pool[i].second));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, pl.ev_pool[i].first, pl.ev_pool[i].second));
+    tot += ms;
+  }
+  *launches = (int32_t)pl.ev_used;
+  *mean_ms = pl.ev_used ? tot / pl.ev_used : 0.0;
+  pl.ev_used = 0;
+  return QBW_OK;
+}
+
+qbw_status qbw_batch_ctransform_pairs(const qbw_batch* B, double* pairs) {
+  if (!B || !pairs) { set_error("NULL argument"); return QBW_E_INVAL; }
+  double s = 0;
+  for (const auto& D : B->plan.hj) s += (double)D.P * (double)D.P;
+  *pairs = s;
   return QBW_OK;
 }
 

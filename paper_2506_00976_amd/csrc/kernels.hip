@@ -244,7 +244,12 @@ __device__ __forceinline__ void ct_tile(const float* __restrict__ src, float* __
     for (int b = 0; b < N; b += R) {
       float phv[R];
 #pragma unroll
-      for (int m = 0; m < R; ++m) phv[m] = ph[b + m];
+      for (int m = 0; m < R; ++m) {
+        phv[m] = ph[b + m];
+        // one v_mov to a VGPR per source: on gfx950 a VALU op with an SGPR
+        // operand issues at about half the rate of the all-VGPR form
+        __asm__("" : "+v"(phv[m]));
+      }
       float tmp[R];
 #pragma unroll
       for (int m = 0; m < R; ++m) {
@@ -537,16 +542,56 @@ __global__ __launch_bounds__(256) void k_tv_partial(const DevJob* __restrict__ j
 
 // ------------------------------------------------------------------ plan cost
 //
-// One work-group per support entry (K, L): sum over X_K x Y_L of a_s_i b_s_j c_ij.
+// S_e = sum over X_K x Y_L of a_s_i b_s_j c_ij for every support entry (K, L).
+//
+// p = 2: with block centres c_K, offsets delta_i = x_i - c_K, eps_j = y_j - c_L
+// and D = c_K - c_L, |x - y|^2 = |D + delta - eps|^2, so
+//   S_e = A0 B0 |D|^2 + 2 D.(A1 B0 - A0 B1) + A2 B0 + A0 B2 - 2 A1.B1
+// with the block moments (A0, A1, A2) of a_s and (B0, B1, B2) of b_s: one
+// thread per entry.  p = 1: brute force, one work-group per entry, target
+// block staged in LDS (value and integer coordinates).
+__device__ __forceinline__ double moment_pair_sq(const double* __restrict__ A, const double* __restrict__ B,
+                                                 double D0, double D1, double D2) {
+  const double dd = D0 * D0 + D1 * D1 + D2 * D2;
+  return A[0] * B[0] * dd
+       + 2.0 * (D0 * (A[1] * B[0] - A[0] * B[1]) + D1 * (A[2] * B[0] - A[0] * B[2]) + D2 * (A[3] * B[0] - A[0] * B[3]))
+       + A[4] * B[0] + A[0] * B[4]
+       - 2.0 * (A[1] * B[1] + A[2] * B[2] + A[3] * B[3]);
+}
+
+__device__ __forceinline__ void block_delta(int K, int L, const DevJob& J, double& D0, double& D1, double& D2) {
+  int k0, k1, k2, l0, l1, l2;
+  pix_coords(K, J.n, J.d, k0, k1, k2);
+  pix_coords(L, J.n, J.d, l0, l1, l2);
+  D0 = (double)J.k * (k0 - l0);
+  D1 = (double)J.k * (k1 - l1);
+  D2 = (double)J.k * (k2 - l2);
+}
+
+__global__ __launch_bounds__(256) void k_plancost2(const DevJob* __restrict__ jobs, int njobs,
+                                                   const int* __restrict__ off, int total) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int e = (it - off[jb]) * 256 + threadIdx.x;
+    if (J.p != 2 || e >= J.nnz) continue;
+    const int K = J.e_row[e], L = J.e_col[e];
+    double D0, D1, D2;
+    block_delta(K, L, J, D0, D1, D2);
+    J.red_pc[e] = moment_pair_sq(J.mom_as + 5 * (size_t)K, J.mom_bs + 5 * (size_t)L, D0, D1, D2);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_plancost(const DevJob* __restrict__ jobs, int njobs,
                                                   const int* __restrict__ off, int total) {
   __shared__ double sh[256];
   __shared__ double sb[1024];
-  __shared__ int sc[1024];
+  __shared__ int sc[1024][3];
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
     const int e = it - off[jb];
+    if (J.p == 2 || e >= J.nnz) continue;
     const int K = J.e_row[e], L = J.e_col[e];
     const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
     double acc = 0.0;
@@ -555,13 +600,18 @@ __global__ __launch_bounds__(256) void k_plancost(const DevJob* __restrict__ job
       for (int q = threadIdx.x; q < tn; q += 256) {
         const int j = block_member(L, t0 + q, J.N, J.n, J.k, J.d);
         sb[q] = J.b_s[j];
-        sc[q] = j;
+        pix_coords(j, J.N, J.d, sc[q][0], sc[q][1], sc[q][2]);
       }
       __syncthreads();
       for (int a = threadIdx.x; a < m; a += 256) {
         const int i = block_member(K, a, J.N, J.n, J.k, J.d);
+        int x0, x1, x2;
+        pix_coords(i, J.N, J.d, x0, x1, x2);
         double s = 0.0;
-        for (int q = 0; q < tn; ++q) s += sb[q] * cost64(i, sc[q], J.N, J.d, J.p);
+        for (int q = 0; q < tn; ++q) {
+          const int e0 = x0 - sc[q][0], e1 = x1 - sc[q][1], e2 = x2 - sc[q][2];
+          s += sb[q] * sqrt((double)(e0 * e0 + e1 * e1 + e2 * e2));
+        }
         acc += J.a_s[i] * s;
       }
       __syncthreads();
@@ -657,8 +707,7 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
 // second moment); p = 1: brute force over the k^(2d) pixel pairs.
 __global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, int njobs,
                                               const int* __restrict__ off, int total,
-                                              double* const* __restrict__ outs,
-                                              const double* const* __restrict__ moms) {
+                                              double* const* __restrict__ outs) {
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
@@ -666,22 +715,14 @@ __global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, i
     const int Q = J.Q;
     if (pr >= (long long)Q * Q) continue;
     const int K = (int)(pr / Q), L = (int)(pr - (long long)K * Q);
-    int k0, k1, k2, l0, l1, l2;
-    pix_coords(K, J.n, J.d, k0, k1, k2);
-    pix_coords(L, J.n, J.d, l0, l1, l2);
-    const double c0 = (double)J.k * (k0 - l0), c1 = (double)J.k * (k1 - l1), c2 = (double)J.k * (k2 - l2);
-    const double dc2 = c0 * c0 + c1 * c1 + c2 * c2;
+    double D0, D1, D2;
+    block_delta(K, L, J, D0, D1, D2);
+    const double dc2 = D0 * D0 + D1 * D1 + D2 * D2;
     const double mK = J.mu_t[K], nL = J.nu_t[L];
     double val;
     if (J.p == 2) {
-      const double* Mm = moms[2 * jb] + (size_t)K * 4;      // (m1_0, m1_1, m1_2, m2)
-      const double* Mn = moms[2 * jb + 1] + (size_t)L * 4;
       if (mK > 0.0 && nL > 0.0) {
-        const double s = mK * nL * dc2
-            + 2.0 * (c0 * (nL * Mm[0] - mK * Mn[0]) + c1 * (nL * Mm[1] - mK * Mn[1]) + c2 * (nL * Mm[2] - mK * Mn[2]))
-            + nL * Mm[3] + mK * Mn[3]
-            - 2.0 * (Mm[0] * Mn[0] + Mm[1] * Mn[1] + Mm[2] * Mn[2]);
-        val = s / (mK * nL);
+        val = moment_pair_sq(J.mom_mu + 5 * (size_t)K, J.mom_nu + 5 * (size_t)L, D0, D1, D2) / (mK * nL);
       } else {
         val = dc2;
       }
@@ -709,31 +750,32 @@ __global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, i
   }
 }
 
-// Pooled moments for C-bar (p = 2): per block (sum m delta_0, delta_1, delta_2, sum m |delta|^2).
+// Block moments about the block centre (5 slots): which = 0 -> (mu, nu) into
+// (mom_mu, mom_nu); which = 1 -> (a_s, b_s) into (mom_as, mom_bs).
 __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs, int njobs,
-                                                 const int* __restrict__ off, int total,
-                                                 double* const* __restrict__ moms) {
+                                                 const int* __restrict__ off, int total, int which) {
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
     const int idx = (it - off[jb]) * 256 + threadIdx.x;
     if (idx >= 2 * J.Q) continue;
     const int side = idx / J.Q, K = idx - side * J.Q;
-    const double* m = side == 0 ? J.mu : J.nu;
+    const double* m = which == 0 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
+    double* o = (which == 0 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs)) + 5 * (size_t)K;
     const int mm = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
     const double h = 0.5 * (J.k - 1);
-    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
     for (int a = 0; a < mm; ++a) {
       const int i = block_member(K, a, J.N, J.n, J.k, J.d);
       int u0, u1, u2;
       pix_coords(a, J.k, J.d, u0, u1, u2);
       const double d0 = J.d == 2 ? 0.0 : u0 - h, d1 = u1 - h, d2 = u2 - h;
       const double w = m[i];
-      s0 += w * d0; s1 += w * d1; s2 += w * d2;
-      s3 += w * (d0 * d0 + d1 * d1 + d2 * d2);
+      s0 += w;
+      s1 += w * d0; s2 += w * d1; s3 += w * d2;
+      s4 += w * (d0 * d0 + d1 * d1 + d2 * d2);
     }
-    double* o = moms[2 * jb + side] + (size_t)K * 4;
-    o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3;
+    o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3; o[4] = s4;
   }
 }
 
@@ -841,12 +883,17 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
   }
 }
 
-// d upper / d mu (side 0) or d nu (side 1): one work-group per coarse block.
-__global__ __launch_bounds__(256) void k_ub_grad(const DevJob* __restrict__ jobs, int njobs,
-                                                 const int* __restrict__ off, int total,
-                                                 const double* __restrict__ du, int side) {
-  __shared__ double sw[1024];
-  __shared__ int sidx[1024];
+// d upper / d mu (side 0) or d nu (side 1): one 64-thread work-group per
+// coarse block B.  For a member x of B the direct term is
+//   h(x) = sum over entries e of B's row (column) of coef_e sum_{y in O_e} w(y) c(x, y)
+// with w = nu (side 0) or mu (side 1) and O_e the other block of the entry.
+// p = 2 uses the moments of w over O_e about its centre: with z = x - c_O,
+//   sum_y w(y) |x - y|^2 = W0 |z|^2 - 2 z.W1 + W2.
+__global__ __launch_bounds__(64) void k_ub_grad(const DevJob* __restrict__ jobs, int njobs,
+                                                const int* __restrict__ off, int total,
+                                                const double* __restrict__ du, int side) {
+  __shared__ double sw[512];
+  __shared__ int sc[512][3];
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
@@ -857,30 +904,58 @@ __global__ __launch_bounds__(256) void k_ub_grad(const DevJob* __restrict__ jobs
     const double s = P > 0.0 ? (J.p == 2 ? 0.5 / sqrt(P) : 1.0) * du[jb] : 0.0;
     const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
     const double* other = side == 0 ? J.nu : J.mu;
+    const double* omom = side == 0 ? J.mom_nu : J.mom_mu;
     const double base_g = side == 0 ? J.gbar_mu[B] : J.gbar_nu[B];
-    // entries of row B (side 0) or column B (side 1)
     const int e0 = side == 0 ? J.csr_ptr[B] : J.csc_ptr[B];
     const int e1 = side == 0 ? J.csr_ptr[B + 1] : J.csc_ptr[B + 1];
-    for (int a0 = 0; a0 < m; a0 += 256) {
+    int b0, b1, b2;
+    pix_coords(B, J.n, J.d, b0, b1, b2);
+    if (J.p == 2) {
+      for (int a = threadIdx.x; a < m; a += 64) {
+        const int i = block_member(B, a, J.N, J.n, J.k, J.d);
+        int x0, x1, x2;
+        pix_coords(i, J.N, J.d, x0, x1, x2);
+        double h = 0.0;
+        for (int q = e0; q < e1; ++q) {
+          const int e = side == 0 ? q : J.csc_idx[q];
+          const int O = side == 0 ? J.e_col[e] : J.e_row[e];
+          int o0, o1, o2;
+          pix_coords(O, J.n, J.d, o0, o1, o2);
+          const double hk = 0.5 * (J.k - 1);
+          const double z0 = J.d == 2 ? 0.0 : x0 - (J.k * o0 + hk);
+          const double z1 = x1 - (J.k * o1 + hk), z2 = x2 - (J.k * o2 + hk);
+          const double* W = omom + 5 * (size_t)O;
+          h += J.coef[e] * (W[0] * (z0 * z0 + z1 * z1 + z2 * z2) - 2.0 * (z0 * W[1] + z1 * W[2] + z2 * W[3]) + W[4]);
+        }
+        grad[i] += s * (h + base_g);
+      }
+      continue;
+    }
+    for (int a0 = 0; a0 < m; a0 += 64) {
       const int a = a0 + threadIdx.x;
       const int i = a < m ? block_member(B, a, J.N, J.n, J.k, J.d) : 0;
+      int x0, x1, x2;
+      pix_coords(i, J.N, J.d, x0, x1, x2);
       double h = 0.0;
       for (int q = e0; q < e1; ++q) {
         const int e = side == 0 ? q : J.csc_idx[q];
-        const int Ot = side == 0 ? J.e_col[e] : J.e_row[e];
+        const int O = side == 0 ? J.e_col[e] : J.e_row[e];
         const double cf = J.coef[e];
-        for (int t0 = 0; t0 < m; t0 += 1024) {
-          const int tn = min(1024, m - t0);
+        for (int t0 = 0; t0 < m; t0 += 512) {
+          const int tn = min(512, m - t0);
           __syncthreads();
-          for (int r = threadIdx.x; r < tn; r += 256) {
-            const int j = block_member(Ot, t0 + r, J.N, J.n, J.k, J.d);
+          for (int r = threadIdx.x; r < tn; r += 64) {
+            const int j = block_member(O, t0 + r, J.N, J.n, J.k, J.d);
             sw[r] = other[j];
-            sidx[r] = j;
+            pix_coords(j, J.N, J.d, sc[r][0], sc[r][1], sc[r][2]);
           }
           __syncthreads();
           if (a < m) {
             double acc = 0.0;
-            for (int r = 0; r < tn; ++r) acc += sw[r] * cost64(i, sidx[r], J.N, J.d, J.p);
+            for (int r = 0; r < tn; ++r) {
+              const int d0 = x0 - sc[r][0], d1 = x1 - sc[r][1], d2 = x2 - sc[r][2];
+              acc += sw[r] * sqrt((double)(d0 * d0 + d1 * d1 + d2 * d2));
+            }
             h += cf * acc;
           }
         }
@@ -1015,20 +1090,24 @@ int launch_plancost(const DevJob* jobs, int njobs, const int* off, int total, vo
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
+int launch_plancost2(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
+  hipLaunchKernelGGL(k_plancost2, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
 int launch_finalize(const DevJob* jobs, int njobs, void* stream) {
   hipLaunchKernelGGL(k_finalize, dim3(njobs), dim3(256), 0, (hipStream_t)stream, jobs, njobs);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_moments(const DevJob* jobs, int njobs, const int* off, int total, double* const* moms,
-                   void* stream) {
-  hipLaunchKernelGGL(k_moments, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, moms);
+int launch_moments(const DevJob* jobs, int njobs, const int* off, int total, int which, void* stream) {
+  hipLaunchKernelGGL(k_moments, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, which);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
 int launch_cbar2(const DevJob* jobs, int njobs, const int* off, int total, double* const* outs,
-                 const double* const* moms, void* stream) {
-  hipLaunchKernelGGL(k_cbar, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, outs, moms);
+                 void* stream) {
+  hipLaunchKernelGGL(k_cbar, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, outs);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
@@ -1044,7 +1123,7 @@ int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int st
 }
 int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* du, int side,
                    void* stream) {
-  hipLaunchKernelGGL(k_ub_grad, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, du, side);
+  hipLaunchKernelGGL(k_ub_grad, dim3(grid_for(total)), dim3(64), 0, (hipStream_t)stream, jobs, njobs, off, total, du, side);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -91,6 +91,12 @@ struct DevJob {
   double* gbar_mu;          // Q: d P / d mu~ (coarse adjoint)
   double* gbar_nu;
   double* coef;             // nnz: d P / d S_e coefficient
+  // per-block moments about the block centre, 5 doubles per block:
+  // (sum m, sum m delta_0, sum m delta_1, sum m delta_2, sum m |delta|^2)
+  double* mom_mu;           // of mu
+  double* mom_nu;           // of nu
+  double* mom_as;           // of the IPF scalings a_s
+  double* mom_bs;           // of b_s
 };
 
 struct CtItem { int job, tile, split, pad; };
@@ -115,10 +121,11 @@ int launch_scalings(const DevJob* jobs, int njobs, const int* off, int total, vo
 int launch_tv_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_plancost(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_finalize(const DevJob* jobs, int njobs, void* stream);
-int launch_moments(const DevJob* jobs, int njobs, const int* off, int total, double* const* moms,
+int launch_moments(const DevJob* jobs, int njobs, const int* off, int total, int which,
                    void* stream);
+int launch_plancost2(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_cbar2(const DevJob* jobs, int njobs, const int* off, int total, double* const* outs,
-                 const double* const* moms, void* stream);
+                 void* stream);
 int launch_lb_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
                    void* stream);
 int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int stride, void* stream);
