@@ -249,9 +249,10 @@ struct Plan {
   int tot_chunk = 0, tot_pool = 0, tot_entry = 0, tot_block = 0, tot_cbar = 0, tot_mom = 0,
       tot_pc1 = 0, tot_pc2 = 0;
   CtItem* items = nullptr;
+  int* qoff = nullptr;   // kQueues + 1 offsets into items
   int n_items = 0;
   int ct_grid = 1;
-  int* ints = nullptr;   // [0..1] work counters, [2..2+njobs) flags
+  int* ints = nullptr;   // [0, 2 kQueues) work counters of the two phases, then njobs flags
   int n_ints = 0;
   double* dl = nullptr;  // per-job upstream gradients
   double* du = nullptr;
@@ -345,26 +346,50 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   const size_t o_jobs = L.add(sizeof(DevJob) * NJ);
   constexpr int kTables = 8;
   const size_t o_offs = L.add(sizeof(int) * kTables * (NJ + 1));
-  // c-transform work items
-  std::vector<CtItem> items;
-  for (int j = 0; j < NJ; ++j) {
-    const auto& J = pl.in[j];
-    const int P = ipow(J.g.N, J.g.d);
-    const int tiles = (P + 64 * J.tiling.R - 1) / (64 * J.tiling.R);
-    for (int s = 0; s < J.tiling.S; ++s)
-      for (int t = 0; t < tiles; ++t) items.push_back({j, t, s, 0});
-  }
-  // longest items first (cost ~ targets x sources of the item)
+  // c-transform work items, one queue per XCD.  Jobs get a home queue by
+  // longest-processing-time assignment of their pair counts; a lone job (or one
+  // too big for a single queue's share) spreads its target tiles over all queues.
   auto item_cost = [&](const CtItem& w) {
     const auto& J = pl.in[w.job];
     const double rows = std::pow((double)J.g.N, J.g.d - 1);
     return 64.0 * J.tiling.R * (rows / J.tiling.S) * J.g.N * (J.g.p == 1 ? 1.4 : 1.0);
   };
-  std::stable_sort(items.begin(), items.end(),
-                   [&](const CtItem& a, const CtItem& b) { return item_cost(a) > item_cost(b); });
+  std::vector<std::vector<CtItem>> queues(kQueues);
+  {
+    std::vector<double> load(kQueues, 0.0);
+    std::vector<int> order(NJ);
+    std::iota(order.begin(), order.end(), 0);
+    auto work = [&](int j) { return std::pow((double)pl.in[j].g.N, 2.0 * pl.in[j].g.d); };
+    double total = 0;
+    for (int j = 0; j < NJ; ++j) total += work(j);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    for (int j : order) {
+      const auto& J = pl.in[j];
+      const int P = ipow(J.g.N, J.g.d);
+      const int tiles = (P + 64 * J.tiling.R - 1) / (64 * J.tiling.R);
+      const bool spread = work(j) > total / kQueues;
+      int home = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      for (int s = 0; s < J.tiling.S; ++s)
+        for (int t = 0; t < tiles; ++t) {
+          CtItem w{j, t, s, 0};
+          const int q = spread ? (t % kQueues) : home;
+          queues[q].push_back(w);
+          load[q] += item_cost(w);
+        }
+    }
+  }
+  std::vector<CtItem> items;
+  std::vector<int> qoff(kQueues + 1, 0);
+  for (int q = 0; q < kQueues; ++q) {
+    std::stable_sort(queues[q].begin(), queues[q].end(),
+                     [&](const CtItem& x, const CtItem& y) { return item_cost(x) > item_cost(y); });
+    items.insert(items.end(), queues[q].begin(), queues[q].end());
+    qoff[q + 1] = (int)items.size();
+  }
   pl.n_items = (int)items.size();
   const size_t o_items = L.add(sizeof(CtItem) * std::max(1, pl.n_items));
-  pl.n_ints = 2 + NJ;
+  const size_t o_qoff = L.add(sizeof(int) * (kQueues + 1));
+  pl.n_ints = 2 * kQueues + NJ;
   const size_t o_ints = L.add(sizeof(int) * pl.n_ints);
   const size_t o_dl = L.add(8 * NJ), o_du = L.add(8 * NJ);
   const size_t o_res = L.add(8 * (size_t)RS_COUNT * NJ);
@@ -429,7 +454,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.red_tv = (double*)(B + O.red_tv);
     D.red_pc = (double*)(B + O.red_pc);
     D.result = (double*)(B + o_res) + (size_t)RS_COUNT * j;
-    D.flags = (int*)(B + o_ints) + 2 + j;
+    D.flags = (int*)(B + o_ints) + 2 * kQueues + j;
     D.grad_a = J.ga;
     D.grad_b = J.gb;
     D.gbar_mu = (double*)(B + O.gbar_mu);
@@ -467,6 +492,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   pl.tot_cbar = off[4 * (NJ + 1) + NJ];
   pl.tot_mom = off[5 * (NJ + 1) + NJ];
   pl.items = (CtItem*)(B + o_items);
+  pl.qoff = (int*)(B + o_qoff);
   pl.ints = (int*)(B + o_ints);
   pl.dl = (double*)(B + o_dl);
   pl.du = (double*)(B + o_du);
@@ -483,6 +509,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   HIPCHK(hipMemcpyAsync(offd, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, st));
   if (pl.n_items)
     HIPCHK(hipMemcpyAsync(pl.items, items.data(), sizeof(CtItem) * items.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pl.qoff, qoff.data(), sizeof(int) * qoff.size(), hipMemcpyHostToDevice, st));
   std::vector<double*> hp(4 * NJ, nullptr);
   HIPCHK(hipMemcpyAsync(ptrs, hp.data(), sizeof(double*) * hp.size(), hipMemcpyHostToDevice, st));
   std::vector<double> ones(NJ, 1.0);
@@ -519,7 +546,7 @@ static int enqueue_ctransforms(Plan& pl, hipStream_t st) {
       ev = &pl.ev_pool[pl.ev_used++];
       HIPCHK(hipEventRecord(ev->first, st));
     }
-    CHK(launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints + phase, phase, pl.ct_grid, st));
+    CHK(launch_ctransform(pl.djobs, pl.items, pl.qoff, kQueues, pl.ints + phase * kQueues, phase, pl.ct_grid, st));
     if (ev) HIPCHK(hipEventRecord(ev->second, st));
     CHK(launch_merge(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
     if (pl.mode & PM_ARGMIN) CHK(launch_argmin(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
@@ -608,7 +635,7 @@ static int pool_and_check(qbw_ctx* ctx, const std::vector<JobIn>& jobs, std::vec
   HIPCHK(hipMemcpyAsync(flags.data(), pl.ints, 4 * pl.n_ints, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   for (int j = 0; j < pl.njobs; ++j) {
-    const int fl = flags[2 + j];
+    const int fl = flags[2 * kQueues + j];
     if (fl & 2) { set_error("job %d: a measure contains NaN", j); return QBW_E_MASS; }
     if (fl & 1) { set_error("job %d: a measure has a negative entry", j); return QBW_E_MASS; }
     double sa = 0, sb = 0;
@@ -919,7 +946,7 @@ qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, 
   if (argmin) pl.hj[0].arg_g = argmin;
   HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints, 0, pl.ct_grid, st));
+  CHK(launch_ctransform(pl.djobs, pl.items, pl.qoff, kQueues, pl.ints, 0, pl.ct_grid, st));
   CHK(launch_merge(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, 0, st));
   if (argmin) CHK(launch_argmin(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, 0, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1020,7 +1047,7 @@ static double time_ctransform(qbw_ctx* ctx, Plan& pl, hipStream_t st, int reps) 
   for (int r = 0; r < reps; ++r) {
     (void)launch_reset_counter(pl.ints, pl.n_ints, st);
     (void)hipEventRecord(e0, st);
-    (void)launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints, 0, pl.ct_grid, st);
+    (void)launch_ctransform(pl.djobs, pl.items, pl.qoff, kQueues, pl.ints, 0, pl.ct_grid, st);
     (void)hipEventRecord(e1, st);
     if (hipEventSynchronize(e1) != hipSuccess) break;
     float ms = 0;

@@ -282,33 +282,50 @@ __device__ __forceinline__ void ct_tile(const float* __restrict__ src, float* __
   }
 }
 
+// XCD (accelerator complex die) the wave runs on: HW_REG_XCC_ID, bits [3:0].
+__device__ __forceinline__ int xcc_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15;
+}
+
+// Persistent c-transform: one work queue per XCD.  The planner gives every job
+// (or, for a single job, every target tile) a home XCD so the source
+// potentials a queue touches stay in that XCD's L2; a wave drains its own
+// XCD's queue first and then steals from the others, so every wave exits once
+// all queues are empty.  counters[q] is queue q's next item; items of queue q
+// are items[qoff[q] .. qoff[q+1]).
 __global__ __launch_bounds__(64) void k_ctransform(const DevJob* __restrict__ jobs,
-                                                   const CtItem* __restrict__ items, int n_items,
-                                                   int* __restrict__ counter, int phase) {
-  for (;;) {
-    int it = 0;
-    if (threadIdx.x == 0) it = atomicAdd(counter, 1);
-    it = __shfl(it, 0);
-    it = __builtin_amdgcn_readfirstlane(it);
-    if (it >= n_items) break;
-    const CtItem w = items[it];
-    const DevJob& J = jobs[w.job];
-    const float* src = phase == 0 ? J.fhat : J.g;
-    float* out = J.part + (size_t)w.split * J.P;
-    const int r0 = (int)(((long long)w.split * J.rows) / J.S);
-    const int r1 = (int)(((long long)(w.split + 1) * J.rows) / J.S);
-    const int key = J.R * 4 + J.p;
-    switch (key) {
-      case 16 * 4 + 2: ct_tile<16, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-      case 16 * 4 + 1: ct_tile<16, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-      case 8 * 4 + 2: ct_tile<8, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-      case 8 * 4 + 1: ct_tile<8, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-      case 4 * 4 + 2: ct_tile<4, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-      case 4 * 4 + 1: ct_tile<4, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-      case 2 * 4 + 2: ct_tile<2, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-      case 2 * 4 + 1: ct_tile<2, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-      case 1 * 4 + 2: ct_tile<1, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-      default: ct_tile<1, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+                                                   const CtItem* __restrict__ items,
+                                                   const int* __restrict__ qoff, int nq,
+                                                   int* __restrict__ counters, int phase) {
+  const int home = xcc_id() % nq;
+  for (int qq = 0; qq < nq; ++qq) {
+    const int q = (home + qq) % nq;
+    const int q0 = qoff[q], qn = qoff[q + 1] - q0;
+    for (;;) {
+      int it = 0;
+      if (threadIdx.x == 0) it = atomicAdd(counters + q, 1);
+      it = __shfl(it, 0);
+      it = __builtin_amdgcn_readfirstlane(it);
+      if (it >= qn) break;
+      const CtItem w = items[q0 + it];
+      const DevJob& J = jobs[w.job];
+      const float* src = phase == 0 ? J.fhat : J.g;
+      float* out = J.part + (size_t)w.split * J.P;
+      const int r0 = (int)(((long long)w.split * J.rows) / J.S);
+      const int r1 = (int)(((long long)(w.split + 1) * J.rows) / J.S);
+      const int key = J.R * 4 + J.p;
+      switch (key) {
+        case 16 * 4 + 2: ct_tile<16, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+        case 16 * 4 + 1: ct_tile<16, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+        case 8 * 4 + 2: ct_tile<8, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+        case 8 * 4 + 1: ct_tile<8, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+        case 4 * 4 + 2: ct_tile<4, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+        case 4 * 4 + 1: ct_tile<4, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+        case 2 * 4 + 2: ct_tile<2, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+        case 2 * 4 + 1: ct_tile<2, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+        case 1 * 4 + 2: ct_tile<1, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+        default: ct_tile<1, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+      }
     }
   }
 }
@@ -1048,10 +1065,10 @@ int launch_reset_counter(int* counter, int n, void* stream) {
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter, int phase,
-                      int grid, void* stream) {
-  hipLaunchKernelGGL(k_ctransform, dim3(grid), dim3(64), 0, (hipStream_t)stream, jobs, items, n_items,
-                     counter, phase);
+int launch_ctransform(const DevJob* jobs, const CtItem* items, const int* qoff, int nq, int* counters,
+                      int phase, int grid, void* stream) {
+  hipLaunchKernelGGL(k_ctransform, dim3(grid), dim3(64), 0, (hipStream_t)stream, jobs, items, qoff, nq,
+                     counters, phase);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

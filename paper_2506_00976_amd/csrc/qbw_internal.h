@@ -111,7 +111,8 @@ struct Launch {
 
 int launch_pool(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
-int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter,
+constexpr int kQueues = 8;  // one c-transform work queue per XCD
+int launch_ctransform(const DevJob* jobs, const CtItem* items, const int* qoff, int nq, int* counters,
                       int phase, int grid, void* stream);
 int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
 int launch_argmin(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
