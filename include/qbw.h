@@ -218,6 +218,24 @@ qbw_status qbw_tv(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const dou
                   const qbw_coarse* coarse, const double* a_s, const double* b_s,
                   double* tv_mu, double* tv_nu, qbw_stream stream);
 
+/* Weighted-cost upper bound (Section 3.2, Algorithm 3; theorem of the
+ * weighted-cost upper bound): L_{C-bar}(a~, b~)^(1/p) >= W_p(a, b).  Pools and
+ * builds C-bar on the device, copies it to the host (n^d x n^d float64) and
+ * solves the coarse problem on it with the host network simplex.  *upper is
+ * the bound, rounded outwards by a relative 2^-40 for the float64 sums;
+ * *objective (may be NULL) = <pi~, C-bar> of the optimal coupling.  Host
+ * outputs.  Errors: as qbw_bounds. */
+qbw_status qbw_weighted_cost_upper(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                                   double* upper, double* objective, qbw_stream stream);
+
+/* Min-cost lower bound (Section 3.3): L_{C^min}(a~, b~)^(1/p) <= W_p(a, b),
+ * C^min_KL = min over x in X_K, y in Y_L of |x - y|^p (closed form on the grid).
+ * The bound is the dual objective of the host simplex's potentials, lowered by
+ * their largest violation of f_K + g_L <= C^min_KL (so any rounding keeps it
+ * valid) and by a relative 2^-40; clipped at 0.  Host outputs. */
+qbw_status qbw_min_cost_lower(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                              double* lower, double* objective, qbw_stream stream);
+
 /* ---- batched path: many pairs of uneven sizes in one persistent launch --- */
 
 typedef struct qbw_job {

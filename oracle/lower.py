@@ -120,6 +120,73 @@ def ctransform_o32(phi32: np.ndarray, N: int, d: int, p: int, targets=None):
     return psi, arg
 
 
+def ctransform_sep_o32(phi32: np.ndarray, N: int, d: int):
+    """p = 2 only, float32 reading of the separable evaluation.
+
+    |x - y|^2 is a sum over axes, so min_i |x_i - y|^2 - phi_i is d nested
+    one-dimensional minimisations.  Passes run over the last axis first:
+        pass 1:  psi_1(.., v) = min_t RN32((t - v)^2 - phi(.., t))
+        pass k:  psi_k(.., v) = min_t RN32((t - v)^2 + psi_{k-1}(.., t))
+    (the later passes add the previous result).  In exact arithmetic this is
+    the c-transform; in float32 every candidate carries one rounding per axis.
+    Arg-min: the lowest index of each pass, composed (this is the lowest flat
+    index among the pairs attaining the nested float32 minimum)."""
+    cur = np.asarray(phi32, dtype=np.float32).reshape((N,) * d)
+    t = np.arange(N)
+    cost1 = ((t[:, None] - t[None, :]) ** 2).astype(np.float32)   # [source t, target v], exact
+    args = []
+    for k, axis in enumerate(reversed(range(d))):
+        arr = np.moveaxis(cur, axis, -1)                              # (..., N sources)
+        if k == 0:
+            vals = cost1 - arr[..., :, None]                          # RN32(c - phi)
+        else:
+            vals = cost1 + arr[..., :, None]                          # RN32(c + psi)
+        assert vals.dtype == np.float32
+        am = vals.argmin(axis=-2)
+        new = np.take_along_axis(vals, am[..., None, :], axis=-2)[..., 0, :]
+        cur = np.moveaxis(new, -1, axis)
+        args.append((axis, np.moveaxis(am, -1, axis)))
+    psi = cur.reshape(-1)
+    # compose the arg-mins: the last pass fixes axis 0, then walk back
+    tgt = np.indices((N,) * d).reshape(d, -1)                        # target coordinates
+    src = tgt.copy()
+    for axis, am in reversed(args):
+        src[axis] = am[tuple(src)]
+    arg = np.ravel_multi_index(tuple(src), (N,) * d)
+    return psi, arg.astype(np.int64)
+
+
+def feasibility_shift_sep(F_hat: float, G: float, Fo: float, N: int, d: int) -> float:
+    """Shift for the separable float32 evaluation (p = 2).  Along the arg-min
+    path the k-th pass rounds a partial value of size at most |g| + C (C =
+    d (N-1)^2 bounds every partial cost), the last one of size |g|:
+        |g32 - g64| <= e_g = u (F + d G + (d-1) C)
+        |f32 - f64| <= e_f = u (d Fo + (d-1) C) + e_g
+    and e_f again bounds the infeasibility; same summation slack as the
+    all-pairs shift."""
+    u = U32
+    C = d * (N - 1) ** 2
+    F = F_hat * (1.0 + 2.0 * u)
+    e_g = u * (F + d * G + (d - 1) * C)
+    e_f = u * (d * Fo + (d - 1) * C) + e_g
+    return (e_f + e_g) * (1.0 + 2.0 ** -10) + 2.0 ** -52 * N ** d * (Fo + G)
+
+
+def lower_bound_sep_o32(mu, nu, ftil, k: int):
+    """Algorithm 5 (p = 2) with the separable float32 c-transforms."""
+    d, N = mu.ndim, mu.shape[0]
+    fhat32 = upscale_potential(ftil, N, d, k).astype(np.float32)
+    g32, ig = ctransform_sep_o32(fhat32, N, d)
+    f32, jf = ctransform_sep_o32(g32, N, d)
+    S32 = fsum_dot(f32, mu.reshape(-1)) + fsum_dot(g32, nu.reshape(-1))
+    s = feasibility_shift_sep(float(np.abs(fhat32).max()), float(np.abs(g32).max()),
+                              float(np.abs(f32).max()), N, d)
+    S_emit = S32 - s
+    return {"fhat32": fhat32, "g32": g32, "f32": f32, "argmin_g": ig, "argmin_f": jf,
+            "S32": S32, "shift": s, "S_emit": S_emit,
+            "lower": max(S_emit, 0.0) ** 0.5, "clipped": S_emit <= 0.0}
+
+
 def fsum_dot(x, w) -> float:
     """sum_i x_i * w_i in float64: products rounded once, then an exactly rounded sum."""
     x = np.asarray(x, dtype=np.float64)

@@ -23,7 +23,8 @@ from ._lib import (QBW_BATCH_AUTOTUNE, QBW_BATCH_BACKWARD, QBW_BATCH_GRAPH, QBW_
 
 __all__ = ["Context", "Coarse", "Batch", "bounds", "wasserstein_bounds", "BoundsFunction",
            "sumpool", "coarse_cost", "cbar", "coarse_solve", "upscale_potential", "ctransform",
-           "ipf", "plan_cost", "tv", "autotune_ctransform", "QbwError", "load"]
+           "ipf", "plan_cost", "tv", "autotune_ctransform", "weighted_cost_upper", "min_cost_lower",
+           "bounds_with_grads", "QbwError", "load"]
 
 _tls = threading.local()
 
@@ -314,6 +315,26 @@ def tv(a, b, k: int, p: int, coarse: Coarse, a_s, b_s):
     check(load().qbw_tv(context(a.device.index).handle, C.byref(grid), _ptr(a), _ptr(b), C.byref(cs),
                         _ptr(a_s), _ptr(b_s), C.byref(tm), C.byref(tn), _stream()), "qbw_tv")
     return tm.value, tn.value
+
+
+def weighted_cost_upper(a, b, k: int, p: int):
+    """Weighted-cost upper bound (Algorithm 3): (bound, coarse objective on C-bar)."""
+    a, b = _dev(a), _dev(b)
+    grid = _grid(a, k, p)
+    ub, obj = C.c_double(), C.c_double()
+    check(load().qbw_weighted_cost_upper(context(a.device.index).handle, C.byref(grid), _ptr(a), _ptr(b),
+                                         C.byref(ub), C.byref(obj), _stream()), "qbw_weighted_cost_upper")
+    return ub.value, obj.value
+
+
+def min_cost_lower(a, b, k: int, p: int):
+    """Min-cost lower bound (Section 3.3): (bound, coarse objective on C^min)."""
+    a, b = _dev(a), _dev(b)
+    grid = _grid(a, k, p)
+    lb, obj = C.c_double(), C.c_double()
+    check(load().qbw_min_cost_lower(context(a.device.index).handle, C.byref(grid), _ptr(a), _ptr(b),
+                                    C.byref(lb), C.byref(obj), _stream()), "qbw_min_cost_lower")
+    return lb.value, obj.value
 
 
 def autotune_ctransform(N: int, d: int, p: int, device: int | None = None):

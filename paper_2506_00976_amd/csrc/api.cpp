@@ -894,6 +894,88 @@ qbw_status qbw_cbar(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const d
   return QBW_OK;
 }
 
+static void min_cost_matrix(const qbw_grid& g, double* out) {
+  const int n = g.N / g.k;
+  const int Q = ipow(n, g.d);
+  for (int K = 0; K < Q; ++K) {
+    int kc[3] = {0, 0, 0}, t = K;
+    for (int a = g.d - 1; a >= 0; --a) { kc[a] = t % n; t /= n; }
+    for (int L = 0; L < Q; ++L) {
+      int lc[3] = {0, 0, 0}, s = L;
+      for (int a = g.d - 1; a >= 0; --a) { lc[a] = s % n; s /= n; }
+      long long d2 = 0;
+      for (int a = 0; a < g.d; ++a) {
+        // closest pixels of two blocks along one axis: k |K - L| - (k - 1) apart, or 0
+        long long gap = (long long)g.k * std::llabs((long long)kc[a] - lc[a]) - (g.k - 1);
+        if (gap < 0) gap = 0;
+        d2 += gap * gap;
+      }
+      out[(size_t)K * Q + L] = g.p == 2 ? (double)d2 : std::sqrt((double)d2);
+    }
+  }
+}
+
+qbw_status qbw_weighted_cost_upper(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                                   double* upper, double* objective, qbw_stream stream) {
+  if (!ctx || !a || !b || !upper) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  hipStream_t st = S(stream);
+  std::vector<std::vector<double>> mt, nt;
+  JobIn J{*grid, a, b, nullptr, nullptr, nullptr, {default_R(grid->N), 1}};
+  CHK(pool_and_check(ctx, {J}, &mt, &nt, st));
+  const int Q = (int)mt[0].size();
+  Plan pl;
+  CHK(plan_build(ctx, pl, {stage_job(grid, a, b)}, PM_CBAR, qbw_default_opts(), false, st));
+  double* dC = nullptr;
+  HIPCHK(hipMalloc(&dC, 8 * (size_t)Q * Q));
+  std::unique_ptr<double, void (*)(double*)> guard(dC, [](double* p) { (void)hipFree(p); });
+  HIPCHK(hipMemcpyAsync(pl.cbar_out, &dC, sizeof(double*), hipMemcpyHostToDevice, st));
+  CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_pool, pl.tot_pool, st));
+  CHK(launch_moments(pl.djobs, 1, pl.off_mom, pl.tot_mom, 0, st));
+  CHK(launch_cbar2(pl.djobs, 1, pl.off_cbar, pl.tot_cbar, pl.cbar_out, st));
+  std::vector<double> C((size_t)Q * Q);
+  HIPCHK(hipMemcpyAsync(C.data(), dC, 8 * C.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  CoarseProblem P{Q, mt[0].data(), nt[0].data(), C.data(), false};
+  CoarseSolution sol;
+  if (coarse_solve(P, &sol) != QBW_OK) { set_error("network simplex failed on C-bar (Q=%d)", Q); return QBW_E_LP; }
+  const double obj = std::max(sol.objective, 0.0) * (1.0 + 9.094947017729282e-13);
+  *upper = grid->p == 2 ? std::sqrt(obj) : obj;
+  if (objective) *objective = sol.objective;
+  return QBW_OK;
+}
+
+qbw_status qbw_min_cost_lower(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                              double* lower, double* objective, qbw_stream stream) {
+  if (!ctx || !a || !b || !lower) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  std::vector<std::vector<double>> mt, nt;
+  JobIn J{*grid, a, b, nullptr, nullptr, nullptr, {default_R(grid->N), 1}};
+  CHK(pool_and_check(ctx, {J}, &mt, &nt, S(stream)));
+  const int Q = (int)mt[0].size();
+  std::vector<double> C((size_t)Q * Q);
+  min_cost_matrix(*grid, C.data());
+  CoarseProblem P{Q, mt[0].data(), nt[0].data(), C.data(), grid->p == 2};
+  CoarseSolution sol;
+  if (coarse_solve(P, &sol) != QBW_OK) { set_error("network simplex failed on C^min (Q=%d)", Q); return QBW_E_LP; }
+  // dual objective of admissible potentials is a lower bound whatever the rounding
+  double viol = 0.0, dual = 0.0, ma = 0.0, mb = 0.0;
+  for (int K = 0; K < Q; ++K)
+    for (int L = 0; L < Q; ++L) viol = std::max(viol, sol.f[K] + sol.g[L] - C[(size_t)K * Q + L]);
+  for (int K = 0; K < Q; ++K) {
+    dual += sol.f[K] * mt[0][K] + sol.g[K] * nt[0][K];
+    ma += mt[0][K];
+    mb += nt[0][K];
+  }
+  double s = dual - viol * std::max(ma, mb);
+  s -= std::fabs(s) * 9.094947017729282e-13;
+  s = std::max(s, 0.0);
+  *lower = grid->p == 2 ? std::sqrt(s) : s;
+  if (objective) *objective = sol.objective;
+  return QBW_OK;
+}
+
 qbw_status qbw_coarse_solve_host(const qbw_grid* grid, const double* a_t, const double* b_t, int32_t* rows,
                                  int32_t* cols, double* vals, int32_t* nnz, double* f, double* g,
                                  double* objective) {

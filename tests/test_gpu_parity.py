@@ -391,3 +391,22 @@ def test_full_size_translation_closed_form():
     W = math.sqrt(5 ** 2 + 9 ** 2)
     assert out["lower"] <= W <= out["upper"]
     assert out["lower"] > 0.9 * W
+
+
+# ------------------------------------------------------------------ Algorithm 3 and Section 3.3
+
+@pytest.mark.parametrize("N,d,k,p", [(16, 2, 4, 2), (16, 2, 4, 1), (32, 2, 8, 2), (8, 3, 2, 2), (8, 3, 4, 1)])
+def test_weighted_cost_and_min_cost_bounds(N, d, k, p):
+    mu, nu = pair(N, d, "gmm", "shapes", 9600 + N + k + p)
+    ub, uobj = qbw.weighted_cost_upper(dev(mu), dev(nu), k, p)
+    lb, lobj = qbw.min_cost_lower(dev(mu), dev(nu), k, p)
+    ref_ub = upper.weighted_cost_upper(mu, nu, k, p)
+    ref_lb = upper.min_cost_lower(mu, nu, k, p)
+    assert ub == pytest.approx(ref_ub, rel=1e-9) and ub >= ref_ub * (1 - 1e-12)
+    assert lb == pytest.approx(ref_lb, rel=1e-9) and lb <= ref_lb * (1 + 1e-12)
+    if N ** d <= 256:
+        W = lp.wasserstein_exact(mu, nu, p)
+        assert lb <= W <= ub
+    # ordering against the primal-upscaling bound on the same pair
+    out = qbw.bounds(dev(mu), dev(nu), k, p)
+    assert lb <= out["upper"] and ub <= out["upper"] * (1 + 1e-9)

@@ -476,3 +476,54 @@ def test_upper_bound_gradient_matches_fd(p):
         fd = (W(mu * (1 + h * vm), nu * (1 + h * vn)) - W(mu * (1 - h * vm), nu * (1 - h * vn))) / (2 * h)
         an = float((gm * (mu * vm).reshape(-1)).sum() + (gn * (nu * vn).reshape(-1)).sum())
         assert fd == pytest.approx(an, rel=1e-6, abs=1e-9)
+
+
+# ---------------------------------------------------------------- separable c-transform (p = 2)
+
+@pytest.mark.parametrize("N,d", [(12, 2), (7, 3), (32, 2)])
+def test_separable_equals_all_pairs_without_rounding(N, d):
+    # integer potentials below 2^20: every float32 operation is exact in both
+    # evaluations, so values and arg-mins (lowest flat index) coincide
+    phi = si.rng(300 + N).integers(-(2 ** 19), 2 ** 19, N ** d).astype(np.float32)
+    phi[::5] = phi[0]                                    # plenty of ties
+    g1, a1 = lower.ctransform_sep_o32(phi, N, d)
+    g2, a2 = lower.ctransform_o32(phi, N, d, 2)
+    assert np.array_equal(g1, g2) and np.array_equal(a1, a2)
+
+
+def test_separable_brute_force_tiny():
+    N, d = 5, 2
+    phi = (si.rng(310).standard_normal(N * N) * 7).astype(np.float32)
+    g, a = lower.ctransform_sep_o32(phi, N, d)
+    P = phi.reshape(N, N)
+    for u in range(N):
+        for v in range(N):
+            h = [min(np.float32(np.float32((t - v) ** 2) - P[s, t]) for t in range(N)) for s in range(N)]
+            vals = [np.float32(np.float32((s - u) ** 2) + h[s]) for s in range(N)]
+            assert g[u * N + v] == min(vals)
+            s_star = int(np.argmin(vals))
+            row = [np.float32(np.float32((t - v) ** 2) - P[s_star, t]) for t in range(N)]
+            assert a[u * N + v] == s_star * N + int(np.argmin(row))
+
+
+@pytest.mark.parametrize("N,d", [(16, 2), (8, 3)])
+def test_separable_error_bounds_and_feasibility(N, d):
+    k = 4 if d == 2 else 2
+    mu, nu = pair(N, d, "grf", "cauchy", 320 + N)
+    *_, ft, gt, _ = upper.coarse_record_lp(mu, nu, k, 2)
+    ft = ft + 3e3                               # offsets stress the rounding
+    Ls = lower.lower_bound_sep_o32(mu, nu, ft, k)
+    L64 = lower.lower_bound_o64(mu, nu, ft, k, 2)
+    u = 2.0 ** -24
+    C = d * (N - 1) ** 2
+    F = np.abs(Ls["fhat32"]).max() * (1 + 2 * u)
+    G = np.abs(Ls["g32"]).max()
+    Fo = np.abs(Ls["f32"]).max()
+    e_g = u * (F + d * G + (d - 1) * C)
+    assert np.abs(Ls["g32"] - L64["g"]).max() <= e_g
+    assert np.abs(Ls["f32"] - L64["f"]).max() <= u * (d * Fo + (d - 1) * C) + e_g
+    X = grid.coords(N, d)
+    Cm = grid.cost64(X, X, 2)
+    f = Ls["f32"].astype(np.float64) - Ls["shift"]
+    assert (f[:, None] + Ls["g32"].astype(np.float64)[None, :] - Cm).max() <= 0.0
+    assert Ls["S_emit"] <= L64["S"]
