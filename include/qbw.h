@@ -65,6 +65,9 @@ typedef struct qbw_grid {
 /* qbw_opts.flags */
 #define QBW_WANT_ARGMIN 1u   /* also compute c-transform arg-mins (needed for d/d f^) */
 #define QBW_SAVE_FOR_BWD 2u  /* keep what qbw_bounds_backward needs */
+#define QBW_SEPARABLE 4u     /* p = 2: evaluate each c-transform as d nested 1-D transforms
+                                (O(N^(d+1)) instead of O(N^(2d)); float32 rounding once per
+                                axis, larger derived shift); ignored for p = 1 */
 
 /* qbw_result.warn bits */
 #define QBW_WARN_IPF_NOT_CONVERGED 1u /* stopped at max_ipf_iter; the upper bound stays valid */
@@ -73,7 +76,7 @@ typedef struct qbw_grid {
 typedef struct qbw_opts {
   double xi;            /* IPF stop: ||a^ - a||_1 + ||b - b^||_1 < xi (default 1e-12) */
   int32_t max_ipf_iter; /* IPF iteration cap (default 50, >= 1) */
-  uint32_t flags;       /* QBW_WANT_ARGMIN | QBW_SAVE_FOR_BWD */
+  uint32_t flags;       /* QBW_WANT_ARGMIN | QBW_SAVE_FOR_BWD | QBW_SEPARABLE */
 } qbw_opts;
 
 typedef struct qbw_result {
@@ -196,6 +199,14 @@ qbw_status qbw_upscale_potential(qbw_ctx* ctx, const qbw_grid* grid, const doubl
  * index attaining it.  src, dst: device float32 (N^d). */
 qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
                           int32_t* argmin, qbw_stream stream);
+
+/* The same c-transform for p = 2 evaluated separably: d nested 1-D
+ * c-transforms, last axis first (pass 1 subtracts src, later passes add the
+ * previous result), each candidate rounded to float32 once per axis; argmin
+ * (may be NULL) = the passes' lowest indices composed.  grid->p must be 2
+ * (QBW_E_GRID otherwise). */
+qbw_status qbw_ctransform_separable(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
+                                    int32_t* argmin, qbw_stream stream);
 
 /* IPF of Algorithm 4 on the uniformly upscaled coupling: from b_s = 1,
  * repeat a_s = a / (pi^ b_s), b_s = b / (pi^T a_s) until the L1 marginal

@@ -18,11 +18,12 @@ import torch
 
 from . import _lib
 from ._lib import (QBW_BATCH_AUTOTUNE, QBW_BATCH_BACKWARD, QBW_BATCH_GRAPH, QBW_SAVE_FOR_BWD,
-                   QBW_WANT_ARGMIN, QBW_WARN_IPF_NOT_CONVERGED, QBW_WARN_LB_CLIPPED, QbwCoarse,
+                   QBW_SEPARABLE, QBW_WANT_ARGMIN, QBW_WARN_IPF_NOT_CONVERGED, QBW_WARN_LB_CLIPPED, QbwCoarse,
                    QbwError, QbwGrid, QbwJob, QbwOpts, QbwResult, check, load)
 
 __all__ = ["Context", "Coarse", "Batch", "bounds", "wasserstein_bounds", "BoundsFunction",
            "sumpool", "coarse_cost", "cbar", "coarse_solve", "upscale_potential", "ctransform",
+           "ctransform_separable",
            "ipf", "plan_cost", "tv", "autotune_ctransform", "weighted_cost_upper", "min_cost_lower",
            "bounds_with_grads", "QbwError", "load"]
 
@@ -128,11 +129,12 @@ def coarse_solve(a_t, b_t, N: int, d: int, k: int, p: int) -> Coarse:
 
 
 def bounds(a, b, k: int, p: int, coarse: Coarse | None = None, xi: float = 1e-12,
-           max_ipf_iter: int = 50, want_argmin: bool = False) -> dict:
-    """Lower and upper bound of W_p(a, b) (no autograd).  Returns the qbw_result fields."""
+           max_ipf_iter: int = 50, want_argmin: bool = False, separable: bool = False) -> dict:
+    """Lower and upper bound of W_p(a, b) (no autograd).  Returns the qbw_result fields.
+    separable=True evaluates the p = 2 c-transforms axis by axis (QBW_SEPARABLE)."""
     a, b = _dev(a), _dev(b)
     grid = _grid(a, k, p)
-    opts = _opts(xi, max_ipf_iter, QBW_WANT_ARGMIN if want_argmin else 0)
+    opts = _opts(xi, max_ipf_iter, (QBW_WANT_ARGMIN if want_argmin else 0) | (QBW_SEPARABLE if separable else 0))
     res = QbwResult()
     lib = load()
     ctx = context(a.device.index)
@@ -162,10 +164,10 @@ class BoundsFunction(torch.autograd.Function):
     the coarse solution frozen (see qbw_bounds_backward)."""
 
     @staticmethod
-    def forward(ctx, a, b, k, p, coarse, xi, max_ipf_iter, want_argmin):
+    def forward(ctx, a, b, k, p, coarse, xi, max_ipf_iter, want_argmin, separable=False):
         a, b = _dev(a), _dev(b)
         grid = _grid(a, k, p)
-        flags = QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_argmin else 0)
+        flags = QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_argmin else 0) | (QBW_SEPARABLE if separable else 0)
         opts = _opts(xi, max_ipf_iter, flags)
         res = QbwResult()
         saved = C.c_void_p()
@@ -196,22 +198,23 @@ class BoundsFunction(torch.autograd.Function):
         check(load().qbw_bounds_backward(context(a.device.index).handle, ctx.saved_handle.handle,
                                          dl, du, _ptr(ga), _ptr(gb), None, _stream()),
               "qbw_bounds_backward")
-        return ga, gb, None, None, None, None, None, None
+        return ga, gb, None, None, None, None, None, None, None
 
 
 def wasserstein_bounds(a, b, k: int, p: int, coarse: Coarse | None = None, xi: float = 1e-12,
-                       max_ipf_iter: int = 50, want_argmin: bool = False):
+                       max_ipf_iter: int = 50, want_argmin: bool = False, separable: bool = False):
     """Differentiable (lower, upper) bounds on W_p(a, b)."""
-    return BoundsFunction.apply(a, b, k, p, coarse, xi, max_ipf_iter, want_argmin)
+    return BoundsFunction.apply(a, b, k, p, coarse, xi, max_ipf_iter, want_argmin, separable)
 
 
 def bounds_with_grads(a, b, k: int, p: int, coarse: Coarse | None = None, dlower: float = 1.0,
                       dupper: float = 1.0, want_fhat_grad: bool = False, xi: float = 1e-12,
-                      max_ipf_iter: int = 50):
+                      max_ipf_iter: int = 50, separable: bool = False):
     """Forward + backward in one call: returns (result dict, grad_a, grad_b, grad_fhat or None)."""
     a, b = _dev(a), _dev(b)
     grid = _grid(a, k, p)
-    opts = _opts(xi, max_ipf_iter, QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_fhat_grad else 0))
+    opts = _opts(xi, max_ipf_iter, QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_fhat_grad else 0) |
+                 (QBW_SEPARABLE if separable else 0))
     res = QbwResult()
     saved = C.c_void_p()
     lib = load()
@@ -279,6 +282,17 @@ def ctransform(src, N: int, d: int, p: int, want_argmin: bool = False):
     arg = torch.empty(src.shape, dtype=torch.int32, device=src.device) if want_argmin else None
     check(load().qbw_ctransform(context(src.device.index).handle, C.byref(grid), _ptr(src), _ptr(dst),
                                 _ptr(arg), _stream()), "qbw_ctransform")
+    return (dst, arg) if want_argmin else dst
+
+
+def ctransform_separable(src, N: int, d: int, want_argmin: bool = False):
+    """p = 2 c-transform as d nested 1-D transforms (qbw_ctransform_separable)."""
+    src = _dev(src, torch.float32)
+    grid = QbwGrid(d, N, 1, 2)
+    dst = torch.empty_like(src)
+    arg = torch.empty(src.shape, dtype=torch.int32, device=src.device) if want_argmin else None
+    check(load().qbw_ctransform_separable(context(src.device.index).handle, C.byref(grid), _ptr(src),
+                                          _ptr(dst), _ptr(arg), _stream()), "qbw_ctransform_separable")
     return (dst, arg) if want_argmin else dst
 
 
@@ -352,7 +366,8 @@ class Batch:
     (optionally captured in a hipGraph and autotuned)."""
 
     def __init__(self, jobs, coarse=None, backward: bool = False, graph: bool = False,
-                 autotune: bool = False, xi: float = 1e-12, max_ipf_iter: int = 50):
+                 autotune: bool = False, xi: float = 1e-12, max_ipf_iter: int = 50,
+                 separable: bool = False):
         """jobs: list of (a, b, k, p) or (a, b, k, p, grad_a, grad_b) with CUDA tensors."""
         lib = load()
         self._keep = []
@@ -377,7 +392,7 @@ class Batch:
             self._keep.append(coarse)
         flags = (QBW_BATCH_BACKWARD if backward else 0) | (QBW_BATCH_GRAPH if graph else 0) | \
                 (QBW_BATCH_AUTOTUNE if autotune else 0)
-        opts = _opts(xi, max_ipf_iter, 0)
+        opts = _opts(xi, max_ipf_iter, QBW_SEPARABLE if separable else 0)
         h = C.c_void_p()
         self.n = len(jobs)
         self.ctx = context(dev)

@@ -231,7 +231,7 @@ struct JobIn {
 };
 
 enum PlanMode : unsigned {
-  PM_FORWARD = 1, PM_ARGMIN = 2, PM_BACKWARD = 4, PM_CBAR = 8,
+  PM_FORWARD = 1, PM_ARGMIN = 2, PM_BACKWARD = 4, PM_CBAR = 8, PM_SEP = 16,
 };
 
 struct Plan {
@@ -245,9 +245,10 @@ struct Plan {
   char* base = nullptr;
   DevJob* djobs = nullptr;
   int *off_chunk = nullptr, *off_pool = nullptr, *off_entry = nullptr, *off_block = nullptr,
-      *off_cbar = nullptr, *off_mom = nullptr, *off_pc1 = nullptr, *off_pc2 = nullptr;
+      *off_cbar = nullptr, *off_mom = nullptr, *off_pc1 = nullptr, *off_pc2 = nullptr,
+      *off_sep = nullptr;
   int tot_chunk = 0, tot_pool = 0, tot_entry = 0, tot_block = 0, tot_cbar = 0, tot_mom = 0,
-      tot_pc1 = 0, tot_pc2 = 0;
+      tot_pc1 = 0, tot_pc2 = 0, tot_sep = 0, max_sep_d = 0;
   CtItem* items = nullptr;
   int* qoff = nullptr;   // kQueues + 1 offsets into items
   int n_items = 0;
@@ -301,7 +302,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   struct Offs {
     size_t mu_t, nu_t, ftil, fhat, g, f, part, win, arg_g, arg_f, e_row, e_col, e_val, csr, csc,
         csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, gbar_mu, gbar_nu, coef, mom_mu, mom_nu,
-        mom_as, mom_bs;
+        mom_as, mom_bs, sep_tmp, sep_arg;
   };
   std::vector<Offs> offs(NJ);
   const bool ub = true;
@@ -342,9 +343,12 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     O.mom_nu = L.add(8 * 5 * (size_t)Q);
     O.mom_as = L.add(8 * 5 * (size_t)Q);
     O.mom_bs = L.add(8 * 5 * (size_t)Q);
+    const bool sep = (mode & PM_SEP) && J.g.p == 2;
+    O.sep_tmp = sep ? L.add(4 * 2 * (size_t)P) : 0;
+    O.sep_arg = (sep && (mode & PM_ARGMIN)) ? L.add(4 * (size_t)d * P) : 0;
   }
   const size_t o_jobs = L.add(sizeof(DevJob) * NJ);
-  constexpr int kTables = 8;
+  constexpr int kTables = 9;
   const size_t o_offs = L.add(sizeof(int) * kTables * (NJ + 1));
   // c-transform work items, one queue per XCD.  Jobs get a home queue by
   // longest-processing-time assignment of their pair counts; a lone job (or one
@@ -365,6 +369,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
     for (int j : order) {
       const auto& J = pl.in[j];
+      if ((mode & PM_SEP) && J.g.p == 2) continue;   // separable jobs use the 1-D passes
       const int P = ipow(J.g.N, J.g.d);
       const int tiles = (P + 64 * J.tiling.R - 1) / (64 * J.tiling.R);
       const bool spread = work(j) > total / kQueues;
@@ -464,6 +469,9 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.mom_nu = (double*)(B + O.mom_nu);
     D.mom_as = (double*)(B + O.mom_as);
     D.mom_bs = (double*)(B + O.mom_bs);
+    D.sep = ((mode & PM_SEP) && D.p == 2) ? 1 : 0;
+    D.sep_tmp = D.sep ? (float*)(B + O.sep_tmp) : nullptr;
+    D.sep_arg = (D.sep && (mode & PM_ARGMIN)) ? (int*)(B + O.sep_arg) : nullptr;
     off[0 * (NJ + 1) + j + 1] = off[0 * (NJ + 1) + j] + D.chunks;
     off[1 * (NJ + 1) + j + 1] = off[1 * (NJ + 1) + j] + (D.Q + 255) / 256;
     off[2 * (NJ + 1) + j + 1] = off[2 * (NJ + 1) + j] + D.nnz;
@@ -472,6 +480,8 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     off[5 * (NJ + 1) + j + 1] = off[5 * (NJ + 1) + j] + (2 * D.Q + 255) / 256;
     off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + (D.p == 1 ? D.nnz : 0);
     off[7 * (NJ + 1) + j + 1] = off[7 * (NJ + 1) + j] + (D.p == 2 ? (D.nnz + 255) / 256 : 0);
+    off[8 * (NJ + 1) + j + 1] = off[8 * (NJ + 1) + j] + (D.sep ? D.rows * ((D.N + 63) / 64) : 0);
+    if (D.sep) pl.max_sep_d = std::max(pl.max_sep_d, D.d);
   }
   pl.djobs = (DevJob*)(B + o_jobs);
   int* offd = (int*)(B + o_offs);
@@ -485,6 +495,8 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   pl.off_pc2 = offd + 7 * (NJ + 1);
   pl.tot_pc1 = off[6 * (NJ + 1) + NJ];
   pl.tot_pc2 = off[7 * (NJ + 1) + NJ];
+  pl.off_sep = offd + 8 * (NJ + 1);
+  pl.tot_sep = off[8 * (NJ + 1) + NJ];
   pl.tot_chunk = off[0 * (NJ + 1) + NJ];
   pl.tot_pool = off[1 * (NJ + 1) + NJ];
   pl.tot_entry = off[2 * (NJ + 1) + NJ];
@@ -532,9 +544,19 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   return QBW_OK;
 }
 
+static int enqueue_sep(Plan& pl, int phase, hipStream_t st) {
+  const int NJ = pl.njobs;
+  for (int pass = 0; pass < pl.max_sep_d; ++pass)
+    CHK(launch_ct1d(pl.djobs, NJ, pl.off_sep, pl.tot_sep, phase, pass, st));
+  if (pl.mode & PM_ARGMIN) CHK(launch_sep_argmin(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
+  return QBW_OK;
+}
+
 static int enqueue_ctransforms(Plan& pl, hipStream_t st) {
   const int NJ = pl.njobs;
   for (int phase = 0; phase < 2; ++phase) {
+    if (pl.tot_sep) CHK(enqueue_sep(pl, phase, st));
+    if (!pl.n_items) continue;
     std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
     if (pl.timing) {
       if (pl.ev_used == pl.ev_pool.size()) {
@@ -776,7 +798,8 @@ static qbw_status bounds_impl(qbw_ctx* ctx, const qbw_grid* grid, const double* 
                               qbw_stream stream, std::vector<CoarseHost>* keep) {
   qbw_opts o = opts ? *opts : qbw_default_opts();
   const bool save = (o.flags & QBW_SAVE_FOR_BWD) && saved;
-  unsigned mode = PM_FORWARD | ((o.flags & QBW_WANT_ARGMIN) ? PM_ARGMIN : 0u);
+  unsigned mode = PM_FORWARD | ((o.flags & QBW_WANT_ARGMIN) ? PM_ARGMIN : 0u) |
+                  ((o.flags & QBW_SEPARABLE) ? PM_SEP : 0u);
   JobIn J{*grid, a, b, nullptr, nullptr, nullptr, lookup_tiling(ctx, *grid)};
   hipStream_t st = S(stream);
   if (save) {
@@ -1035,6 +1058,24 @@ qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, 
   return QBW_OK;
 }
 
+qbw_status qbw_ctransform_separable(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
+                                    int32_t* argmin, qbw_stream stream) {
+  if (!ctx || !src || !dst) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  if (grid->p != 2) { set_error("the separable c-transform needs p = 2"); return QBW_E_GRID; }
+  Plan pl;
+  hipStream_t st = S(stream);
+  CHK(plan_build(ctx, pl, {stage_job(grid, nullptr, nullptr)}, PM_SEP | (argmin ? PM_ARGMIN : 0u),
+                 qbw_default_opts(), false, st));
+  pl.hj[0].fhat = const_cast<float*>(src);
+  pl.hj[0].g = dst;
+  if (argmin) pl.hj[0].arg_g = argmin;
+  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
+  CHK(enqueue_sep(pl, 0, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
 static qbw_status coarse_stage_plan(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
                                     const qbw_coarse* coarse, const qbw_opts* opts, Plan& pl, CoarseHost& ch,
                                     hipStream_t st) {
@@ -1229,7 +1270,8 @@ qbw_status qbw_batch_create(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs, co
   }
   for (int j = 0; j < njobs; ++j) in[j].coarse = &B->coarse[j];
   const unsigned mode = PM_FORWARD | ((batch_flags & QBW_BATCH_BACKWARD) ? PM_BACKWARD : 0u) |
-                        ((o.flags & QBW_WANT_ARGMIN) ? PM_ARGMIN : 0u);
+                        ((o.flags & QBW_WANT_ARGMIN) ? PM_ARGMIN : 0u) |
+                        ((o.flags & QBW_SEPARABLE) ? PM_SEP : 0u);
   load_tune_cache(ctx);
   if (batch_flags & QBW_BATCH_AUTOTUNE) {
     // batch-level tuning: targets per lane and the total number of waves the

@@ -341,6 +341,7 @@ __global__ __launch_bounds__(256) void k_merge(const DevJob* __restrict__ jobs, 
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
+    if (J.sep) continue;
     const int base = (it - off[jb]) * kChunk;
     float* dst = phase == 0 ? J.g : J.f;
     for (int q = threadIdx.x; q < kChunk; q += 256) {
@@ -364,6 +365,7 @@ __global__ __launch_bounds__(256) void k_argmin(const DevJob* __restrict__ jobs,
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
+    if (J.sep) continue;
     const int base = (it - off[jb]) * kChunk;
     const float* src = phase == 0 ? J.fhat : J.g;
     const float* dst = phase == 0 ? J.g : J.f;
@@ -387,6 +389,88 @@ __global__ __launch_bounds__(256) void k_argmin(const DevJob* __restrict__ jobs,
         if (c - src[i] == target) found = i;
       }
       arg[j] = found;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ separable c-transform (p = 2)
+//
+// |x - y|^2 is a sum over axes, so the c-transform is d nested 1-D transforms.
+// Pass k (0-based) runs along axis a = d-1-k; a line is one index tuple of the
+// other axes and its element e sits at base + e * N^k.  Pass 0 subtracts the
+// potential, later passes add the previous pass's result:
+//   dst[v] = min_t RN32((t - v)^2 -/+ src[t]),  arg = lowest t attaining it.
+// One wave per (job, line, chunk of 64 targets); the cost is updated exactly
+// (c += D, D += 2) and the source values are wave-uniform scalar loads.
+__global__ __launch_bounds__(64) void k_ct1d(const DevJob* __restrict__ jobs, int njobs,
+                                             const int* __restrict__ off, int total, int phase,
+                                             int pass) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    if (!J.sep || pass >= J.d) continue;
+    const int N = J.N, P = J.P;
+    const int chunks = (N + 63) / 64;
+    const int local = it - off[jb];
+    const int line = local / chunks, ch = local - line * chunks;
+    int stride = 1;
+    for (int q = 0; q < pass; ++q) stride *= N;
+    const int hi = line / stride, lo = line - hi * stride;
+    const int base = hi * stride * N + lo;
+    const float* src = pass == 0 ? (phase == 0 ? J.fhat : J.g) : J.sep_tmp + (size_t)((pass - 1) & 1) * P;
+    float* dst = pass == J.d - 1 ? (phase == 0 ? J.g : J.f) : J.sep_tmp + (size_t)(pass & 1) * P;
+    int* arg = J.sep_arg ? J.sep_arg + (size_t)pass * P : nullptr;
+    const_fptr s = (const_fptr)(src + base);
+    const int v = ch * 64 + (int)(threadIdx.x & 63);
+    float c = (float)(v * v);
+    float D = (float)(1 - 2 * v);
+    float best = INFINITY;
+    int barg = 0;
+    if (pass == 0) {
+      for (int t = 0; t < N; ++t) {
+        const float val = c - s[(size_t)t * stride];
+        if (val < best) { best = val; barg = t; }
+        c += D;
+        D += 2.0f;
+      }
+    } else {
+      for (int t = 0; t < N; ++t) {
+        const float val = c + s[(size_t)t * stride];
+        if (val < best) { best = val; barg = t; }
+        c += D;
+        D += 2.0f;
+      }
+    }
+    if (v < N) {
+      dst[base + (size_t)v * stride] = best;
+      if (arg) arg[base + (size_t)v * stride] = barg;
+    }
+  }
+}
+
+// Compose the passes' arg-mins into the source index (last pass fixes axis 0).
+__global__ __launch_bounds__(256) void k_sep_argmin(const DevJob* __restrict__ jobs, int njobs,
+                                                    const int* __restrict__ off, int total, int phase) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    if (!J.sep || !J.sep_arg) continue;
+    int* out = phase == 0 ? J.arg_g : J.arg_f;
+    if (!out) continue;
+    const int base = (it - off[jb]) * kChunk;
+    const int N = J.N, P = J.P;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int j = base + q;
+      if (j >= P) break;
+      int x[3];
+      pix_coords(j, N, J.d, x[0], x[1], x[2]);   // 2D: x[1], x[2] hold the coordinates
+      const int a0 = J.d == 2 ? 1 : 0;           // first used slot
+      for (int pass = J.d - 1; pass >= 0; --pass) {
+        const int slot = a0 + (J.d - 1 - pass);   // axis d-1-pass
+        const int cur = J.d == 2 ? x[1] * N + x[2] : (x[0] * N + x[1]) * N + x[2];
+        x[slot] = J.sep_arg[(size_t)pass * P + cur];
+      }
+      out[j] = J.d == 2 ? x[1] * N + x[2] : (x[0] * N + x[1]) * N + x[2];
     }
   }
 }
@@ -677,8 +761,16 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   const double u = 5.9604644775390625e-08;
   const double up = J.p == 1 ? u : 0.0;
   const double F = mh * (1.0 + 2.0 * u);
-  const double e_g = (u + up) * (mg + F);
-  const double e_f = u * mf + up * (mf + mg) + e_g;
+  double e_g, e_f;
+  if (J.sep) {
+    // separable evaluation: one rounding per axis of partial values <= |g| + d (N-1)^2
+    const double Cm = (double)J.d * (J.N - 1) * (J.N - 1);
+    e_g = u * (F + J.d * mg + (J.d - 1) * Cm);
+    e_f = u * (J.d * mf + (J.d - 1) * Cm) + e_g;
+  } else {
+    e_g = (u + up) * (mg + F);
+    e_f = u * mf + up * (mf + mg) + e_g;
+  }
   const double shift = (e_f + e_g) * (1.0 + 0.0009765625) + 2.220446049250313e-16 * J.P * (mf + mg);
   const double S32 = sf + sg;
   const double Se = S32 - shift;
@@ -1146,6 +1238,17 @@ int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, con
 }
 int launch_tv_prep(const DevJob* jobs, int njobs, void* stream) {
   hipLaunchKernelGGL(k_tv_prep, dim3(njobs), dim3(1024), 0, (hipStream_t)stream, jobs, njobs);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_ct1d(const DevJob* jobs, int njobs, const int* off, int total, int phase, int pass,
+                void* stream) {
+  hipLaunchKernelGGL(k_ct1d, dim3(grid_for(total)), dim3(64), 0, (hipStream_t)stream, jobs, njobs, off, total, phase, pass);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_sep_argmin(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream) {
+  hipLaunchKernelGGL(k_sep_argmin, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, phase);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -97,6 +97,10 @@ struct DevJob {
   double* mom_nu;           // of nu
   double* mom_as;           // of the IPF scalings a_s
   double* mom_bs;           // of b_s
+  // separable c-transform (p = 2): two float32 ping-pong buffers and d arg-min planes
+  int sep;
+  float* sep_tmp;           // 2 x P
+  int* sep_arg;             // d x P or null
 };
 
 struct CtItem { int job, tile, split, pad; };
@@ -135,6 +139,10 @@ int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, con
 int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
                       double* const* outs, void* stream);
 int launch_tv_prep(const DevJob* jobs, int njobs, void* stream);
+int launch_ct1d(const DevJob* jobs, int njobs, const int* off, int total, int phase, int pass,
+                void* stream);
+int launch_sep_argmin(const DevJob* jobs, int njobs, const int* off, int total, int phase,
+                      void* stream);
 int launch_reset_counter(int* counter, int n, void* stream);
 
 }  // namespace qbw

@@ -410,3 +410,57 @@ def test_weighted_cost_and_min_cost_bounds(N, d, k, p):
     # ordering against the primal-upscaling bound on the same pair
     out = qbw.bounds(dev(mu), dev(nu), k, p)
     assert lb <= out["upper"] and ub <= out["upper"] * (1 + 1e-9)
+
+
+# ------------------------------------------------------------------ separable c-transform (p = 2)
+
+@pytest.mark.parametrize("N,d", [(32, 2), (16, 3), (24, 2), (15, 2), (9, 3), (70, 2), (256, 2)])
+def test_ctransform_separable_bit_exact(N, d):
+    phi = (si.rng(9700 + N).standard_normal(N ** d) * N * N / 4).astype(np.float32)
+    out, arg = qbw.ctransform_separable(dev(phi), N, d, want_argmin=True)
+    ref, refarg = lower.ctransform_sep_o32(phi, N, d)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    assert np.array_equal(arg.cpu().numpy().astype(np.int64), refarg)
+
+
+@pytest.mark.parametrize("N,d,k", [(32, 2, 4), (64, 2, 8), (16, 3, 2), (24, 2, 3)])
+def test_bounds_separable(N, d, k):
+    mu, nu = pair(N, d, "grf", "cauchy", 9800 + N + k)
+    rec, (r, c, v, ft, gt, obj) = record(mu, nu, k, 2)
+    out = qbw.bounds(dev(mu), dev(nu), k, 2, coarse=rec, separable=True)
+    Ls = lower.lower_bound_sep_o32(mu, nu, ft, k)
+    L64 = lower.lower_bound_o64(mu, nu, ft, k, 2)
+    assert out["lower_S"] == pytest.approx(Ls["S_emit"], rel=1e-9)
+    assert out["feas_shift"] == pytest.approx(Ls["shift"], rel=1e-12)
+    assert out["lower"] <= L64["lower"]
+    allp = qbw.bounds(dev(mu), dev(nu), k, 2, coarse=rec)
+    assert out["upper"] == allp["upper"]
+    assert abs(out["lower"] - allp["lower"]) <= 1e-3 * allp["lower"]
+    res, ga, gb, gf = qbw.bounds_with_grads(dev(mu), dev(nu), k, 2, coarse=rec, dlower=1.0, dupper=0.0,
+                                            separable=True, want_fhat_grad=True)
+    lgm, lgn = ograd.lower_grad(Ls["f32"], Ls["g32"], Ls["S_emit"], 2)
+    scale = np.abs(lgm).max()
+    assert np.allclose(ga.cpu().numpy().reshape(-1), lgm, rtol=1e-9, atol=1e-12 * scale)
+    s = 0.5 / math.sqrt(Ls["S_emit"])
+    ref = np.zeros(N ** d)
+    np.add.at(ref, Ls["argmin_g"][Ls["argmin_f"]], s * mu.reshape(-1))
+    np.add.at(ref, Ls["argmin_g"], -s * nu.reshape(-1))
+    assert np.allclose(gf.cpu().numpy(), ref, rtol=1e-12, atol=1e-15)
+
+
+def test_batch_separable_mixed_p():
+    specs = [(32, 2, 4, 2), (16, 3, 2, 1), (24, 2, 3, 2), (16, 3, 4, 2), (32, 2, 8, 1)]
+    jobs, recs = [], []
+    for i, (N, d, k, p) in enumerate(specs):
+        mu, nu = pair(N, d, "gmm", "grf", 9900 + 2 * i)
+        rec, _ = record(mu, nu, k, p)
+        jobs.append((dev(mu), dev(nu), k, p))
+        recs.append(rec)
+    B = qbw.Batch(jobs, coarse=recs, graph=True, backward=True, separable=True)
+    B.run()
+    out = B.results()
+    for (a, b, k, p), rec, o, (ga, gb) in zip(jobs, recs, out, B.grads):
+        s, sa, sb, _ = qbw.bounds_with_grads(a, b, k, p, coarse=rec, separable=True)
+        for key in ("lower", "upper", "lower_S", "feas_shift", "upper_cost"):
+            assert s[key] == o[key], key
+        assert torch.allclose(ga, sa, rtol=1e-12, atol=0)
