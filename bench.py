@@ -202,6 +202,19 @@ def main():
     plain_fb = nplain / (time.perf_counter() - t0)
     log(f"[bench] plain: fwd {plain_fwd:.1f} pairs/s, fwd+bwd {plain_fb:.1f} pairs/s")
 
+    # ---- the same batch with the separable p = 2 c-transforms (QBW_SEPARABLE)
+    sep = qbw.Batch(jobs, coarse=recs, backward=True, graph=True, separable=True)
+    for _ in range(args.warmup):
+        sep.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sep.run()
+    torch.cuda.synchronize()
+    ms_sep = (time.perf_counter() - t0) * 1e3 / args.steps
+    rsep = sep.results()
+    log(f"[bench] separable: {ms_sep:.3f} ms/step -> {B / (ms_sep / 1e3):.1f} pairs/s")
+
     # consistency of the timed results with the single-pair path
     ref = qbw.bounds(A[0], Bm[0], k, p, coarse=recs[0])
     assert ref["lower"] == res[0]["lower"] and ref["upper"] == res[0]["upper"], (ref, res[0])
@@ -229,6 +242,10 @@ def main():
                      "pairs_per_launch": pairs_per_launch},
         "plain": {"fwd_pairs_per_s": plain_fwd, "fwd_bwd_pairs_per_s": plain_fb,
                   "batched_over_plain_fwd_bwd": value / plain_fb},
+        "separable_p2": {"pairs_per_s": B / (ms_sep / 1e3), "ms_per_step": ms_sep,
+                         "note": "same batch, c-transforms as d nested 1-D transforms (O(N^3) here); "
+                                 "float32 rounding once per axis, larger derived shift",
+                         "lower_sample": rsep[0]["lower"], "upper_sample": rsep[0]["upper"]},
         "end_to_end": {"coarse_seconds": t_coarse, "host_threads": workers,
                        "pairs_per_s_sequential": B / (t_coarse + ms_step / 1e3),
                        "pairs_per_s_pipelined": B / max(t_coarse, ms_step / 1e3)},
