@@ -144,7 +144,7 @@ def main():
     t0 = time.perf_counter()
     mts = [qbw.sumpool(a, k).cpu().numpy() for a in A]
     nts = [qbw.sumpool(b, k).cpu().numpy() for b in Bm]
-    workers = os.cpu_count() or 1
+    workers = min(os.cpu_count() or 1, 16)
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         recs = list(ex.map(lambda t: qbw.coarse_solve(t[0], t[1], N, d, k, p), zip(mts, nts)))
     t_coarse = time.perf_counter() - t0

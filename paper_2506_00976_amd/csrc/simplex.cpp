@@ -36,6 +36,24 @@ namespace qbw {
 
 namespace {
 
+// Smallest reduced cost c_j + pk - pl_j over one cost row segment.  Built for
+// several instruction sets and picked at load time by the CPU's features.
+__attribute__((target_clones("avx512f", "avx2", "default")))
+int64_t row_min(const int64_t* cr, int64_t pk, const int64_t* pl, int len) {
+  int64_t v = std::numeric_limits<int64_t>::max();
+  for (int j = 0; j < len; ++j) v = std::min(v, cr[j] + pk - pl[j]);
+  return v;
+}
+__attribute__((target_clones("avx512f", "avx2", "default")))
+double row_min(const double* cr, double pk, const double* pl, int len) {
+  double v = std::numeric_limits<double>::infinity();
+  for (int j = 0; j < len; ++j) {
+    const double r = cr[j] + pk - pl[j];
+    v = r < v ? r : v;
+  }
+  return v;
+}
+
 template <typename Cost>
 struct TransportSimplex {
   // Problem: n sources (supply s_k > 0), m sinks (demand t_l > 0), dense
@@ -50,11 +68,13 @@ struct TransportSimplex {
     int64_t arc;     // real arc id k*m + l, or -1 for an artificial arc
     int64_t flow;
   };
-  std::vector<Edge> edges;                 // tree edges (n + m of them)
-  std::vector<int> parent, pred, depth;    // pred = edge index to the parent
+  std::vector<Edge> edges;  // tree edges (n + m of them)
+  // Spanning tree: parent and the edge to it (pred); a circular preorder list
+  // (thread / rthread) with, per node, its subtree size and the last node of
+  // its subtree in that order.  A subtree is a contiguous run of the list.
+  std::vector<int> parent, pred, thread, rthread, size, last;
   std::vector<Cost> pi;
-  std::vector<std::vector<int>> adj;       // tree edges incident to each node
-  std::vector<int> queue;
+  std::vector<int> path, seq;
   int64_t next_arc = 0;
   int64_t pivots = 0;
 
@@ -65,25 +85,32 @@ struct TransportSimplex {
     root = n + m;
     parent.assign(N, -1);
     pred.assign(N, -1);
-    depth.assign(N, 0);
+    thread.assign(N, 0);
+    rthread.assign(N, 0);
+    size.assign(N, 1);
+    last.assign(N, 0);
     pi.assign(N, Cost(0));
-    adj.assign(N, {});
     edges.clear();
     for (int v = 0; v < n + m; ++v) {
       Edge e;
       if (v < n) { e.a = v; e.b = root; e.flow = supply[v]; }
       else       { e.a = root; e.b = v; e.flow = -supply[v]; }
       e.arc = -1;
-      int id = (int)edges.size();
+      pred[v] = (int)edges.size();
       edges.push_back(e);
       parent[v] = root;
-      pred[v] = id;
-      depth[v] = 1;
+      last[v] = v;
       // tree arcs have zero reduced cost: cost + pi[a] - pi[b] = 0
       pi[v] = (v < n) ? Cost(-art) : art;
-      adj[v].push_back(id);
-      adj[root].push_back(id);
     }
+    // preorder: root, 0, 1, ..., n+m-1, back to root
+    for (int v = 0; v < N; ++v) {
+      const int nx = v == root ? 0 : (v + 1 == n + m ? root : v + 1);
+      thread[v] = nx;
+      rthread[nx] = v;
+    }
+    size[root] = N;
+    last[root] = n + m - 1;
   }
 
   Cost reduced(int64_t arc) const {
@@ -91,38 +118,52 @@ struct TransportSimplex {
     return c[arc] + pi[k] - pi[n + l];
   }
 
-  // Block search pricing: scan arcs cyclically in blocks, return the most
-  // negative reduced cost found in the first block that has one.
+  // Block search pricing: scan arcs cyclically in blocks of about sqrt(n m),
+  // return the most negative reduced cost of the first block that has one
+  // (lowest arc in scan order on ties).  Arcs are visited row by row, so the
+  // inner loop runs over one contiguous cost row with one source potential.
   int64_t find_entering(Cost eps) {
     const int64_t A = (int64_t)n * m;
-    int64_t block = std::max<int64_t>(64, (int64_t)std::sqrt((double)A));
-    Cost best = -eps;
-    int64_t best_arc = -1, cnt = 0;
-    int64_t e = next_arc;
-    for (int64_t scanned = 0; scanned < A; ++scanned) {
-      int k = (int)(e / m), l = (int)(e % m);
-      Cost rc = c[e] + pi[k] - pi[n + l];
-      if (rc < best) { best = rc; best_arc = e; }
-      if (++cnt == block) {
-        if (best_arc >= 0) { next_arc = e + 1 == A ? 0 : e + 1; return best_arc; }
-        cnt = 0;
+    const int64_t block = std::max<int64_t>(64, (int64_t)std::sqrt((double)A));
+    const Cost* pl = pi.data() + n;
+    int k = (int)(next_arc / m), l = (int)(next_arc % m);
+    for (int64_t scanned = 0; scanned < A;) {
+      const int64_t len = std::min(block, A - scanned);
+      Cost best = -eps;
+      int bk = -1, bl = -1;
+      for (int64_t left = len; left > 0;) {
+        const int seg = (int)std::min<int64_t>(left, m - l);
+        const Cost* cr = c + (int64_t)k * m;
+        const Cost pk = pi[k];
+        const Cost smin = row_min(cr + l, pk, pl + l, seg);
+        if (smin < best) {
+          int j = l;
+          while (cr[j] + pk - pl[j] != smin) ++j;   // first arc attaining it
+          best = smin; bk = k; bl = j;
+        }
+        left -= seg;
+        l += seg;
+        if (l == m) { l = 0; if (++k == n) k = 0; }
       }
-      if (++e == A) e = 0;
+      scanned += len;
+      if (bk >= 0) {
+        next_arc = (int64_t)k * m + l;
+        return (int64_t)bk * m + bl;
+      }
     }
-    if (best_arc >= 0) next_arc = best_arc + 1 == A ? 0 : best_arc + 1;
-    return best_arc;
+    return -1;
   }
 
   bool up(int v) const { return edges[pred[v]].a == v; }  // pred edge points v -> parent
 
   void pivot(int64_t in_arc) {
     const int first = (int)(in_arc / m), second = n + (int)(in_arc % m);
-    // join node of the cycle
+    // join node of the cycle: climb from the endpoint with the smaller
+    // subtree (an ancestor always has the larger one)
     int u = first, v = second;
     while (u != v) {
-      if (depth[u] > depth[v]) u = parent[u];
-      else if (depth[v] > depth[u]) v = parent[v];
-      else { u = parent[u]; v = parent[v]; }
+      if (size[u] < size[v]) u = parent[u];
+      else v = parent[v];
     }
     const int join = u;
     // leaving edge: the cycle runs first -> second -> ... -> join -> ... -> first
@@ -148,42 +189,64 @@ struct TransportSimplex {
       for (int x = second; x != join; x = parent[x])
         edges[pred[x]].flow += up(x) ? delta : -delta;
     }
-    // replace the leaving edge by the entering arc
-    const int eid = pred[out];
-    const int pout = parent[out];
-    auto& ao = adj[out];
-    ao.erase(std::find(ao.begin(), ao.end(), eid));
-    auto& ap = adj[pout];
-    ap.erase(std::find(ap.begin(), ap.end(), eid));
-    // subtree S hanging below `out` contains `first` or `second`
+    // The subtree S below `out` is cut off and re-hung, rooted at the
+    // entering arc's endpoint inside it, below the other endpoint.
     const int u_in = out_first ? first : second;   // endpoint inside S
     const int v_in = out_first ? second : first;   // endpoint outside S
+    const int eid = pred[out];
+    const int pout = parent[out];
+    const int nS = size[out];
+    // path u_in = w_0, w_1, ..., w_k = out
+    path.clear();
+    for (int x = u_in; ; x = parent[x]) { path.push_back(x); if (x == out) break; }
+    // S in its new preorder: the subtree of w_0, then for each i >= 1 the
+    // run of w_i's subtree with the run of w_{i-1}'s subtree taken out
+    seq.clear();
+    for (int x = u_in; ; x = thread[x]) { seq.push_back(x); if (x == last[u_in]) break; }
+    for (size_t i = 1; i < path.size(); ++i) {
+      const int w = path[i], wc = path[i - 1];
+      for (int x = w; x != wc; x = thread[x]) seq.push_back(x);
+      if (last[wc] != last[w])
+        for (int x = thread[last[wc]]; ; x = thread[x]) { seq.push_back(x); if (x == last[w]) break; }
+    }
+    const int lastS = seq.back();
+    // unlink S's old run from the preorder and fix the subtree ends above it
+    {
+      const int before = rthread[out], after = thread[last[out]];
+      thread[before] = after;
+      rthread[after] = before;
+      const int oldlast = last[out];
+      for (int a = pout; a >= 0 && last[a] == oldlast; a = parent[a]) last[a] = before;
+    }
+    for (int a = pout; a != join; a = parent[a]) size[a] -= nS;
+    // link S's new run right after v_in
+    {
+      const int after = thread[v_in];
+      int prev = v_in;
+      for (int x : seq) { thread[prev] = x; rthread[x] = prev; prev = x; }
+      thread[lastS] = after;
+      rthread[after] = lastS;
+      for (int a = v_in; a >= 0 && last[a] == v_in; a = parent[a]) last[a] = lastS;
+    }
+    for (int a = v_in; a != join; a = parent[a]) size[a] += nS;
+    // re-root S along the path (sizes and preds from the old values, top down)
+    for (size_t i = path.size() - 1; i >= 1; --i) {
+      const int w = path[i], wc = path[i - 1];
+      size[w] = nS - size[wc];
+      parent[w] = wc;
+      pred[w] = pred[wc];
+      last[w] = lastS;
+    }
+    size[u_in] = nS;
+    last[u_in] = lastS;
+    parent[u_in] = v_in;
+    pred[u_in] = eid;
     Edge& E = edges[eid];
     E.a = first; E.b = second; E.arc = in_arc; E.flow = delta;
-    adj[u_in].push_back(eid);
-    adj[v_in].push_back(eid);
     // potentials of S shift so that the entering arc has zero reduced cost
     const Cost rc = c[in_arc] + pi[first] - pi[second];
     const Cost sigma = out_first ? Cost(-rc) : rc;   // first in S: pi[first] -= rc
-    parent[u_in] = v_in;
-    pred[u_in] = eid;
-    depth[u_in] = depth[v_in] + 1;
-    pi[u_in] += sigma;
-    queue.clear();
-    queue.push_back(u_in);
-    for (size_t qi = 0; qi < queue.size(); ++qi) {
-      const int x = queue[qi];
-      for (int id : adj[x]) {
-        if (id == pred[x]) continue;
-        const Edge& ed = edges[id];
-        const int y = ed.a == x ? ed.b : ed.a;
-        parent[y] = x;
-        pred[y] = id;
-        depth[y] = depth[x] + 1;
-        pi[y] += sigma;
-        queue.push_back(y);
-      }
-    }
+    for (int x : seq) pi[x] += sigma;
     ++pivots;
   }
 
@@ -233,23 +296,12 @@ int solve_typed(int n, int m, const Cost* cost, const double* a, const double* b
   for (const auto& e : S.edges)
     if (e.arc < 0 && e.flow != 0) return QBW_E_LP;
   out->pivots = S.pivots;
-  // float64 flows from the tree: peel leaves in reverse BFS order from the root
+  // float64 flows from the tree: peel leaves in reverse preorder
   const int NN = n + m + 1;
   std::vector<int> order;
   order.reserve(NN);
-  order.push_back(S.root);
-  std::vector<int> par(NN, -1);
-  par[S.root] = S.root;
-  for (size_t qi = 0; qi < order.size(); ++qi) {
-    int x = order[qi];
-    for (int id : S.adj[x]) {
-      const auto& ed = S.edges[id];
-      int y = ed.a == x ? ed.b : ed.a;
-      if (par[y] >= 0) continue;
-      par[y] = x;
-      order.push_back(y);
-    }
-  }
+  for (int x = S.root; ; ) { order.push_back(x); x = S.thread[x]; if (x == S.root) break; }
+  if ((int)order.size() != NN) return QBW_E_LP;
   std::vector<double> ex(NN, 0.0);
   for (int i = 0; i < n; ++i) ex[i] = a[i];
   for (int j = 0; j < m; ++j) ex[n + j] = -b[j];
@@ -259,7 +311,7 @@ int solve_typed(int n, int m, const Cost* cost, const double* a, const double* b
     int id = S.pred[x];
     const auto& ed = S.edges[id];
     fl[id] = (ed.a == x) ? ex[x] : -ex[x];
-    ex[par[x]] += ex[x];
+    ex[S.parent[x]] += ex[x];
   }
   out->rows.clear(); out->cols.clear(); out->vals.clear();
   for (size_t id = 0; id < S.edges.size(); ++id) {
