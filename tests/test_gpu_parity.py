@@ -464,3 +464,59 @@ def test_batch_separable_mixed_p():
         for key in ("lower", "upper", "lower_S", "feas_shift", "upper_cost"):
             assert s[key] == o[key], key
         assert torch.allclose(ga, sa, rtol=1e-12, atol=0)
+
+
+# ------------------------------------------------------------------ degenerate and extreme cases
+
+def test_degenerate_grids_and_measures():
+    # k = N: one coarse block (the coarse problem is trivial)
+    N, d = 16, 2
+    mu, nu = pair(N, d, "gmm", "grf", 10000)
+    out = qbw.bounds(dev(mu), dev(nu), N, 2)
+    W = lp.wasserstein_exact(mu, nu, 2)
+    assert out["lower"] <= W <= out["upper"]
+    # k = 1: the coarse problem is the fine one: the lower bound is W up to the shift
+    N = 8
+    mu, nu = pair(N, d, "gmm", "cauchy", 10002)
+    out = qbw.bounds(dev(mu), dev(nu), 1, 2)
+    W = lp.wasserstein_exact(mu, nu, 2)
+    assert out["lower"] <= W <= out["upper"]
+    assert out["lower"] == pytest.approx(W, rel=1e-4)
+    assert out["upper"] == pytest.approx(W, rel=1e-4)
+    # identical measures: the lower bound clips to 0; the coarse plan is the
+    # identity, so the upscaled plan moves mass only inside blocks (each move
+    # at most sqrt(d) (k - 1)), and it matches the oracle's upper bound
+    m = si.grf(32, 2, si.rng(10004))
+    out = qbw.bounds(dev(m), dev(m), 4, 2)
+    assert out["lower"] == 0.0 and out["warn"] & qbw.QBW_WARN_LB_CLIPPED
+    assert 0.0 < out["upper"] <= math.sqrt(2) * 3
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(m, m, 4, 2)
+    assert abs(obj) <= 1e-12
+    U = upper.upper_bound_o64(m, m, r, c, v, 4, 2)
+    assert U["upper"] <= out["upper"] <= U["upper"] + ub_tol(m, m, 32, 2, 2, U["upper"])
+    # Dirac pair: most blocks empty; W = |x - y|
+    for p in (1, 2):
+        a, b, x, y = si.dirac_pair(32, 2, si.rng(10006 + p))
+        out = qbw.bounds(dev(a), dev(b), 4, p)
+        W = float(np.linalg.norm(x - y))
+        assert out["lower"] <= W * (1 + 1e-12) and W <= out["upper"] * (1 + 1e-12)
+    # 3D with k = N and with k = 1
+    mu, nu = pair(8, 3, "grf", "gmm", 10010)
+    for k in (8, 1):
+        out = qbw.bounds(dev(mu), dev(nu), k, 1)
+        W = lp.wasserstein_exact(mu, nu, 1)
+        assert out["lower"] <= W <= out["upper"]
+
+
+def test_large_grid_runs():
+    # 1024 x 1024 (P = 2^20): the all-pairs transform is 1.1e12 pairs per launch
+    N, d, k, p = 1024, 2, 64, 2
+    mu, nu = si.translated_pair(N, d, (40, -25), si.rng(10020))
+    out = qbw.bounds(dev(mu), dev(nu), k, p, separable=True)
+    W = math.sqrt(40 ** 2 + 25 ** 2)
+    assert out["lower"] <= W <= out["upper"]
+    phi = (si.rng(10021).standard_normal(N * N) * 1e4).astype(np.float32)
+    g = qbw.ctransform(dev(phi), N, d, p)
+    tg = si.rng(10022).choice(N * N, 8, replace=False)
+    ref, _ = lower.ctransform_o32(phi, N, d, p, targets=tg)
+    assert np.array_equal(g.cpu().numpy()[tg], ref)
