@@ -39,11 +39,13 @@ class Context:
         check(lib.qbw_create(C.byref(h), int(device)), "qbw_create")
         self.handle = h
         self.device = int(device)
+        self._lib = lib   # held for __del__: module globals may be gone at exit
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            _lib.load().qbw_destroy(h)
+        lib = getattr(self, "_lib", None)
+        if h is not None and h.value and lib is not None:
+            lib.qbw_destroy(h)
             self.handle = None
 
 
@@ -399,6 +401,7 @@ class Batch:
         check(lib.qbw_batch_create(self.ctx.handle, arr, len(jobs), cs, C.byref(opts), flags, C.byref(h),
                                    _stream()), "qbw_batch_create")
         self.handle = h
+        self._lib = lib   # held for __del__: module globals may be gone at exit
         self._jobs = arr
 
     def run(self, dlower=None, dupper=None):
@@ -435,6 +438,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            _lib.load().qbw_batch_destroy(h)
+        lib = getattr(self, "_lib", None)
+        if h is not None and h.value and lib is not None:
+            lib.qbw_batch_destroy(h)
             self.handle = None

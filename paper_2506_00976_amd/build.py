@@ -22,6 +22,9 @@ ARCH = "gfx950"
 # Packed FP32 instructions are kept out of the device code on purpose.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # the R = 32 c-transform tile is one fully unrolled block of ~1.7k
+             # instructions; let the unroller go that far where asked to
+             "-mllvm", "-pragma-unroll-threshold=200000",
              "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-D__HIP_PLATFORM_AMD__",
              "-I", os.path.join(ROCM, "include"), "-I", os.path.join(ROOT, "include"), "-Wall"]

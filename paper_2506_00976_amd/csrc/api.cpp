@@ -137,7 +137,7 @@ struct Layout {
 struct Tiling { int R, S; };
 
 static int default_R(int N) {
-  for (int r : {16, 8, 4, 2})
+  for (int r : {32, 16, 8, 4, 2})
     if (N % r == 0) return r;
   return 1;
 }
@@ -779,7 +779,10 @@ qbw_status qbw_create(qbw_ctx** ctx, int32_t device) {
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
     c->num_cu = cu;
-  c->target_waves = c->num_cu * 16;
+  // one full round of resident c-transform waves: equal-sized work items then
+  // finish together instead of leaving a partly filled last round
+  const int occ = qbw::ctransform_waves_per_cu();
+  c->target_waves = c->num_cu * (occ > 0 ? occ : 16);
   *ctx = c;
   return QBW_OK;
 }
@@ -1278,7 +1281,7 @@ qbw_status qbw_batch_create(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs, co
     // source splits aim for; every candidate times the whole batch's c-transform
     double best_t = 1e30;
     int best_R = 0, best_w = ctx->target_waves;
-    for (int R : {16, 8, 4}) {
+    for (int R : {32, 16, 8}) {
       for (int waves : {ctx->num_cu * 4, ctx->num_cu * 8, ctx->num_cu * 16, ctx->num_cu * 32}) {
         std::vector<JobIn> cand = in;
         for (auto& J : cand) J.tiling = {(J.g.N % R == 0) ? R : default_R(J.g.N), 0};

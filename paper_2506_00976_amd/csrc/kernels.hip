@@ -203,11 +203,16 @@ __global__ __launch_bounds__(256) void k_upscale(const DevJob* __restrict__ jobs
 // c(A, t + 1 - v0) is new (an exact integer update for p = 2, plus one
 // correctly rounded square root for p = 1).  With the window held in R
 // registers whose roles rotate through a fully unrolled block of R steps,
-// each (source, target) pair costs one subtraction plus half of a v_min3.
+// each (source, target) pair costs one subtraction plus half of a v_min3:
+// the block runs over pairs of sources, and for every target the two
+// candidates and the running minimum meet in one v_min3 (so only two
+// candidates are live at a time and R = 32 fits in 128 VGPRs).
 // The source potential is wave-uniform and comes through scalar loads.
 // Source potentials are read through the constant address space: the data
 // is not written during the launch and every lane reads the same address, so
 // the loads become scalar (s_load) and the values feed the VALU as SGPRs.
+// The next block's potentials are requested before the current block's
+// arithmetic, so the scalar-load latency hides behind it.
 typedef const __attribute__((address_space(4))) float* const_fptr;
 
 template <int R, int PP>
@@ -224,61 +229,114 @@ __device__ __forceinline__ void ct_tile(const float* __restrict__ src, float* __
   float mn[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) mn[q] = INFINITY;
+  const float sq0 = (float)(v0 * v0);
+  const float inc0 = (float)(2 * v0 + 1);
+  const_fptr cbase = (const_fptr)src;
+  const size_t end = (size_t)r1 * N;
+  float nxt[R];
+  if (r0 < r1) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) nxt[m] = cbase[(size_t)r0 * N + m];
+  }
 
   for (int sr = r0; sr < r1; ++sr) {
     int sa, sb;
     if (d == 2) { sa = 0; sb = sr; } else { sa = sr / N; sb = sr - sa * N; }
     const int da = sa - ta, db = sb - tb;
     const float A = (float)(da * da + db * db);
+    // W[q] = A + (v0 + q)^2 by exact increments 2 (v0 + q) - 1.  The chain
+    // starts from a copy the compiler cannot see through, so it is rebuilt
+    // per source row instead of R row-invariant squares being kept live (and
+    // spilled) across the whole sweep.
+    float inc = inc0;
+    __asm__ volatile("" : "+v"(inc));
     float W[R];
-    float n0 = 0.0f;
+    float nk = A + sq0;
+    const float n0_row = nk;
+    W[0] = (PP == 2) ? nk : sqrt_rn_int(nk);
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int e = v0 + q;
-      const float nk = A + (float)(e * e);
+    for (int q = 1; q < R; ++q) {
+      nk = nk + inc;
+      inc = inc + 2.0f;
       W[q] = (PP == 2) ? nk : sqrt_rn_int(nk);
-      if (q == 0) n0 = nk;
     }
+    float n0 = n0_row;
     float D = (float)(1 - 2 * v0);
-    const_fptr ph = (const_fptr)(src + (size_t)sr * N);
     for (int b = 0; b < N; b += R) {
-      float phv[R];
+      float cur[R];
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        phv[m] = ph[b + m];
-        // one v_mov to a VGPR per source: on gfx950 a VALU op with an SGPR
-        // operand issues at about half the rate of the all-VGPR form
-        __asm__("" : "+v"(phv[m]));
+      for (int m = 0; m < R; ++m) cur[m] = nxt[m];
+      // prefetch the next block of source potentials (the next row's first
+      // block at the end of a row; the current block again after the last)
+      {
+        const size_t cb = (size_t)sr * N + b;
+        const size_t nb = cb + R;
+        const_fptr np = cbase + (nb < end ? nb : cb);
+#pragma unroll
+        for (int m = 0; m < R; ++m) nxt[m] = np[m];
       }
-      float tmp[R];
+      // keep the prefetch ahead of the block's arithmetic
+      __builtin_amdgcn_sched_barrier(0);
+      if (R == 1) {
+        float p0 = cur[0];
+        __asm__("" : "+v"(p0));
+        mn[0] = fminf(mn[0], W[0] - p0);
+        if (PP == 2) { W[0] = W[0] + D; } else { n0 = n0 + D; W[0] = sqrt_rn_int(n0); }
+        D += 2.0f;
+      } else {
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
+        for (int m = 0; m < R; m += 2) {
+          // two sources per step pair; each is moved to a VGPR once (on
+          // gfx950 a VALU op with an SGPR operand issues at about half rate)
+          float p0 = cur[m], p1 = cur[m + 1];
+          __asm__("" : "+v"(p0));
+          __asm__("" : "+v"(p1));
+          // Target q = R-1 first: it is the last reader of the two window
+          // slots this pair of steps replaces, so their new values can take
+          // the same registers (no register rotation at the loop back-edge).
+          {
+            const float t0 = W[(R - 1 - m + R) % R] - p0;
+            const float t1 = W[(R - 2 - m + 2 * R) % R] - p1;
+            mn[R - 1] = fminf(mn[R - 1], fminf(t0, t1));
+            __asm__("" : "+v"(mn[R - 1]));
+          }
+          // slot (R-1-m) % R takes the cost of the source after m; target 0
+          // reads it for source m+1
+          if (PP == 2) {
+            W[(R - 1 - m + R) % R] = W[(R - m) % R] + D;
+          } else {
+            n0 = n0 + D;
+            W[(R - 1 - m + R) % R] = sqrt_rn_int(n0);
+          }
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const float t = W[(q - m + R) % R] - phv[m];
-          if (R == 1) {
-            mn[q] = fminf(mn[q], t);
-          } else if (m & 1) {
-            mn[q] = fminf(mn[q], fminf(tmp[q], t));
+          for (int q = 0; q < R - 1; ++q) {
+            const float t0 = W[(q - m + R) % R] - p0;
+            const float t1 = W[(q - m - 1 + 2 * R) % R] - p1;
+            mn[q] = fminf(mn[q], fminf(t0, t1));
             // keep the running minimum a chain of v_min3 (no re-association)
             __asm__("" : "+v"(mn[q]));
-          } else {
-            tmp[q] = t;
           }
+          if (PP == 2) {
+            W[(R - 2 - m + 2 * R) % R] = W[(R - 1 - m + R) % R] + (D + 2.0f);
+          } else {
+            n0 = n0 + (D + 2.0f);
+            W[(R - 2 - m + 2 * R) % R] = sqrt_rn_int(n0);
+          }
+          D += 4.0f;
         }
-        if (PP == 2) {
-          W[(R - 1 - m + R) % R] = W[(R - m) % R] + D;
-        } else {
-          n0 = n0 + D;
-          W[(R - 1 - m + R) % R] = sqrt_rn_int(n0);
-        }
-        D += 2.0f;
       }
     }
   }
   if (valid) {
+    if constexpr (R % 4 == 0) {
+      // 16-byte stores: j0 and the split's row start are multiples of 4 floats
+      float4* o4 = reinterpret_cast<float4*>(out + j0);
 #pragma unroll
-    for (int q = 0; q < R; ++q) out[j0 + q] = mn[q];
+      for (int q = 0; q < R; q += 4) o4[q / 4] = make_float4(mn[q], mn[q + 1], mn[q + 2], mn[q + 3]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) out[j0 + q] = mn[q];
+    }
   }
 }
 
@@ -293,6 +351,9 @@ __device__ __forceinline__ int xcc_id() {
 // XCD's queue first and then steals from the others, so every wave exits once
 // all queues are empty.  counters[q] is queue q's next item; items of queue q
 // are items[qoff[q] .. qoff[q+1]).
+// Four waves per SIMD: the R = 32 tile holds 32 running minima, a 32-entry
+// cost window and the step pair's temporaries in at most 128 VGPRs.
+__attribute__((amdgpu_waves_per_eu(4)))
 __global__ __launch_bounds__(64) void k_ctransform(const DevJob* __restrict__ jobs,
                                                    const CtItem* __restrict__ items,
                                                    const int* __restrict__ qoff, int nq,
@@ -315,6 +376,8 @@ __global__ __launch_bounds__(64) void k_ctransform(const DevJob* __restrict__ jo
       const int r1 = (int)(((long long)(w.split + 1) * J.rows) / J.S);
       const int key = J.R * 4 + J.p;
       switch (key) {
+        case 32 * 4 + 2: ct_tile<32, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+        case 32 * 4 + 1: ct_tile<32, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
         case 16 * 4 + 2: ct_tile<16, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
         case 16 * 4 + 1: ct_tile<16, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
         case 8 * 4 + 2: ct_tile<8, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
@@ -1151,6 +1214,11 @@ int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, voi
   hipLaunchKernelGGL(k_upscale, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
+}
+int ctransform_waves_per_cu() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_ctransform, 64, 0) != hipSuccess) return 0;
+  return blocks;   // one wave per work-group
 }
 int launch_reset_counter(int* counter, int n, void* stream) {
   hipLaunchKernelGGL(k_reset_counter, dim3((n + 63) / 64), dim3(64), 0, (hipStream_t)stream, counter, n);

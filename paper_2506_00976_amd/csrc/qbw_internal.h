@@ -116,6 +116,8 @@ struct Launch {
 int launch_pool(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 constexpr int kQueues = 8;  // one c-transform work queue per XCD
+// Waves of k_ctransform resident per compute unit (0 if the runtime cannot say).
+int ctransform_waves_per_cu();
 int launch_ctransform(const DevJob* jobs, const CtItem* items, const int* qoff, int nq, int* counters,
                       int phase, int grid, void* stream);
 int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
