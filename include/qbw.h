@@ -115,9 +115,12 @@ typedef void* qbw_stream; /* hipStream_t */
 /* ---- context ----------------------------------------------------------- */
 
 /* Create a context bound to HIP device `device` (workspaces grow on demand).
- * Errors: QBW_E_HIP if the device cannot be set, QBW_E_NOMEM. */
+ * A context is used by one thread at a time; saved records (below) may be
+ * freed from any thread.  Errors: QBW_E_HIP if the device cannot be set,
+ * QBW_E_NOMEM. */
 qbw_status qbw_create(qbw_ctx** ctx, int32_t device);
-/* Free a context and its workspaces (NULL is a no-op). */
+/* Free a context and its workspaces (NULL is a no-op).  Saved records still
+ * alive are detached and stay valid until qbw_saved_free. */
 void qbw_destroy(qbw_ctx* ctx);
 /* Thread-local message of the last failure (never NULL). */
 const char* qbw_last_error(void);
@@ -157,6 +160,8 @@ qbw_status qbw_bounds_with_coarse(qbw_ctx* ctx, const qbw_grid* grid, const doub
 qbw_status qbw_bounds_backward(qbw_ctx* ctx, const qbw_saved* saved, double dlower, double dupper,
                                double* grad_a, double* grad_b, double* grad_fhat,
                                qbw_stream stream);
+/* Free a saved record (NULL is a no-op).  Its device memory goes back to the
+ * context that made it, if that context still exists, for the next record. */
 void qbw_saved_free(qbw_saved* saved);
 
 /* ---- stages (each follows one step of the method) ---------------------- */

@@ -154,10 +154,11 @@ def bounds(a, b, k: int, p: int, coarse: Coarse | None = None, xi: float = 1e-12
 class _Saved:
     def __init__(self, handle):
         self.handle = handle
+        self._lib = load()   # held for __del__: module globals may be gone at exit
 
     def __del__(self):
         if self.handle is not None and self.handle.value:
-            _lib.load().qbw_saved_free(self.handle)
+            self._lib.qbw_saved_free(self.handle)
             self.handle = None
 
 

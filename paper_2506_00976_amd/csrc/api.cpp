@@ -18,6 +18,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <numeric>
 #include <sstream>
 #include <string>
@@ -103,6 +104,18 @@ void centre_cost(const qbw_grid& g, double* out) {
 struct Arena {
   char* base = nullptr;
   size_t cap = 0;
+  Arena() = default;
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  Arena(Arena&& o) noexcept : base(o.base), cap(o.cap) { o.base = nullptr; o.cap = 0; }
+  Arena& operator=(Arena&& o) noexcept {
+    if (this != &o) {
+      if (base) (void)hipFree(base);
+      base = o.base; cap = o.cap;
+      o.base = nullptr; o.cap = 0;
+    }
+    return *this;
+  }
   ~Arena() { if (base) (void)hipFree(base); }
   int reserve(size_t bytes) {
     if (bytes <= cap) return QBW_OK;
@@ -152,6 +165,20 @@ struct qbw_ctx {
   qbw::Arena work;      // scratch for single-pair calls that keep nothing
   std::map<std::tuple<int, int, int>, qbw::Tiling> tuned;  // (d, N, p) -> tiling
   int target_waves = 4096;
+  // pinned staging for the planner's one host-to-device copy; `staged` marks
+  // a copy in flight (completion recorded in `staged_ev`)
+  char* stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t staged_ev = nullptr;
+  bool staged = false;
+  // Device arenas of freed saved-for-backward records, reused by the next
+  // ones (a forward + backward per call would otherwise allocate and free
+  // each time), and the live records, detached when the context goes first.
+  // Saved records may be freed from another thread: both lists take `mu`.
+  std::mutex mu;
+  std::vector<qbw::Arena> spare;
+  std::set<qbw_saved*> live;
+  ~qbw_ctx();
 };
 
 namespace qbw {
@@ -315,7 +342,6 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     Offs& O = offs[j];
     O.mu_t = L.add(8 * Q);
     O.nu_t = L.add(8 * Q);
-    O.ftil = L.add(8 * Q);
     O.fhat = L.add(4 * (size_t)P);
     O.g = L.add(4 * (size_t)P);
     O.f = L.add(4 * (size_t)P);
@@ -323,12 +349,6 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     O.win = L.add(4 * (size_t)P);
     O.arg_g = (mode & PM_ARGMIN) ? L.add(4 * (size_t)P) : 0;
     O.arg_f = (mode & PM_ARGMIN) ? L.add(4 * (size_t)P) : 0;
-    O.e_row = L.add(4 * (size_t)nnz);
-    O.e_col = L.add(4 * (size_t)nnz);
-    O.e_val = L.add(8 * (size_t)nnz);
-    O.csr = L.add(4 * (size_t)(Q + 1));
-    O.csc = L.add(4 * (size_t)(Q + 1));
-    O.csc_idx = L.add(4 * (size_t)nnz);
     O.ipf_u = L.add(8 * (size_t)Q * (o.max_ipf_iter + 2));
     O.ipf_v = L.add(8 * (size_t)Q * (o.max_ipf_iter + 2));
     O.a_s = ub ? L.add(8 * (size_t)P) : 0;
@@ -347,17 +367,18 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     O.sep_tmp = sep ? L.add(4 * 2 * (size_t)P) : 0;
     O.sep_arg = (sep && (mode & PM_ARGMIN)) ? L.add(4 * (size_t)d * P) : 0;
   }
-  const size_t o_jobs = L.add(sizeof(DevJob) * NJ);
   constexpr int kTables = 9;
-  const size_t o_offs = L.add(sizeof(int) * kTables * (NJ + 1));
   // c-transform work items, one queue per XCD.  Jobs get a home queue by
   // longest-processing-time assignment of their pair counts; a lone job (or one
   // too big for a single queue's share) spreads its target tiles over all queues.
-  auto item_cost = [&](const CtItem& w) {
-    const auto& J = pl.in[w.job];
+  // modelled cost of one item of each job (all of a job's items are alike)
+  std::vector<double> job_item_cost(NJ);
+  for (int j = 0; j < NJ; ++j) {
+    const auto& J = pl.in[j];
     const double rows = std::pow((double)J.g.N, J.g.d - 1);
-    return 64.0 * J.tiling.R * (rows / J.tiling.S) * J.g.N * (J.g.p == 1 ? 1.4 : 1.0);
-  };
+    job_item_cost[j] = 64.0 * J.tiling.R * (rows / J.tiling.S) * J.g.N * (J.g.p == 1 ? 1.4 : 1.0);
+  }
+  auto item_cost = [&](const CtItem& w) { return job_item_cost[w.job]; };
   std::vector<std::vector<CtItem>> queues(kQueues);
   {
     std::vector<double> load(kQueues, 0.0);
@@ -392,17 +413,36 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     qoff[q + 1] = (int)items.size();
   }
   pl.n_items = (int)items.size();
-  const size_t o_items = L.add(sizeof(CtItem) * std::max(1, pl.n_items));
-  const size_t o_qoff = L.add(sizeof(int) * (kQueues + 1));
   pl.n_ints = 2 * kQueues + NJ;
   const size_t o_ints = L.add(sizeof(int) * pl.n_ints);
-  const size_t o_dl = L.add(8 * NJ), o_du = L.add(8 * NJ);
   const size_t o_res = L.add(8 * (size_t)RS_COUNT * NJ);
   size_t maxQ = 1;
   for (auto& J : pl.in) maxQ = std::max<size_t>(maxQ, ipow(J.g.N / J.g.k, J.g.d));
   const size_t o_bwd = L.add(8 * 4 * maxQ * NJ);
   pl.max_q = (int)maxQ;
+  // Everything the host supplies sits in one contiguous region [u0, u1),
+  // filled in pinned staging memory and copied with a single transfer.
+  const size_t u0 = L.add(0);
+  const size_t o_jobs = L.add(sizeof(DevJob) * NJ);
+  const size_t o_offs = L.add(sizeof(int) * kTables * (NJ + 1));
+  const size_t o_items = L.add(sizeof(CtItem) * std::max(1, pl.n_items));
+  const size_t o_qoff = L.add(sizeof(int) * (kQueues + 1));
+  const size_t o_dl = L.add(8 * NJ), o_du = L.add(8 * NJ);
   const size_t o_ptrs = L.add(sizeof(double*) * 4 * NJ);
+  for (int j = 0; j < NJ; ++j) {
+    const auto& J = pl.in[j];
+    const int Q = ipow(J.g.N / J.g.k, J.g.d);
+    const int nnz = J.coarse ? J.coarse->nnz : 1;
+    Offs& O = offs[j];
+    O.ftil = L.add(8 * (size_t)Q);
+    O.e_row = L.add(4 * (size_t)nnz);
+    O.e_col = L.add(4 * (size_t)nnz);
+    O.e_val = L.add(8 * (size_t)nnz);
+    O.csr = L.add(4 * (size_t)(Q + 1));
+    O.csc = L.add(4 * (size_t)(Q + 1));
+    O.csc_idx = L.add(4 * (size_t)nnz);
+  }
+  const size_t u1 = L.size;
 
   if (own_memory) {
     CHK(pl.own.reserve(L.size));
@@ -516,31 +556,56 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   // persistent grid: enough waves to fill the chip, never more than the items
   pl.ct_grid = std::max(1, std::min(pl.n_items, ctx->num_cu * 4 * 8));
 
-  // uploads
-  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob) * NJ, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(offd, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, st));
-  if (pl.n_items)
-    HIPCHK(hipMemcpyAsync(pl.items, items.data(), sizeof(CtItem) * items.size(), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(pl.qoff, qoff.data(), sizeof(int) * qoff.size(), hipMemcpyHostToDevice, st));
-  std::vector<double*> hp(4 * NJ, nullptr);
-  HIPCHK(hipMemcpyAsync(ptrs, hp.data(), sizeof(double*) * hp.size(), hipMemcpyHostToDevice, st));
-  std::vector<double> ones(NJ, 1.0);
-  HIPCHK(hipMemcpyAsync(pl.dl, ones.data(), 8 * NJ, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(pl.du, ones.data(), 8 * NJ, hipMemcpyHostToDevice, st));
+  // uploads: the previous staged copy must have landed before the staging
+  // memory is rewritten
+  if (ctx->staged) {
+    HIPCHK(hipEventSynchronize(ctx->staged_ev));
+    ctx->staged = false;
+  }
+  const size_t ubytes = u1 - u0;
+  if (ubytes > ctx->stage_cap) {
+    if (ctx->stage) HIPCHK(hipHostFree(ctx->stage));
+    ctx->stage = nullptr;
+    ctx->stage_cap = 0;
+    const size_t want = std::max(ubytes, (size_t)1 << 20);
+    if (hipHostMalloc((void**)&ctx->stage, want, hipHostMallocDefault) != hipSuccess) {
+      ctx->stage = nullptr;
+      set_error("pinned host allocation of %zu bytes failed", want);
+      return QBW_E_NOMEM;
+    }
+    ctx->stage_cap = want;
+  }
+  if (!ctx->staged_ev) HIPCHK(hipEventCreateWithFlags(&ctx->staged_ev, hipEventDisableTiming));
+  // host image of the region: at(off) mirrors B + off
+  auto at = [&](size_t off) { return ctx->stage + (off - u0); };
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(at(off), src, bytes);
+  };
+  put(o_jobs, pl.hj.data(), sizeof(DevJob) * NJ);
+  put(o_offs, off.data(), sizeof(int) * off.size());
+  put(o_items, items.data(), sizeof(CtItem) * items.size());
+  put(o_qoff, qoff.data(), sizeof(int) * qoff.size());
+  std::memset(at(o_ptrs), 0, sizeof(double*) * 4 * NJ);
+  {
+    const std::vector<double> ones(NJ, 1.0);
+    put(o_dl, ones.data(), 8 * (size_t)NJ);
+    put(o_du, ones.data(), 8 * (size_t)NJ);
+  }
   for (int j = 0; j < NJ; ++j) {
     const CoarseHost* C = pl.in[j].coarse;
     if (!C) continue;
     const Offs& O = offs[j];
-    HIPCHK(hipMemcpyAsync(B + O.ftil, C->f.data(), 8 * C->Q, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(B + O.e_row, C->rows.data(), 4 * C->nnz, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(B + O.e_col, C->cols.data(), 4 * C->nnz, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(B + O.e_val, C->vals.data(), 8 * C->nnz, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(B + O.csr, C->csr_ptr.data(), 4 * (C->Q + 1), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(B + O.csc, C->csc_ptr.data(), 4 * (C->Q + 1), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(B + O.csc_idx, C->csc_idx.data(), 4 * C->nnz, hipMemcpyHostToDevice, st));
+    put(O.ftil, C->f.data(), 8 * (size_t)C->Q);
+    put(O.e_row, C->rows.data(), 4 * (size_t)C->nnz);
+    put(O.e_col, C->cols.data(), 4 * (size_t)C->nnz);
+    put(O.e_val, C->vals.data(), 8 * (size_t)C->nnz);
+    put(O.csr, C->csr_ptr.data(), 4 * (size_t)(C->Q + 1));
+    put(O.csc, C->csc_ptr.data(), 4 * (size_t)(C->Q + 1));
+    put(O.csc_idx, C->csc_idx.data(), 4 * (size_t)C->nnz);
   }
-  // the uploads read pageable host vectors that go out of scope: finish them
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpyAsync(B + u0, ctx->stage, ubytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(ctx->staged_ev, st));
+  ctx->staged = true;
   return QBW_OK;
 }
 
@@ -740,7 +805,18 @@ using namespace qbw;
 struct qbw_saved {
   Plan plan;
   std::vector<CoarseHost> coarse;
+  qbw_ctx* ctx = nullptr;   // where the arena goes back to; null once detached
 };
+
+qbw_ctx::~qbw_ctx() {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (qbw_saved* sv : live) sv->ctx = nullptr;
+    live.clear();
+  }
+  if (staged_ev) { (void)hipEventSynchronize(staged_ev); (void)hipEventDestroy(staged_ev); }
+  if (stage) (void)hipHostFree(stage);
+}
 
 struct qbw_batch {
   qbw_ctx* ctx = nullptr;
@@ -808,12 +884,21 @@ static qbw_status bounds_impl(qbw_ctx* ctx, const qbw_grid* grid, const double* 
   if (save) {
     auto* sv = new (std::nothrow) qbw_saved();
     if (!sv) { set_error("out of host memory"); return QBW_E_NOMEM; }
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      if (!ctx->spare.empty()) {
+        sv->plan.own = std::move(ctx->spare.back());
+        ctx->spare.pop_back();
+      }
+      ctx->live.insert(sv);
+      sv->ctx = ctx;
+    }
     sv->coarse = std::move(*keep);
     J.coarse = &sv->coarse[0];
     int rc = plan_build(ctx, sv->plan, {J}, mode | PM_BACKWARD, o, true, st);
     if (rc == QBW_OK) rc = enqueue_forward(sv->plan, st);
     if (rc == QBW_OK) rc = fetch_results(sv->plan, st);
-    if (rc != QBW_OK) { delete sv; return (qbw_status)rc; }
+    if (rc != QBW_OK) { qbw_saved_free(sv); return (qbw_status)rc; }
     to_result(sv->plan.host_results.data(), out);
     *saved = sv;
     return QBW_OK;
@@ -875,7 +960,17 @@ qbw_status qbw_bounds_backward(qbw_ctx* ctx, const qbw_saved* saved, double dlow
   return QBW_OK;
 }
 
-void qbw_saved_free(qbw_saved* saved) { delete saved; }
+void qbw_saved_free(qbw_saved* saved) {
+  if (!saved) return;
+  if (qbw_ctx* ctx = saved->ctx) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->live.erase(saved);
+    // keep a few arenas for reuse; the plan's work on them has finished (every
+    // entry point that uses a saved record synchronizes before returning)
+    if (saved->plan.own.base && ctx->spare.size() < 4) ctx->spare.push_back(std::move(saved->plan.own));
+  }
+  delete saved;
+}
 
 // ---------------------------------------------------------------- stages
 
@@ -1215,7 +1310,7 @@ qbw_status qbw_autotune_ctransform(qbw_ctx* ctx, const qbw_grid* grid, int32_t* 
   const int P = ipow(N, d), rows = ipow(N, d - 1);
   Tiling best{default_R(N), 1};
   double best_t = 1e30;
-  for (int R : {16, 8, 4}) {
+  for (int R : {32, 16, 8, 4}) {
     if (N % R) continue;
     const int tiles = (P + 64 * R - 1) / (64 * R);
     for (int waves : {ctx->num_cu * 4, ctx->num_cu * 8, ctx->num_cu * 16, ctx->num_cu * 32}) {

@@ -347,10 +347,41 @@ __device__ __forceinline__ int xcc_id() {
 
 // Persistent c-transform: one work queue per XCD.  The planner gives every job
 // (or, for a single job, every target tile) a home XCD so the source
-// potentials a queue touches stay in that XCD's L2; a wave drains its own
-// XCD's queue first and then steals from the others, so every wave exits once
-// all queues are empty.  counters[q] is queue q's next item; items of queue q
-// are items[qoff[q] .. qoff[q+1]).
+// potentials a queue touches stay in that XCD's L2.
+//
+// Round one is static: work-group b takes item b / nq of queue b % nq (the
+// dispatcher deals work-groups to the XCDs in turn, so that is normally the
+// wave's own XCD's queue).  No atomics are needed for it, which matters: the
+// counters are shared by all XCDs, so every read-modify-write on them goes to
+// the memory side and thousands of them at a launch's start and end serialize.
+// Later rounds are dynamic: counters[q] counts items taken from queue q past
+// the static ones; a wave drains its own XCD's queue first and then steals, and
+// reads a counter before incrementing it so that exhausted queues cost no
+// atomics.  Every wave exits once all queues are empty.  Items of queue q are
+// items[qoff[q] .. qoff[q+1]).
+__device__ __forceinline__ void ct_item(const DevJob* __restrict__ jobs, const CtItem& w, int phase) {
+  const DevJob& J = jobs[w.job];
+  const float* src = phase == 0 ? J.fhat : J.g;
+  float* out = J.part + (size_t)w.split * J.P;
+  const int r0 = (int)(((long long)w.split * J.rows) / J.S);
+  const int r1 = (int)(((long long)(w.split + 1) * J.rows) / J.S);
+  const int key = J.R * 4 + J.p;
+  switch (key) {
+    case 32 * 4 + 2: ct_tile<32, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    case 32 * 4 + 1: ct_tile<32, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    case 16 * 4 + 2: ct_tile<16, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    case 16 * 4 + 1: ct_tile<16, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    case 8 * 4 + 2: ct_tile<8, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    case 8 * 4 + 1: ct_tile<8, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    case 4 * 4 + 2: ct_tile<4, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    case 4 * 4 + 1: ct_tile<4, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    case 2 * 4 + 2: ct_tile<2, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    case 2 * 4 + 1: ct_tile<2, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    case 1 * 4 + 2: ct_tile<1, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+    default: ct_tile<1, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
+  }
+}
+
 // Four waves per SIMD: the R = 32 tile holds 32 running minima, a 32-entry
 // cost window and the step pair's temporaries in at most 128 VGPRs.
 __attribute__((amdgpu_waves_per_eu(4)))
@@ -358,37 +389,28 @@ __global__ __launch_bounds__(64) void k_ctransform(const DevJob* __restrict__ jo
                                                    const CtItem* __restrict__ items,
                                                    const int* __restrict__ qoff, int nq,
                                                    int* __restrict__ counters, int phase) {
+  const int G = gridDim.x;
+  {
+    const int q = blockIdx.x % nq, idx = blockIdx.x / nq;
+    const int q0 = qoff[q];
+    if (idx < qoff[q + 1] - q0) ct_item(jobs, items[q0 + idx], phase);
+  }
   const int home = xcc_id() % nq;
   for (int qq = 0; qq < nq; ++qq) {
     const int q = (home + qq) % nq;
     const int q0 = qoff[q], qn = qoff[q + 1] - q0;
+    const int taken = (G - q + nq - 1) / nq;   // work-groups b < G with b % nq == q
     for (;;) {
-      int it = 0;
-      if (threadIdx.x == 0) it = atomicAdd(counters + q, 1);
+      int it = qn;
+      if (threadIdx.x == 0) {
+        // counters only grow: a stale read can only lead to the atomic below
+        const int seen = __hip_atomic_load(counters + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (taken + seen < qn) it = taken + atomicAdd(counters + q, 1);
+      }
       it = __shfl(it, 0);
       it = __builtin_amdgcn_readfirstlane(it);
       if (it >= qn) break;
-      const CtItem w = items[q0 + it];
-      const DevJob& J = jobs[w.job];
-      const float* src = phase == 0 ? J.fhat : J.g;
-      float* out = J.part + (size_t)w.split * J.P;
-      const int r0 = (int)(((long long)w.split * J.rows) / J.S);
-      const int r1 = (int)(((long long)(w.split + 1) * J.rows) / J.S);
-      const int key = J.R * 4 + J.p;
-      switch (key) {
-        case 32 * 4 + 2: ct_tile<32, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        case 32 * 4 + 1: ct_tile<32, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        case 16 * 4 + 2: ct_tile<16, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        case 16 * 4 + 1: ct_tile<16, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        case 8 * 4 + 2: ct_tile<8, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        case 8 * 4 + 1: ct_tile<8, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        case 4 * 4 + 2: ct_tile<4, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        case 4 * 4 + 1: ct_tile<4, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        case 2 * 4 + 2: ct_tile<2, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        case 2 * 4 + 1: ct_tile<2, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        case 1 * 4 + 2: ct_tile<1, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-        default: ct_tile<1, 1>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
-      }
+      ct_item(jobs, items[q0 + it], phase);
     }
   }
 }
@@ -399,26 +421,36 @@ __global__ void k_reset_counter(int* counter, int n) {
 }
 
 // Minimum over source splits; the winning split is the lowest one attaining it.
+// One thread per target: blockIdx.y picks the quarter of the 1024-target chunk,
+// and four splits are read per step to keep several loads in flight.
 __global__ __launch_bounds__(256) void k_merge(const DevJob* __restrict__ jobs, int njobs,
                                                const int* __restrict__ off, int total, int phase) {
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
     if (J.sep) continue;
-    const int base = (it - off[jb]) * kChunk;
+    const int j = (it - off[jb]) * kChunk + blockIdx.y * 256 + threadIdx.x;
+    if (j >= J.P) continue;
     float* dst = phase == 0 ? J.g : J.f;
-    for (int q = threadIdx.x; q < kChunk; q += 256) {
-      const int j = base + q;
-      if (j >= J.P) break;
-      float best = INFINITY;
-      int win = 0;
-      for (int s = 0; s < J.S; ++s) {
-        const float v = J.part[(size_t)s * J.P + j];
-        if (v < best) { best = v; win = s; }
-      }
-      dst[j] = best;
-      J.win[j] = win;
+    const float* pp = J.part + j;
+    const size_t P = (size_t)J.P;
+    float best = INFINITY;
+    int win = 0;
+    int s = 0;
+    for (; s + 4 <= J.S; s += 4) {
+      const float v0 = pp[(size_t)s * P], v1 = pp[(size_t)(s + 1) * P];
+      const float v2 = pp[(size_t)(s + 2) * P], v3 = pp[(size_t)(s + 3) * P];
+      if (v0 < best) { best = v0; win = s; }
+      if (v1 < best) { best = v1; win = s + 1; }
+      if (v2 < best) { best = v2; win = s + 2; }
+      if (v3 < best) { best = v3; win = s + 3; }
     }
+    for (; s < J.S; ++s) {
+      const float v = pp[(size_t)s * P];
+      if (v < best) { best = v; win = s; }
+    }
+    dst[j] = best;
+    J.win[j] = win;
   }
 }
 
@@ -1233,7 +1265,8 @@ int launch_ctransform(const DevJob* jobs, const CtItem* items, const int* qoff, 
   return QBW_OK;
 }
 int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream) {
-  hipLaunchKernelGGL(k_merge, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, phase);
+  hipLaunchKernelGGL(k_merge, dim3(grid_for(total), kChunk / 256), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off,
+                     total, phase);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -520,3 +520,30 @@ def test_large_grid_runs():
     tg = si.rng(10022).choice(N * N, 8, replace=False)
     ref, _ = lower.ctransform_o32(phi, N, d, p, targets=tg)
     assert np.array_equal(g.cpu().numpy()[tg], ref)
+
+
+def test_saved_records_reuse_and_outlive_context():
+    # repeated forward+backward calls reuse freed device arenas: identical results
+    N, d, k, p = 32, 2, 4, 2
+    mu, nu = pair(N, d, "gmm", "grf", 10100)
+    a, b = dev(mu), dev(nu)
+    runs = [qbw.bounds_with_grads(a, b, k, p) for _ in range(3)]
+    for res, ga, gb, _ in runs[1:]:
+        assert res["lower"] == runs[0][0]["lower"] and res["upper"] == runs[0][0]["upper"]
+        assert torch.equal(ga, runs[0][1]) and torch.equal(gb, runs[0][2])
+    # a saved record may outlive its context: it is detached, then freed
+    import ctypes as C
+    from paper_2506_00976_amd import _lib
+    lib = _lib.load()
+    h = C.c_void_p()
+    assert lib.qbw_create(C.byref(h), 0) == 0
+    grid = _lib.QbwGrid(d, N, k, p)
+    opts = _lib.QbwOpts(1e-12, 50, _lib.QBW_SAVE_FOR_BWD)
+    res = _lib.QbwResult()
+    saved = C.c_void_p()
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert lib.qbw_bounds(h, C.byref(grid), C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                          C.byref(opts), C.byref(res), C.byref(saved), stream) == 0
+    assert res.lower == runs[0][0]["lower"]
+    lib.qbw_destroy(h)
+    lib.qbw_saved_free(saved)
