@@ -68,6 +68,11 @@ typedef struct qbw_grid {
 #define QBW_SEPARABLE 4u     /* p = 2: evaluate each c-transform as d nested 1-D transforms
                                 (O(N^(d+1)) instead of O(N^(2d)); float32 rounding once per
                                 axis, larger derived shift); ignored for p = 1 */
+/* Interpolation R of the coarse potential (Section 3.5 admits any; the
+ * default is multilinear, as in the paper's experiments).  At most one. */
+#define QBW_INTERP_NEAREST 8u  /* f^ = f~ of the pixel's own block (its nearest centre) */
+#define QBW_INTERP_CUBIC 16u   /* separable Catmull-Rom cubic convolution through the
+                                  block centres, edge taps replicated */
 
 /* qbw_result.warn bits */
 #define QBW_WARN_IPF_NOT_CONVERGED 1u /* stopped at max_ipf_iter; the upper bound stays valid */
@@ -76,7 +81,8 @@ typedef struct qbw_grid {
 typedef struct qbw_opts {
   double xi;            /* IPF stop: ||a^ - a||_1 + ||b - b^||_1 < xi (default 1e-12) */
   int32_t max_ipf_iter; /* IPF iteration cap (default 50, >= 1) */
-  uint32_t flags;       /* QBW_WANT_ARGMIN | QBW_SAVE_FOR_BWD | QBW_SEPARABLE */
+  uint32_t flags;       /* QBW_WANT_ARGMIN | QBW_SAVE_FOR_BWD | QBW_SEPARABLE |
+                           QBW_INTERP_NEAREST or QBW_INTERP_CUBIC */
 } qbw_opts;
 
 typedef struct qbw_result {
@@ -197,6 +203,16 @@ qbw_status qbw_coarse_solve_host(const qbw_grid* grid, const double* a_t, const 
  * outside the hull of the block centres take the nearest edge value. */
 qbw_status qbw_upscale_potential(qbw_ctx* ctx, const qbw_grid* grid, const double* ftil,
                                  float* fhat, qbw_stream stream);
+
+/* The same with another interpolation R (Section 3.5): interp is 0
+ * (multilinear), QBW_INTERP_NEAREST or QBW_INTERP_CUBIC.  Cubic: along each
+ * axis, at coarse position t = (2x - (k-1)) / (2k) clamped to [0, n-1],
+ * i = floor(t), s = t - i, the taps F[i-1..i+2] (indices clamped to the
+ * grid) weighted (2s^2-s^3-s)/2, (3s^3-5s^2+2)/2, (4s^2-3s^3+s)/2,
+ * (s^3-s^2)/2, in float64; axes nested, last axis innermost; rounded once
+ * to float32.  Errors: QBW_E_INVAL for another interp value. */
+qbw_status qbw_upscale_potential_interp(qbw_ctx* ctx, const qbw_grid* grid, uint32_t interp,
+                                        const double* ftil, float* fhat, qbw_stream stream);
 
 /* Lazy c-transform (Section 4, eq. of the lazy c-transform):
  * dst[j] = min_i RN32(RN32(|x_i - x_j|^p) - src[i]) over all N^d pixels,

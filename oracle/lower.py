@@ -57,7 +57,15 @@ def _axis_weights(N: int, k: int):
     return K0, K1, w
 
 
-def upscale_potential(ftil: np.ndarray, N: int, d: int, k: int) -> np.ndarray:
+def upscale_potential(ftil: np.ndarray, N: int, d: int, k: int, interp: str = "linear") -> np.ndarray:
+    """R(f~) on the fine grid.  interp: "linear" (multilinear, the paper's
+    experiments), "nearest" or "cubic" (Section 3.5 allows any interpolation)."""
+    if interp == "nearest":
+        return upscale_nearest(ftil, N, d, k)
+    if interp == "cubic":
+        return upscale_cubic(ftil, N, d, k)
+    if interp != "linear":
+        raise ValueError(f"unknown interpolation {interp!r}")
     n = N // k
     F = np.asarray(ftil, dtype=np.float64).reshape((n,) * d)
     X = coords(N, d)
@@ -70,6 +78,72 @@ def upscale_potential(ftil: np.ndarray, N: int, d: int, k: int) -> np.ndarray:
         lo = rec(axis + 1, idx + [K0[xa]])
         hi = rec(axis + 1, idx + [K1[xa]])
         return lo + W[xa] * (hi - lo)
+
+    return rec(0, [])
+
+
+def upscale_nearest(ftil: np.ndarray, N: int, d: int, k: int) -> np.ndarray:
+    """Nearest-neighbour interpolation: the nearest block centre to a pixel is
+    the centre of its own block, so f^_i = f~ of the block containing i."""
+    n = N // k
+    F = np.asarray(ftil, dtype=np.float64).reshape((n,) * d)
+    X = coords(N, d)
+    return F[tuple(X[:, a] // k for a in range(d))].copy()
+
+
+# Cubic reading: separable cubic convolution with the Catmull-Rom kernel (the
+# Keys kernel with a = -1/2), through the block centres.  Along one axis the
+# pixel sits at coarse position t = (2x - (k-1)) / (2k), clamped to [0, n-1]
+# (pixels outside the hull of the centres take the edge value, as for the
+# multilinear reading); with i = floor(t) and s = t - i the value is
+#   w_{-1} F[i-1] + w_0 F[i] + w_1 F[i+1] + w_2 F[i+2],
+#   w_{-1} = (2 s^2 - s^3 - s)/2,  w_0 = (3 s^3 - 5 s^2 + 2)/2,
+#   w_1 = (4 s^2 - 3 s^3 + s)/2,   w_2 = (s^3 - s^2)/2,
+# taps beyond the edge replaced by the edge value.  Evaluation order (each
+# float64 operation rounded separately): s = r / (2k) from the integer
+# remainder r; s2 = s*s; s3 = s2*s; each weight as written above, grouped
+# as ((a - b) - c) * 0.5 etc. in ``_cubic_weights``; the four taps summed
+# left to right; axes nested with the last axis innermost.
+
+def _cubic_weights(s):
+    s2 = s * s
+    s3 = s2 * s
+    wm1 = 0.5 * ((2.0 * s2 - s3) - s)
+    w0 = 0.5 * ((3.0 * s3 - 5.0 * s2) + 2.0)
+    w1 = 0.5 * ((4.0 * s2 - 3.0 * s3) + s)
+    w2 = 0.5 * (s3 - s2)
+    return wm1, w0, w1, w2
+
+
+def _axis_cubic(N: int, k: int):
+    """Per fine coordinate x: the four clamped tap indices and their weights."""
+    n = N // k
+    x = np.arange(N, dtype=np.int64)
+    t = 2 * x - (k - 1)
+    den = 2 * k
+    i = np.floor_divide(t, den)
+    r = t - den * i
+    low = t <= 0
+    high = i >= n - 1
+    i = np.where(low, 0, np.where(high, n - 1, i))
+    r = np.where(low | high, 0, r)
+    s = r.astype(np.float64) / float(den)
+    taps = [np.clip(i + o, 0, n - 1) for o in (-1, 0, 1, 2)]
+    return taps, _cubic_weights(s)
+
+
+def upscale_cubic(ftil: np.ndarray, N: int, d: int, k: int) -> np.ndarray:
+    n = N // k
+    F = np.asarray(ftil, dtype=np.float64).reshape((n,) * d)
+    X = coords(N, d)
+    taps, W = _axis_cubic(N, k)
+
+    def rec(axis, idx):
+        if axis == d:
+            return F[tuple(idx)]
+        xa = X[:, axis]
+        v = [rec(axis + 1, idx + [taps[o][xa]]) for o in range(4)]
+        return ((W[0][xa] * v[0] + W[1][xa] * v[1]) + W[2][xa] * v[2]) + W[3][xa] * v[3]
 
     return rec(0, [])
 
@@ -172,10 +246,10 @@ def feasibility_shift_sep(F_hat: float, G: float, Fo: float, N: int, d: int) -> 
     return (e_f + e_g) * (1.0 + 2.0 ** -10) + 2.0 ** -52 * N ** d * (Fo + G)
 
 
-def lower_bound_sep_o32(mu, nu, ftil, k: int):
+def lower_bound_sep_o32(mu, nu, ftil, k: int, interp: str = "linear"):
     """Algorithm 5 (p = 2) with the separable float32 c-transforms."""
     d, N = mu.ndim, mu.shape[0]
-    fhat32 = upscale_potential(ftil, N, d, k).astype(np.float32)
+    fhat32 = upscale_potential(ftil, N, d, k, interp).astype(np.float32)
     g32, ig = ctransform_sep_o32(fhat32, N, d)
     f32, jf = ctransform_sep_o32(g32, N, d)
     S32 = fsum_dot(f32, mu.reshape(-1)) + fsum_dot(g32, nu.reshape(-1))
@@ -198,10 +272,10 @@ def fsum_dot(x, w) -> float:
 # Bound assembly
 # ----------------------------------------------------------------------------
 
-def lower_bound_o64(mu, nu, ftil, k: int, p: int):
+def lower_bound_o64(mu, nu, ftil, k: int, p: int, interp: str = "linear"):
     """Algorithm 5 in float64: returns f^, g, f, S = <f,mu> + <g,nu>, lower bound."""
     d, N = mu.ndim, mu.shape[0]
-    fhat = upscale_potential(ftil, N, d, k)
+    fhat = upscale_potential(ftil, N, d, k, interp)
     g, ig = ctransform_o64(fhat, N, d, p)
     f, jf = ctransform_o64(g, N, d, p)
     S = fsum_dot(f, mu.reshape(-1)) + fsum_dot(g, nu.reshape(-1))
@@ -234,11 +308,11 @@ def feasibility_shift(F_hat: float, G: float, Fo: float, p: int, P: int) -> floa
     return (e_f + e_g) * (1.0 + 2.0 ** -10) + 2.0 ** -52 * P * (Fo + G)
 
 
-def lower_bound_o32(mu, nu, ftil, k: int, p: int):
+def lower_bound_o32(mu, nu, ftil, k: int, p: int, interp: str = "linear"):
     """Algorithm 5 in the float32 reading, with the float64 sums and shift."""
     d, N = mu.ndim, mu.shape[0]
     P = N ** d
-    fhat64 = upscale_potential(ftil, N, d, k)
+    fhat64 = upscale_potential(ftil, N, d, k, interp)
     fhat32 = fhat64.astype(np.float32)
     g32, ig = ctransform_o32(fhat32, N, d, p)
     f32, jf = ctransform_o32(g32, N, d, p)

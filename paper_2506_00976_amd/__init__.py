@@ -17,8 +17,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (QBW_BATCH_AUTOTUNE, QBW_BATCH_BACKWARD, QBW_BATCH_GRAPH, QBW_SAVE_FOR_BWD,
-                   QBW_SEPARABLE, QBW_WANT_ARGMIN, QBW_WARN_IPF_NOT_CONVERGED, QBW_WARN_LB_CLIPPED, QbwCoarse,
+from ._lib import (QBW_BATCH_AUTOTUNE, QBW_BATCH_BACKWARD, QBW_BATCH_GRAPH, QBW_INTERP_CUBIC,
+                   QBW_INTERP_NEAREST, QBW_SAVE_FOR_BWD, QBW_SEPARABLE, QBW_WANT_ARGMIN, QBW_WARN_IPF_NOT_CONVERGED, QBW_WARN_LB_CLIPPED, QbwCoarse,
                    QbwError, QbwGrid, QbwJob, QbwOpts, QbwResult, check, load)
 
 __all__ = ["Context", "Coarse", "Batch", "bounds", "wasserstein_bounds", "BoundsFunction",
@@ -86,6 +86,16 @@ def _opts(xi, max_ipf_iter, flags) -> QbwOpts:
     return QbwOpts(float(xi), int(max_ipf_iter), int(flags))
 
 
+_INTERP = {"linear": 0, "nearest": QBW_INTERP_NEAREST, "cubic": QBW_INTERP_CUBIC}
+
+
+def _interp(interp: str) -> int:
+    """Flag bits of the interpolation R of the coarse potential (Section 3.5)."""
+    if interp not in _INTERP:
+        raise QbwError(f"interp must be one of {sorted(_INTERP)}, got {interp!r}")
+    return _INTERP[interp]
+
+
 class Coarse:
     """A coarse solution (coupling pi~ as COO, potential f~), held in host memory."""
 
@@ -131,12 +141,15 @@ def coarse_solve(a_t, b_t, N: int, d: int, k: int, p: int) -> Coarse:
 
 
 def bounds(a, b, k: int, p: int, coarse: Coarse | None = None, xi: float = 1e-12,
-           max_ipf_iter: int = 50, want_argmin: bool = False, separable: bool = False) -> dict:
+           max_ipf_iter: int = 50, want_argmin: bool = False, separable: bool = False,
+           interp: str = "linear") -> dict:
     """Lower and upper bound of W_p(a, b) (no autograd).  Returns the qbw_result fields.
-    separable=True evaluates the p = 2 c-transforms axis by axis (QBW_SEPARABLE)."""
+    separable=True evaluates the p = 2 c-transforms axis by axis (QBW_SEPARABLE);
+    interp picks the interpolation of the coarse potential ("linear", "nearest", "cubic")."""
     a, b = _dev(a), _dev(b)
     grid = _grid(a, k, p)
-    opts = _opts(xi, max_ipf_iter, (QBW_WANT_ARGMIN if want_argmin else 0) | (QBW_SEPARABLE if separable else 0))
+    opts = _opts(xi, max_ipf_iter, (QBW_WANT_ARGMIN if want_argmin else 0) | (QBW_SEPARABLE if separable else 0) |
+                 _interp(interp))
     res = QbwResult()
     lib = load()
     ctx = context(a.device.index)
@@ -167,10 +180,11 @@ class BoundsFunction(torch.autograd.Function):
     the coarse solution frozen (see qbw_bounds_backward)."""
 
     @staticmethod
-    def forward(ctx, a, b, k, p, coarse, xi, max_ipf_iter, want_argmin, separable=False):
+    def forward(ctx, a, b, k, p, coarse, xi, max_ipf_iter, want_argmin, separable=False, interp="linear"):
         a, b = _dev(a), _dev(b)
         grid = _grid(a, k, p)
-        flags = QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_argmin else 0) | (QBW_SEPARABLE if separable else 0)
+        flags = QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_argmin else 0) | (QBW_SEPARABLE if separable else 0) | \
+            _interp(interp)
         opts = _opts(xi, max_ipf_iter, flags)
         res = QbwResult()
         saved = C.c_void_p()
@@ -201,23 +215,24 @@ class BoundsFunction(torch.autograd.Function):
         check(load().qbw_bounds_backward(context(a.device.index).handle, ctx.saved_handle.handle,
                                          dl, du, _ptr(ga), _ptr(gb), None, _stream()),
               "qbw_bounds_backward")
-        return ga, gb, None, None, None, None, None, None, None
+        return ga, gb, None, None, None, None, None, None, None, None
 
 
 def wasserstein_bounds(a, b, k: int, p: int, coarse: Coarse | None = None, xi: float = 1e-12,
-                       max_ipf_iter: int = 50, want_argmin: bool = False, separable: bool = False):
+                       max_ipf_iter: int = 50, want_argmin: bool = False, separable: bool = False,
+                       interp: str = "linear"):
     """Differentiable (lower, upper) bounds on W_p(a, b)."""
-    return BoundsFunction.apply(a, b, k, p, coarse, xi, max_ipf_iter, want_argmin, separable)
+    return BoundsFunction.apply(a, b, k, p, coarse, xi, max_ipf_iter, want_argmin, separable, interp)
 
 
 def bounds_with_grads(a, b, k: int, p: int, coarse: Coarse | None = None, dlower: float = 1.0,
                       dupper: float = 1.0, want_fhat_grad: bool = False, xi: float = 1e-12,
-                      max_ipf_iter: int = 50, separable: bool = False):
+                      max_ipf_iter: int = 50, separable: bool = False, interp: str = "linear"):
     """Forward + backward in one call: returns (result dict, grad_a, grad_b, grad_fhat or None)."""
     a, b = _dev(a), _dev(b)
     grid = _grid(a, k, p)
     opts = _opts(xi, max_ipf_iter, QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_fhat_grad else 0) |
-                 (QBW_SEPARABLE if separable else 0))
+                 (QBW_SEPARABLE if separable else 0) | _interp(interp))
     res = QbwResult()
     saved = C.c_void_p()
     lib = load()
@@ -269,12 +284,13 @@ def cbar(a, b, k: int, p: int):
     return out
 
 
-def upscale_potential(ftil, N: int, d: int, k: int):
+def upscale_potential(ftil, N: int, d: int, k: int, interp: str = "linear"):
     ftil = _dev(ftil)
     grid = QbwGrid(d, N, k, 2)
     out = torch.empty(N ** d, dtype=torch.float32, device=ftil.device)
-    check(load().qbw_upscale_potential(context(ftil.device.index).handle, C.byref(grid), _ptr(ftil),
-                                       _ptr(out), _stream()), "qbw_upscale_potential")
+    check(load().qbw_upscale_potential_interp(context(ftil.device.index).handle, C.byref(grid),
+                                              _interp(interp), _ptr(ftil), _ptr(out), _stream()),
+          "qbw_upscale_potential_interp")
     return out
 
 
@@ -370,7 +386,7 @@ class Batch:
 
     def __init__(self, jobs, coarse=None, backward: bool = False, graph: bool = False,
                  autotune: bool = False, xi: float = 1e-12, max_ipf_iter: int = 50,
-                 separable: bool = False):
+                 separable: bool = False, interp: str = "linear"):
         """jobs: list of (a, b, k, p) or (a, b, k, p, grad_a, grad_b) with CUDA tensors."""
         lib = load()
         self._keep = []
@@ -395,7 +411,7 @@ class Batch:
             self._keep.append(coarse)
         flags = (QBW_BATCH_BACKWARD if backward else 0) | (QBW_BATCH_GRAPH if graph else 0) | \
                 (QBW_BATCH_AUTOTUNE if autotune else 0)
-        opts = _opts(xi, max_ipf_iter, QBW_SEPARABLE if separable else 0)
+        opts = _opts(xi, max_ipf_iter, (QBW_SEPARABLE if separable else 0) | _interp(interp))
         h = C.c_void_p()
         self.n = len(jobs)
         self.ctx = context(dev)

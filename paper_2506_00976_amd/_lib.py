@@ -10,6 +10,8 @@ LIB_PATH = os.path.join(HERE, "libqbw.so")
 QBW_WANT_ARGMIN = 1
 QBW_SAVE_FOR_BWD = 2
 QBW_SEPARABLE = 4
+QBW_INTERP_NEAREST = 8
+QBW_INTERP_CUBIC = 16
 QBW_WARN_IPF_NOT_CONVERGED = 1
 QBW_WARN_LB_CLIPPED = 2
 QBW_BATCH_BACKWARD = 1
@@ -67,6 +69,7 @@ SIGNATURES = [
     ("qbw_cbar", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
     ("qbw_coarse_solve_host", C.c_int, [_pg, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("qbw_upscale_potential", C.c_int, [_vp, _pg, _vp, _vp, _vp]),
+    ("qbw_upscale_potential_interp", C.c_int, [_vp, _pg, C.c_uint32, _vp, _vp, _vp]),
     ("qbw_ctransform", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
     ("qbw_ctransform_separable", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
     ("qbw_ipf", C.c_int, [_vp, _pg, _vp, _vp, _pc, _po, _vp, _vp, _vp, _vp, _vp]),

@@ -471,6 +471,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.nnz = J.coarse ? J.coarse->nnz : 0;
     D.max_iter = o.max_ipf_iter;
     D.want_argmin = (mode & PM_ARGMIN) ? 1 : 0;
+    D.interp = (o.flags & QBW_INTERP_CUBIC) ? 2 : (o.flags & QBW_INTERP_NEAREST) ? 1 : 0;
     D.xi = o.xi;
     D.coarse_obj = J.coarse ? J.coarse->obj : 0.0;
     D.mu = J.a;
@@ -869,6 +870,10 @@ static int check_opts(const qbw_opts* o) {
   if (!o) return QBW_OK;
   if (o->max_ipf_iter < 1 || o->max_ipf_iter > 100000) { set_error("max_ipf_iter must be in [1, 1e5]"); return QBW_E_INVAL; }
   if (!(o->xi > 0) && !(o->xi <= 0)) { set_error("xi is NaN"); return QBW_E_INVAL; }
+  if ((o->flags & QBW_INTERP_NEAREST) && (o->flags & QBW_INTERP_CUBIC)) {
+    set_error("QBW_INTERP_NEAREST and QBW_INTERP_CUBIC are exclusive");
+    return QBW_E_INVAL;
+  }
   return QBW_OK;
 }
 
@@ -1122,11 +1127,22 @@ qbw_status qbw_coarse_solve_host(const qbw_grid* grid, const double* a_t, const 
 
 qbw_status qbw_upscale_potential(qbw_ctx* ctx, const qbw_grid* grid, const double* ftil, float* fhat,
                                  qbw_stream stream) {
+  return qbw_upscale_potential_interp(ctx, grid, 0u, ftil, fhat, stream);
+}
+
+qbw_status qbw_upscale_potential_interp(qbw_ctx* ctx, const qbw_grid* grid, uint32_t interp,
+                                        const double* ftil, float* fhat, qbw_stream stream) {
   if (!ctx || !ftil || !fhat) { set_error("NULL argument"); return QBW_E_INVAL; }
   CHK(check_grid(grid));
+  if (interp != 0u && interp != QBW_INTERP_NEAREST && interp != QBW_INTERP_CUBIC) {
+    set_error("interp must be 0, QBW_INTERP_NEAREST or QBW_INTERP_CUBIC (got %u)", interp);
+    return QBW_E_INVAL;
+  }
   Plan pl;
   hipStream_t st = S(stream);
-  CHK(plan_build(ctx, pl, {stage_job(grid, nullptr, nullptr)}, 0, qbw_default_opts(), false, st));
+  qbw_opts o = qbw_default_opts();
+  o.flags = interp;
+  CHK(plan_build(ctx, pl, {stage_job(grid, nullptr, nullptr)}, 0, o, false, st));
   pl.hj[0].ftil = ftil;
   pl.hj[0].fhat = fhat;
   HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));

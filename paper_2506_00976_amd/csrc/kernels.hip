@@ -148,6 +148,37 @@ __device__ __forceinline__ double lerp_nc(double a, double b, double w) {
   return a + w * (b - a);
 }
 
+// Catmull-Rom cubic convolution along one axis at fine coordinate x: the four
+// tap indices (clamped to the coarse grid) and weights.  The pixel's coarse
+// position t = (2x - (k-1)) / (2k) is clamped to [0, n-1]; i = floor(t),
+// s = t - i = r / (2k) from the integer remainder r.  Every float64 operation
+// is rounded on its own, in the order written.
+__device__ __forceinline__ void axis_cubic(int x, int k, int n, int (&K)[4], double (&w)[4]) {
+#pragma clang fp contract(off)
+  const int t = 2 * x - (k - 1);
+  const int den = 2 * k;
+  int i, r;
+  if (t <= 0) { i = 0; r = 0; }
+  else {
+    i = t / den;
+    r = t - den * i;
+    if (i >= n - 1) { i = n - 1; r = 0; }
+  }
+  for (int o = 0; o < 4; ++o) K[o] = min(max(i + o - 1, 0), n - 1);
+  const double s = (double)r / (double)den;
+  const double s2 = s * s;
+  const double s3 = s2 * s;
+  w[0] = 0.5 * ((2.0 * s2 - s3) - s);
+  w[1] = 0.5 * ((3.0 * s3 - 5.0 * s2) + 2.0);
+  w[2] = 0.5 * ((4.0 * s2 - 3.0 * s3) + s);
+  w[3] = 0.5 * (s3 - s2);
+}
+
+__device__ __forceinline__ double cubic_sum(const double (&w)[4], double v0, double v1, double v2, double v3) {
+#pragma clang fp contract(off)
+  return ((w[0] * v0 + w[1] * v1) + w[2] * v2) + w[3] * v3;
+}
+
 __global__ __launch_bounds__(256) void k_upscale(const DevJob* __restrict__ jobs, int njobs,
                                                  const int* __restrict__ off, int total) {
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
@@ -162,7 +193,38 @@ __global__ __launch_bounds__(256) void k_upscale(const DevJob* __restrict__ jobs
       int x0, x1, x2;
       pix_coords(i, J.N, J.d, x0, x1, x2);
       double val;
-      if (J.d == 2) {
+      if (J.interp == 1) {
+        // nearest centre = the centre of the pixel's own block
+        const int b1 = x1 / J.k, b2 = x2 / J.k;
+        val = J.d == 2 ? F[b1 * n + b2] : F[((x0 / J.k) * n + b1) * n + b2];
+      } else if (J.interp == 2) {
+        int B[4], C[4];
+        double wb[4], wc[4];
+        axis_cubic(x1, J.k, n, B, wb);
+        axis_cubic(x2, J.k, n, C, wc);
+        if (J.d == 2) {
+          double r[4];
+          for (int u = 0; u < 4; ++u) {
+            const double* row = F + B[u] * n;
+            r[u] = cubic_sum(wc, row[C[0]], row[C[1]], row[C[2]], row[C[3]]);
+          }
+          val = cubic_sum(wb, r[0], r[1], r[2], r[3]);
+        } else {
+          int A[4];
+          double wa[4];
+          axis_cubic(x0, J.k, n, A, wa);
+          double sa[4];
+          for (int t = 0; t < 4; ++t) {
+            double r[4];
+            for (int u = 0; u < 4; ++u) {
+              const double* row = F + (A[t] * n + B[u]) * n;
+              r[u] = cubic_sum(wc, row[C[0]], row[C[1]], row[C[2]], row[C[3]]);
+            }
+            sa[t] = cubic_sum(wb, r[0], r[1], r[2], r[3]);
+          }
+          val = cubic_sum(wa, sa[0], sa[1], sa[2], sa[3]);
+        }
+      } else if (J.d == 2) {
         int A0, A1, B0, B1;
         double wa, wb;
         axis_weight(x1, J.k, n, A0, A1, wa);

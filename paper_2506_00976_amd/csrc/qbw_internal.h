@@ -55,6 +55,7 @@ struct DevJob {
   int nnz;                  // coarse coupling entries
   int max_iter;             // IPF cap
   int want_argmin;
+  int interp;               // 0 multilinear, 1 nearest, 2 cubic
   double xi;
   double coarse_obj;
   const double* mu;         // fine measures

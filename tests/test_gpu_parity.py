@@ -547,3 +547,67 @@ def test_saved_records_reuse_and_outlive_context():
     assert res.lower == runs[0][0]["lower"]
     lib.qbw_destroy(h)
     lib.qbw_saved_free(saved)
+
+
+# ------------------------------------------------------------------ other interpolants (Section 3.5)
+
+@pytest.mark.parametrize("interp", ["nearest", "cubic"])
+@pytest.mark.parametrize("N,d,k", [(32, 2, 4), (30, 2, 3), (16, 3, 2), (16, 2, 16), (12, 2, 1), (8, 3, 8),
+                                   (15, 2, 5), (20, 3, 4)])
+def test_upscale_interpolants_bit_exact(interp, N, d, k):
+    n = N // k
+    ft = si.rng(10200 + N + k).standard_normal(n ** d) * 100
+    out = qbw.upscale_potential(dev(ft), N, d, k, interp=interp)
+    ref = lower.upscale_potential(ft, N, d, k, interp).astype(np.float32)
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("interp", ["nearest", "cubic"])
+@pytest.mark.parametrize("N,d,k,p", [(16, 2, 4, 2), (16, 2, 4, 1), (8, 3, 2, 2)])
+def test_bounds_with_interpolants(interp, N, d, k, p):
+    mu, nu = pair(N, d, "gmm", "grf", 10300 + N + p)
+    rec, (r, c, v, ft, gt, obj) = record(mu, nu, k, p)
+    out = qbw.bounds(dev(mu), dev(nu), k, p, coarse=rec, interp=interp)
+    L = lower.lower_bound_o32(mu, nu, ft, k, p, interp)
+    assert out["lower"] == pytest.approx(L["lower"], rel=1e-9)
+    assert out["feas_shift"] == pytest.approx(L["shift"], rel=1e-12)
+    L64 = lower.lower_bound_o64(mu, nu, ft, k, p, interp)
+    assert out["lower"] <= L64["lower"] * (1 + 1e-12)
+    W = lp.wasserstein_exact(mu, nu, p)
+    assert out["lower"] <= W <= out["upper"]
+    # the upper bound does not depend on the interpolation of the potential
+    lin = qbw.bounds(dev(mu), dev(nu), k, p, coarse=rec)
+    assert out["upper"] == lin["upper"]
+
+
+def test_batch_with_interpolant_matches_single():
+    jobs_np = [(16, 2, 4, 2), (16, 2, 4, 1), (8, 3, 2, 2), (24, 2, 3, 2)]
+    jobs, recs = [], []
+    for i, (N, d, k, p) in enumerate(jobs_np):
+        mu, nu = pair(N, d, "grf", "gmm", 10400 + i)
+        rec, _ = record(mu, nu, k, p)
+        jobs.append((dev(mu), dev(nu), k, p))
+        recs.append(rec)
+    B = qbw.Batch(jobs, coarse=recs, graph=True, interp="cubic")
+    B.run()
+    out = B.results()
+    for (a, b, k, p), rec, o in zip(jobs, recs, out):
+        s = qbw.bounds(a, b, k, p, coarse=rec, interp="cubic")
+        assert s["lower"] == o["lower"] and s["upper"] == o["upper"]
+    with pytest.raises(qbw.QbwError):
+        qbw.upscale_potential(dev(np.zeros(16)), 16, 2, 4, interp="spline")
+
+
+def test_interpolant_flags_are_exclusive():
+    import ctypes as C
+    from paper_2506_00976_amd import _lib
+    lib = _lib.load()
+    mu, nu = pair(16, 2, "grf", "gmm", 10500)
+    a, b = dev(mu), dev(nu)
+    grid = _lib.QbwGrid(2, 16, 4, 2)
+    opts = _lib.QbwOpts(1e-12, 50, _lib.QBW_INTERP_NEAREST | _lib.QBW_INTERP_CUBIC)
+    res = _lib.QbwResult()
+    rc = lib.qbw_bounds(qbw.context(0).handle, C.byref(grid), C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                        C.byref(opts), C.byref(res), None, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 1   # QBW_E_INVAL
+    assert b"exclusive" in lib.qbw_last_error()

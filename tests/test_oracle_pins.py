@@ -211,6 +211,93 @@ def test_upscale_affine_is_exact_in_3d_interior():
     assert np.allclose(fh[inside], 3.0 + X[inside] @ beta, rtol=0, atol=1e-13)
 
 
+def test_upscale_nearest_is_own_block_by_brute_force():
+    for N, d, k in [(12, 2, 3), (8, 3, 2), (10, 2, 5)]:
+        n = N // k
+        ft = si.rng(44).standard_normal(n ** d)
+        fh = lower.upscale_potential(ft, N, d, k, "nearest")
+        X = grid.coords(N, d)
+        C = coarse.centres(N, d, k)
+        for i in range(N ** d):
+            dist = ((C - X[i]) ** 2).sum(1)
+            K = int(np.argmin(dist))                    # nearest centre, unique
+            assert np.sum(dist == dist[K]) == 1
+            assert fh[i] == ft[K]
+
+
+def _catmull_rom_hermite(F, t):
+    """Independent 1-D form: cubic Hermite segment with tangents (F[i+1] - F[i-1]) / 2,
+    edge samples replicated, t clamped to [0, n-1]."""
+    n = len(F)
+    t = min(max(t, 0.0), n - 1.0)
+    i = min(int(math.floor(t)), n - 1)
+    s = t - i
+    at = lambda j: F[min(max(j, 0), n - 1)]
+    m0 = (at(i + 1) - at(i - 1)) / 2.0
+    m1 = (at(i + 2) - at(i)) / 2.0
+    h00 = 2 * s ** 3 - 3 * s ** 2 + 1
+    h10 = s ** 3 - 2 * s ** 2 + s
+    h01 = -2 * s ** 3 + 3 * s ** 2
+    h11 = s ** 3 - s ** 2
+    return h00 * at(i) + h10 * m0 + h01 * at(i + 1) + h11 * m1
+
+
+def test_upscale_cubic_matches_hermite_form_and_separates():
+    N, k = 24, 4
+    n = N // k
+    u = si.rng(45).standard_normal(n)
+    v = si.rng(46).standard_normal(n)
+    t = (2 * np.arange(N) - (k - 1)) / (2 * k)
+    cu = np.array([_catmull_rom_hermite(u, x) for x in t])
+    cv = np.array([_catmull_rom_hermite(v, x) for x in t])
+    fh = lower.upscale_potential(np.repeat(u, n), N, 2, k, "cubic").reshape(N, N)
+    assert np.allclose(fh[:, 7], cu, rtol=0, atol=1e-13)          # varies along axis 0 only
+    fh = lower.upscale_potential(np.outer(u, v).reshape(-1), N, 2, k, "cubic").reshape(N, N)
+    assert np.allclose(fh, np.outer(cu, cv), rtol=0, atol=1e-12)  # tensor product
+
+
+def test_upscale_cubic_interpolates_and_reproduces_quadratics():
+    N, d, k = 15, 2, 3                      # odd k: block centres are pixels
+    n = N // k
+    ft = si.rng(47).standard_normal(n ** d)
+    fh = lower.upscale_potential(ft, N, d, k, "cubic").reshape(N, N)
+    for K in range(n):
+        for L in range(n):
+            assert fh[k * K + 1, k * L + 1] == ft[K * n + L]
+    const = lower.upscale_potential(np.full(n * n, -7.25), N, d, k, "cubic")
+    assert np.allclose(const, -7.25, rtol=4e-16, atol=0)
+    # a quadratic in the coarse coordinates is reproduced wherever no tap is clamped
+    for N, d, k in [(32, 2, 4), (18, 3, 3)]:
+        n = N // k
+        Cc = (coarse.centres(N, d, k) - (k - 1) / 2) / k          # coarse coordinates
+        q = lambda Z: 0.5 + Z @ np.arange(1.0, d + 1) + 0.25 * (Z ** 2).sum(1) - 0.125 * Z[:, 0] * Z[:, -1]
+        fh = lower.upscale_potential(q(Cc), N, d, k, "cubic")
+        T = (2 * grid.coords(N, d) - (k - 1)) / (2 * k)
+        inside = np.all((T >= 1) & (T <= n - 2), axis=1)
+        assert inside.sum() > 0
+        assert np.allclose(fh[inside], q(T[inside]), rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("interp", ["nearest", "cubic"])
+def test_other_interpolants_keep_the_bound(interp):
+    # any interpolation R keeps Algorithm 5 a lower bound (the proposition of
+    # Section 3.5): bracketing of the exact LP, and exact admissibility in float32
+    N, d, k, p = 8, 2, 2, 2
+    mu, nu = pair(N, d, "gmm", "cauchy", 48)
+    W = lp.wasserstein_exact(mu, nu, p)
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
+    L64 = lower.lower_bound_o64(mu, nu, ft, k, p, interp)
+    L32 = lower.lower_bound_o32(mu, nu, ft, k, p, interp)
+    assert L32["lower"] <= L64["lower"] * (1 + 1e-12) <= W * (1 + 1e-12)
+    X = grid.coords(N, d)
+    Cm = grid.cost64(X, X, p)
+    f = L32["f32"].astype(np.float64) - L32["shift"]
+    g = L32["g32"].astype(np.float64)
+    assert np.all(f[:, None] + g[None, :] <= Cm)
+    Llin = lower.lower_bound_o64(mu, nu, ft, k, p)
+    assert L64["lower"] != Llin["lower"]
+
+
 # ---------------------------------------------------------------- c-transform
 
 @pytest.mark.parametrize("N,d,p", [(4, 2, 2), (4, 2, 1), (3, 3, 2), (3, 3, 1)])
