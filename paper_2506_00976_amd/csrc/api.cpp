@@ -276,6 +276,7 @@ struct Plan {
       *off_sep = nullptr;
   int tot_chunk = 0, tot_pool = 0, tot_entry = 0, tot_block = 0, tot_cbar = 0, tot_mom = 0,
       tot_pc1 = 0, tot_pc2 = 0, tot_sep = 0, max_sep_d = 0;
+  bool has_p1 = false, has_p2 = false;  // grid cost exponents present
   CtItem* items = nullptr;
   int* qoff = nullptr;   // kQueues + 1 offsets into items
   int n_items = 0;
@@ -523,6 +524,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     off[7 * (NJ + 1) + j + 1] = off[7 * (NJ + 1) + j] + (D.p == 2 ? (D.nnz + 255) / 256 : 0);
     off[8 * (NJ + 1) + j + 1] = off[8 * (NJ + 1) + j] + (D.sep ? D.rows * ((D.N + 63) / 64) : 0);
     if (D.sep) pl.max_sep_d = std::max(pl.max_sep_d, D.d);
+    (D.p == 1 ? pl.has_p1 : pl.has_p2) = true;
   }
   pl.djobs = (DevJob*)(B + o_jobs);
   int* offd = (int*)(B + o_offs);
@@ -659,11 +661,10 @@ static int enqueue_forward(Plan& pl, hipStream_t st) {
   // lower bound (Algorithm 5)
   CHK(launch_upscale(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
   CHK(enqueue_ctransforms(pl, st));
-  CHK(launch_lb_partial(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
-  // upper bound (Algorithm 4)
+  // upper bound (Algorithm 4): coarse IPF, then one sweep over the pixels for
+  // the lower-bound sums, the fine scalings and the weighted-TV sums
   CHK(launch_ipf(pl.djobs, NJ, st));
-  CHK(launch_scalings(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
-  CHK(launch_tv_partial(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
+  CHK(launch_fwd_pixels(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
   CHK(enqueue_plancost(pl, st));
   CHK(launch_finalize(pl.djobs, NJ, st));
   return QBW_OK;
@@ -671,11 +672,16 @@ static int enqueue_forward(Plan& pl, hipStream_t st) {
 
 static int enqueue_backward(Plan& pl, hipStream_t st) {
   const int NJ = pl.njobs;
-  CHK(launch_lb_grad(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, st));
+  // p = 1 jobs: separate lower- and upper-bound passes (the latter over
+  // support blocks); p = 2 jobs: one fused pass over pixels after the moments
+  if (pl.has_p1) CHK(launch_lb_grad(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, st));
   if (pl.tot_pc2) CHK(launch_moments(pl.djobs, NJ, pl.off_mom, pl.tot_mom, 0, st));
   CHK(launch_ub_coarse_bwd2(pl.djobs, NJ, pl.bwd_scratch, pl.max_q, st));
-  CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 0, st));
-  CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 1, st));
+  if (pl.has_p1) {
+    CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 0, st));
+    CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 1, st));
+  }
+  if (pl.has_p2) CHK(launch_grad2(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, pl.du, st));
   return QBW_OK;
 }
 

@@ -632,37 +632,6 @@ __global__ __launch_bounds__(256) void k_sep_argmin(const DevJob* __restrict__ j
   }
 }
 
-// ------------------------------------------------------------------ lower-bound sums
-
-__global__ __launch_bounds__(256) void k_lb_partial(const DevJob* __restrict__ jobs, int njobs,
-                                                    const int* __restrict__ off, int total) {
-  __shared__ double sh[256];
-  for (int it = blockIdx.x; it < total; it += gridDim.x) {
-    const int jb = find_job(off, njobs, it);
-    const DevJob& J = jobs[jb];
-    const int c = it - off[jb];
-    const int base = c * kChunk;
-    double sf = 0.0, sg = 0.0, mh = 0.0, mg = 0.0, mf = 0.0;
-    for (int q = threadIdx.x; q < kChunk; q += 256) {
-      const int i = base + q;
-      if (i >= J.P) break;
-      const double f = J.f[i], g = J.g[i];
-      sf += f * J.mu[i];
-      sg += g * J.nu[i];
-      mh = fmax(mh, fabs((double)J.fhat[i]));
-      mg = fmax(mg, fabs(g));
-      mf = fmax(mf, fabs(f));
-    }
-    double* r = J.red_lb + (size_t)c * kRedSlotsLB;
-    sf = block_sum<256>(sf, sh);
-    sg = block_sum<256>(sg, sh);
-    mh = block_max<256>(mh, sh);
-    mg = block_max<256>(mg, sh);
-    mf = block_max<256>(mf, sh);
-    if (threadIdx.x == 0) { r[0] = sf; r[1] = sg; r[2] = mh; r[3] = mg; r[4] = mf; }
-  }
-}
-
 // ------------------------------------------------------------------ IPF (Algorithm 4)
 //
 // With the uniform kernel, pi^ b is constant on every block:
@@ -752,6 +721,76 @@ __global__ __launch_bounds__(256) void k_scalings(const DevJob* __restrict__ job
       const int K = J.d == 2 ? (x1 / k) * n + x2 / k : ((x0 / k) * n + x1 / k) * n + x2 / k;
       J.a_s[i] = u[K] > 0.0 ? J.mu[i] / u[K] : 0.0;
       J.b_s[i] = v[K] > 0.0 ? J.nu[i] / v[K] : 0.0;
+    }
+  }
+}
+
+// The forward pass's pixel sweep after IPF (one read of f, g, f^, mu, nu for
+// three jobs): per chunk the lower-bound sums <f, mu>, <g, nu> and the maxima
+// |f^|, |g|, |f| of the feasibility shift; the fine scalings of k_scalings
+// (written out for the plan cost and the backward pass); the weighted-TV
+// partials of k_tv_partial, with the same arithmetic as those two kernels.
+// Every partial goes to its chunk's slot; k_finalize adds them in order.
+__global__ __launch_bounds__(256) void k_fwd_pixels(const DevJob* __restrict__ jobs, int njobs,
+                                                    const int* __restrict__ off, int total) {
+  __shared__ double sh[256];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    const int T = (int)J.result[RS_IPF_ITERS];
+    const double* u = J.ipf_u + (size_t)T * J.Q;
+    const double* un = J.ipf_u + (size_t)(T + 1) * J.Q;
+    const double* v = J.ipf_v + (size_t)T * J.Q;
+    const int c = it - off[jb];
+    const int base = c * kChunk;
+    const double hN = 0.5 * (J.N - 1);
+    const int n = J.n, k = J.k;
+    double sf = 0.0, sg = 0.0, mh = 0.0, mg = 0.0, mf = 0.0;
+    double tm = 0.0, tn = 0.0, wm = 0.0, wn = 0.0;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int i = base + q;
+      if (i >= J.P) break;
+      const double mu = J.mu[i], nu = J.nu[i];
+      // lower bound
+      const double f = J.f[i], g = J.g[i];
+      sf += f * mu;
+      sg += g * nu;
+      mh = fmax(mh, fabs((double)J.fhat[i]));
+      mg = fmax(mg, fabs(g));
+      mf = fmax(mf, fabs(f));
+      // scalings
+      int x0, x1, x2;
+      pix_coords(i, J.N, J.d, x0, x1, x2);
+      const int K = J.d == 2 ? (x1 / k) * n + x2 / k : ((x0 / k) * n + x1 / k) * n + x2 / k;
+      const double as = u[K] > 0.0 ? mu / u[K] : 0.0;
+      const double bs = v[K] > 0.0 ? nu / v[K] : 0.0;
+      J.a_s[i] = as;
+      J.b_s[i] = bs;
+      // weighted TV
+      const double d0 = J.d == 2 ? 0.0 : x0 - hN, d1 = x1 - hN, d2 = x2 - hN;
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double w = J.p == 2 ? r2 : sqrt(r2);
+      const double muh = as * un[K];
+      const double nuh = bs * v[K];
+      tm += w * fabs(muh - mu);
+      tn += w * fabs(nu - nuh);
+      wm += w * mu;
+      wn += w * nu;
+    }
+    sf = block_sum<256>(sf, sh);
+    sg = block_sum<256>(sg, sh);
+    mh = block_max<256>(mh, sh);
+    mg = block_max<256>(mg, sh);
+    mf = block_max<256>(mf, sh);
+    tm = block_sum<256>(tm, sh);
+    tn = block_sum<256>(tn, sh);
+    wm = block_sum<256>(wm, sh);
+    wn = block_sum<256>(wn, sh);
+    if (threadIdx.x == 0) {
+      double* r = J.red_lb + (size_t)c * kRedSlotsLB;
+      r[0] = sf; r[1] = sg; r[2] = mh; r[3] = mg; r[4] = mf;
+      double* t = J.red_tv + (size_t)c * kRedSlotsTV;
+      t[0] = tm; t[1] = tn; t[2] = wm; t[3] = wn;
     }
   }
 }
@@ -1053,7 +1092,7 @@ __global__ __launch_bounds__(256) void k_lb_grad(const DevJob* __restrict__ jobs
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
-    if (!J.grad_a || !J.grad_b) continue;
+    if (!J.grad_a || !J.grad_b || J.p == 2) continue;   // p = 2: k_grad2
     const double Se = J.result[RS_LOWER_S];
     const double s = Se > 0.0 ? (J.p == 2 ? 0.5 / sqrt(Se) : 1.0) * dl[jb] : 0.0;
     const int base = (it - off[jb]) * kChunk;
@@ -1153,8 +1192,61 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
 // coarse block B.  For a member x of B the direct term is
 //   h(x) = sum over entries e of B's row (column) of coef_e sum_{y in O_e} w(y) c(x, y)
 // with w = nu (side 0) or mu (side 1) and O_e the other block of the entry.
-// p = 2 uses the moments of w over O_e about its centre: with z = x - c_O,
-//   sum_y w(y) |x - y|^2 = W0 |z|^2 - 2 z.W1 + W2.
+// (k_ub_grad below handles p = 1 this way, y by y through LDS tiles.)
+// Gradients of dl * lower + du * upper for p = 2 jobs, one thread per pixel
+// (coalesced): the lower-bound term s_L f_i (resp. s_L g_j), then the
+// upper-bound term s_U (h_i + gbar_K) with
+//   h_i = sum over the support entries e of the pixel's block row (column):
+//         coef_e * sum_{j in block L} nu_j |x_i - x_j|^2,
+// the inner sum taken from the block moments of nu (mu) about the block
+// centre c_L: with z = x_i - c_L, it is M0 |z|^2 - 2 z . M1 + M2.
+__global__ __launch_bounds__(256) void k_grad2(const DevJob* __restrict__ jobs, int njobs,
+                                               const int* __restrict__ off, int total,
+                                               const double* __restrict__ dl, const double* __restrict__ du) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    if (J.p != 2) continue;
+    const bool lb = J.grad_a && J.grad_b;
+    const double Se = J.result[RS_LOWER_S];
+    const double sL = Se > 0.0 ? 0.5 / sqrt(Se) * dl[jb] : 0.0;
+    const double Pc = J.result[RS_PCOST_RAW];
+    const double sU = Pc > 0.0 ? 0.5 / sqrt(Pc) * du[jb] : 0.0;
+    const int base = (it - off[jb]) * kChunk;
+    const int n = J.n, k = J.k;
+    const double hk = 0.5 * (k - 1);
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int i = base + q;
+      if (i >= J.P) break;
+      int x0, x1, x2;
+      pix_coords(i, J.N, J.d, x0, x1, x2);
+      const int B = J.d == 2 ? (x1 / k) * n + x2 / k : ((x0 / k) * n + x1 / k) * n + x2 / k;
+      for (int side = 0; side < 2; ++side) {
+        double* grad = side == 0 ? J.grad_a : J.grad_b;
+        if (!grad) continue;
+        const double* omom = side == 0 ? J.mom_nu : J.mom_mu;
+        const int e0 = side == 0 ? J.csr_ptr[B] : J.csc_ptr[B];
+        const int e1 = side == 0 ? J.csr_ptr[B + 1] : J.csc_ptr[B + 1];
+        double h = 0.0;
+        for (int qq = e0; qq < e1; ++qq) {
+          const int e = side == 0 ? qq : J.csc_idx[qq];
+          const int O = side == 0 ? J.e_col[e] : J.e_row[e];
+          int o0, o1, o2;
+          pix_coords(O, n, J.d, o0, o1, o2);
+          const double z0 = J.d == 2 ? 0.0 : x0 - (k * o0 + hk);
+          const double z1 = x1 - (k * o1 + hk), z2 = x2 - (k * o2 + hk);
+          const double* W = omom + 5 * (size_t)O;
+          h += J.coef[e] * (W[0] * (z0 * z0 + z1 * z1 + z2 * z2) - 2.0 * (z0 * W[1] + z1 * W[2] + z2 * W[3]) + W[4]);
+        }
+        double g = grad[i];
+        if (lb) g += sL * (double)(side == 0 ? J.f[i] : J.g[i]);
+        g += sU * (h + (side == 0 ? J.gbar_mu[B] : J.gbar_nu[B]));
+        grad[i] = g;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(64) void k_ub_grad(const DevJob* __restrict__ jobs, int njobs,
                                                 const int* __restrict__ off, int total,
                                                 const double* __restrict__ du, int side) {
@@ -1164,39 +1256,15 @@ __global__ __launch_bounds__(64) void k_ub_grad(const DevJob* __restrict__ jobs,
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
     double* grad = side == 0 ? J.grad_a : J.grad_b;
-    if (!grad) continue;
+    if (!grad || J.p == 2) continue;   // p = 2 jobs: k_grad2
     const int B = it - off[jb];
     const double P = J.result[RS_PCOST_RAW];
-    const double s = P > 0.0 ? (J.p == 2 ? 0.5 / sqrt(P) : 1.0) * du[jb] : 0.0;
+    const double s = P > 0.0 ? du[jb] : 0.0;   // d P^(1/p) / d P = 1 for p = 1
     const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
     const double* other = side == 0 ? J.nu : J.mu;
-    const double* omom = side == 0 ? J.mom_nu : J.mom_mu;
     const double base_g = side == 0 ? J.gbar_mu[B] : J.gbar_nu[B];
     const int e0 = side == 0 ? J.csr_ptr[B] : J.csc_ptr[B];
     const int e1 = side == 0 ? J.csr_ptr[B + 1] : J.csc_ptr[B + 1];
-    int b0, b1, b2;
-    pix_coords(B, J.n, J.d, b0, b1, b2);
-    if (J.p == 2) {
-      for (int a = threadIdx.x; a < m; a += 64) {
-        const int i = block_member(B, a, J.N, J.n, J.k, J.d);
-        int x0, x1, x2;
-        pix_coords(i, J.N, J.d, x0, x1, x2);
-        double h = 0.0;
-        for (int q = e0; q < e1; ++q) {
-          const int e = side == 0 ? q : J.csc_idx[q];
-          const int O = side == 0 ? J.e_col[e] : J.e_row[e];
-          int o0, o1, o2;
-          pix_coords(O, J.n, J.d, o0, o1, o2);
-          const double hk = 0.5 * (J.k - 1);
-          const double z0 = J.d == 2 ? 0.0 : x0 - (J.k * o0 + hk);
-          const double z1 = x1 - (J.k * o1 + hk), z2 = x2 - (J.k * o2 + hk);
-          const double* W = omom + 5 * (size_t)O;
-          h += J.coef[e] * (W[0] * (z0 * z0 + z1 * z1 + z2 * z2) - 2.0 * (z0 * W[1] + z1 * W[2] + z2 * W[3]) + W[4]);
-        }
-        grad[i] += s * (h + base_g);
-      }
-      continue;
-    }
     for (int a0 = 0; a0 < m; a0 += 64) {
       const int a = a0 + threadIdx.x;
       const int i = a < m ? block_member(B, a, J.N, J.n, J.k, J.d) : 0;
@@ -1337,11 +1405,6 @@ int launch_argmin(const DevJob* jobs, int njobs, const int* off, int total, int 
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_lb_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
-  hipLaunchKernelGGL(k_lb_partial, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
-  HIP_TRY(hipGetLastError());
-  return QBW_OK;
-}
 int launch_ipf(const DevJob* jobs, int njobs, void* stream) {
   hipLaunchKernelGGL(k_ipf, dim3(njobs), dim3(1024), 0, (hipStream_t)stream, jobs, njobs);
   HIP_TRY(hipGetLastError());
@@ -1396,6 +1459,17 @@ int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int st
 int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* du, int side,
                    void* stream) {
   hipLaunchKernelGGL(k_ub_grad, dim3(grid_for(total)), dim3(64), 0, (hipStream_t)stream, jobs, njobs, off, total, du, side);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
+  hipLaunchKernelGGL(k_fwd_pixels, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl, const double* du,
+                 void* stream) {
+  hipLaunchKernelGGL(k_grad2, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, dl, du);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -123,7 +123,6 @@ int launch_ctransform(const DevJob* jobs, const CtItem* items, const int* qoff, 
                       int phase, int grid, void* stream);
 int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
 int launch_argmin(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
-int launch_lb_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_ipf(const DevJob* jobs, int njobs, void* stream);
 int launch_scalings(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_tv_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
@@ -141,6 +140,9 @@ int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, con
                    int side, void* stream);
 int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
                       double* const* outs, void* stream);
+int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+int launch_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl, const double* du,
+                 void* stream);
 int launch_tv_prep(const DevJob* jobs, int njobs, void* stream);
 int launch_ct1d(const DevJob* jobs, int njobs, const int* off, int total, int phase, int pass,
                 void* stream);
