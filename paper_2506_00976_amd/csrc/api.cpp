@@ -329,7 +329,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   Layout L;
   struct Offs {
     size_t mu_t, nu_t, ftil, fhat, g, f, part, win, arg_g, arg_f, e_row, e_col, e_val, csr, csc,
-        csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, gbar_mu, gbar_nu, coef, mom_mu, mom_nu,
+        csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, gbar_mu, gbar_nu, coef, gquad, mom_mu, mom_nu,
         mom_as, mom_bs, sep_tmp, sep_arg;
   };
   std::vector<Offs> offs(NJ);
@@ -360,6 +360,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     O.gbar_mu = L.add(8 * (size_t)Q);
     O.gbar_nu = L.add(8 * (size_t)Q);
     O.coef = L.add(8 * (size_t)nnz);
+    O.gquad = L.add(8 * 10 * (size_t)Q);
     O.mom_mu = L.add(8 * 5 * (size_t)Q);
     O.mom_nu = L.add(8 * 5 * (size_t)Q);
     O.mom_as = L.add(8 * 5 * (size_t)Q);
@@ -507,6 +508,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.gbar_mu = (double*)(B + O.gbar_mu);
     D.gbar_nu = (double*)(B + O.gbar_nu);
     D.coef = (double*)(B + O.coef);
+    D.gquad = (double*)(B + O.gquad);
     D.mom_mu = (double*)(B + O.mom_mu);
     D.mom_nu = (double*)(B + O.mom_nu);
     D.mom_as = (double*)(B + O.mom_as);
@@ -681,7 +683,10 @@ static int enqueue_backward(Plan& pl, hipStream_t st) {
     CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 0, st));
     CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 1, st));
   }
-  if (pl.has_p2) CHK(launch_grad2(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, pl.du, st));
+  if (pl.has_p2) {
+    CHK(launch_grad2_quad(pl.djobs, NJ, pl.off_block, pl.tot_block, st));
+    CHK(launch_grad2(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, pl.du, st));
+  }
   return QBW_OK;
 }
 

@@ -1193,13 +1193,55 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
 //   h(x) = sum over entries e of B's row (column) of coef_e sum_{y in O_e} w(y) c(x, y)
 // with w = nu (side 0) or mu (side 1) and O_e the other block of the entry.
 // (k_ub_grad below handles p = 1 this way, y by y through LDS tiles.)
+// For p = 2 the direct upper-bound term of a pixel x in block K is a quadratic
+// in z = x - c_K (c_K the block centre).  With D_e = c_K - c_L for the other
+// block L of a support entry e and the moments W0 = sum w_y, W1 = sum w_y
+// (y - c_L), W2 = sum w_y |y - c_L|^2 of w (nu for side 0, mu for side 1)
+// over L:
+//   sum_y w_y |x - y|^2 = W0 |z + D_e|^2 - 2 (z + D_e).W1 + W2,
+// so h(x) = sum_e coef_e (...) = A |z|^2 + B.z + C with
+//   A = sum coef_e W0,  B = sum coef_e (2 W0 D_e - 2 W1),
+//   C = sum coef_e (W0 |D_e|^2 - 2 D_e.W1 + W2).
+// One thread per coarse block and side writes (A, B0, B1, B2, C).
+__global__ __launch_bounds__(256) void k_grad2_quad(const DevJob* __restrict__ jobs, int njobs,
+                                                    const int* __restrict__ off, int total) {
+  for (int gi = blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += gridDim.x * blockDim.x) {
+    const int jb = find_job(off, njobs, gi);
+    const DevJob& J = jobs[jb];
+    if (J.p != 2) continue;
+    const int K = gi - off[jb];
+    const int n = J.n;
+    int k0, k1, k2;
+    pix_coords(K, n, J.d, k0, k1, k2);
+    for (int side = 0; side < 2; ++side) {
+      const double* omom = side == 0 ? J.mom_nu : J.mom_mu;
+      const int e0 = side == 0 ? J.csr_ptr[K] : J.csc_ptr[K];
+      const int e1 = side == 0 ? J.csr_ptr[K + 1] : J.csc_ptr[K + 1];
+      double A = 0.0, B0 = 0.0, B1 = 0.0, B2 = 0.0, C = 0.0;
+      for (int q = e0; q < e1; ++q) {
+        const int e = side == 0 ? q : J.csc_idx[q];
+        const int O = side == 0 ? J.e_col[e] : J.e_row[e];
+        int o0, o1, o2;
+        pix_coords(O, n, J.d, o0, o1, o2);
+        const double D0 = J.d == 2 ? 0.0 : (double)(J.k * (k0 - o0));
+        const double D1 = (double)(J.k * (k1 - o1)), D2 = (double)(J.k * (k2 - o2));
+        const double* W = omom + 5 * (size_t)O;
+        const double cf = J.coef[e];
+        A += cf * W[0];
+        B0 += cf * (2.0 * W[0] * D0 - 2.0 * W[1]);
+        B1 += cf * (2.0 * W[0] * D1 - 2.0 * W[2]);
+        B2 += cf * (2.0 * W[0] * D2 - 2.0 * W[3]);
+        C += cf * (W[0] * (D0 * D0 + D1 * D1 + D2 * D2) - 2.0 * (D0 * W[1] + D1 * W[2] + D2 * W[3]) + W[4]);
+      }
+      double* o = J.gquad + (size_t)10 * K + 5 * side;
+      o[0] = A; o[1] = B0; o[2] = B1; o[3] = B2; o[4] = C;
+    }
+  }
+}
+
 // Gradients of dl * lower + du * upper for p = 2 jobs, one thread per pixel
 // (coalesced): the lower-bound term s_L f_i (resp. s_L g_j), then the
-// upper-bound term s_U (h_i + gbar_K) with
-//   h_i = sum over the support entries e of the pixel's block row (column):
-//         coef_e * sum_{j in block L} nu_j |x_i - x_j|^2,
-// the inner sum taken from the block moments of nu (mu) about the block
-// centre c_L: with z = x_i - c_L, it is M0 |z|^2 - 2 z . M1 + M2.
+// upper-bound term s_U (h(x_i) + gbar_K) from the block's quadratic.
 __global__ __launch_bounds__(256) void k_grad2(const DevJob* __restrict__ jobs, int njobs,
                                                const int* __restrict__ off, int total,
                                                const double* __restrict__ dl, const double* __restrict__ du) {
@@ -1220,27 +1262,19 @@ __global__ __launch_bounds__(256) void k_grad2(const DevJob* __restrict__ jobs, 
       if (i >= J.P) break;
       int x0, x1, x2;
       pix_coords(i, J.N, J.d, x0, x1, x2);
-      const int B = J.d == 2 ? (x1 / k) * n + x2 / k : ((x0 / k) * n + x1 / k) * n + x2 / k;
+      const int b0 = x0 / k, b1 = x1 / k, b2 = x2 / k;
+      const int K = J.d == 2 ? b1 * n + b2 : (b0 * n + b1) * n + b2;
+      const double z0 = J.d == 2 ? 0.0 : x0 - (k * b0 + hk);
+      const double z1 = x1 - (k * b1 + hk), z2 = x2 - (k * b2 + hk);
+      const double zz = z0 * z0 + z1 * z1 + z2 * z2;
       for (int side = 0; side < 2; ++side) {
         double* grad = side == 0 ? J.grad_a : J.grad_b;
         if (!grad) continue;
-        const double* omom = side == 0 ? J.mom_nu : J.mom_mu;
-        const int e0 = side == 0 ? J.csr_ptr[B] : J.csc_ptr[B];
-        const int e1 = side == 0 ? J.csr_ptr[B + 1] : J.csc_ptr[B + 1];
-        double h = 0.0;
-        for (int qq = e0; qq < e1; ++qq) {
-          const int e = side == 0 ? qq : J.csc_idx[qq];
-          const int O = side == 0 ? J.e_col[e] : J.e_row[e];
-          int o0, o1, o2;
-          pix_coords(O, n, J.d, o0, o1, o2);
-          const double z0 = J.d == 2 ? 0.0 : x0 - (k * o0 + hk);
-          const double z1 = x1 - (k * o1 + hk), z2 = x2 - (k * o2 + hk);
-          const double* W = omom + 5 * (size_t)O;
-          h += J.coef[e] * (W[0] * (z0 * z0 + z1 * z1 + z2 * z2) - 2.0 * (z0 * W[1] + z1 * W[2] + z2 * W[3]) + W[4]);
-        }
+        const double* c = J.gquad + (size_t)10 * K + 5 * side;
+        const double h = c[0] * zz + (c[1] * z0 + c[2] * z1 + c[3] * z2) + c[4];
         double g = grad[i];
         if (lb) g += sL * (double)(side == 0 ? J.f[i] : J.g[i]);
-        g += sU * (h + (side == 0 ? J.gbar_mu[B] : J.gbar_nu[B]));
+        g += sU * (h + (side == 0 ? J.gbar_mu[K] : J.gbar_nu[K]));
         grad[i] = g;
       }
     }
@@ -1464,6 +1498,12 @@ int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, con
 }
 int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
   hipLaunchKernelGGL(k_fwd_pixels, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_grad2_quad(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
+  const int blocks = total < 1 ? 1 : std::min((total + 255) / 256, 65535);
+  hipLaunchKernelGGL(k_grad2_quad, dim3(blocks), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -92,6 +92,7 @@ struct DevJob {
   double* gbar_mu;          // Q: d P / d mu~ (coarse adjoint)
   double* gbar_nu;
   double* coef;             // nnz: d P / d S_e coefficient
+  double* gquad;            // Q x 2 x 5: per block and side, h(x) = A |z|^2 + B.z + C, z = x - centre
   // per-block moments about the block centre, 5 doubles per block:
   // (sum m, sum m delta_0, sum m delta_1, sum m delta_2, sum m |delta|^2)
   double* mom_mu;           // of mu
@@ -141,6 +142,7 @@ int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, con
 int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
                       double* const* outs, void* stream);
 int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+int launch_grad2_quad(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl, const double* du,
                  void* stream);
 int launch_tv_prep(const DevJob* jobs, int njobs, void* stream);
