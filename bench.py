@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the 128-job uneven batch (its coarse solves take seconds of host time)")
     ap.add_argument("--profile", action="store_true",
                     help="only the timed steps (for rocprofv3 runs)")
     ap.add_argument("--eager", action="store_true",
@@ -215,6 +217,46 @@ def main():
     rsep = sep.results()
     log(f"[bench] separable: {ms_sep:.3f} ms/step -> {B / (ms_sep / 1e3):.1f} pairs/s")
 
+    # ---- uneven batch: 128 jobs over 2D/3D grids, k in {2,4,8}, p in {1,2},
+    # one persistent launch per stage in a hipGraph, autotuned tiling
+    uneven = None
+    if not args.no_uneven:
+        import synth_inputs as si
+        jobs5 = si.config5_jobs(128)
+        J5 = [(torch.tensor(mu, device=dev), torch.tensor(nu, device=dev), kk, pp)
+              for (_, _, kk, pp, mu, nu) in jobs5]
+        t0 = time.perf_counter()
+        pooled = [(qbw.sumpool(a, kk).cpu().numpy(), qbw.sumpool(b, kk).cpu().numpy(), a.shape[0], a.dim(), kk, pp)
+                  for a, b, kk, pp in J5]
+        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            recs5 = list(ex.map(lambda t: qbw.coarse_solve(*t), pooled))
+        t_c5 = time.perf_counter() - t0
+        log(f"[bench] uneven batch: coarse solves {t_c5:.1f} s for {len(J5)} jobs on {workers} threads")
+        b5 = qbw.Batch(J5, coarse=recs5, backward=True, graph=True, autotune=True)
+        for _ in range(args.warmup):
+            b5.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b5.run()
+        torch.cuda.synchronize()
+        ms5 = (time.perf_counter() - t0) * 1e3 / args.steps
+        ev5 = qbw.Batch(J5, coarse=recs5, backward=True, graph=False)
+        ev5.run()
+        torch.cuda.synchronize()
+        ev5.set_timing(True)
+        for _ in range(3):
+            ev5.run()
+        m5, _ = ev5.ctransform_time()
+        pairs5 = ev5.ctransform_pairs()
+        log(f"[bench] uneven batch: {ms5:.3f} ms/step -> {len(J5) / (ms5 / 1e3):.1f} jobs/s; "
+            f"c-transform {pairs5 / (m5 / 1e3) / 1e12:.2f} Tpair/s")
+        uneven = {"jobs": len(J5), "jobs_per_s": len(J5) / (ms5 / 1e3), "ms_per_step": ms5,
+                  "workload": "128 jobs: 32^2, 64^2, 128^2, 16^3, 32^3 grids x k in {2,4,8} x p in {1,2}, "
+                              "GRF measures, forward+backward, hipGraph, autotuned; coarse pre-solved",
+                  "ctransform_Tpair_per_s": pairs5 / (m5 / 1e3) / 1e12,
+                  "ctransform_ms_per_launch": m5, "coarse_seconds": t_c5}
+
     # consistency of the timed results with the single-pair path
     ref = qbw.bounds(A[0], Bm[0], k, p, coarse=recs[0])
     assert ref["lower"] == res[0]["lower"] and ref["upper"] == res[0]["upper"], (ref, res[0])
@@ -251,6 +293,8 @@ def main():
                        "pairs_per_s_pipelined": B / max(t_coarse, ms_step / 1e3)},
         "bounds_sample": {"lower": res[0]["lower"], "upper": res[0]["upper"]},
     }
+    if uneven is not None:
+        out["uneven_batch"] = uneven
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(N, k, p)

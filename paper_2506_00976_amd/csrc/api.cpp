@@ -273,12 +273,11 @@ struct Plan {
   DevJob* djobs = nullptr;
   int *off_chunk = nullptr, *off_pool = nullptr, *off_entry = nullptr, *off_block = nullptr,
       *off_cbar = nullptr, *off_mom = nullptr, *off_pc1 = nullptr, *off_pc2 = nullptr,
-      *off_sep = nullptr;
+      *off_sep = nullptr, *off_ubg = nullptr;
   int tot_chunk = 0, tot_pool = 0, tot_entry = 0, tot_block = 0, tot_cbar = 0, tot_mom = 0,
-      tot_pc1 = 0, tot_pc2 = 0, tot_sep = 0, max_sep_d = 0;
+      tot_pc1 = 0, tot_pc2 = 0, tot_sep = 0, max_sep_d = 0, tot_ubg = 0;
   bool has_p1 = false, has_p2 = false;  // grid cost exponents present
   CtItem* items = nullptr;
-  int* qoff = nullptr;   // kQueues + 1 offsets into items
   int n_items = 0;
   int ct_grid = 1;
   int* ints = nullptr;   // [0, 2 kQueues) work counters of the two phases, then njobs flags
@@ -307,11 +306,17 @@ static int choose_splits(std::vector<JobIn>& in, int target_waves) {
     if (j.tiling.R <= 0) j.tiling.R = default_R(j.g.N);
     const int tiles = (P + 64 * j.tiling.R - 1) / (64 * j.tiling.R);
     if (j.tiling.S <= 0) {
+      // the job's share of one round of resident waves, rounded down so the
+      // batch never spills a few items into a second round (equal-sized items
+      // then finish together), and at least one split per tile
       const double share = std::pow((double)j.g.N, 2.0 * j.g.d) / total;
-      const double items = std::max<double>(tiles, share * target_waves);
-      j.tiling.S = (int)std::ceil(items / tiles);
+      j.tiling.S = std::max(1, (int)std::floor(share * target_waves / tiles));
     }
     j.tiling.S = std::max(1, std::min(j.tiling.S, rows));
+    // splits take whole source rows: with r = ceil(rows / S) rows per split,
+    // use no more splits than needed, so no split is longer than r rows
+    const int r = (rows + j.tiling.S - 1) / j.tiling.S;
+    j.tiling.S = (rows + r - 1) / r;
   }
   return QBW_OK;
 }
@@ -369,7 +374,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     O.sep_tmp = sep ? L.add(4 * 2 * (size_t)P) : 0;
     O.sep_arg = (sep && (mode & PM_ARGMIN)) ? L.add(4 * (size_t)d * P) : 0;
   }
-  constexpr int kTables = 9;
+  constexpr int kTables = 10;
   // c-transform work items, one queue per XCD.  Jobs get a home queue by
   // longest-processing-time assignment of their pair counts; a lone job (or one
   // too big for a single queue's share) spreads its target tiles over all queues.
@@ -406,14 +411,35 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
         }
     }
   }
-  std::vector<CtItem> items;
-  std::vector<int> qoff(kQueues + 1, 0);
+  // Item table: position b < G (the grid) is the item work-group b takes in
+  // the static round.  The dispatcher deals work-groups to the XCDs in turn,
+  // so positions b = q (mod kQueues) are XCD q's: they get queue q's items
+  // (largest first); surplus items of longer queues fill the positions left
+  // free by shorter ones, and what exceeds the grid forms the dynamic tail.
+  int n_all = 0;
   for (int q = 0; q < kQueues; ++q) {
     std::stable_sort(queues[q].begin(), queues[q].end(),
                      [&](const CtItem& x, const CtItem& y) { return item_cost(x) > item_cost(y); });
-    items.insert(items.end(), queues[q].begin(), queues[q].end());
-    qoff[q + 1] = (int)items.size();
+    n_all += (int)queues[q].size();
   }
+  // persistent grid: one work-group per item, at most 32 per compute unit
+  const int G = std::min(n_all, ctx->num_cu * 4 * 8);
+  std::vector<CtItem> items(n_all);
+  std::vector<CtItem> surplus;
+  std::vector<int> free_pos;
+  for (int q = 0; q < kQueues; ++q) {
+    size_t used = 0;
+    for (int b = q; b < G; b += kQueues) {
+      if (used < queues[q].size()) items[b] = queues[q][used++];
+      else free_pos.push_back(b);
+    }
+    surplus.insert(surplus.end(), queues[q].begin() + used, queues[q].end());
+  }
+  std::stable_sort(surplus.begin(), surplus.end(),
+                   [&](const CtItem& x, const CtItem& y) { return item_cost(x) > item_cost(y); });
+  size_t si = 0;
+  for (int b : free_pos) items[b] = surplus[si++];
+  for (int b = G; b < n_all; ++b) items[b] = surplus[si++];
   pl.n_items = (int)items.size();
   pl.n_ints = 2 * kQueues + NJ;
   const size_t o_ints = L.add(sizeof(int) * pl.n_ints);
@@ -428,7 +454,6 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   const size_t o_jobs = L.add(sizeof(DevJob) * NJ);
   const size_t o_offs = L.add(sizeof(int) * kTables * (NJ + 1));
   const size_t o_items = L.add(sizeof(CtItem) * std::max(1, pl.n_items));
-  const size_t o_qoff = L.add(sizeof(int) * (kQueues + 1));
   const size_t o_dl = L.add(8 * NJ), o_du = L.add(8 * NJ);
   const size_t o_ptrs = L.add(sizeof(double*) * 4 * NJ);
   for (int j = 0; j < NJ; ++j) {
@@ -525,6 +550,9 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + (D.p == 1 ? D.nnz : 0);
     off[7 * (NJ + 1) + j + 1] = off[7 * (NJ + 1) + j] + (D.p == 2 ? (D.nnz + 255) / 256 : 0);
     off[8 * (NJ + 1) + j + 1] = off[8 * (NJ + 1) + j] + (D.sep ? D.rows * ((D.N + 63) / 64) : 0);
+    // p = 1 upper-bound gradient: one item per 64 pixels of every block
+    const int mblk = ipow(D.k, D.d);
+    off[9 * (NJ + 1) + j + 1] = off[9 * (NJ + 1) + j] + (D.p == 1 ? D.Q * ((mblk + 63) / 64) : 0);
     if (D.sep) pl.max_sep_d = std::max(pl.max_sep_d, D.d);
     (D.p == 1 ? pl.has_p1 : pl.has_p2) = true;
   }
@@ -542,6 +570,8 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   pl.tot_pc2 = off[7 * (NJ + 1) + NJ];
   pl.off_sep = offd + 8 * (NJ + 1);
   pl.tot_sep = off[8 * (NJ + 1) + NJ];
+  pl.off_ubg = offd + 9 * (NJ + 1);
+  pl.tot_ubg = off[9 * (NJ + 1) + NJ];
   pl.tot_chunk = off[0 * (NJ + 1) + NJ];
   pl.tot_pool = off[1 * (NJ + 1) + NJ];
   pl.tot_entry = off[2 * (NJ + 1) + NJ];
@@ -549,7 +579,6 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   pl.tot_cbar = off[4 * (NJ + 1) + NJ];
   pl.tot_mom = off[5 * (NJ + 1) + NJ];
   pl.items = (CtItem*)(B + o_items);
-  pl.qoff = (int*)(B + o_qoff);
   pl.ints = (int*)(B + o_ints);
   pl.dl = (double*)(B + o_dl);
   pl.du = (double*)(B + o_du);
@@ -558,8 +587,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   double** ptrs = (double**)(B + o_ptrs);
   pl.cbar_out = ptrs;
   pl.fhat_grad_out = ptrs + 3 * NJ;
-  // persistent grid: enough waves to fill the chip, never more than the items
-  pl.ct_grid = std::max(1, std::min(pl.n_items, ctx->num_cu * 4 * 8));
+  pl.ct_grid = std::max(1, G);
 
   // uploads: the previous staged copy must have landed before the staging
   // memory is rewritten
@@ -589,7 +617,6 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   put(o_jobs, pl.hj.data(), sizeof(DevJob) * NJ);
   put(o_offs, off.data(), sizeof(int) * off.size());
   put(o_items, items.data(), sizeof(CtItem) * items.size());
-  put(o_qoff, qoff.data(), sizeof(int) * qoff.size());
   std::memset(at(o_ptrs), 0, sizeof(double*) * 4 * NJ);
   {
     const std::vector<double> ones(NJ, 1.0);
@@ -638,7 +665,7 @@ static int enqueue_ctransforms(Plan& pl, hipStream_t st) {
       ev = &pl.ev_pool[pl.ev_used++];
       HIPCHK(hipEventRecord(ev->first, st));
     }
-    CHK(launch_ctransform(pl.djobs, pl.items, pl.qoff, kQueues, pl.ints + phase * kQueues, phase, pl.ct_grid, st));
+    CHK(launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints + phase * kQueues, phase, pl.ct_grid, st));
     if (ev) HIPCHK(hipEventRecord(ev->second, st));
     CHK(launch_merge(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
     if (pl.mode & PM_ARGMIN) CHK(launch_argmin(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
@@ -680,8 +707,8 @@ static int enqueue_backward(Plan& pl, hipStream_t st) {
   if (pl.tot_pc2) CHK(launch_moments(pl.djobs, NJ, pl.off_mom, pl.tot_mom, 0, st));
   CHK(launch_ub_coarse_bwd2(pl.djobs, NJ, pl.bwd_scratch, pl.max_q, st));
   if (pl.has_p1) {
-    CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 0, st));
-    CHK(launch_ub_grad(pl.djobs, NJ, pl.off_block, pl.tot_block, pl.du, 1, st));
+    CHK(launch_ub_grad(pl.djobs, NJ, pl.off_ubg, pl.tot_ubg, pl.du, 0, st));
+    CHK(launch_ub_grad(pl.djobs, NJ, pl.off_ubg, pl.tot_ubg, pl.du, 1, st));
   }
   if (pl.has_p2) {
     CHK(launch_grad2_quad(pl.djobs, NJ, pl.off_block, pl.tot_block, st));
@@ -1176,7 +1203,7 @@ qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, 
   if (argmin) pl.hj[0].arg_g = argmin;
   HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_ctransform(pl.djobs, pl.items, pl.qoff, kQueues, pl.ints, 0, pl.ct_grid, st));
+  CHK(launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints, 0, pl.ct_grid, st));
   CHK(launch_merge(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, 0, st));
   if (argmin) CHK(launch_argmin(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, 0, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1295,7 +1322,7 @@ static double time_ctransform(qbw_ctx* ctx, Plan& pl, hipStream_t st, int reps) 
   for (int r = 0; r < reps; ++r) {
     (void)launch_reset_counter(pl.ints, pl.n_ints, st);
     (void)hipEventRecord(e0, st);
-    (void)launch_ctransform(pl.djobs, pl.items, pl.qoff, kQueues, pl.ints, 0, pl.ct_grid, st);
+    (void)launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints, 0, pl.ct_grid, st);
     (void)hipEventRecord(e1, st);
     if (hipEventSynchronize(e1) != hipSuccess) break;
     float ms = 0;

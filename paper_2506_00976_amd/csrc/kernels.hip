@@ -402,25 +402,15 @@ __device__ __forceinline__ void ct_tile(const float* __restrict__ src, float* __
   }
 }
 
-// XCD (accelerator complex die) the wave runs on: HW_REG_XCC_ID, bits [3:0].
-__device__ __forceinline__ int xcc_id() {
-  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15;
-}
-
-// Persistent c-transform: one work queue per XCD.  The planner gives every job
-// (or, for a single job, every target tile) a home XCD so the source
-// potentials a queue touches stay in that XCD's L2.
-//
-// Round one is static: work-group b takes item b / nq of queue b % nq (the
-// dispatcher deals work-groups to the XCDs in turn, so that is normally the
-// wave's own XCD's queue).  No atomics are needed for it, which matters: the
-// counters are shared by all XCDs, so every read-modify-write on them goes to
-// the memory side and thousands of them at a launch's start and end serialize.
-// Later rounds are dynamic: counters[q] counts items taken from queue q past
-// the static ones; a wave drains its own XCD's queue first and then steals, and
-// reads a counter before incrementing it so that exhausted queues cost no
-// atomics.  Every wave exits once all queues are empty.  Items of queue q are
-// items[qoff[q] .. qoff[q+1]).
+// Persistent c-transform.  The planner lays the items out so that position
+// b < G (the grid) is work-group b's item for the first round, positions
+// b = q (mod 8) holding XCD q's share: the dispatcher deals work-groups to the
+// XCDs in turn, so each XCD's source potentials stay in its own L2.  No atomics
+// are needed for that round, which matters: the counter is shared by all
+// XCDs, so every read-modify-write on it goes to the memory side and thousands
+// of them at a launch's start and end serialize.  Only when there are more
+// items than work-groups does a wave take further items (largest first) from
+// the tail through the counter; every wave exits once the tail is empty.
 __device__ __forceinline__ void ct_item(const DevJob* __restrict__ jobs, const CtItem& w, int phase) {
   const DevJob& J = jobs[w.job];
   const float* src = phase == 0 ? J.fhat : J.g;
@@ -448,32 +438,18 @@ __device__ __forceinline__ void ct_item(const DevJob* __restrict__ jobs, const C
 // cost window and the step pair's temporaries in at most 128 VGPRs.
 __attribute__((amdgpu_waves_per_eu(4)))
 __global__ __launch_bounds__(64) void k_ctransform(const DevJob* __restrict__ jobs,
-                                                   const CtItem* __restrict__ items,
-                                                   const int* __restrict__ qoff, int nq,
-                                                   int* __restrict__ counters, int phase) {
+                                                   const CtItem* __restrict__ items, int n_items,
+                                                   int* __restrict__ counter, int phase) {
   const int G = gridDim.x;
-  {
-    const int q = blockIdx.x % nq, idx = blockIdx.x / nq;
-    const int q0 = qoff[q];
-    if (idx < qoff[q + 1] - q0) ct_item(jobs, items[q0 + idx], phase);
-  }
-  const int home = xcc_id() % nq;
-  for (int qq = 0; qq < nq; ++qq) {
-    const int q = (home + qq) % nq;
-    const int q0 = qoff[q], qn = qoff[q + 1] - q0;
-    const int taken = (G - q + nq - 1) / nq;   // work-groups b < G with b % nq == q
-    for (;;) {
-      int it = qn;
-      if (threadIdx.x == 0) {
-        // counters only grow: a stale read can only lead to the atomic below
-        const int seen = __hip_atomic_load(counters + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (taken + seen < qn) it = taken + atomicAdd(counters + q, 1);
-      }
-      it = __shfl(it, 0);
-      it = __builtin_amdgcn_readfirstlane(it);
-      if (it >= qn) break;
-      ct_item(jobs, items[q0 + it], phase);
-    }
+  if ((int)blockIdx.x < n_items) ct_item(jobs, items[blockIdx.x], phase);
+  if (n_items <= G) return;
+  for (;;) {
+    int it = 0;
+    if (threadIdx.x == 0) it = G + atomicAdd(counter, 1);
+    it = __shfl(it, 0);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= n_items) break;
+    ct_item(jobs, items[it], phase);
   }
 }
 
@@ -879,6 +855,26 @@ __global__ __launch_bounds__(256) void k_plancost2(const DevJob* __restrict__ jo
   }
 }
 
+// sum_r w[r] |x - y_r| over an LDS tile (p = 1 cost: float64 square root of
+// the exact integer squared distance), in four interleaved partial sums so
+// that the additions do not form one long dependency chain.
+__device__ __forceinline__ double dist_dot(int x0, int x1, int x2, const double* w, const int (*c)[3], int tn) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int r = 0;
+  auto term = [&](int q) {
+    const int e0 = x0 - c[q][0], e1 = x1 - c[q][1], e2 = x2 - c[q][2];
+    return w[q] * sqrt((double)(e0 * e0 + e1 * e1 + e2 * e2));
+  };
+  for (; r + 4 <= tn; r += 4) {
+    s0 += term(r);
+    s1 += term(r + 1);
+    s2 += term(r + 2);
+    s3 += term(r + 3);
+  }
+  for (; r < tn; ++r) s0 += term(r);
+  return (s0 + s1) + (s2 + s3);
+}
+
 __global__ __launch_bounds__(256) void k_plancost(const DevJob* __restrict__ jobs, int njobs,
                                                   const int* __restrict__ off, int total) {
   __shared__ double sh[256];
@@ -904,12 +900,7 @@ __global__ __launch_bounds__(256) void k_plancost(const DevJob* __restrict__ job
         const int i = block_member(K, a, J.N, J.n, J.k, J.d);
         int x0, x1, x2;
         pix_coords(i, J.N, J.d, x0, x1, x2);
-        double s = 0.0;
-        for (int q = 0; q < tn; ++q) {
-          const int e0 = x0 - sc[q][0], e1 = x1 - sc[q][1], e2 = x2 - sc[q][2];
-          s += sb[q] * sqrt((double)(e0 * e0 + e1 * e1 + e2 * e2));
-        }
-        acc += J.a_s[i] * s;
+        acc += J.a_s[i] * dist_dot(x0, x1, x2, sb, sc, tn);
       }
       __syncthreads();
     }
@@ -1188,11 +1179,12 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
   }
 }
 
-// d upper / d mu (side 0) or d nu (side 1): one 64-thread work-group per
-// coarse block B.  For a member x of B the direct term is
+// d upper / d mu (side 0) or d nu (side 1).  For a member x of block B the
+// direct term is
 //   h(x) = sum over entries e of B's row (column) of coef_e sum_{y in O_e} w(y) c(x, y)
 // with w = nu (side 0) or mu (side 1) and O_e the other block of the entry.
-// (k_ub_grad below handles p = 1 this way, y by y through LDS tiles.)
+// k_ub_grad (p = 1) sums it y by y through LDS tiles, one 64-thread
+// work-group per (block, 64 of its pixels) so large blocks spread over many.
 // For p = 2 the direct upper-bound term of a pixel x in block K is a quadratic
 // in z = x - c_K (c_K the block centre).  With D_e = c_K - c_L for the other
 // block L of a support entry e and the moments W0 = sum w_y, W1 = sum w_y
@@ -1291,45 +1283,41 @@ __global__ __launch_bounds__(64) void k_ub_grad(const DevJob* __restrict__ jobs,
     const DevJob& J = jobs[jb];
     double* grad = side == 0 ? J.grad_a : J.grad_b;
     if (!grad || J.p == 2) continue;   // p = 2 jobs: k_grad2
-    const int B = it - off[jb];
+    // item = (block B, chunk of 64 of its pixels)
+    const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    const int per = (m + 63) / 64;
+    const int li = it - off[jb];
+    const int B = li / per;
+    const int a = (li - B * per) * 64 + threadIdx.x;
     const double P = J.result[RS_PCOST_RAW];
     const double s = P > 0.0 ? du[jb] : 0.0;   // d P^(1/p) / d P = 1 for p = 1
-    const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
     const double* other = side == 0 ? J.nu : J.mu;
     const double base_g = side == 0 ? J.gbar_mu[B] : J.gbar_nu[B];
     const int e0 = side == 0 ? J.csr_ptr[B] : J.csc_ptr[B];
     const int e1 = side == 0 ? J.csr_ptr[B + 1] : J.csc_ptr[B + 1];
-    for (int a0 = 0; a0 < m; a0 += 64) {
-      const int a = a0 + threadIdx.x;
-      const int i = a < m ? block_member(B, a, J.N, J.n, J.k, J.d) : 0;
-      int x0, x1, x2;
-      pix_coords(i, J.N, J.d, x0, x1, x2);
-      double h = 0.0;
-      for (int q = e0; q < e1; ++q) {
-        const int e = side == 0 ? q : J.csc_idx[q];
-        const int O = side == 0 ? J.e_col[e] : J.e_row[e];
-        const double cf = J.coef[e];
-        for (int t0 = 0; t0 < m; t0 += 512) {
-          const int tn = min(512, m - t0);
-          __syncthreads();
-          for (int r = threadIdx.x; r < tn; r += 64) {
-            const int j = block_member(O, t0 + r, J.N, J.n, J.k, J.d);
-            sw[r] = other[j];
-            pix_coords(j, J.N, J.d, sc[r][0], sc[r][1], sc[r][2]);
-          }
-          __syncthreads();
-          if (a < m) {
-            double acc = 0.0;
-            for (int r = 0; r < tn; ++r) {
-              const int d0 = x0 - sc[r][0], d1 = x1 - sc[r][1], d2 = x2 - sc[r][2];
-              acc += sw[r] * sqrt((double)(d0 * d0 + d1 * d1 + d2 * d2));
-            }
-            h += cf * acc;
-          }
+    const int i = a < m ? block_member(B, a, J.N, J.n, J.k, J.d) : 0;
+    int x0, x1, x2;
+    pix_coords(i, J.N, J.d, x0, x1, x2);
+    double h = 0.0;
+    for (int q = e0; q < e1; ++q) {
+      const int e = side == 0 ? q : J.csc_idx[q];
+      const int O = side == 0 ? J.e_col[e] : J.e_row[e];
+      const double cf = J.coef[e];
+      for (int t0 = 0; t0 < m; t0 += 512) {
+        const int tn = min(512, m - t0);
+        __syncthreads();
+        for (int r = threadIdx.x; r < tn; r += 64) {
+          const int j = block_member(O, t0 + r, J.N, J.n, J.k, J.d);
+          sw[r] = other[j];
+          pix_coords(j, J.N, J.d, sc[r][0], sc[r][1], sc[r][2]);
+        }
+        __syncthreads();
+        if (a < m) {
+          h += cf * dist_dot(x0, x1, x2, sw, sc, tn);
         }
       }
-      if (a < m) grad[i] += s * (h + base_g);
     }
+    if (a < m) grad[i] += s * (h + base_g);
   }
 }
 
@@ -1421,10 +1409,10 @@ int launch_reset_counter(int* counter, int n, void* stream) {
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_ctransform(const DevJob* jobs, const CtItem* items, const int* qoff, int nq, int* counters,
-                      int phase, int grid, void* stream) {
-  hipLaunchKernelGGL(k_ctransform, dim3(grid), dim3(64), 0, (hipStream_t)stream, jobs, items, qoff, nq,
-                     counters, phase);
+int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter, int phase, int grid,
+                      void* stream) {
+  hipLaunchKernelGGL(k_ctransform, dim3(grid), dim3(64), 0, (hipStream_t)stream, jobs, items, n_items, counter,
+                     phase);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -117,11 +117,11 @@ struct Launch {
 
 int launch_pool(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
-constexpr int kQueues = 8;  // one c-transform work queue per XCD
+constexpr int kQueues = 8;  // XCDs: the planner groups c-transform items per XCD
 // Waves of k_ctransform resident per compute unit (0 if the runtime cannot say).
 int ctransform_waves_per_cu();
-int launch_ctransform(const DevJob* jobs, const CtItem* items, const int* qoff, int nq, int* counters,
-                      int phase, int grid, void* stream);
+int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter, int phase, int grid,
+                      void* stream);
 int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
 int launch_argmin(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
 int launch_ipf(const DevJob* jobs, int njobs, void* stream);

@@ -611,3 +611,17 @@ def test_interpolant_flags_are_exclusive():
                         C.byref(opts), C.byref(res), None, C.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert rc == 1   # QBW_E_INVAL
     assert b"exclusive" in lib.qbw_last_error()
+
+
+def test_ctransform_with_dynamic_tail():
+    # 725 is odd, so each lane owns one target: 8213 tiles of 64 targets, more
+    # than the persistent grid's 8192 work-groups, so the last items are taken
+    # through the work counter after the static round
+    N, d, p = 725, 2, 2
+    phi = (si.rng(10600).standard_normal(N * N) * 2e4).astype(np.float32)
+    out, arg = qbw.ctransform(dev(phi), N, d, p, want_argmin=True)
+    P = N * N
+    tg = np.concatenate([si.rng(10601).choice(P, 12, replace=False), np.arange(P - 4, P)])
+    ref, refarg = lower.ctransform_o32(phi, N, d, p, targets=tg)
+    assert np.array_equal(out.cpu().numpy()[tg], ref)
+    assert np.array_equal(arg.cpu().numpy()[tg].astype(np.int64), refarg)
