@@ -280,7 +280,7 @@ struct Plan {
   CtItem* items = nullptr;
   int n_items = 0;
   int ct_grid = 1;
-  int* ints = nullptr;   // [0, 2 kQueues) work counters of the two phases, then njobs flags
+  int* ints = nullptr;   // ints[0], ints[kQueues]: the two phases' tail counters; from 2 kQueues: njobs flags
   int n_ints = 0;
   double* dl = nullptr;  // per-job upstream gradients
   double* du = nullptr;
@@ -375,9 +375,9 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     O.sep_arg = (sep && (mode & PM_ARGMIN)) ? L.add(4 * (size_t)d * P) : 0;
   }
   constexpr int kTables = 10;
-  // c-transform work items, one queue per XCD.  Jobs get a home queue by
+  // c-transform work items, grouped per XCD.  Jobs get a home XCD by
   // longest-processing-time assignment of their pair counts; a lone job (or one
-  // too big for a single queue's share) spreads its target tiles over all queues.
+  // too big for a single XCD's share) spreads its target tiles over all XCDs.
   // modelled cost of one item of each job (all of a job's items are alike)
   std::vector<double> job_item_cost(NJ);
   for (int j = 0; j < NJ; ++j) {

@@ -2,8 +2,9 @@
 //
 // Every kernel works on a table of jobs (DevJob), so one launch serves one
 // pair or a batch of pairs of uneven sizes.  Work items are mapped to jobs by
-// a prefix table (find_job); the c-transform instead pulls items from a
-// global work queue (persistent kernel).  Reductions are deterministic:
+// a prefix table (find_job); the c-transform is a persistent launch over a
+// planner-built item table (one item per work-group, the rest through a
+// counter).  Reductions are deterministic:
 // per-work-group partials in a fixed tree order, combined by a finalize
 // kernel in a fixed order - repeated runs are bitwise identical.
 #include <hip/hip_runtime.h>
