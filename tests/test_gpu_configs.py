@@ -11,6 +11,8 @@ arithmetic, so bit-for-bit) and, on sampled jobs, with the CPU oracle.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -154,3 +156,30 @@ def test_config5_uneven_batch_one_launch():
             L = lower.lower_bound_o32(mu, nu, ft, k, p)
             assert res["lower"] == pytest.approx(L["lower"], rel=1e-9)
             break
+
+
+@pytest.mark.parametrize("N,k", [(256, 16), (256, 32), (512, 16)])
+def test_config3_other_pooling_factors(N, k):
+    # the remaining (size, k) pairs of the 256^2 / 512^2 configuration: sampled
+    # c-transform targets bit-exact on the oracle's coarse potential, the plan
+    # cost equal to <pi~, C-bar> (uniform kernel), and bracketing of a translate
+    d, p = 2, 2
+    mu, nu = si.config3_pair(N, "grf")
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
+    rec = qbw.Coarse(r, c, v, ft)
+    fh_ref = lower.upscale_potential(ft, N, d, k).astype(np.float32)
+    fhat = qbw.upscale_potential(dev(ft), N, d, k)
+    assert np.array_equal(fhat.cpu().numpy(), fh_ref)
+    g, garg = qbw.ctransform(fhat, N, d, p, want_argmin=True)
+    tg = si.rng(9600 + N + k).choice(N * N, 24, replace=False)
+    ref, refarg = lower.ctransform_o32(fh_ref, N, d, p, targets=tg)
+    assert np.array_equal(g.cpu().numpy()[tg], ref)
+    assert np.array_equal(garg.cpu().numpy()[tg].astype(np.int64), refarg)
+    out = qbw.bounds(dev(mu), dev(nu), k, p, coarse=rec)
+    Cb = qbw.cbar(dev(mu), dev(nu), k, p).cpu().numpy()
+    assert out["upper_cost"] == pytest.approx(float((Cb[r, c] * v).sum()), rel=1e-8)
+    assert 0.0 <= out["lower"] <= out["upper"]
+    a, b = si.translated_pair(N, d, (13, -7), si.rng(9700 + N + k))
+    t = qbw.bounds(dev(a), dev(b), k, p)
+    W = math.sqrt(13 ** 2 + 7 ** 2)
+    assert t["lower"] <= W <= t["upper"]
