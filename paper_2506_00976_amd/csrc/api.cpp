@@ -542,11 +542,12 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.sep_tmp = D.sep ? (float*)(B + O.sep_tmp) : nullptr;
     D.sep_arg = (D.sep && (mode & PM_ARGMIN)) ? (int*)(B + O.sep_arg) : nullptr;
     off[0 * (NJ + 1) + j + 1] = off[0 * (NJ + 1) + j] + D.chunks;
-    off[1 * (NJ + 1) + j + 1] = off[1 * (NJ + 1) + j] + (D.Q + 255) / 256;
+    const int bpw = 64 / reduce_group(ipow(D.k, D.d));   // blocks per wave in pooling / moments
+    off[1 * (NJ + 1) + j + 1] = off[1 * (NJ + 1) + j] + (D.Q + 4 * bpw - 1) / (4 * bpw);
     off[2 * (NJ + 1) + j + 1] = off[2 * (NJ + 1) + j] + D.nnz;
     off[3 * (NJ + 1) + j + 1] = off[3 * (NJ + 1) + j] + D.Q;
     off[4 * (NJ + 1) + j + 1] = off[4 * (NJ + 1) + j] + (int)(((long long)D.Q * D.Q + 255) / 256);
-    off[5 * (NJ + 1) + j + 1] = off[5 * (NJ + 1) + j] + (2 * D.Q + 255) / 256;
+    off[5 * (NJ + 1) + j + 1] = off[5 * (NJ + 1) + j] + (2 * D.Q + 4 * bpw - 1) / (4 * bpw);
     off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + (D.p == 1 ? D.nnz : 0);
     off[7 * (NJ + 1) + j + 1] = off[7 * (NJ + 1) + j] + (D.p == 2 ? (D.nnz + 255) / 256 : 0);
     off[8 * (NJ + 1) + j + 1] = off[8 * (NJ + 1) + j] + (D.sep ? D.rows * ((D.N + 63) / 64) : 0);

@@ -106,27 +106,48 @@ __device__ __forceinline__ float sqrt_rn_int(float x) {
 
 // ------------------------------------------------------------------ pooling
 
+// Blocks are reduced by groups of g lanes, g the smallest power of two
+// >= min(k^d, 64): a wave takes 64 / g blocks (small blocks share a wave, a
+// large block spreads over all 64 lanes).  Group sums use a butterfly over the
+// group's lanes, in a fixed order.
+__device__ __forceinline__ double group_sum(double v, int g) {
+  for (int o = g >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block sums (SumPool) of a and b, four waves per work-group; negative and NaN
+// entries raise the job's flags.
 __global__ __launch_bounds__(256) void k_pool(const DevJob* __restrict__ jobs, int njobs,
                                               const int* __restrict__ off, int total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
-    const int K = (it - off[jb]) * 256 + threadIdx.x;
-    if (K >= J.Q) continue;
     const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    const int g = reduce_group(m);
+    const int K = ((it - off[jb]) * 4 + wv) * (64 / g) + lane / g;
+    const int sub = lane & (g - 1);
+    const bool ok = K < J.Q;
     double sm = 0.0, sn = 0.0;
     int bad = 0;
-    for (int t = 0; t < m; ++t) {
-      const int i = block_member(K, t, J.N, J.n, J.k, J.d);
-      const double x = J.mu[i], y = J.nu[i];
-      sm += x;
-      sn += y;
-      bad |= (x < 0.0 || y < 0.0) ? 1 : 0;
-      bad |= (x != x || y != y) ? 2 : 0;
+    if (ok) {
+      for (int t = sub; t < m; t += g) {
+        const int i = block_member(K, t, J.N, J.n, J.k, J.d);
+        const double x = J.mu[i], y = J.nu[i];
+        sm += x;
+        sn += y;
+        bad |= (x < 0.0 || y < 0.0) ? 1 : 0;
+        bad |= (x != x || y != y) ? 2 : 0;
+      }
     }
-    J.mu_t[K] = sm;
-    J.nu_t[K] = sn;
-    if (bad) atomicOr(J.flags, bad);
+    sm = group_sum(sm, g);
+    sn = group_sum(sn, g);
+    for (int o = g >> 1; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
+    if (ok && sub == 0) {
+      J.mu_t[K] = sm;
+      J.nu_t[K] = sn;
+      if (bad) atomicOr(J.flags, bad);
+    }
   }
 }
 
@@ -1051,28 +1072,38 @@ __global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, i
 // (mom_mu, mom_nu); which = 1 -> (a_s, b_s) into (mom_as, mom_bs).
 __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs, int njobs,
                                                  const int* __restrict__ off, int total, int which) {
+  // (side, block) pairs reduced by lane groups as in k_pool
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
-    const int idx = (it - off[jb]) * 256 + threadIdx.x;
-    if (idx >= 2 * J.Q) continue;
-    const int side = idx / J.Q, K = idx - side * J.Q;
-    const double* m = which == 0 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
-    double* o = (which == 0 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs)) + 5 * (size_t)K;
     const int mm = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    const int g = reduce_group(mm);
+    const int idx = ((it - off[jb]) * 4 + wv) * (64 / g) + lane / g;
+    const int sub = lane & (g - 1);
+    const bool ok = idx < 2 * J.Q;
+    const int side = ok ? idx / J.Q : 0, K = ok ? idx - side * J.Q : 0;
+    const double* m = which == 0 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
     const double h = 0.5 * (J.k - 1);
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
-    for (int a = 0; a < mm; ++a) {
-      const int i = block_member(K, a, J.N, J.n, J.k, J.d);
-      int u0, u1, u2;
-      pix_coords(a, J.k, J.d, u0, u1, u2);
-      const double d0 = J.d == 2 ? 0.0 : u0 - h, d1 = u1 - h, d2 = u2 - h;
-      const double w = m[i];
-      s0 += w;
-      s1 += w * d0; s2 += w * d1; s3 += w * d2;
-      s4 += w * (d0 * d0 + d1 * d1 + d2 * d2);
+    if (ok) {
+      for (int a = sub; a < mm; a += g) {
+        const int i = block_member(K, a, J.N, J.n, J.k, J.d);
+        int u0, u1, u2;
+        pix_coords(a, J.k, J.d, u0, u1, u2);
+        const double d0 = J.d == 2 ? 0.0 : u0 - h, d1 = u1 - h, d2 = u2 - h;
+        const double w = m[i];
+        s0 += w;
+        s1 += w * d0; s2 += w * d1; s3 += w * d2;
+        s4 += w * (d0 * d0 + d1 * d1 + d2 * d2);
+      }
     }
-    o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3; o[4] = s4;
+    s0 = group_sum(s0, g); s1 = group_sum(s1, g); s2 = group_sum(s2, g);
+    s3 = group_sum(s3, g); s4 = group_sum(s4, g);
+    if (ok && sub == 0) {
+      double* o = (which == 0 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs)) + 5 * (size_t)K;
+      o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3; o[4] = s4;
+    }
   }
 }
 

@@ -41,6 +41,13 @@ enum ResultSlot {
   RS_COUNT = 24
 };
 
+// Lanes that reduce one coarse block in the pooling and moment kernels: the
+// smallest power of two >= min(m, 64), m = pixels per block.
+constexpr int reduce_group(int m) {
+  int g = 1;
+  while (g < m && g < 64) g <<= 1;
+  return g;
+}
 constexpr int kChunk = 1024;       // pixels per work-group in the O(P) kernels
 constexpr int kRedSlotsLB = 5;     // per chunk: sum f*mu, sum g*nu, max|fhat|, max|g|, max|f|
 constexpr int kRedSlotsTV = 4;     // per chunk: sum w|mu^-mu|, sum w|nu-nu^|, sum w mu, sum w nu
