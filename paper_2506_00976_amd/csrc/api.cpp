@@ -334,7 +334,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   Layout L;
   struct Offs {
     size_t mu_t, nu_t, ftil, fhat, g, f, part, win, arg_g, arg_f, e_row, e_col, e_val, csr, csc,
-        csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, gbar_mu, gbar_nu, coef, gquad, mom_mu, mom_nu,
+        csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, gbar_mu, gbar_nu, coef, gquad, part1, mom_mu, mom_nu,
         mom_as, mom_bs, sep_tmp, sep_arg;
   };
   std::vector<Offs> offs(NJ);
@@ -366,6 +366,10 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     O.gbar_nu = L.add(8 * (size_t)Q);
     O.coef = L.add(8 * (size_t)nnz);
     O.gquad = L.add(8 * 10 * (size_t)Q);
+    {
+      const int mb = ipow(J.g.k, d);
+      O.part1 = J.g.p == 1 ? L.add(8 * (size_t)nnz * ((mb + 63) / 64) * 64) : 0;
+    }
     O.mom_mu = L.add(8 * 5 * (size_t)Q);
     O.mom_nu = L.add(8 * 5 * (size_t)Q);
     O.mom_as = L.add(8 * 5 * (size_t)Q);
@@ -534,6 +538,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.gbar_nu = (double*)(B + O.gbar_nu);
     D.coef = (double*)(B + O.coef);
     D.gquad = (double*)(B + O.gquad);
+    D.part1 = D.p == 1 ? (double*)(B + O.part1) : nullptr;
     D.mom_mu = (double*)(B + O.mom_mu);
     D.mom_nu = (double*)(B + O.mom_nu);
     D.mom_as = (double*)(B + O.mom_as);
@@ -548,12 +553,13 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     off[3 * (NJ + 1) + j + 1] = off[3 * (NJ + 1) + j] + D.Q;
     off[4 * (NJ + 1) + j + 1] = off[4 * (NJ + 1) + j] + (int)(((long long)D.Q * D.Q + 255) / 256);
     off[5 * (NJ + 1) + j + 1] = off[5 * (NJ + 1) + j] + (2 * D.Q + 4 * bpw - 1) / (4 * bpw);
-    off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + (D.p == 1 ? D.nnz : 0);
+    // p = 1 plan cost: one item per (entry, 64 pixels of its row block)
+    off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + (D.p == 1 ? D.nnz * ((ipow(D.k, D.d) + 63) / 64) : 0);
     off[7 * (NJ + 1) + j + 1] = off[7 * (NJ + 1) + j] + (D.p == 2 ? (D.nnz + 255) / 256 : 0);
     off[8 * (NJ + 1) + j + 1] = off[8 * (NJ + 1) + j] + (D.sep ? D.rows * ((D.N + 63) / 64) : 0);
-    // p = 1 upper-bound gradient: one item per 64 pixels of every block
+    // p = 1 upper-bound gradient: one item per (entry, 64 pixels of the block)
     const int mblk = ipow(D.k, D.d);
-    off[9 * (NJ + 1) + j + 1] = off[9 * (NJ + 1) + j] + (D.p == 1 ? D.Q * ((mblk + 63) / 64) : 0);
+    off[9 * (NJ + 1) + j + 1] = off[9 * (NJ + 1) + j] + (D.p == 1 ? D.nnz * ((mblk + 63) / 64) : 0);
     if (D.sep) pl.max_sep_d = std::max(pl.max_sep_d, D.d);
     (D.p == 1 ? pl.has_p1 : pl.has_p2) = true;
   }
@@ -680,7 +686,10 @@ static int enqueue_plancost(Plan& pl, hipStream_t st) {
     CHK(launch_moments(pl.djobs, NJ, pl.off_mom, pl.tot_mom, 1, st));
     CHK(launch_plancost2(pl.djobs, NJ, pl.off_pc2, pl.tot_pc2, st));
   }
-  if (pl.tot_pc1) CHK(launch_plancost(pl.djobs, NJ, pl.off_pc1, pl.tot_pc1, st));
+  if (pl.tot_pc1) {
+    CHK(launch_plancost(pl.djobs, NJ, pl.off_pc1, pl.tot_pc1, st));
+    CHK(launch_pc1_sum(pl.djobs, NJ, st));
+  }
   return QBW_OK;
 }
 
@@ -708,8 +717,10 @@ static int enqueue_backward(Plan& pl, hipStream_t st) {
   if (pl.tot_pc2) CHK(launch_moments(pl.djobs, NJ, pl.off_mom, pl.tot_mom, 0, st));
   CHK(launch_ub_coarse_bwd2(pl.djobs, NJ, pl.bwd_scratch, pl.max_q, st));
   if (pl.has_p1) {
-    CHK(launch_ub_grad(pl.djobs, NJ, pl.off_ubg, pl.tot_ubg, pl.du, 0, st));
-    CHK(launch_ub_grad(pl.djobs, NJ, pl.off_ubg, pl.tot_ubg, pl.du, 1, st));
+    for (int side = 0; side < 2; ++side) {   // per-entry partials, then per-pixel sums
+      CHK(launch_ub_grad(pl.djobs, NJ, pl.off_ubg, pl.tot_ubg, pl.du, side, st));
+      CHK(launch_ub_grad_sum(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.du, side, st));
+    }
   }
   if (pl.has_p2) {
     CHK(launch_grad2_quad(pl.djobs, NJ, pl.off_block, pl.tot_block, st));

@@ -877,15 +877,28 @@ __global__ __launch_bounds__(256) void k_plancost2(const DevJob* __restrict__ jo
   }
 }
 
-// sum_r w[r] |x - y_r| over an LDS tile (p = 1 cost: float64 square root of
-// the exact integer squared distance), in four interleaved partial sums so
-// that the additions do not form one long dependency chain.
+// sqrt(n) for an integer 0 <= n < 2^24 in float64 to a relative error below
+// 2^-42: the float32 reciprocal square root r (within a few units of 2^-24)
+// refined by one Newton step on y = n r, y + (r/2)(n - y^2), whose error is
+// 1.5 times the square of r's.  Used for the p = 1 plan cost and gradient
+// sums; the emitted upper bound's outward allowance covers it.
+__device__ __forceinline__ double sqrt_int_f64(int n) {
+  const double r = (double)__builtin_amdgcn_rsqf((float)n);
+  const double dn = (double)n;
+  const double y = dn * r;
+  const double z = fma(0.5 * r, fma(-y, y, dn), y);
+  return n > 0 ? z : 0.0;
+}
+
+// sum_r w[r] |x - y_r| over an LDS tile (p = 1 cost of the exact integer
+// squared distance), in four interleaved partial sums so that the additions
+// do not form one long dependency chain.
 __device__ __forceinline__ double dist_dot(int x0, int x1, int x2, const double* w, const int (*c)[3], int tn) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int r = 0;
   auto term = [&](int q) {
     const int e0 = x0 - c[q][0], e1 = x1 - c[q][1], e2 = x2 - c[q][2];
-    return w[q] * sqrt((double)(e0 * e0 + e1 * e1 + e2 * e2));
+    return w[q] * sqrt_int_f64(e0 * e0 + e1 * e1 + e2 * e2);
   };
   for (; r + 4 <= tn; r += 4) {
     s0 += term(r);
@@ -897,37 +910,58 @@ __device__ __forceinline__ double dist_dot(int x0, int x1, int x2, const double*
   return (s0 + s1) + (s2 + s3);
 }
 
-__global__ __launch_bounds__(256) void k_plancost(const DevJob* __restrict__ jobs, int njobs,
-                                                  const int* __restrict__ off, int total) {
-  __shared__ double sh[256];
+// p = 1 plan cost: item = (support entry e = (K, L), 64 of K's pixels); the
+// work-group's partial sum of a_s_i b_s_j |x_i - y_j| goes to part1, and
+// k_pc1_sum adds an entry's partials in order into red_pc[e] = S_e.
+__global__ __launch_bounds__(64) void k_plancost(const DevJob* __restrict__ jobs, int njobs,
+                                                 const int* __restrict__ off, int total) {
+  __shared__ double sh[64];
   __shared__ double sb[1024];
   __shared__ int sc[1024][3];
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
-    const int e = it - off[jb];
-    if (J.p == 2 || e >= J.nnz) continue;
-    const int K = J.e_row[e], L = J.e_col[e];
+    if (J.p == 2) continue;
     const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    const int pcc = (m + 63) / 64;
+    const int li = it - off[jb];
+    const int e = li / pcc, c = li - e * pcc;
+    const int K = J.e_row[e], L = J.e_col[e];
+    const int a = c * 64 + threadIdx.x;
+    int x0 = 0, x1 = 0, x2 = 0;
+    double wa = 0.0;
+    if (a < m) {
+      const int i = block_member(K, a, J.N, J.n, J.k, J.d);
+      pix_coords(i, J.N, J.d, x0, x1, x2);
+      wa = J.a_s[i];
+    }
     double acc = 0.0;
     for (int t0 = 0; t0 < m; t0 += 1024) {
       const int tn = min(1024, m - t0);
-      for (int q = threadIdx.x; q < tn; q += 256) {
+      __syncthreads();
+      for (int q = threadIdx.x; q < tn; q += 64) {
         const int j = block_member(L, t0 + q, J.N, J.n, J.k, J.d);
         sb[q] = J.b_s[j];
         pix_coords(j, J.N, J.d, sc[q][0], sc[q][1], sc[q][2]);
       }
       __syncthreads();
-      for (int a = threadIdx.x; a < m; a += 256) {
-        const int i = block_member(K, a, J.N, J.n, J.k, J.d);
-        int x0, x1, x2;
-        pix_coords(i, J.N, J.d, x0, x1, x2);
-        acc += J.a_s[i] * dist_dot(x0, x1, x2, sb, sc, tn);
-      }
-      __syncthreads();
+      if (a < m) acc += wa * dist_dot(x0, x1, x2, sb, sc, tn);
     }
-    acc = block_sum<256>(acc, sh);
-    if (threadIdx.x == 0) J.red_pc[e] = acc;
+    acc = block_sum<64>(acc, sh);
+    if (threadIdx.x == 0) J.part1[(size_t)e * pcc + c] = acc;
+  }
+}
+
+// S_e of every p = 1 entry: its partials added in order (one work-group per job).
+__global__ __launch_bounds__(256) void k_pc1_sum(const DevJob* __restrict__ jobs) {
+  const DevJob& J = jobs[blockIdx.x];
+  if (J.p == 2) return;
+  const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+  const int pcc = (m + 63) / 64;
+  for (int e = threadIdx.x; e < J.nnz; e += 256) {
+    double s = 0.0;
+    for (int c = 0; c < pcc; ++c) s += J.part1[(size_t)e * pcc + c];
+    J.red_pc[e] = s;
   }
 }
 
@@ -988,8 +1022,11 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   if (Se > 0.0) lower = J.p == 2 ? sqrt(Se) : Se;
   else warn |= QBW_WARN_LB_CLIPPED;
   // upper bound with outward rounding allowances: relative 2^-40 on the plan
-  // cost, absolute 2^-40 <w, mu> (resp. nu) on each TV sum
-  const double pe = pc * (1.0 + 9.094947017729282e-13);
+  // cost (p = 1: plus (k^2d + nnz) 2^-52, the linear bound for the float64 sums
+  // of nonnegative terms, which also covers the 2^-42 of the refined square
+  // roots), absolute 2^-40 <w, mu> (resp. nu) on each TV sum
+  const double rel = 9.094947017729282e-13 + (J.p == 1 ? (kd * kd + J.nnz) * 2.220446049250313e-16 : 0.0);
+  const double pe = pc * (1.0 + rel);
   const double c1 = J.p == 2 ? 1.4142135623730951 : 1.0;
   auto root = [&](double x) { return J.p == 2 ? sqrt(x) : x; };
   const double tvm = c1 * root(tm + 9.094947017729282e-13 * wm);
@@ -1216,7 +1253,8 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
 //   h(x) = sum over entries e of B's row (column) of coef_e sum_{y in O_e} w(y) c(x, y)
 // with w = nu (side 0) or mu (side 1) and O_e the other block of the entry.
 // k_ub_grad (p = 1) sums it y by y through LDS tiles, one 64-thread
-// work-group per (block, 64 of its pixels) so large blocks spread over many.
+// work-group per (support entry, 64 pixels of the block), each entry's share
+// kept apart; k_ub_grad_sum adds a pixel's shares in a fixed order.
 // For p = 2 the direct upper-bound term of a pixel x in block K is a quadratic
 // in z = x - c_K (c_K the block centre).  With D_e = c_K - c_L for the other
 // block L of a support entry e and the moments W0 = sum w_y, W1 = sum w_y
@@ -1315,41 +1353,65 @@ __global__ __launch_bounds__(64) void k_ub_grad(const DevJob* __restrict__ jobs,
     const DevJob& J = jobs[jb];
     double* grad = side == 0 ? J.grad_a : J.grad_b;
     if (!grad || J.p == 2) continue;   // p = 2 jobs: k_grad2
-    // item = (block B, chunk of 64 of its pixels)
+    // item = (support entry e, 64 pixels of its block on this side)
     const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
     const int per = (m + 63) / 64;
     const int li = it - off[jb];
-    const int B = li / per;
-    const int a = (li - B * per) * 64 + threadIdx.x;
-    const double P = J.result[RS_PCOST_RAW];
-    const double s = P > 0.0 ? du[jb] : 0.0;   // d P^(1/p) / d P = 1 for p = 1
+    const int e = li / per, c = li - e * per;
+    const int B = side == 0 ? J.e_row[e] : J.e_col[e];
+    const int O = side == 0 ? J.e_col[e] : J.e_row[e];
     const double* other = side == 0 ? J.nu : J.mu;
-    const double base_g = side == 0 ? J.gbar_mu[B] : J.gbar_nu[B];
-    const int e0 = side == 0 ? J.csr_ptr[B] : J.csc_ptr[B];
-    const int e1 = side == 0 ? J.csr_ptr[B + 1] : J.csc_ptr[B + 1];
-    const int i = a < m ? block_member(B, a, J.N, J.n, J.k, J.d) : 0;
-    int x0, x1, x2;
-    pix_coords(i, J.N, J.d, x0, x1, x2);
-    double h = 0.0;
-    for (int q = e0; q < e1; ++q) {
-      const int e = side == 0 ? q : J.csc_idx[q];
-      const int O = side == 0 ? J.e_col[e] : J.e_row[e];
-      const double cf = J.coef[e];
-      for (int t0 = 0; t0 < m; t0 += 512) {
-        const int tn = min(512, m - t0);
-        __syncthreads();
-        for (int r = threadIdx.x; r < tn; r += 64) {
-          const int j = block_member(O, t0 + r, J.N, J.n, J.k, J.d);
-          sw[r] = other[j];
-          pix_coords(j, J.N, J.d, sc[r][0], sc[r][1], sc[r][2]);
-        }
-        __syncthreads();
-        if (a < m) {
-          h += cf * dist_dot(x0, x1, x2, sw, sc, tn);
-        }
+    const int a = c * 64 + threadIdx.x;
+    int x0 = 0, x1 = 0, x2 = 0;
+    if (a < m) pix_coords(block_member(B, a, J.N, J.n, J.k, J.d), J.N, J.d, x0, x1, x2);
+    double acc = 0.0;
+    for (int t0 = 0; t0 < m; t0 += 512) {
+      const int tn = min(512, m - t0);
+      __syncthreads();
+      for (int r = threadIdx.x; r < tn; r += 64) {
+        const int j = block_member(O, t0 + r, J.N, J.n, J.k, J.d);
+        sw[r] = other[j];
+        pix_coords(j, J.N, J.d, sc[r][0], sc[r][1], sc[r][2]);
       }
+      __syncthreads();
+      if (a < m) acc += dist_dot(x0, x1, x2, sw, sc, tn);
     }
-    if (a < m) grad[i] += s * (h + base_g);
+    J.part1[((size_t)e * per + c) * 64 + threadIdx.x] = J.coef[e] * acc;
+  }
+}
+
+// p = 1: h(x) = sum over the entries of x's block row (side 0) or column
+// (side 1), in the order of the coupling's lists, of the partials above; then
+// grad += du (h + gbar).  One thread per pixel.
+__global__ __launch_bounds__(256) void k_ub_grad_sum(const DevJob* __restrict__ jobs, int njobs,
+                                                     const int* __restrict__ off, int total,
+                                                     const double* __restrict__ du, int side) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    double* grad = side == 0 ? J.grad_a : J.grad_b;
+    if (!grad || J.p == 2) continue;
+    const double s = J.result[RS_PCOST_RAW] > 0.0 ? du[jb] : 0.0;   // d P / d P for p = 1
+    const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    const int per = (m + 63) / 64;
+    const int k = J.k, n = J.n;
+    const int base = (it - off[jb]) * kChunk;
+    for (int q = threadIdx.x; q < kChunk; q += 256) {
+      const int i = base + q;
+      if (i >= J.P) break;
+      int x0, x1, x2;
+      pix_coords(i, J.N, J.d, x0, x1, x2);
+      const int B = J.d == 2 ? (x1 / k) * n + x2 / k : ((x0 / k) * n + x1 / k) * n + x2 / k;
+      const int a = J.d == 2 ? (x1 % k) * k + x2 % k : ((x0 % k) * k + x1 % k) * k + x2 % k;
+      const int e0 = side == 0 ? J.csr_ptr[B] : J.csc_ptr[B];
+      const int e1 = side == 0 ? J.csr_ptr[B + 1] : J.csc_ptr[B + 1];
+      double h = 0.0;
+      for (int qq = e0; qq < e1; ++qq) {
+        const int e = side == 0 ? qq : J.csc_idx[qq];
+        h += J.part1[(size_t)e * per * 64 + a];
+      }
+      grad[i] += s * (h + (side == 0 ? J.gbar_mu[B] : J.gbar_nu[B]));
+    }
   }
 }
 
@@ -1475,7 +1537,7 @@ int launch_tv_partial(const DevJob* jobs, int njobs, const int* off, int total, 
   return QBW_OK;
 }
 int launch_plancost(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
-  hipLaunchKernelGGL(k_plancost, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  hipLaunchKernelGGL(k_plancost, dim3(grid_for(total)), dim3(64), 0, (hipStream_t)stream, jobs, njobs, off, total);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
@@ -1518,6 +1580,18 @@ int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, con
 }
 int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
   hipLaunchKernelGGL(k_fwd_pixels, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_pc1_sum(const DevJob* jobs, int njobs, void* stream) {
+  hipLaunchKernelGGL(k_pc1_sum, dim3(njobs), dim3(256), 0, (hipStream_t)stream, jobs);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_ub_grad_sum(const DevJob* jobs, int njobs, const int* off, int total, const double* du, int side,
+                       void* stream) {
+  hipLaunchKernelGGL(k_ub_grad_sum, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off,
+                     total, du, side);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

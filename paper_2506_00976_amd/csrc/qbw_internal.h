@@ -100,6 +100,8 @@ struct DevJob {
   double* gbar_nu;
   double* coef;             // nnz: d P / d S_e coefficient
   double* gquad;            // Q x 2 x 5: per block and side, h(x) = A |z|^2 + B.z + C, z = x - centre
+  double* part1;            // p = 1 partial sums: nnz x ceil(k^d / 64) (plan cost), then
+                            // nnz x ceil(k^d / 64) x 64 (upper-bound gradient, one side at a time)
   // per-block moments about the block centre, 5 doubles per block:
   // (sum m, sum m delta_0, sum m delta_1, sum m delta_2, sum m |delta|^2)
   double* mom_mu;           // of mu
@@ -149,6 +151,9 @@ int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, con
 int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
                       double* const* outs, void* stream);
 int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+int launch_pc1_sum(const DevJob* jobs, int njobs, void* stream);
+int launch_ub_grad_sum(const DevJob* jobs, int njobs, const int* off, int total, const double* du, int side,
+                       void* stream);
 int launch_grad2_quad(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl, const double* du,
                  void* stream);
