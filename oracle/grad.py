@@ -36,10 +36,11 @@ def _safe_div(x, y):
     return torch.where(pos, x / torch.where(pos, y, torch.ones_like(y)), torch.zeros_like(x))
 
 
-def plan_cost_fn(mu, nu, rows, cols, vals, k: int, p: int, iters: int):
-    """Returns a closure (mu_t, nu_t) -> W^ as a torch float64 scalar."""
+def plan_cost_fn(mu, nu, rows, cols, vals, k: int, p: int, iters: int, kernel=None):
+    """Returns a closure (mu_t, nu_t) -> W^ as a torch float64 scalar
+    (``kernel``: the coupling upscaling kernel, None = uniform)."""
     d, N = mu.ndim, mu.shape[0]
-    I, J, V = upscale_plan(rows, cols, vals, N, d, k)
+    I, J, V = upscale_plan(rows, cols, vals, N, d, k, kernel)
     X = coords(N, d)
     diff = X[I] - X[J]
     d2 = (diff * diff).sum(1).astype(np.float64)
@@ -62,9 +63,9 @@ def plan_cost_fn(mu, nu, rows, cols, vals, k: int, p: int, iters: int):
     return W
 
 
-def upper_grad(mu, nu, rows, cols, vals, k: int, p: int, iters: int):
+def upper_grad(mu, nu, rows, cols, vals, k: int, p: int, iters: int, kernel=None):
     """(d W^/d mu, d W^/d nu) with the coarse coupling and T = ``iters`` frozen."""
-    W = plan_cost_fn(mu, nu, rows, cols, vals, k, p, iters)
+    W = plan_cost_fn(mu, nu, rows, cols, vals, k, p, iters, kernel)
     mu_t = torch.tensor(mu.reshape(-1), dtype=torch.float64, requires_grad=True)
     nu_t = torch.tensor(nu.reshape(-1), dtype=torch.float64, requires_grad=True)
     val = W(mu_t, nu_t)

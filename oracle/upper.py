@@ -4,7 +4,9 @@ quantization bounds of Sections 3.2-3.3.
 Algorithm 4, given a coupling pi~ of the coarse measures:
 
 1. up-scaled coupling pi^ = pi~ (tensor) K with the uniform kernel
-   K = kappa^(-2d) on [kappa]^(2d): pi^_ij = kappa^(-2d) pi~_{k(i) l(j)};
+   K = kappa^(-2d) on [kappa]^(2d): pi^_ij = kappa^(-2d) pi~_{k(i) l(j)}
+   (Section 3.4 admits any normalised nonnegative kernel; upscale_plan takes
+   one, and then IPF no longer converges in one iteration);
 2. iterative proportional fitting, starting from b = 1:
        a <- mu / (pi^ b);  b <- nu / (pi^T a);
        mu^ <- a * (pi^ b); nu^ <- b * (pi^T a)
@@ -29,9 +31,18 @@ from .grid import coords
 from .lp import solve_ot
 
 
-def upscale_plan(rows, cols, vals, N: int, d: int, k: int):
+def upscale_plan(rows, cols, vals, N: int, d: int, k: int, kernel=None):
     """Support of pi^ as COO (i, j, value): every coarse entry (K, L) becomes the
-    k^d x k^d block X_K x Y_L, each fine entry worth pi~_KL / k^(2d)."""
+    k^d x k^d block X_K x Y_L.
+
+    Section 3.4 upscales the coarse coupling tensor by a Kronecker product with
+    a normalised nonnegative kernel tensor on [k]^(2d).  ``kernel`` is that
+    tensor as a (k^d, k^d) matrix: entry [s, t] weighs source offset s against
+    target offset t, where an offset is the C-order flat index of a pixel's
+    position inside its block (which, since block members are listed in
+    ascending flat index, is the member's rank).  The fine entry is then
+    pi~_KL kernel[s, t].  ``None`` is Algorithm 4's uniform kernel, each fine
+    entry worth pi~_KL / k^(2d)."""
     blk = block_of(N, d, k)
     order = np.argsort(blk, kind="stable")
     members = order.reshape(-1, k ** d)          # fine pixels of each block, ascending
@@ -40,8 +51,25 @@ def upscale_plan(rows, cols, vals, N: int, d: int, k: int):
     m = k ** d
     I = np.repeat(mI, m, axis=1).reshape(-1)
     J = np.tile(mJ, (1, m)).reshape(-1)
-    V = np.repeat(np.asarray(vals, dtype=np.float64) / float(k) ** (2 * d), m * m)
+    if kernel is None:
+        V = np.repeat(np.asarray(vals, dtype=np.float64) / float(k) ** (2 * d), m * m)
+    else:
+        Km = np.asarray(kernel, dtype=np.float64).reshape(m, m)
+        V = (np.asarray(vals, dtype=np.float64)[:, None, None] * Km[None, :, :]).reshape(-1)
     return I, J, V
+
+
+def plan_kernel_gaussian(k: int, d: int, sigma: float) -> np.ndarray:
+    """A non-uniform kernel for the coupling upscaling of Section 3.4: weight
+    exp(-|s - t|^2 / (2 sigma^2)) between in-block offsets s and t (integer
+    offset vectors in [k]^d, C order), normalised to total 1.  It keeps the
+    relative position of a pixel inside its block when the coarse plan moves
+    the block; sigma -> infinity gives the uniform kernel."""
+    offs = np.array([[(s // k ** (d - 1 - a)) % k for a in range(d)] for s in range(k ** d)],
+                    dtype=np.float64)
+    dist2 = ((offs[:, None, :] - offs[None, :, :]) ** 2).sum(axis=2)
+    w = np.exp(-dist2 / (2.0 * sigma * sigma))
+    return w / w.sum()
 
 
 def _matvec(I, J, V, x, n):
@@ -98,11 +126,12 @@ def plan_cost(I, J, V, a, b, N: int, d: int, p: int) -> float:
 
 
 def upper_bound_o64(mu, nu, rows, cols, vals, k: int, p: int,
-                    xi: float = 1e-12, max_iter: int = 50):
-    """Algorithm 4 in float64 from a given coarse coupling (rows, cols, vals)."""
+                    xi: float = 1e-12, max_iter: int = 50, kernel=None):
+    """Algorithm 4 in float64 from a given coarse coupling (rows, cols, vals);
+    ``kernel`` as in upscale_plan (None: the uniform kernel)."""
     d, N = mu.ndim, mu.shape[0]
     muf, nuf = mu.reshape(-1), nu.reshape(-1)
-    I, J, V = upscale_plan(rows, cols, vals, N, d, k)
+    I, J, V = upscale_plan(rows, cols, vals, N, d, k, kernel)
     a, b, mu_hat, nu_hat, T, err = ipf(muf, nuf, I, J, V, xi, max_iter)
     cost = plan_cost(I, J, V, a, b, N, d, p)
     w = tv_weights(N, d, p)

@@ -231,3 +231,21 @@ def config5_jobs(n_jobs: int = 128):
         nu = grf(N, d, rng(5000 + 2 * j + 2), ell=4.0)
         jobs.append((N, d, k, p, mu, nu))
     return jobs
+
+
+# --------------------------------------------------------------------------
+# Kernels for upscaling a coarse coupling (inputs, not part of the method)
+# --------------------------------------------------------------------------
+
+def random_plan_kernel(k: int, d: int, g: np.random.Generator, zero_frac: float = 0.0) -> np.ndarray:
+    """A random nonnegative (k^d, k^d) kernel matrix with total 1: i.i.d.
+    U(0.05, 1) entries, a fraction ``zero_frac`` of them set to 0 (every row
+    and column keeps at least one positive entry)."""
+    m = k ** d
+    w = g.uniform(0.05, 1.0, size=(m, m))
+    if zero_frac > 0:
+        drop = g.uniform(size=(m, m)) < zero_frac
+        keep = np.zeros((m, m), dtype=bool)
+        keep[np.arange(m), g.permutation(m)] = True
+        w = np.where(drop & ~keep, 0.0, w)
+    return np.ascontiguousarray(w / w.sum())

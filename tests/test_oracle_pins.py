@@ -614,3 +614,186 @@ def test_separable_error_bounds_and_feasibility(N, d):
     f = Ls["f32"].astype(np.float64) - Ls["shift"]
     assert (f[:, None] + Ls["g32"].astype(np.float64)[None, :] - Cm).max() <= 0.0
     assert Ls["S_emit"] <= L64["S"]
+
+
+# ---------------------------------------------------------------- upscaling kernels (Section 3.4)
+
+def _random_coupling(N, d, k, g):
+    n = N // k
+    mt = g.uniform(0.1, 1.0, n ** d)
+    nt = g.uniform(0.1, 1.0, n ** d)
+    return lp.northwest_corner(mt / mt.sum(), nt / nt.sum())
+
+
+def _kron_plan(r, c, v, N, d, k, Km):
+    """The upscaled coupling by the paper's definition: the coarse coupling as a
+    2d-tensor, Kronecker product with the kernel as a 2d-tensor, reshaped."""
+    n = N // k
+    Pt = np.zeros((n ** d, n ** d))
+    np.add.at(Pt, (np.asarray(r), np.asarray(c)), v)
+    big = np.kron(Pt.reshape((n,) * (2 * d)), np.asarray(Km).reshape((k,) * (2 * d)))
+    return big.reshape(N ** d, N ** d)
+
+
+@pytest.mark.parametrize("N,d,k", [(6, 2, 3), (8, 2, 2), (4, 3, 2)])
+def test_kernel_upscale_is_the_kronecker_product(N, d, k):
+    g = si.rng(600 + N + d)
+    r, c, v = _random_coupling(N, d, k, g)
+    for Km in (si.random_plan_kernel(k, d, g), si.random_plan_kernel(k, d, g, zero_frac=0.5),
+               np.full((k ** d, k ** d), float(k) ** (-2 * d))):
+        I, J, V = upper.upscale_plan(r, c, v, N, d, k, Km)
+        dense = np.zeros((N ** d, N ** d))
+        np.add.at(dense, (I, J), V)
+        assert np.allclose(dense, _kron_plan(r, c, v, N, d, k, Km), rtol=1e-15, atol=0)
+    I, J, V = upper.upscale_plan(r, c, v, N, d, k)
+    dense = np.zeros((N ** d, N ** d))
+    np.add.at(dense, (I, J), V)
+    assert np.allclose(dense, _kron_plan(r, c, v, N, d, k, np.full((k ** d,) * 2, float(k) ** (-2 * d))),
+                       rtol=1e-15, atol=0)
+
+
+def test_kernel_plan_is_a_coupling_of_block_consistent_marginals():
+    # the lemma on normalised kernels: pi^ >= 0 with total 1, and every block of
+    # its marginals carries the coarse coupling's marginal
+    N, d, k = 12, 2, 3
+    g = si.rng(610)
+    r, c, v = _random_coupling(N, d, k, g)
+    Km = si.random_plan_kernel(k, d, g, zero_frac=0.3)
+    I, J, V = upper.upscale_plan(r, c, v, N, d, k, Km)
+    assert (V >= 0).all() and math.isclose(V.sum(), 1.0, rel_tol=1e-14)
+    blk = coarse.block_of(N, d, k)
+    Q = (N // k) ** d
+    row = np.bincount(blk[I], V, Q)
+    col = np.bincount(blk[J], V, Q)
+    assert np.allclose(row, np.bincount(r, v, Q), rtol=1e-13, atol=1e-16)
+    assert np.allclose(col, np.bincount(c, v, Q), rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_uniform_kernel_given_explicitly_is_algorithm_4(p):
+    N, d, k = 16, 2, 4
+    mu, nu = pair(N, d, "grf", "gmm", 620 + p)
+    r, c, v, *_ = upper.coarse_record_lp(mu, nu, k, p)
+    v = v * np.exp(0.2 * si.rng(622).standard_normal(len(v)))   # several IPF iterations
+    U0 = upper.upper_bound_o64(mu, nu, r, c, v, k, p)
+    U1 = upper.upper_bound_o64(mu, nu, r, c, v, k, p, kernel=np.full((k ** d,) * 2, float(k) ** (-2 * d)))
+    assert U0["iters"] == U1["iters"] and U0["iters"] >= 2
+    assert U1["plan_cost"] == pytest.approx(U0["plan_cost"], rel=1e-13)
+    assert U1["upper"] == pytest.approx(U0["upper"], rel=1e-12)
+
+
+def _permuted_translation(N, d, k, shift_blocks, g):
+    """mu random on the blocks whose translate by ``shift_blocks`` stays on the
+    grid; nu moves pixel (block K, offset s) to (block K + shift, offset
+    s + 1 mod k^d).  Returns mu, nu, the pixel map and the block map."""
+    n, m = N // k, k ** d
+    mu = np.zeros((N,) * d)
+    nu = np.zeros((N,) * d)
+    sigma = {}
+    blocks = {}
+    for Kv in itertools.product(range(n), repeat=d):
+        Lv = tuple(a + b for a, b in zip(Kv, shift_blocks))
+        if not all(0 <= x < n for x in Lv):
+            continue
+        Kf = int(np.ravel_multi_index(Kv, (n,) * d))
+        Lf = int(np.ravel_multi_index(Lv, (n,) * d))
+        blocks[Kf] = Lf
+        for s in range(m):
+            off = np.unravel_index(s, (k,) * d)
+            toff = np.unravel_index((s + 1) % m, (k,) * d)
+            x = tuple(kk * k + o for kk, o in zip(Kv, off))
+            y = tuple(ll * k + o for ll, o in zip(Lv, toff))
+            w = g.uniform(0.2, 1.0)
+            mu[x] = w
+            nu[y] = w
+            sigma[np.ravel_multi_index(x, (N,) * d)] = np.ravel_multi_index(y, (N,) * d)
+    tot = mu.sum()
+    return mu / tot, nu / tot, sigma, blocks
+
+
+@pytest.mark.parametrize("N,d,k,shift", [(8, 2, 2, (1, 1)), (12, 2, 3, (0, 2)), (4, 3, 2, (1, 0, 1))])
+@pytest.mark.parametrize("p", [1, 2])
+def test_permutation_kernel_is_exact_on_permuted_translation(N, d, k, shift, p):
+    # closed form: with the kernel that sends offset s to offset s + 1 (mod k^d)
+    # and the block translation as coarse coupling, the upscaled coupling is the
+    # pixel map itself; IPF stops after one iteration and the bound is that
+    # map's cost, with no TV correction.  The transposed kernel cannot fit.
+    g = si.rng(630 + N + p)
+    mu, nu, sigma, blocks = _permuted_translation(N, d, k, shift, g)
+    m = k ** d
+    Km = np.zeros((m, m))
+    Km[np.arange(m), (np.arange(m) + 1) % m] = 1.0 / m
+    mt = coarse.sumpool(mu, k)
+    rows = np.array(sorted(blocks), dtype=np.int64)
+    cols = np.array([blocks[K] for K in rows], dtype=np.int64)
+    vals = mt[rows]
+    U = upper.upper_bound_o64(mu, nu, rows, cols, vals, k, p, kernel=Km)
+    X = grid.coords(N, d)
+    muf = mu.reshape(-1)
+    cost = 0.0
+    for i, j in sigma.items():
+        dd = float(((X[i] - X[j]) ** 2).sum())
+        cost += muf[i] * (dd if p == 2 else math.sqrt(dd))
+    assert U["iters"] == 1
+    assert U["plan_cost"] == pytest.approx(cost, rel=1e-13)
+    assert U["residual"] < 1e-14
+    assert U["upper"] == pytest.approx(cost ** (1.0 / p), rel=1e-6)
+    Ut = upper.upper_bound_o64(mu, nu, rows, cols, vals, k, p, kernel=Km.T.copy(), max_iter=5)
+    assert Ut["residual"] > 0.1
+
+
+def test_gaussian_plan_kernel_factorises_over_axes():
+    for k, d, sigma in [(4, 2, 1.0), (3, 3, 0.7), (8, 2, 2.5)]:
+        Km = upper.plan_kernel_gaussian(k, d, sigma)
+        u = np.arange(k, dtype=np.float64)
+        g1 = np.exp(-(u[:, None] - u[None, :]) ** 2 / (2 * sigma ** 2))
+        ref = g1
+        for _ in range(d - 1):
+            ref = np.kron(ref, g1)
+        assert np.allclose(Km, ref / ref.sum(), rtol=1e-14, atol=0)
+        assert math.isclose(Km.sum(), 1.0, rel_tol=1e-14) and np.allclose(Km, Km.T, rtol=0, atol=0)
+    assert np.allclose(upper.plan_kernel_gaussian(4, 2, 1e6), 1.0 / 256, rtol=1e-9)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("which", ["gaussian", "random"])
+def test_kernel_upper_bound_brackets_exact(p, which):
+    N, d, k = 16, 2, 4
+    mu, nu = pair(N, d, "gmm", "cauchy", 640 + p)
+    W = lp.wasserstein_exact(mu, nu, p)
+    r, c, v, *_ = upper.coarse_record_lp(mu, nu, k, p)
+    Km = upper.plan_kernel_gaussian(k, d, 1.0) if which == "gaussian" else \
+        si.random_plan_kernel(k, d, si.rng(642), zero_frac=0.3)
+    U = upper.upper_bound_o64(mu, nu, r, c, v, k, p, kernel=Km, max_iter=200)
+    assert U["iters"] > 1
+    assert U["upper"] >= W * (1 - 1e-12)
+    I, J, V = upper.upscale_plan(r, c, v, N, d, k, Km)
+    fitted = U["a"][I] * V * U["b"][J]
+    P = N ** d
+    err = np.abs(np.bincount(I, fitted, P) - mu.reshape(-1)).sum() + \
+        np.abs(np.bincount(J, fitted, P) - nu.reshape(-1)).sum()
+    assert err == pytest.approx(U["residual"], rel=1e-6, abs=1e-15)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_kernel_upper_bound_gradient_matches_fd(p):
+    N, d, k = 8, 2, 2
+    mu, nu = pair(N, d, "gmm", "grf", 650 + p)
+    r, c, v, *_ = upper.coarse_record_lp(mu, nu, k, p)
+    Km = si.random_plan_kernel(k, d, si.rng(652))
+    U = upper.upper_bound_o64(mu, nu, r, c, v, k, p, kernel=Km, max_iter=6)
+    T = U["iters"]
+    gm, gn, val = ograd.upper_grad(mu, nu, r, c, v, k, p, T, kernel=Km)
+    assert val == pytest.approx(U["plan_cost"] ** (1 / p), rel=1e-12)
+    g = si.rng(653)
+    h = 1e-4
+
+    def W(m_, n_):
+        U2 = upper.upper_bound_o64(m_, n_, r, c, v, k, p, xi=-1.0, max_iter=T, kernel=Km)
+        return U2["plan_cost"] ** (1 / p)
+
+    for _ in range(2):
+        vm, vn = _mass_preserving_direction(mu, g), _mass_preserving_direction(nu, g)
+        fd = (W(mu * (1 + h * vm), nu * (1 + h * vn)) - W(mu * (1 - h * vm), nu * (1 - h * vn))) / (2 * h)
+        an = float((gm * (mu * vm).reshape(-1)).sum() + (gn * (nu * vn).reshape(-1)).sum())
+        assert fd == pytest.approx(an, rel=1e-6, abs=1e-9)
