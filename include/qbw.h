@@ -250,6 +250,37 @@ qbw_status qbw_tv(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const dou
                   const qbw_coarse* coarse, const double* a_s, const double* b_s,
                   double* tv_mu, double* tv_nu, qbw_stream stream);
 
+/* Upper bound of Algorithm 4 with a caller-chosen kernel for upscaling the
+ * coarse coupling (Section 3.4, eq. of the upscaled coupling tensor and the
+ * lemma on normalised kernels; the paper's algorithm takes the uniform one).
+ * The upscaled coupling is pi^_ij = pi~_KL kernel[s(i) * m + t(j)] for pixel
+ * i in block K and j in block L, m = k^d, where s(i) and t(j) are the
+ * C-order flat indices of the pixels' positions inside their blocks
+ * (0 .. m-1).  kernel: host, m x m float64, row-major, nonnegative and
+ * finite, summing to 1 within 1e-12 (QBW_E_INVAL otherwise); m <= 4096
+ * (QBW_E_GRID otherwise).  With a non-uniform kernel the fitting no longer
+ * stops after one iteration: it runs on fine vectors, from b_s = 1, until
+ * ||a^ - a||_1 + ||b - b^||_1 < opts->xi or opts->max_ipf_iter iterations
+ * (0/0 := 0; opts->flags are ignored), then the plan cost over the support
+ * and the weighted-TV corrections follow as in qbw_bounds.  out (host): the
+ * upper-bound fields, rounded outwards (relative 2^-40 + (m^2 + nnz) 2^-52
+ * on the plan cost, absolute 2^-40 <w, a> and <w, b> on the TV sums), the
+ * fitting's iterations, residual and warning; lower, lower_S and feas_shift
+ * are 0.  a_s, b_s: device float64 (N^d), may be NULL; receive the final
+ * scalings.  a, b: device.  Synchronises `stream`.  Errors: QBW_E_GRID,
+ * QBW_E_INVAL, QBW_E_HIP, QBW_E_NOMEM. */
+qbw_status qbw_upper_kernel(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                            const qbw_coarse* coarse, const double* kernel, const qbw_opts* opts,
+                            qbw_result* out, double* a_s, double* b_s, qbw_stream stream);
+
+/* A kernel for qbw_upper_kernel: weight exp(-|s - t|^2 / (2 sigma^2))
+ * between in-block offsets s, t (integer vectors in [k]^d), normalised to
+ * total 1; it keeps a pixel's relative position inside its block when the
+ * coarse coupling moves the block.  sigma = +inf gives the uniform kernel.
+ * out: host, k^d x k^d float64.  Errors: QBW_E_INVAL, QBW_E_GRID
+ * (k^d > 4096).  No device work. */
+qbw_status qbw_plan_kernel_gaussian(int32_t k, int32_t d, double sigma, double* out);
+
 /* Weighted-cost upper bound (Section 3.2, Algorithm 3; theorem of the
  * weighted-cost upper bound): L_{C-bar}(a~, b~)^(1/p) >= W_p(a, b).  Pools and
  * builds C-bar on the device, copies it to the host (n^d x n^d float64) and

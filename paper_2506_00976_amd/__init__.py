@@ -24,7 +24,7 @@ from ._lib import (QBW_BATCH_AUTOTUNE, QBW_BATCH_BACKWARD, QBW_BATCH_GRAPH, QBW_
 __all__ = ["Context", "Coarse", "Batch", "bounds", "wasserstein_bounds", "BoundsFunction",
            "sumpool", "coarse_cost", "cbar", "coarse_solve", "upscale_potential", "ctransform",
            "ctransform_separable",
-           "ipf", "plan_cost", "tv", "autotune_ctransform", "weighted_cost_upper", "min_cost_lower",
+           "ipf", "plan_cost", "tv", "upper_kernel", "plan_kernel_gaussian", "autotune_ctransform", "weighted_cost_upper", "min_cost_lower",
            "bounds_with_grads", "QbwError", "load"]
 
 _tls = threading.local()
@@ -348,6 +348,48 @@ def tv(a, b, k: int, p: int, coarse: Coarse, a_s, b_s):
     check(load().qbw_tv(context(a.device.index).handle, C.byref(grid), _ptr(a), _ptr(b), C.byref(cs),
                         _ptr(a_s), _ptr(b_s), C.byref(tm), C.byref(tn), _stream()), "qbw_tv")
     return tm.value, tn.value
+
+
+def plan_kernel_gaussian(k: int, d: int, sigma: float) -> np.ndarray:
+    """(k^d, k^d) kernel for upper_kernel: Gaussian in the in-block offset
+    difference, normalised to total 1 (qbw_plan_kernel_gaussian)."""
+    m = k ** d
+    out = np.empty((m, m), dtype=np.float64)
+    check(load().qbw_plan_kernel_gaussian(int(k), int(d), float(sigma), out.ctypes.data),
+          "qbw_plan_kernel_gaussian")
+    return out
+
+
+def upper_kernel(a, b, k: int, p: int, kernel, coarse: Coarse | None = None, xi: float = 1e-12,
+                 max_ipf_iter: int = 50, return_scalings: bool = False):
+    """Upper bound of Algorithm 4 with the coarse coupling upscaled by ``kernel``
+    ((k^d, k^d) float64, nonnegative, total 1; entry [s, t] weighs in-block
+    offset s of the source block against offset t of the target block).
+    Returns the result dict (plus the final scalings a_s, b_s on request)."""
+    a, b = _dev(a), _dev(b)
+    if coarse is None:
+        coarse = coarse_solve(sumpool(a, k).cpu().numpy(), sumpool(b, k).cpu().numpy(),
+                              a.shape[0], a.dim(), k, p)
+    grid = _grid(a, k, p)
+    opts = _opts(xi, max_ipf_iter, 0)
+    kern = np.ascontiguousarray(kernel, dtype=np.float64)
+    if kern.size != (k ** a.dim()) ** 2:
+        raise ValueError(f"kernel must have (k^d)^2 = {(k ** a.dim()) ** 2} entries, got {kern.size}")
+    res = QbwResult()
+    a_s = b_s = None
+    if return_scalings:
+        a_s = torch.empty(a.numel(), dtype=torch.float64, device=a.device)
+        b_s = torch.empty_like(a_s)
+    cs = coarse.struct()
+    check(load().qbw_upper_kernel(context(a.device.index).handle, C.byref(grid), _ptr(a), _ptr(b),
+                                  C.byref(cs), kern.ctypes.data, C.byref(opts), C.byref(res),
+                                  _ptr(a_s) if a_s is not None else None,
+                                  _ptr(b_s) if b_s is not None else None, _stream()),
+          "qbw_upper_kernel")
+    out = res.as_dict()
+    if return_scalings:
+        out["a_s"], out["b_s"] = a_s, b_s
+    return out
 
 
 def weighted_cost_upper(a, b, k: int, p: int):

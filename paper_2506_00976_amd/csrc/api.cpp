@@ -1318,6 +1318,170 @@ qbw_status qbw_tv(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const dou
   return QBW_OK;
 }
 
+// ---------------------------------------------------------------- upper bound with any upscaling kernel
+
+constexpr int kMaxKernelOffsets = 4096;  // k^d: the kernel matrix is k^d x k^d float64
+
+static int check_plan_kernel(int m, const double* K) {
+  // compensated (Neumaier) sum, so that the 1e-12 test does not depend on m
+  double sum = 0.0, comp = 0.0;
+  for (size_t q = 0; q < (size_t)m * m; ++q) {
+    const double v = K[q];
+    if (!(v >= 0.0) || !std::isfinite(v)) {
+      set_error("kernel entry %zu is negative or not finite", q);
+      return QBW_E_INVAL;
+    }
+    const double t = sum + v;
+    comp += std::fabs(sum) >= v ? (sum - t) + v : (v - t) + sum;
+    sum = t;
+  }
+  sum += comp;
+  if (!(std::fabs(sum - 1.0) <= 1e-12)) {
+    set_error("kernel entries sum to %.17g, not 1", sum);
+    return QBW_E_INVAL;
+  }
+  return QBW_OK;
+}
+
+qbw_status qbw_upper_kernel(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
+                            const qbw_coarse* coarse, const double* kernel, const qbw_opts* opts,
+                            qbw_result* out, double* a_s, double* b_s, qbw_stream stream) {
+  if (!ctx || !grid || !a || !b || !coarse || !kernel || !out) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  CHK(check_opts(opts));
+  const qbw_opts o = opts ? *opts : qbw_default_opts();
+  const int m = ipow(grid->k, grid->d);
+  if (m > kMaxKernelOffsets) {
+    set_error("kernel upscaling needs k^d <= %d, got %d", kMaxKernelOffsets, m);
+    return QBW_E_GRID;
+  }
+  CHK(check_plan_kernel(m, kernel));
+  CoarseHost ch;
+  CHK(make_coarse(*grid, coarse, &ch));
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = S(stream);
+
+  KubJob J{};
+  J.d = grid->d; J.N = grid->N; J.k = grid->k; J.p = grid->p;
+  J.n = J.N / J.k; J.P = ipow(J.N, J.d); J.Q = ch.Q; J.m = m; J.nnz = ch.nnz;
+  J.max_iter = o.max_ipf_iter;
+  J.nt = m <= 64 ? 64 : 256;
+  J.cpb = (m + J.nt - 1) / J.nt;
+  J.chunks = (J.P + kChunk - 1) / kChunk;
+  J.xi = o.xi;
+  J.coarse_obj = ch.obj;
+  J.mu = a;
+  J.nu = b;
+  // uploaded tables first (one copy), device-only buffers after them
+  Layout lay;
+  const size_t mm = (size_t)m * m, P = J.P, Q = J.Q, nnz = J.nnz;
+  const size_t oKst = lay.add(8 * mm), oKts = lay.add(8 * mm), oVal = lay.add(8 * nnz),
+               oRes = lay.add(8 * RS_COUNT), oRow = lay.add(4 * nnz), oCol = lay.add(4 * nnz),
+               oCsr = lay.add(4 * (Q + 1)), oCsc = lay.add(4 * (Q + 1)), oIdx = lay.add(4 * nnz),
+               oState = lay.add(4 * 2);
+  const size_t up = lay.size;
+  const size_t oA0 = lay.add(8 * P), oA1 = lay.add(8 * P), oB = lay.add(8 * P), oMuh = lay.add(8 * P),
+               oNuh = lay.add(8 * P), oPm = lay.add(8 * Q * J.cpb), oPn = lay.add(8 * Q * J.cpb),
+               oPc = lay.add(8 * nnz * J.cpb), oTv = lay.add(8 * (size_t)J.chunks * kRedSlotsTV);
+  CHK(ctx->work.reserve(lay.size));
+  char* base = ctx->work.base;
+  std::vector<char> blob(up, 0);
+  double* kst = (double*)(blob.data() + oKst);
+  double* kts = (double*)(blob.data() + oKts);
+  for (int s = 0; s < m; ++s)
+    for (int t = 0; t < m; ++t) {
+      kst[(size_t)s * m + t] = kernel[(size_t)s * m + t];
+      kts[(size_t)t * m + s] = kernel[(size_t)s * m + t];
+    }
+  std::memcpy(blob.data() + oVal, ch.vals.data(), 8 * nnz);
+  std::memcpy(blob.data() + oRow, ch.rows.data(), 4 * nnz);
+  std::memcpy(blob.data() + oCol, ch.cols.data(), 4 * nnz);
+  std::memcpy(blob.data() + oCsr, ch.csr_ptr.data(), 4 * (Q + 1));
+  std::memcpy(blob.data() + oCsc, ch.csc_ptr.data(), 4 * (Q + 1));
+  std::memcpy(blob.data() + oIdx, ch.csc_idx.data(), 4 * nnz);
+  HIPCHK(hipMemcpyAsync(base, blob.data(), up, hipMemcpyHostToDevice, st));
+  J.Kst = (const double*)(base + oKst);
+  J.Kts = (const double*)(base + oKts);
+  J.e_val = (const double*)(base + oVal);
+  J.result = (double*)(base + oRes);
+  J.e_row = (const int*)(base + oRow);
+  J.e_col = (const int*)(base + oCol);
+  J.csr_ptr = (const int*)(base + oCsr);
+  J.csc_ptr = (const int*)(base + oCsc);
+  J.csc_idx = (const int*)(base + oIdx);
+  J.state = (int*)(base + oState);
+  J.a0 = (double*)(base + oA0);
+  J.a1 = (double*)(base + oA1);
+  J.b = (double*)(base + oB);
+  J.muh = (double*)(base + oMuh);
+  J.nuh = (double*)(base + oNuh);
+  J.part_mu = (double*)(base + oPm);
+  J.part_nu = (double*)(base + oPn);
+  J.pc_part = (double*)(base + oPc);
+  J.red_tv = (double*)(base + oTv);
+
+  // Algorithm 4's fitting: row(0) gives a^1; then col(t), row(t), check(t).
+  // The host looks at the stop flag every kGroup iterations; passes enqueued
+  // after the stop return at once.
+  constexpr int kGroup = 16;
+  CHK(launch_kub_row(J, 0, st));
+  for (int t0 = 1; t0 <= J.max_iter; t0 += kGroup) {
+    const int t1 = std::min(J.max_iter, t0 + kGroup - 1);
+    for (int t = t0; t <= t1; ++t) {
+      CHK(launch_kub_col(J, t, st));
+      CHK(launch_kub_row(J, t, st));
+      CHK(launch_kub_check(J, t, st));
+    }
+    int stopped = 0;
+    HIPCHK(hipMemcpyAsync(&stopped, J.state, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (stopped) break;
+  }
+  CHK(launch_kub_plancost(J, st));
+  CHK(launch_kub_tv(J, st));
+  CHK(launch_kub_finalize(J, st));
+  std::vector<double> res(RS_COUNT);
+  HIPCHK(hipMemcpyAsync(res.data(), J.result, 8 * RS_COUNT, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  to_result(res.data(), out);
+  const int T = out->ipf_iters;
+  if (a_s) HIPCHK(hipMemcpyAsync(a_s, (T & 1) ? J.a1 : J.a0, 8 * P, hipMemcpyDeviceToDevice, st));
+  if (b_s) HIPCHK(hipMemcpyAsync(b_s, J.b, 8 * P, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
+qbw_status qbw_plan_kernel_gaussian(int32_t k, int32_t d, double sigma, double* out) {
+  if (!out || k < 1 || (d != 2 && d != 3) || !(sigma > 0.0)) {
+    set_error("plan kernel needs k >= 1, d in {2, 3}, sigma > 0 and an output array");
+    return QBW_E_INVAL;
+  }
+  const int m = ipow(k, d);
+  if (m > kMaxKernelOffsets) {
+    set_error("kernel upscaling needs k^d <= %d, got %d", kMaxKernelOffsets, m);
+    return QBW_E_GRID;
+  }
+  // one factor per axis, exp(-(u - v)^2 / (2 sigma^2)); the kernel is their product
+  std::vector<double> g1((size_t)k * k);
+  for (int u = 0; u < k; ++u)
+    for (int v = 0; v < k; ++v) g1[(size_t)u * k + v] = std::exp(-(double)((u - v) * (u - v)) / (2.0 * sigma * sigma));
+  double tot = 0.0;
+  for (int s = 0; s < m; ++s)
+    for (int t = 0; t < m; ++t) {
+      double w = 1.0;
+      int rs = s, rt = t;
+      for (int a = 0; a < d; ++a) {
+        w *= g1[(size_t)(rs % k) * k + (rt % k)];
+        rs /= k;
+        rt /= k;
+      }
+      out[(size_t)s * m + t] = w;
+      tot += w;
+    }
+  for (size_t q = 0; q < (size_t)m * m; ++q) out[q] /= tot;
+  return QBW_OK;
+}
+
 // ---------------------------------------------------------------- batches
 
 static qbw_status batch_enqueue(qbw_batch* B, hipStream_t st) {

@@ -1479,6 +1479,241 @@ __global__ __launch_bounds__(1024) void k_tv_prep(const DevJob* __restrict__ job
   if (threadIdx.x == 0) J.result[RS_IPF_ITERS] = 1.0;
 }
 
+// ------------------------------------------------------------------ upper bound with any upscaling kernel
+//
+// Section 3.4 upscales the coarse coupling by a Kronecker product with a
+// normalised nonnegative kernel tensor on [k]^(2d); Algorithm 4 takes the
+// uniform one.  For a general kernel, pi^ restricted to X_K x Y_L is
+// pi~_KL times the m x m kernel matrix (m = k^d, rows and columns indexed by
+// the in-block offsets in C order), so
+//   (pi^ x)_i   = sum_{L: (K,L) in supp} pi~_KL sum_t Kst[s(i), t] x_(L,t),
+//   (pi^T y)_j  = sum_{K: (K,L) in supp} pi~_KL sum_s Kst[s, t(j)] y_(K,s),
+// and the fitting runs on fine vectors.  One work-group handles nt offsets of
+// one block (grid Q x cpb), stages the other side's block in LDS for each
+// coupling entry, and reads the kernel matrix coalesced (Kts for rows, Kst
+// for columns).  Every pass returns at once after the fitting has stopped.
+//
+// Iteration t (t = 1 .. T) of Algorithm 4 is k_kub_col(t) then k_kub_row(t):
+//   col(t): v = pi^T a^t, b^t = nu / v, nu^ = b^t v        (0/0 := 0)
+//   row(t): u = pi^ b^t,  mu^ = a^t u, a^(t+1) = mu / u
+// with a^1 = mu / (pi^ 1) from row(0); k_kub_check(t) then adds the L1
+// residual partials in a fixed order and stops the fitting once it is below
+// xi (or at max_iter).  a^t alternates between a0 (t even) and a1 (t odd), so
+// a^T survives the row pass that follows it.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_kub_row(KubJob J, int t) {
+  if (J.state[0]) return;
+  extern __shared__ double xs[];  // m values of the target block
+  __shared__ double sh[NT];
+  const int K = blockIdx.x, c = blockIdx.y, m = J.m;
+  const int s = c * NT + threadIdx.x;
+  double acc = 0.0;
+  for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) {
+    const int L = J.e_col[e];
+    __syncthreads();
+    for (int q = threadIdx.x; q < m; q += NT)
+      xs[q] = t == 0 ? 1.0 : J.b[block_member(L, q, J.N, J.n, J.k, J.d)];
+    __syncthreads();
+    if (s < m) {
+      double r = 0.0;
+      for (int q = 0; q < m; ++q) r += J.Kts[(size_t)q * m + s] * xs[q];
+      acc += J.e_val[e] * r;
+    }
+  }
+  double part = 0.0;
+  if (s < m) {
+    const int i = block_member(K, s, J.N, J.n, J.k, J.d);
+    const double mu = J.mu[i];
+    if (t >= 1) {
+      const double muh = ((t & 1) ? J.a1 : J.a0)[i] * acc;
+      J.muh[i] = muh;
+      part = fabs(muh - mu);
+    }
+    (((t + 1) & 1) ? J.a1 : J.a0)[i] = acc > 0.0 ? mu / acc : 0.0;
+  }
+  if (t >= 1) {
+    part = block_sum<NT>(part, sh);
+    if (threadIdx.x == 0) J.part_mu[(size_t)K * J.cpb + c] = part;
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_kub_col(KubJob J, int t) {
+  if (J.state[0]) return;
+  extern __shared__ double xs[];  // m values of the source block
+  __shared__ double sh[NT];
+  const int L = blockIdx.x, c = blockIdx.y, m = J.m;
+  const int o = c * NT + threadIdx.x;
+  const double* a = (t & 1) ? J.a1 : J.a0;
+  double acc = 0.0;
+  for (int q0 = J.csc_ptr[L]; q0 < J.csc_ptr[L + 1]; ++q0) {
+    const int e = J.csc_idx[q0];
+    const int K = J.e_row[e];
+    __syncthreads();
+    for (int q = threadIdx.x; q < m; q += NT) xs[q] = a[block_member(K, q, J.N, J.n, J.k, J.d)];
+    __syncthreads();
+    if (o < m) {
+      double r = 0.0;
+      for (int q = 0; q < m; ++q) r += J.Kst[(size_t)q * m + o] * xs[q];
+      acc += J.e_val[e] * r;
+    }
+  }
+  double part = 0.0;
+  if (o < m) {
+    const int j = block_member(L, o, J.N, J.n, J.k, J.d);
+    const double nu = J.nu[j];
+    const double b = acc > 0.0 ? nu / acc : 0.0;
+    const double nuh = b * acc;
+    J.b[j] = b;
+    J.nuh[j] = nuh;
+    part = fabs(nu - nuh);
+  }
+  part = block_sum<NT>(part, sh);
+  if (threadIdx.x == 0) J.part_nu[(size_t)L * J.cpb + c] = part;
+}
+
+__global__ __launch_bounds__(256) void k_kub_check(KubJob J, int t) {
+  if (J.state[0]) return;
+  __shared__ double sh[256];
+  const int n = J.Q * J.cpb;
+  double sm = 0.0, sn = 0.0;
+  for (int q = threadIdx.x; q < n; q += 256) {
+    sm += J.part_mu[q];
+    sn += J.part_nu[q];
+  }
+  sm = block_sum<256>(sm, sh);
+  sn = block_sum<256>(sn, sh);
+  if (threadIdx.x == 0) {
+    const double err = sm + sn;
+    J.result[RS_IPF_RESID] = err;
+    J.result[RS_IPF_ITERS] = (double)t;
+    const bool conv = err < J.xi;
+    if (conv || t >= J.max_iter) {
+      J.result[RS_WARN] = conv ? 0.0 : (double)QBW_WARN_IPF_NOT_CONVERGED;
+      J.state[0] = 1;
+    }
+  }
+}
+
+// Plan cost: per (coupling entry e = (K, L), nt source offsets) the sum over
+// the offsets s and all target offsets t of a_(K,s) Kst[s,t] b_(L,t) c_st,
+// target block staged in LDS by tiles of 1024 (values and coordinates);
+// k_kub_finalize multiplies by pi~_e and adds everything in a fixed order.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_kub_plancost(KubJob J) {
+  __shared__ double sh[NT];
+  __shared__ double sb[1024];
+  __shared__ int sc[1024][3];
+  const int e = blockIdx.x, c = blockIdx.y, m = J.m;
+  const int T = (int)J.result[RS_IPF_ITERS];
+  const double* a = (T & 1) ? J.a1 : J.a0;
+  const int K = J.e_row[e], L = J.e_col[e];
+  const int s = c * NT + threadIdx.x;
+  int x0 = 0, x1 = 0, x2 = 0;
+  double wa = 0.0;
+  if (s < m) {
+    const int i = block_member(K, s, J.N, J.n, J.k, J.d);
+    pix_coords(i, J.N, J.d, x0, x1, x2);
+    wa = a[i];
+  }
+  double acc = 0.0;
+  for (int t0 = 0; t0 < m; t0 += 1024) {
+    const int tn = min(1024, m - t0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < tn; q += NT) {
+      const int j = block_member(L, t0 + q, J.N, J.n, J.k, J.d);
+      sb[q] = J.b[j];
+      pix_coords(j, J.N, J.d, sc[q][0], sc[q][1], sc[q][2]);
+    }
+    __syncthreads();
+    if (s < m) {
+      for (int q = 0; q < tn; ++q) {
+        const int e0 = x0 - sc[q][0], e1 = x1 - sc[q][1], e2 = x2 - sc[q][2];
+        const double d2 = (double)(e0 * e0 + e1 * e1 + e2 * e2);
+        const double cst = J.p == 2 ? d2 : sqrt(d2);
+        acc += J.Kts[(size_t)(t0 + q) * m + s] * sb[q] * cst;
+      }
+    }
+  }
+  acc = block_sum<NT>(wa * acc, sh);
+  if (threadIdx.x == 0) J.pc_part[(size_t)e * J.cpb + c] = acc;
+}
+
+// Weighted-TV partials per chunk of kChunk pixels: w_i = |x_i - x-bar|^p.
+__global__ __launch_bounds__(256) void k_kub_tv(KubJob J) {
+  __shared__ double sh[256];
+  const int c = blockIdx.x;
+  const double h = 0.5 * (J.N - 1);
+  double tm = 0.0, tn = 0.0, wm = 0.0, wn = 0.0;
+  for (int q = threadIdx.x; q < kChunk; q += 256) {
+    const int i = c * kChunk + q;
+    if (i >= J.P) break;
+    int x0, x1, x2;
+    pix_coords(i, J.N, J.d, x0, x1, x2);
+    const double d0 = J.d == 2 ? 0.0 : x0 - h, d1 = x1 - h, d2 = x2 - h;
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const double w = J.p == 2 ? r2 : sqrt(r2);
+    const double mu = J.mu[i], nu = J.nu[i];
+    tm += w * fabs(J.muh[i] - mu);
+    tn += w * fabs(nu - J.nuh[i]);
+    wm += w * mu;
+    wn += w * nu;
+  }
+  tm = block_sum<256>(tm, sh);
+  tn = block_sum<256>(tn, sh);
+  wm = block_sum<256>(wm, sh);
+  wn = block_sum<256>(wn, sh);
+  if (threadIdx.x == 0) {
+    double* r = J.red_tv + (size_t)c * kRedSlotsTV;
+    r[0] = tm; r[1] = tn; r[2] = wm; r[3] = wn;
+  }
+}
+
+// The bound with outward rounding allowances: relative 2^-40 + (m^2 + nnz) 2^-52
+// on the plan cost (the linear bound for float64 sums of m^2 nonnegative
+// terms per entry and nnz entries, with room for the square roots of p = 1),
+// absolute 2^-40 <w, mu> (resp. nu) on each TV sum.
+__global__ __launch_bounds__(256) void k_kub_finalize(KubJob J) {
+  __shared__ double sh[256];
+  double pc = 0.0;
+  for (int e = threadIdx.x; e < J.nnz; e += 256) {
+    double s = 0.0;
+    for (int c = 0; c < J.cpb; ++c) s += J.pc_part[(size_t)e * J.cpb + c];
+    pc += J.e_val[e] * s;
+  }
+  pc = block_sum<256>(pc, sh);
+  double tm = 0.0, tn = 0.0, wm = 0.0, wn = 0.0;
+  for (int c = threadIdx.x; c < J.chunks; c += 256) {
+    const double* r = J.red_tv + (size_t)c * kRedSlotsTV;
+    tm += r[0]; tn += r[1]; wm += r[2]; wn += r[3];
+  }
+  tm = block_sum<256>(tm, sh);
+  tn = block_sum<256>(tn, sh);
+  wm = block_sum<256>(wm, sh);
+  wn = block_sum<256>(wn, sh);
+  if (threadIdx.x != 0) return;
+  const double mm = (double)J.m * J.m;
+  const double rel = 9.094947017729282e-13 + (mm + J.nnz) * 2.220446049250313e-16;
+  const double pe = pc * (1.0 + rel);
+  const double c1 = J.p == 2 ? 1.4142135623730951 : 1.0;
+  auto root = [&](double x) { return J.p == 2 ? sqrt(x) : x; };
+  const double tvm = c1 * root(tm + 9.094947017729282e-13 * wm);
+  const double tvn = c1 * root(tn + 9.094947017729282e-13 * wn);
+  double* res = J.result;
+  res[RS_UPPER] = root(pe) + tvm + tvn;
+  res[RS_UPPER_COST] = pe;
+  res[RS_TV_MU] = tvm;
+  res[RS_TV_NU] = tvn;
+  res[RS_COARSE_OBJ] = J.coarse_obj;
+  res[RS_PCOST_RAW] = pc;
+  res[RS_TVSUM_MU] = tm;
+  res[RS_TVSUM_NU] = tn;
+  res[RS_MW_MU] = wm;
+  res[RS_MW_NU] = wn;
+  res[RS_TV_RAW_MU] = c1 * root(tm);
+  res[RS_TV_RAW_NU] = c1 * root(tn);
+}
+
 // ------------------------------------------------------------------ launchers
 
 static inline int grid_for(int total, int cap = 65535) { return total < 1 ? 1 : (total < cap ? total : cap); }
@@ -1626,6 +1861,48 @@ int launch_sep_argmin(const DevJob* jobs, int njobs, const int* off, int total, 
 int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
                       double* const* outs, void* stream) {
   hipLaunchKernelGGL(k_fhat_grad, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, dl, outs);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+
+int launch_kub_row(const KubJob& J, int t, void* stream) {
+  const size_t lds = sizeof(double) * (size_t)J.m;
+  if (J.nt == 64)
+    hipLaunchKernelGGL(k_kub_row<64>, dim3(J.Q, J.cpb), dim3(64), lds, (hipStream_t)stream, J, t);
+  else
+    hipLaunchKernelGGL(k_kub_row<256>, dim3(J.Q, J.cpb), dim3(256), lds, (hipStream_t)stream, J, t);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_kub_col(const KubJob& J, int t, void* stream) {
+  const size_t lds = sizeof(double) * (size_t)J.m;
+  if (J.nt == 64)
+    hipLaunchKernelGGL(k_kub_col<64>, dim3(J.Q, J.cpb), dim3(64), lds, (hipStream_t)stream, J, t);
+  else
+    hipLaunchKernelGGL(k_kub_col<256>, dim3(J.Q, J.cpb), dim3(256), lds, (hipStream_t)stream, J, t);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_kub_check(const KubJob& J, int t, void* stream) {
+  hipLaunchKernelGGL(k_kub_check, dim3(1), dim3(256), 0, (hipStream_t)stream, J, t);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_kub_plancost(const KubJob& J, void* stream) {
+  if (J.nt == 64)
+    hipLaunchKernelGGL(k_kub_plancost<64>, dim3(J.nnz, J.cpb), dim3(64), 0, (hipStream_t)stream, J);
+  else
+    hipLaunchKernelGGL(k_kub_plancost<256>, dim3(J.nnz, J.cpb), dim3(256), 0, (hipStream_t)stream, J);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_kub_tv(const KubJob& J, void* stream) {
+  hipLaunchKernelGGL(k_kub_tv, dim3(J.chunks), dim3(256), 0, (hipStream_t)stream, J);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_kub_finalize(const KubJob& J, void* stream) {
+  hipLaunchKernelGGL(k_kub_finalize, dim3(1), dim3(256), 0, (hipStream_t)stream, J);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -116,6 +116,47 @@ struct DevJob {
 
 struct CtItem { int job, tile, split, pad; };
 
+// One pair's upper bound with a caller-chosen kernel for upscaling the coarse
+// coupling (Section 3.4): pi^_ij = pi~_KL Kst[s(i) m + t(j)], s and t the
+// in-block offsets (C order), m = k^d.  The fitting no longer stays on coarse
+// vectors: a, b, mu^, nu^ are fine.  Passed to the kernels by value.
+struct KubJob {
+  int d, N, k, p, n, P, Q, m, nnz, max_iter;
+  int nt;                   // threads per work-group in the passes (64 or 256)
+  int cpb;                  // work-groups per block: ceil(m / nt)
+  int chunks;               // ceil(P / kChunk)
+  double xi;
+  double coarse_obj;
+  const double* mu;         // fine measures
+  const double* nu;
+  const int* e_row;         // coarse coupling, entries sorted by row
+  const int* e_col;
+  const double* e_val;
+  const int* csr_ptr;       // Q+1
+  const int* csc_ptr;       // Q+1
+  const int* csc_idx;       // nnz: entry ids by column
+  const double* Kst;        // m x m, [s][t]
+  const double* Kts;        // m x m, [t][s] (the transpose, for coalesced reads)
+  double* a0;               // a^t for even t
+  double* a1;               // a^t for odd t
+  double* b;                // b^t
+  double* muh;              // mu^ = a^t (pi^ b^t)
+  double* nuh;              // nu^ = b^t (pi^T a^t)
+  double* part_mu;          // Q x cpb: sums of |mu^ - mu|
+  double* part_nu;          // Q x cpb: sums of |nu - nu^|
+  double* pc_part;          // nnz x cpb: plan-cost partials
+  double* red_tv;           // chunks x kRedSlotsTV
+  int* state;               // [0]: fitting stopped
+  double* result;           // RS_COUNT
+};
+
+int launch_kub_row(const KubJob& J, int t, void* stream);
+int launch_kub_col(const KubJob& J, int t, void* stream);
+int launch_kub_check(const KubJob& J, int t, void* stream);
+int launch_kub_plancost(const KubJob& J, void* stream);
+int launch_kub_tv(const KubJob& J, void* stream);
+int launch_kub_finalize(const KubJob& J, void* stream);
+
 // Kernel launchers (kernels.hip).  All enqueue on `stream`.
 struct Launch {
   const DevJob* jobs;  // device array

@@ -122,3 +122,16 @@ def test_device_calls_fail_loudly_without_gpu(lib):
     import paper_2506_00976_amd as qbw
     with pytest.raises(qbw.QbwError):
         qbw.bounds(torch.zeros(8, 8, dtype=torch.float64), torch.zeros(8, 8, dtype=torch.float64), 2, 2)
+
+
+def test_gaussian_plan_kernel_host(lib):
+    import paper_2506_00976_amd as qbw
+    from oracle import upper
+    for k, d, sigma in [(4, 2, 1.0), (3, 3, 0.7), (8, 2, 2.5), (2, 3, 5.0)]:
+        K = qbw.plan_kernel_gaussian(k, d, sigma)
+        assert np.allclose(K, upper.plan_kernel_gaussian(k, d, sigma), rtol=1e-14, atol=0)
+    assert np.allclose(qbw.plan_kernel_gaussian(4, 2, float("inf")), 1.0 / 256, rtol=1e-15, atol=0)
+    with pytest.raises(qbw.QbwError):
+        qbw.plan_kernel_gaussian(4, 2, 0.0)
+    with pytest.raises(qbw.QbwError):
+        qbw.plan_kernel_gaussian(32, 3, 1.0)     # k^d = 32768 offsets

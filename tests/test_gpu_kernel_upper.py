@@ -1,0 +1,212 @@
+"""Parity of the upper bound with a caller-chosen kernel for upscaling the
+coarse coupling (Section 3.4) - qbw_upper_kernel through the C ABI - with the
+CPU oracle's Algorithm 4 on the same kernel.
+
+Tolerances: the fitting's iteration count is equal; scalings, plan cost and
+bound agree to 1e-9 relative; the emitted plan cost and bound are rounded
+outwards, so they are never below the oracle's; the bound exceeds the
+oracle's by at most 1e-9 relative plus the TV allowance (as for the uniform
+kernel).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+from oracle import coarse, grid, upper
+
+pytestmark = pytest.mark.gpu
+
+qbw = pytest.importorskip("paper_2506_00976_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qbw.load()
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), device="cuda:0")
+
+
+def ub_tol(mu, nu, N, d, p, ub):
+    w = upper.tv_weights(N, d, p)
+    Mw = max(float(w @ mu.reshape(-1)), float(w @ nu.reshape(-1)))
+    c1 = 2.0 ** (1 - 1 / p)
+    return 1e-9 * ub + 2 * 2 * c1 * (2.0 ** -39 * Mw) ** (1 / p)
+
+
+def make_kernel(kind, k, d, seed):
+    if kind == "gaussian":
+        return upper.plan_kernel_gaussian(k, d, 1.0)
+    if kind == "wide":
+        return upper.plan_kernel_gaussian(k, d, 3.0)
+    if kind == "random":
+        return si.random_plan_kernel(k, d, si.rng(seed))
+    if kind == "sparse":
+        return si.random_plan_kernel(k, d, si.rng(seed), zero_frac=0.6)
+    m = k ** d
+    return np.full((m, m), 1.0 / (m * m))
+
+
+def check_against_oracle(mu, nu, k, p, K, max_iter, xi=1e-12):
+    N, d = mu.shape[0], mu.ndim
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
+    rec = qbw.Coarse(r, c, v, ft, gt, obj)
+    res = qbw.upper_kernel(dev(mu), dev(nu), k, p, K, coarse=rec, xi=xi, max_ipf_iter=max_iter,
+                           return_scalings=True)
+    U = upper.upper_bound_o64(mu, nu, r, c, v, k, p, xi=xi, max_iter=max_iter, kernel=K)
+    print(f"N={N} d={d} k={k} p={p} iters={res['ipf_iters']}/{U['iters']} "
+          f"upper={res['upper']:.12g} oracle={U['upper']:.12g}", flush=True)
+    assert res["ipf_iters"] == U["iters"]
+    assert bool(res["warn"] & qbw.QBW_WARN_IPF_NOT_CONVERGED) == (U["residual"] >= xi)
+    assert res["ipf_residual"] == pytest.approx(U["residual"], rel=1e-6, abs=1e-13)
+    a_s, b_s = res["a_s"].cpu().numpy(), res["b_s"].cpu().numpy()
+    sa = np.abs(U["a"]).max()
+    sb = np.abs(U["b"]).max()
+    assert np.abs(a_s - U["a"]).max() <= 1e-9 * sa
+    assert np.abs(b_s - U["b"]).max() <= 1e-9 * sb
+    assert res["upper_cost"] >= U["plan_cost"]
+    assert res["upper_cost"] == pytest.approx(U["plan_cost"], rel=1e-9)
+    assert U["upper"] <= res["upper"] <= U["upper"] + ub_tol(mu, nu, N, d, p, U["upper"])
+    assert res["lower"] == 0.0
+    return res, U
+
+
+KCASES = [
+    # N, d, k, p, kernel kind    (m = k^d: 16, 9, 64, 64, 8, 64, 100, 256, 512, 1024)
+    (16, 2, 4, 2, "gaussian"),
+    (24, 2, 3, 1, "random"),
+    (32, 2, 8, 2, "random"),
+    (32, 2, 8, 1, "gaussian"),
+    (8, 3, 2, 2, "sparse"),
+    (16, 3, 4, 1, "wide"),
+    (40, 2, 10, 2, "sparse"),
+    (64, 2, 16, 1, "random"),
+    (16, 3, 8, 2, "gaussian"),
+    (64, 2, 32, 2, "random"),
+]
+
+
+@pytest.mark.parametrize("N,d,k,p,kind", KCASES)
+def test_kernel_upper_matches_oracle(N, d, k, p, kind):
+    mu = si.family("grf", N, d, si.rng(8000 + N + k))
+    nu = si.family("cauchy" if d == 2 else "gmm", N, d, si.rng(8001 + N + k))
+    K = make_kernel(kind, k, d, 8002 + N)
+    check_against_oracle(mu, nu, k, p, K, max_iter=25)
+
+
+def test_kernel_upper_zero_mass_blocks_and_convergence():
+    # shapes: zero-mass pixels and blocks (0/0 := 0 in the fitting); a loose xi
+    # lets the fitting stop before the cap
+    N, d, k, p = 32, 2, 4, 2
+    mu = si.family("shapes", N, d, si.rng(8100))
+    nu = si.family("shapes", N, d, si.rng(8101))
+    K = make_kernel("sparse", k, d, 8102)
+    res, U = check_against_oracle(mu, nu, k, p, K, max_iter=400, xi=1e-4)
+    assert U["iters"] < 400 and not (res["warn"] & qbw.QBW_WARN_IPF_NOT_CONVERGED)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_uniform_kernel_equals_the_built_in_upper_bound(p):
+    N, d, k = 64, 2, 8
+    mu = si.family("gmm", N, d, si.rng(8200 + p))
+    nu = si.family("grf", N, d, si.rng(8201 + p))
+    K = make_kernel("uniform", k, d, 0)
+    res, U = check_against_oracle(mu, nu, k, p, K, max_iter=50)
+    assert res["ipf_iters"] == 1
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
+    base = qbw.bounds(dev(mu), dev(nu), k, p, coarse=qbw.Coarse(r, c, v, ft, gt, obj))
+    assert res["upper"] == pytest.approx(base["upper"], rel=1e-9)
+
+
+def _permuted_translation(N, d, k, shift_blocks, g):
+    n, m = N // k, k ** d
+    mu = np.zeros((N,) * d)
+    nu = np.zeros((N,) * d)
+    sigma = {}
+    blocks = {}
+    for Kv in np.ndindex(*((n,) * d)):
+        Lv = tuple(a + b for a, b in zip(Kv, shift_blocks))
+        if not all(0 <= x < n for x in Lv):
+            continue
+        blocks[int(np.ravel_multi_index(Kv, (n,) * d))] = int(np.ravel_multi_index(Lv, (n,) * d))
+        for s in range(m):
+            off = np.unravel_index(s, (k,) * d)
+            toff = np.unravel_index((s + 1) % m, (k,) * d)
+            x = tuple(kk * k + o for kk, o in zip(Kv, off))
+            y = tuple(ll * k + o for ll, o in zip(Lv, toff))
+            w = g.uniform(0.2, 1.0)
+            mu[x] = w
+            nu[y] = w
+            sigma[np.ravel_multi_index(x, (N,) * d)] = np.ravel_multi_index(y, (N,) * d)
+    tot = mu.sum()
+    return mu / tot, nu / tot, sigma, blocks
+
+
+@pytest.mark.parametrize("N,d,k,shift,p", [(32, 2, 4, (2, -1), 2), (32, 2, 4, (1, 3), 1),
+                                           (12, 3, 2, (1, 0, -2), 2)])
+def test_permutation_kernel_closed_form(N, d, k, shift, p):
+    # kernel sending offset s to s + 1 (mod k^d), coarse coupling = the block
+    # translation: the upscaled coupling is the pixel map, fitted in one
+    # iteration, and the bound is that map's cost (closed form)
+    g = si.rng(8300 + N + p)
+    mu, nu, sigma, blocks = _permuted_translation(N, d, k, shift, g)
+    m = k ** d
+    K = np.zeros((m, m))
+    K[np.arange(m), (np.arange(m) + 1) % m] = 1.0 / m
+    mt = coarse.sumpool(mu, k)
+    rows = np.array(sorted(blocks), dtype=np.int32)
+    cols = np.array([blocks[int(q)] for q in rows], dtype=np.int32)
+    rec = qbw.Coarse(rows, cols, mt[rows], np.zeros(mt.size), None, None)
+    res = qbw.upper_kernel(dev(mu), dev(nu), k, p, K, coarse=rec)
+    X = grid.coords(N, d)
+    muf = mu.reshape(-1)
+    cost = 0.0
+    for i, j in sigma.items():
+        dd = float(((X[i] - X[j]) ** 2).sum())
+        cost += muf[i] * (dd if p == 2 else math.sqrt(dd))
+    assert res["ipf_iters"] == 1
+    assert res["upper_cost"] == pytest.approx(cost, rel=1e-9) and res["upper_cost"] >= cost
+    assert res["upper"] == pytest.approx(cost ** (1.0 / p), rel=1e-5)
+
+
+def test_kernel_upper_full_size():
+    # 256^2, k = 8 (m = 64, Q = 1024): Gaussian kernel, 12 iterations
+    N, d, k, p = 256, 2, 8, 2
+    mu, nu = si.config3_pair(256, "grf")
+    K = make_kernel("gaussian", k, d, 0)
+    check_against_oracle(mu, nu, k, p, K, max_iter=12)
+
+
+def test_kernel_upper_rejects_bad_kernels():
+    N, d, k, p = 16, 2, 4, 2
+    mu = si.family("grf", N, d, si.rng(8400))
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, mu, k, p)
+    rec = qbw.Coarse(r, c, v, ft, gt, obj)
+    K = make_kernel("random", k, d, 8401)
+    with pytest.raises(qbw.QbwError, match="sum"):
+        qbw.upper_kernel(dev(mu), dev(mu), k, p, 2 * K, coarse=rec)
+    bad = K.copy()
+    bad[0, 1] = -bad[0, 1]
+    with pytest.raises(qbw.QbwError, match="negative"):
+        qbw.upper_kernel(dev(mu), dev(mu), k, p, bad, coarse=rec)
+    with pytest.raises(ValueError):
+        qbw.upper_kernel(dev(mu), dev(mu), k, p, K[:4], coarse=rec)
+    # k^d = 32^3 offsets: refused from the grid alone, before the kernel is read
+    import ctypes as C
+    lib = qbw.load()
+    big = dev(si.family("grf", 32, 3, si.rng(8402)))
+    grid3 = qbw.QbwGrid(3, 32, 32, 2)
+    tiny = np.zeros(1)
+    out = qbw.QbwResult()
+    cs = rec.struct()
+    rc = lib.qbw_upper_kernel(qbw.context(0).handle, C.byref(grid3), big.data_ptr(), big.data_ptr(),
+                              C.byref(cs), tiny.ctypes.data, None, C.byref(out), None, None, None)
+    assert rc == 2 and "4096" in lib.qbw_last_error().decode()
