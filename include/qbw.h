@@ -267,11 +267,18 @@ qbw_status qbw_tv(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const dou
  * on the plan cost, absolute 2^-40 <w, a> and <w, b> on the TV sums), the
  * fitting's iterations, residual and warning; lower, lower_S and feas_shift
  * are 0.  a_s, b_s: device float64 (N^d), may be NULL; receive the final
- * scalings.  a, b: device.  Synchronises `stream`.  Errors: QBW_E_GRID,
+ * scalings.  grad_a, grad_b: device float64 (N^d), may be NULL; if either is
+ * given, dupper * d upper / d a and dupper * d upper / d b are added (+=) into
+ * the non-NULL ones, through the plan cost and the fitting's iterations with the coarse
+ * coupling, the kernel and the iteration count frozen, the TV corrections
+ * taken as constants (as qbw_bounds_backward); every iterate is kept, which
+ * needs 8 N^d (2 max_ipf_iter + 8) bytes of device memory (QBW_E_NOMEM above
+ * 32 GiB).  a, b: device.  Synchronises `stream`.  Errors: QBW_E_GRID,
  * QBW_E_INVAL, QBW_E_HIP, QBW_E_NOMEM. */
 qbw_status qbw_upper_kernel(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
                             const qbw_coarse* coarse, const double* kernel, const qbw_opts* opts,
-                            qbw_result* out, double* a_s, double* b_s, qbw_stream stream);
+                            qbw_result* out, double* a_s, double* b_s, double dupper,
+                            double* grad_a, double* grad_b, qbw_stream stream);
 
 /* A kernel for qbw_upper_kernel: weight exp(-|s - t|^2 / (2 sigma^2))
  * between in-block offsets s, t (integer vectors in [k]^d), normalised to

@@ -24,7 +24,8 @@ from ._lib import (QBW_BATCH_AUTOTUNE, QBW_BATCH_BACKWARD, QBW_BATCH_GRAPH, QBW_
 __all__ = ["Context", "Coarse", "Batch", "bounds", "wasserstein_bounds", "BoundsFunction",
            "sumpool", "coarse_cost", "cbar", "coarse_solve", "upscale_potential", "ctransform",
            "ctransform_separable",
-           "ipf", "plan_cost", "tv", "upper_kernel", "plan_kernel_gaussian", "autotune_ctransform", "weighted_cost_upper", "min_cost_lower",
+           "ipf", "plan_cost", "tv", "upper_kernel", "upper_kernel_bound", "UpperKernelFunction",
+           "plan_kernel_gaussian", "autotune_ctransform", "weighted_cost_upper", "min_cost_lower",
            "bounds_with_grads", "QbwError", "load"]
 
 _tls = threading.local()
@@ -361,11 +362,15 @@ def plan_kernel_gaussian(k: int, d: int, sigma: float) -> np.ndarray:
 
 
 def upper_kernel(a, b, k: int, p: int, kernel, coarse: Coarse | None = None, xi: float = 1e-12,
-                 max_ipf_iter: int = 50, return_scalings: bool = False):
+                 max_ipf_iter: int = 50, return_scalings: bool = False, dupper: float | None = None,
+                 grad_a=None, grad_b=None):
     """Upper bound of Algorithm 4 with the coarse coupling upscaled by ``kernel``
     ((k^d, k^d) float64, nonnegative, total 1; entry [s, t] weighs in-block
     offset s of the source block against offset t of the target block).
-    Returns the result dict (plus the final scalings a_s, b_s on request)."""
+    Returns the result dict (plus the final scalings a_s, b_s on request).
+    With ``dupper``, dupper * d upper / d(a, b) is added into ``grad_a`` /
+    ``grad_b`` (float64 tensors shaped like a; created as zeros when None and
+    returned in the dict)."""
     a, b = _dev(a), _dev(b)
     if coarse is None:
         coarse = coarse_solve(sumpool(a, k).cpu().numpy(), sumpool(b, k).cpu().numpy(),
@@ -380,16 +385,54 @@ def upper_kernel(a, b, k: int, p: int, kernel, coarse: Coarse | None = None, xi:
     if return_scalings:
         a_s = torch.empty(a.numel(), dtype=torch.float64, device=a.device)
         b_s = torch.empty_like(a_s)
+    if dupper is not None:
+        grad_a = torch.zeros_like(a) if grad_a is None else grad_a
+        grad_b = torch.zeros_like(b) if grad_b is None else grad_b
     cs = coarse.struct()
     check(load().qbw_upper_kernel(context(a.device.index).handle, C.byref(grid), _ptr(a), _ptr(b),
                                   C.byref(cs), kern.ctypes.data, C.byref(opts), C.byref(res),
-                                  _ptr(a_s) if a_s is not None else None,
-                                  _ptr(b_s) if b_s is not None else None, _stream()),
+                                  _ptr(a_s), _ptr(b_s), float(dupper or 0.0),
+                                  _ptr(grad_a) if dupper is not None else None,
+                                  _ptr(grad_b) if dupper is not None else None, _stream()),
           "qbw_upper_kernel")
     out = res.as_dict()
     if return_scalings:
         out["a_s"], out["b_s"] = a_s, b_s
+    if dupper is not None:
+        out["grad_a"], out["grad_b"] = grad_a, grad_b
     return out
+
+
+class UpperKernelFunction(torch.autograd.Function):
+    """upper = f(a, b) for the kernel-upscaled upper bound; backward re-runs the
+    library's forward with every fitting iterate kept, then its reverse pass
+    (qbw_upper_kernel with gradient outputs)."""
+
+    @staticmethod
+    def forward(ctx, a, b, k, p, kernel, coarse, xi, max_ipf_iter):
+        a, b = _dev(a), _dev(b)
+        if coarse is None:
+            coarse = coarse_solve(sumpool(a, k).cpu().numpy(), sumpool(b, k).cpu().numpy(),
+                                  a.shape[0], a.dim(), k, p)
+        res = upper_kernel(a, b, k, p, kernel, coarse=coarse, xi=xi, max_ipf_iter=max_ipf_iter)
+        ctx.save_for_backward(a, b)
+        ctx.args = (k, p, kernel, coarse, xi, max_ipf_iter)
+        ctx.result = res
+        return torch.tensor(res["upper"], dtype=torch.float64, device=a.device)
+
+    @staticmethod
+    def backward(ctx, dupper):
+        a, b = ctx.saved_tensors
+        k, p, kernel, coarse, xi, max_ipf_iter = ctx.args
+        res = upper_kernel(a, b, k, p, kernel, coarse=coarse, xi=xi, max_ipf_iter=max_ipf_iter,
+                           dupper=float(dupper))
+        return res["grad_a"], res["grad_b"], None, None, None, None, None, None
+
+
+def upper_kernel_bound(a, b, k: int, p: int, kernel, coarse: Coarse | None = None, xi: float = 1e-12,
+                       max_ipf_iter: int = 50):
+    """Differentiable kernel-upscaled upper bound on W_p(a, b) (a 0-d tensor)."""
+    return UpperKernelFunction.apply(a, b, k, p, kernel, coarse, xi, max_ipf_iter)
 
 
 def weighted_cost_upper(a, b, k: int, p: int):

@@ -75,7 +75,7 @@ SIGNATURES = [
     ("qbw_ipf", C.c_int, [_vp, _pg, _vp, _vp, _pc, _po, _vp, _vp, _vp, _vp, _vp]),
     ("qbw_plan_cost", C.c_int, [_vp, _pg, _pc, _vp, _vp, _vp, _vp]),
     ("qbw_tv", C.c_int, [_vp, _pg, _vp, _vp, _pc, _vp, _vp, _vp, _vp, _vp]),
-    ("qbw_upper_kernel", C.c_int, [_vp, _pg, _vp, _vp, _pc, _vp, _po, _pr, _vp, _vp, _vp]),
+    ("qbw_upper_kernel", C.c_int, [_vp, _pg, _vp, _vp, _pc, _vp, _po, _pr, _vp, _vp, _d, _vp, _vp, _vp]),
     ("qbw_plan_kernel_gaussian", C.c_int, [_i32, _i32, _d, _vp]),
     ("qbw_weighted_cost_upper", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp, _vp]),
     ("qbw_min_cost_lower", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp, _vp]),

@@ -1345,7 +1345,8 @@ static int check_plan_kernel(int m, const double* K) {
 
 qbw_status qbw_upper_kernel(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const double* b,
                             const qbw_coarse* coarse, const double* kernel, const qbw_opts* opts,
-                            qbw_result* out, double* a_s, double* b_s, qbw_stream stream) {
+                            qbw_result* out, double* a_s, double* b_s, double dupper, double* grad_a,
+                            double* grad_b, qbw_stream stream) {
   if (!ctx || !grid || !a || !b || !coarse || !kernel || !out) { set_error("NULL argument"); return QBW_E_INVAL; }
   CHK(check_grid(grid));
   CHK(check_opts(opts));
@@ -1383,6 +1384,20 @@ qbw_status qbw_upper_kernel(qbw_ctx* ctx, const qbw_grid* grid, const double* a,
   const size_t oA0 = lay.add(8 * P), oA1 = lay.add(8 * P), oB = lay.add(8 * P), oMuh = lay.add(8 * P),
                oNuh = lay.add(8 * P), oPm = lay.add(8 * Q * J.cpb), oPn = lay.add(8 * Q * J.cpb),
                oPc = lay.add(8 * nnz * J.cpb), oTv = lay.add(8 * (size_t)J.chunks * kRedSlotsTV);
+  // gradient: every iterate u^t, v^t is kept, plus five adjoint vectors
+  const bool grad = grad_a || grad_b;
+  size_t oHu = 0, oHv = 0, oG = 0;
+  if (grad) {
+    const double hist = 8.0 * P * (2.0 * J.max_iter + 8.0);
+    if (hist > 32.0 * (1ull << 30)) {
+      set_error("gradient needs %.1f GiB of checkpointed iterates (max_ipf_iter %d); the cap is 32 GiB",
+                hist / (1ull << 30), J.max_iter);
+      return QBW_E_NOMEM;
+    }
+    oHu = lay.add(8 * P * (size_t)(J.max_iter + 2));
+    oHv = lay.add(8 * P * (size_t)(J.max_iter + 1));
+    oG = lay.add(8 * P * 5);
+  }
   CHK(ctx->work.reserve(lay.size));
   char* base = ctx->work.base;
   std::vector<char> blob(up, 0);
@@ -1419,6 +1434,16 @@ qbw_status qbw_upper_kernel(qbw_ctx* ctx, const qbw_grid* grid, const double* a,
   J.part_nu = (double*)(base + oPn);
   J.pc_part = (double*)(base + oPc);
   J.red_tv = (double*)(base + oTv);
+  if (grad) {
+    J.hist_u = (double*)(base + oHu);
+    J.hist_v = (double*)(base + oHv);
+    double* g = (double*)(base + oG);
+    J.g_mu = g;
+    J.g_nu = g + P;
+    J.g_abar = g + 2 * P;
+    J.g_ubar = g + 3 * P;
+    J.g_vbar = g + 4 * P;
+  }
 
   // Algorithm 4's fitting: row(0) gives a^1; then col(t), row(t), check(t).
   // The host looks at the stop flag every kGroup iterations; passes enqueued
@@ -1445,6 +1470,7 @@ qbw_status qbw_upper_kernel(qbw_ctx* ctx, const qbw_grid* grid, const double* a,
   HIPCHK(hipStreamSynchronize(st));
   to_result(res.data(), out);
   const int T = out->ipf_iters;
+  if (grad) CHK(launch_kub_backward(J, T, dupper, grad_a, grad_b, st));
   if (a_s) HIPCHK(hipMemcpyAsync(a_s, (T & 1) ? J.a1 : J.a0, 8 * P, hipMemcpyDeviceToDevice, st));
   if (b_s) HIPCHK(hipMemcpyAsync(b_s, J.b, 8 * P, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));

@@ -1500,30 +1500,69 @@ __global__ __launch_bounds__(1024) void k_tv_prep(const DevJob* __restrict__ job
 // residual partials in a fixed order and stops the fitting once it is below
 // xi (or at max_iter).  a^t alternates between a0 (t even) and a1 (t odd), so
 // a^T survives the row pass that follows it.
-template <int NT>
-__global__ __launch_bounds__(NT) void k_kub_row(KubJob J, int t) {
+// Thread share g (of S) of sum_q Kmat[q m + o] xs[q], in four independent
+// partial sums so that several loads of the kernel matrix are in flight.
+template <int S>
+__device__ __forceinline__ double kub_dot(const double* __restrict__ Km, const double* xs, int m, int o, int g) {
+  const int per = (m + S - 1) / S;
+  const int q0 = min(m, g * per), q1 = min(m, q0 + per);
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+  int q = q0;
+#pragma unroll 2
+  for (; q + 4 <= q1; q += 4) {
+    r0 += Km[(size_t)q * m + o] * xs[q];
+    r1 += Km[(size_t)(q + 1) * m + o] * xs[q + 1];
+    r2 += Km[(size_t)(q + 2) * m + o] * xs[q + 2];
+    r3 += Km[(size_t)(q + 3) * m + o] * xs[q + 3];
+  }
+  for (; q < q1; ++q) r0 += Km[(size_t)q * m + o] * xs[q];
+  return (r0 + r1) + (r2 + r3);
+}
+
+// Adds the S shares of each offset (threads o, o + OFF, ...) in order; the
+// result is valid in the first OFF threads.  Called by every thread.
+template <int S, int OFF>
+__device__ __forceinline__ double kub_combine(double v, double* sh) {
+  if (S == 1) return v;
+  __syncthreads();
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  double r = v;
+  if ((int)threadIdx.x < OFF) {
+    r = sh[threadIdx.x];
+    for (int g = 1; g < S; ++g) r += sh[g * OFF + threadIdx.x];
+  }
+  __syncthreads();
+  return r;
+}
+
+// The passes run 256 threads per work-group over OFF offsets of one block:
+// OFF = 64 (k^d <= 64) splits each offset's sum over four waves, OFF = 256
+// gives every thread its own offset.
+template <int OFF>
+__global__ __launch_bounds__(256) void k_kub_row(KubJob J, int t) {
+  constexpr int S = 256 / OFF;
   if (J.state[0]) return;
   extern __shared__ double xs[];  // m values of the target block
-  __shared__ double sh[NT];
+  __shared__ double sh[256];
   const int K = blockIdx.x, c = blockIdx.y, m = J.m;
-  const int s = c * NT + threadIdx.x;
+  const int g = threadIdx.x / OFF;
+  const int s = c * OFF + (threadIdx.x - g * OFF);
   double acc = 0.0;
   for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) {
     const int L = J.e_col[e];
     __syncthreads();
-    for (int q = threadIdx.x; q < m; q += NT)
+    for (int q = threadIdx.x; q < m; q += 256)
       xs[q] = t == 0 ? 1.0 : J.b[block_member(L, q, J.N, J.n, J.k, J.d)];
     __syncthreads();
-    if (s < m) {
-      double r = 0.0;
-      for (int q = 0; q < m; ++q) r += J.Kts[(size_t)q * m + s] * xs[q];
-      acc += J.e_val[e] * r;
-    }
+    if (s < m) acc += J.e_val[e] * kub_dot<S>(J.Kts, xs, m, s, g);
   }
+  acc = kub_combine<S, OFF>(acc, sh);
   double part = 0.0;
-  if (s < m) {
+  if (g == 0 && s < m) {
     const int i = block_member(K, s, J.N, J.n, J.k, J.d);
     const double mu = J.mu[i];
+    if (J.hist_u) J.hist_u[(size_t)(t + 1) * J.P + i] = acc;
     if (t >= 1) {
       const double muh = ((t & 1) ? J.a1 : J.a0)[i] * acc;
       J.muh[i] = muh;
@@ -1532,43 +1571,43 @@ __global__ __launch_bounds__(NT) void k_kub_row(KubJob J, int t) {
     (((t + 1) & 1) ? J.a1 : J.a0)[i] = acc > 0.0 ? mu / acc : 0.0;
   }
   if (t >= 1) {
-    part = block_sum<NT>(part, sh);
+    part = block_sum<256>(part, sh);
     if (threadIdx.x == 0) J.part_mu[(size_t)K * J.cpb + c] = part;
   }
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_kub_col(KubJob J, int t) {
+template <int OFF>
+__global__ __launch_bounds__(256) void k_kub_col(KubJob J, int t) {
+  constexpr int S = 256 / OFF;
   if (J.state[0]) return;
   extern __shared__ double xs[];  // m values of the source block
-  __shared__ double sh[NT];
+  __shared__ double sh[256];
   const int L = blockIdx.x, c = blockIdx.y, m = J.m;
-  const int o = c * NT + threadIdx.x;
+  const int g = threadIdx.x / OFF;
+  const int o = c * OFF + (threadIdx.x - g * OFF);
   const double* a = (t & 1) ? J.a1 : J.a0;
   double acc = 0.0;
   for (int q0 = J.csc_ptr[L]; q0 < J.csc_ptr[L + 1]; ++q0) {
     const int e = J.csc_idx[q0];
     const int K = J.e_row[e];
     __syncthreads();
-    for (int q = threadIdx.x; q < m; q += NT) xs[q] = a[block_member(K, q, J.N, J.n, J.k, J.d)];
+    for (int q = threadIdx.x; q < m; q += 256) xs[q] = a[block_member(K, q, J.N, J.n, J.k, J.d)];
     __syncthreads();
-    if (o < m) {
-      double r = 0.0;
-      for (int q = 0; q < m; ++q) r += J.Kst[(size_t)q * m + o] * xs[q];
-      acc += J.e_val[e] * r;
-    }
+    if (o < m) acc += J.e_val[e] * kub_dot<S>(J.Kst, xs, m, o, g);
   }
+  acc = kub_combine<S, OFF>(acc, sh);
   double part = 0.0;
-  if (o < m) {
+  if (g == 0 && o < m) {
     const int j = block_member(L, o, J.N, J.n, J.k, J.d);
     const double nu = J.nu[j];
+    if (J.hist_v) J.hist_v[(size_t)t * J.P + j] = acc;
     const double b = acc > 0.0 ? nu / acc : 0.0;
     const double nuh = b * acc;
     J.b[j] = b;
     J.nuh[j] = nuh;
     part = fabs(nu - nuh);
   }
-  part = block_sum<NT>(part, sh);
+  part = block_sum<256>(part, sh);
   if (threadIdx.x == 0) J.part_nu[(size_t)L * J.cpb + c] = part;
 }
 
@@ -1712,6 +1751,135 @@ __global__ __launch_bounds__(256) void k_kub_finalize(KubJob J) {
   res[RS_MW_NU] = wn;
   res[RS_TV_RAW_MU] = c1 * root(tm);
   res[RS_TV_RAW_NU] = c1 * root(tn);
+}
+
+// Gradient of the plan cost P = sum a^T_i pi^_ij b^T_j c_ij through the T
+// fitting iterations (coarse coupling, kernel and T frozen), from the
+// checkpointed u^t, v^t.  With a^t = mu / u^t, b^t = nu / v^t (0 where the
+// denominator is 0), reverse mode gives, for t = T .. 1,
+//   b-bar = (t = T ? d P / d b^T : pi^T u-bar^(t+1)),
+//   d mu_nu += b-bar / v^t,   v-bar = -b-bar nu / (v^t)^2,
+//   a-bar = (t = T ? d P / d a^T : 0) + pi^ v-bar,
+//   d mu += a-bar / u^t,      u-bar = -a-bar mu / (u^t)^2,
+// with d P / d a^T = (pi^ o C) b^T and d P / d b^T = (pi^ o C)^T a^T.  The
+// column half of step t is fused into the pass that produces b-bar.
+
+// Cost-weighted passes for d P / d a^T (rows) and d P / d b^T (columns, with
+// step T's column half).  Other-side block staged in LDS by tiles of 1024.
+template <int NT, bool COLS>
+__global__ __launch_bounds__(NT) void k_kub_pgrad(KubJob J, int T) {
+  __shared__ double sb[1024];
+  __shared__ int sc[1024][3];
+  const int B = blockIdx.x, c = blockIdx.y, m = J.m;
+  const int o = c * NT + threadIdx.x;
+  const double* aT = (T & 1) ? J.a1 : J.a0;
+  int x0 = 0, x1 = 0, x2 = 0, i = 0;
+  if (o < m) {
+    i = block_member(B, o, J.N, J.n, J.k, J.d);
+    pix_coords(i, J.N, J.d, x0, x1, x2);
+  }
+  double acc = 0.0;
+  const int q0 = COLS ? J.csc_ptr[B] : J.csr_ptr[B];
+  const int q1 = COLS ? J.csc_ptr[B + 1] : J.csr_ptr[B + 1];
+  for (int q = q0; q < q1; ++q) {
+    const int e = COLS ? J.csc_idx[q] : q;
+    const int O = COLS ? J.e_row[e] : J.e_col[e];   // the other side's block
+    const double* w = COLS ? aT : J.b;
+    double r = 0.0;
+    for (int t0 = 0; t0 < m; t0 += 1024) {
+      const int tn = min(1024, m - t0);
+      __syncthreads();
+      for (int z = threadIdx.x; z < tn; z += NT) {
+        const int j = block_member(O, t0 + z, J.N, J.n, J.k, J.d);
+        sb[z] = w[j];
+        pix_coords(j, J.N, J.d, sc[z][0], sc[z][1], sc[z][2]);
+      }
+      __syncthreads();
+      if (o < m) {
+        for (int z = 0; z < tn; ++z) {
+          const int e0 = x0 - sc[z][0], e1 = x1 - sc[z][1], e2 = x2 - sc[z][2];
+          const double d2 = (double)(e0 * e0 + e1 * e1 + e2 * e2);
+          const double cst = J.p == 2 ? d2 : sqrt(d2);
+          // rows: Kst[o, t0+z] = Kts[(t0+z) m + o]; columns: Kst[t0+z, o]
+          const double kw = COLS ? J.Kst[(size_t)(t0 + z) * m + o] : J.Kts[(size_t)(t0 + z) * m + o];
+          r += kw * sb[z] * cst;
+        }
+      }
+    }
+    acc += J.e_val[e] * r;
+  }
+  if (o >= m) return;
+  if (!COLS) {
+    J.g_abar[i] = acc;
+  } else {
+    const double v = J.hist_v[(size_t)T * J.P + i];
+    J.g_nu[i] = v > 0.0 ? acc / v : 0.0;
+    J.g_vbar[i] = v > 0.0 ? -acc * J.nu[i] / (v * v) : 0.0;
+  }
+}
+
+// Row half of reverse step t: a-bar = (t = T ? g_abar : 0) + pi^ v-bar.
+template <int OFF>
+__global__ __launch_bounds__(256) void k_kub_rev_row(KubJob J, int t, int T) {
+  constexpr int S = 256 / OFF;
+  extern __shared__ double xs[];
+  __shared__ double sh[256];
+  const int K = blockIdx.x, c = blockIdx.y, m = J.m;
+  const int g = threadIdx.x / OFF;
+  const int s = c * OFF + (threadIdx.x - g * OFF);
+  double acc = 0.0;
+  for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) {
+    const int L = J.e_col[e];
+    __syncthreads();
+    for (int q = threadIdx.x; q < m; q += 256) xs[q] = J.g_vbar[block_member(L, q, J.N, J.n, J.k, J.d)];
+    __syncthreads();
+    if (s < m) acc += J.e_val[e] * kub_dot<S>(J.Kts, xs, m, s, g);
+  }
+  acc = kub_combine<S, OFF>(acc, sh);
+  if (g != 0 || s >= m) return;
+  const int i = block_member(K, s, J.N, J.n, J.k, J.d);
+  const double abar = (t == T ? J.g_abar[i] : 0.0) + acc;
+  const double u = J.hist_u[(size_t)t * J.P + i];
+  const double gm = u > 0.0 ? abar / u : 0.0;
+  J.g_mu[i] = (t == T ? 0.0 : J.g_mu[i]) + gm;
+  J.g_ubar[i] = u > 0.0 ? -abar * J.mu[i] / (u * u) : 0.0;
+}
+
+// b-bar = pi^T u-bar^(t+1), then the column half of step t (t < T).
+template <int OFF>
+__global__ __launch_bounds__(256) void k_kub_rev_col(KubJob J, int t) {
+  constexpr int S = 256 / OFF;
+  extern __shared__ double xs[];
+  __shared__ double sh[256];
+  const int L = blockIdx.x, c = blockIdx.y, m = J.m;
+  const int g = threadIdx.x / OFF;
+  const int o = c * OFF + (threadIdx.x - g * OFF);
+  double acc = 0.0;
+  for (int q0 = J.csc_ptr[L]; q0 < J.csc_ptr[L + 1]; ++q0) {
+    const int e = J.csc_idx[q0];
+    const int K = J.e_row[e];
+    __syncthreads();
+    for (int q = threadIdx.x; q < m; q += 256) xs[q] = J.g_ubar[block_member(K, q, J.N, J.n, J.k, J.d)];
+    __syncthreads();
+    if (o < m) acc += J.e_val[e] * kub_dot<S>(J.Kst, xs, m, o, g);
+  }
+  acc = kub_combine<S, OFF>(acc, sh);
+  if (g != 0 || o >= m) return;
+  const int j = block_member(L, o, J.N, J.n, J.k, J.d);
+  const double v = J.hist_v[(size_t)t * J.P + j];
+  J.g_nu[j] += v > 0.0 ? acc / v : 0.0;
+  J.g_vbar[j] = v > 0.0 ? -acc * J.nu[j] / (v * v) : 0.0;
+}
+
+// grad += dupper d(P^(1/p)) / d(mu, nu), P^(1/p)' = P^(1/p - 1) / p (0 at P = 0).
+__global__ __launch_bounds__(256) void k_kub_grad_out(KubJob J, double dupper, double* __restrict__ ga,
+                                                      double* __restrict__ gb) {
+  const double pc = J.result[RS_PCOST_RAW];
+  const double sc = pc > 0.0 ? dupper * (J.p == 2 ? 0.5 / sqrt(pc) : 1.0) : 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < J.P; i += gridDim.x * 256) {
+    if (ga) ga[i] += sc * J.g_mu[i];
+    if (gb) gb[i] += sc * J.g_nu[i];
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1868,7 +2036,7 @@ int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, 
 int launch_kub_row(const KubJob& J, int t, void* stream) {
   const size_t lds = sizeof(double) * (size_t)J.m;
   if (J.nt == 64)
-    hipLaunchKernelGGL(k_kub_row<64>, dim3(J.Q, J.cpb), dim3(64), lds, (hipStream_t)stream, J, t);
+    hipLaunchKernelGGL(k_kub_row<64>, dim3(J.Q, J.cpb), dim3(256), lds, (hipStream_t)stream, J, t);
   else
     hipLaunchKernelGGL(k_kub_row<256>, dim3(J.Q, J.cpb), dim3(256), lds, (hipStream_t)stream, J, t);
   HIP_TRY(hipGetLastError());
@@ -1877,7 +2045,7 @@ int launch_kub_row(const KubJob& J, int t, void* stream) {
 int launch_kub_col(const KubJob& J, int t, void* stream) {
   const size_t lds = sizeof(double) * (size_t)J.m;
   if (J.nt == 64)
-    hipLaunchKernelGGL(k_kub_col<64>, dim3(J.Q, J.cpb), dim3(64), lds, (hipStream_t)stream, J, t);
+    hipLaunchKernelGGL(k_kub_col<64>, dim3(J.Q, J.cpb), dim3(256), lds, (hipStream_t)stream, J, t);
   else
     hipLaunchKernelGGL(k_kub_col<256>, dim3(J.Q, J.cpb), dim3(256), lds, (hipStream_t)stream, J, t);
   HIP_TRY(hipGetLastError());
@@ -1903,6 +2071,32 @@ int launch_kub_tv(const KubJob& J, void* stream) {
 }
 int launch_kub_finalize(const KubJob& J, void* stream) {
   hipLaunchKernelGGL(k_kub_finalize, dim3(1), dim3(256), 0, (hipStream_t)stream, J);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+
+int launch_kub_backward(const KubJob& J, int T, double dupper, double* grad_a, double* grad_b, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const size_t lds = sizeof(double) * (size_t)J.m;
+  const dim3 g(J.Q, J.cpb);
+  if (J.nt == 64) {
+    hipLaunchKernelGGL((k_kub_pgrad<64, false>), g, dim3(64), 0, st, J, T);
+    hipLaunchKernelGGL((k_kub_pgrad<64, true>), g, dim3(64), 0, st, J, T);
+    for (int t = T; t >= 1; --t) {
+      hipLaunchKernelGGL(k_kub_rev_row<64>, g, dim3(256), lds, st, J, t, T);
+      if (t > 1) hipLaunchKernelGGL(k_kub_rev_col<64>, g, dim3(256), lds, st, J, t - 1);
+    }
+  } else {
+    hipLaunchKernelGGL((k_kub_pgrad<256, false>), g, dim3(256), 0, st, J, T);
+    hipLaunchKernelGGL((k_kub_pgrad<256, true>), g, dim3(256), 0, st, J, T);
+    for (int t = T; t >= 1; --t) {
+      hipLaunchKernelGGL(k_kub_rev_row<256>, g, dim3(256), lds, st, J, t, T);
+      if (t > 1) hipLaunchKernelGGL(k_kub_rev_col<256>, g, dim3(256), lds, st, J, t - 1);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  const int blocks = std::min((J.P + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_kub_grad_out, dim3(blocks), dim3(256), 0, st, J, dupper, grad_a, grad_b);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -122,7 +122,7 @@ struct CtItem { int job, tile, split, pad; };
 // vectors: a, b, mu^, nu^ are fine.  Passed to the kernels by value.
 struct KubJob {
   int d, N, k, p, n, P, Q, m, nnz, max_iter;
-  int nt;                   // threads per work-group in the passes (64 or 256)
+  int nt;                   // offsets per work-group (64 or 256)
   int cpb;                  // work-groups per block: ceil(m / nt)
   int chunks;               // ceil(P / kChunk)
   double xi;
@@ -148,6 +148,14 @@ struct KubJob {
   double* red_tv;           // chunks x kRedSlotsTV
   int* state;               // [0]: fitting stopped
   double* result;           // RS_COUNT
+  // gradient (null without): checkpointed iterates and adjoints
+  double* hist_u;           // (max_iter + 2) x P: row t holds u^t = pi^ b^(t-1)
+  double* hist_v;           // (max_iter + 1) x P: row t holds v^t = pi^T a^t
+  double* g_mu;             // d P / d mu (P = plan cost), accumulated over the iterations
+  double* g_nu;
+  double* g_abar;           // d P / d a^T through the plan cost
+  double* g_ubar;           // adjoint of u^t
+  double* g_vbar;           // adjoint of v^t
 };
 
 int launch_kub_row(const KubJob& J, int t, void* stream);
@@ -156,6 +164,7 @@ int launch_kub_check(const KubJob& J, int t, void* stream);
 int launch_kub_plancost(const KubJob& J, void* stream);
 int launch_kub_tv(const KubJob& J, void* stream);
 int launch_kub_finalize(const KubJob& J, void* stream);
+int launch_kub_backward(const KubJob& J, int T, double dupper, double* grad_a, double* grad_b, void* stream);
 
 // Kernel launchers (kernels.hip).  All enqueue on `stream`.
 struct Launch {

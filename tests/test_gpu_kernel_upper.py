@@ -18,6 +18,7 @@ import torch
 
 import synth_inputs as si
 from oracle import coarse, grid, upper
+from oracle import grad as ograd
 
 pytestmark = pytest.mark.gpu
 
@@ -208,5 +209,53 @@ def test_kernel_upper_rejects_bad_kernels():
     out = qbw.QbwResult()
     cs = rec.struct()
     rc = lib.qbw_upper_kernel(qbw.context(0).handle, C.byref(grid3), big.data_ptr(), big.data_ptr(),
-                              C.byref(cs), tiny.ctypes.data, None, C.byref(out), None, None, None)
+                              C.byref(cs), tiny.ctypes.data, None, C.byref(out), None, None, 0.0, None, None,
+                              None)
     assert rc == 2 and "4096" in lib.qbw_last_error().decode()
+
+
+# ------------------------------------------------------------------ gradient
+
+GCASES = [(16, 2, 4, 2, "random", 6), (16, 2, 4, 1, "gaussian", 8), (8, 3, 2, 2, "sparse", 5),
+          (32, 2, 8, 2, "gaussian", 10), (40, 2, 10, 1, "random", 4), (16, 3, 8, 2, "wide", 3)]
+
+
+@pytest.mark.parametrize("N,d,k,p,kind,iters", GCASES)
+def test_kernel_upper_gradient_matches_oracle(N, d, k, p, kind, iters):
+    mu = si.family("gmm", N, d, si.rng(8500 + N + k))
+    nu = si.family("grf", N, d, si.rng(8501 + N + k))
+    K = make_kernel(kind, k, d, 8502 + N)
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
+    rec = qbw.Coarse(r, c, v, ft, gt, obj)
+    du = 0.7
+    pre = torch.ones(N ** d, dtype=torch.float64, device="cuda:0").reshape((N,) * d)
+    res = qbw.upper_kernel(dev(mu), dev(nu), k, p, K, coarse=rec, max_ipf_iter=iters, dupper=du,
+                           grad_a=pre.clone())
+    T = res["ipf_iters"]
+    gm, gn, val = ograd.upper_grad(mu, nu, r, c, v, k, p, T, kernel=K)
+    print(f"N={N} d={d} k={k} p={p} T={T} |g|={np.abs(gm).max():.3e}", flush=True)
+    ga = res["grad_a"].cpu().numpy().reshape(-1) - 1.0      # accumulated onto ones
+    gb = res["grad_b"].cpu().numpy().reshape(-1)
+    scale = max(np.abs(gm).max(), np.abs(gn).max())
+    assert np.abs(ga - du * gm).max() <= 1e-9 * du * scale
+    assert np.abs(gb - du * gn).max() <= 1e-9 * du * scale
+    assert res["upper_cost"] ** (1.0 / p) == pytest.approx(val, rel=1e-9)
+
+
+def test_kernel_upper_autograd():
+    N, d, k, p = 32, 2, 4, 2
+    mu = si.family("cauchy", N, d, si.rng(8600))
+    nu = si.family("gmm", N, d, si.rng(8601))
+    K = make_kernel("gaussian", k, d, 0)
+    r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
+    rec = qbw.Coarse(r, c, v, ft, gt, obj)
+    a = dev(mu).requires_grad_(True)
+    b = dev(nu).requires_grad_(True)
+    ub = qbw.upper_kernel_bound(a, b, k, p, K, coarse=rec, max_ipf_iter=7)
+    (3.0 * ub).backward()
+    fwd = qbw.upper_kernel(dev(mu), dev(nu), k, p, K, coarse=rec, max_ipf_iter=7)
+    assert float(ub) == fwd["upper"]
+    gm, gn, _ = ograd.upper_grad(mu, nu, r, c, v, k, p, fwd["ipf_iters"], kernel=K)
+    scale = max(np.abs(gm).max(), np.abs(gn).max())
+    assert np.abs(a.grad.cpu().numpy().reshape(-1) - 3.0 * gm).max() <= 3e-9 * scale
+    assert np.abs(b.grad.cpu().numpy().reshape(-1) - 3.0 * gn).max() <= 3e-9 * scale
