@@ -277,6 +277,7 @@ struct Plan {
   int tot_chunk = 0, tot_pool = 0, tot_entry = 0, tot_block = 0, tot_cbar = 0, tot_mom = 0,
       tot_pc1 = 0, tot_pc2 = 0, tot_sep = 0, max_sep_d = 0, tot_ubg = 0;
   bool has_p1 = false, has_p2 = false;  // grid cost exponents present
+  unsigned sep_kinds = 0;  // separable passes present: bit 0 k_ct1d, bits 4, 8, 16 k_ct1d_fast<R>
   CtItem* items = nullptr;
   int n_items = 0;
   int ct_grid = 1;
@@ -546,6 +547,8 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.sep = ((mode & PM_SEP) && D.p == 2) ? 1 : 0;
     D.sep_tmp = D.sep ? (float*)(B + O.sep_tmp) : nullptr;
     D.sep_arg = (D.sep && (mode & PM_ARGMIN)) ? (int*)(B + O.sep_arg) : nullptr;
+    D.sep_R = (D.sep && !(mode & PM_ARGMIN)) ? ct1d_fast_R(D.N) : 0;
+    if (D.sep) pl.sep_kinds |= D.sep_R ? (unsigned)D.sep_R : 1u;
     off[0 * (NJ + 1) + j + 1] = off[0 * (NJ + 1) + j] + D.chunks;
     const int bpw = 64 / reduce_group(ipow(D.k, D.d));   // blocks per wave in pooling / moments
     off[1 * (NJ + 1) + j + 1] = off[1 * (NJ + 1) + j] + (D.Q + 4 * bpw - 1) / (4 * bpw);
@@ -556,7 +559,8 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     // p = 1 plan cost: one item per (entry, 64 pixels of its row block)
     off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + (D.p == 1 ? D.nnz * ((ipow(D.k, D.d) + 63) / 64) : 0);
     off[7 * (NJ + 1) + j + 1] = off[7 * (NJ + 1) + j] + (D.p == 2 ? (D.nnz + 255) / 256 : 0);
-    off[8 * (NJ + 1) + j + 1] = off[8 * (NJ + 1) + j] + (D.sep ? D.rows * ((D.N + 63) / 64) : 0);
+    // separable passes: one item per line (fast kernel) or per (line, 64 targets)
+    off[8 * (NJ + 1) + j + 1] = off[8 * (NJ + 1) + j] + (D.sep ? D.rows * (D.sep_R ? 1 : (D.N + 63) / 64) : 0);
     // p = 1 upper-bound gradient: one item per (entry, 64 pixels of the block)
     const int mblk = ipow(D.k, D.d);
     off[9 * (NJ + 1) + j + 1] = off[9 * (NJ + 1) + j] + (D.p == 1 ? D.nnz * ((mblk + 63) / 64) : 0);
@@ -650,8 +654,11 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
 
 static int enqueue_sep(Plan& pl, int phase, hipStream_t st) {
   const int NJ = pl.njobs;
-  for (int pass = 0; pass < pl.max_sep_d; ++pass)
-    CHK(launch_ct1d(pl.djobs, NJ, pl.off_sep, pl.tot_sep, phase, pass, st));
+  for (int pass = 0; pass < pl.max_sep_d; ++pass) {
+    if (pl.sep_kinds & 1u) CHK(launch_ct1d(pl.djobs, NJ, pl.off_sep, pl.tot_sep, phase, pass, st));
+    for (int R : {4, 8, 16})
+      if (pl.sep_kinds & (unsigned)R) CHK(launch_ct1d_fast(pl.djobs, NJ, pl.off_sep, pl.tot_sep, phase, pass, R, st));
+  }
   if (pl.mode & PM_ARGMIN) CHK(launch_sep_argmin(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
   return QBW_OK;
 }

@@ -563,7 +563,7 @@ __global__ __launch_bounds__(64) void k_ct1d(const DevJob* __restrict__ jobs, in
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
-    if (!J.sep || pass >= J.d) continue;
+    if (!J.sep || J.sep_R != 0 || pass >= J.d) continue;
     const int N = J.N, P = J.P;
     const int chunks = (N + 63) / 64;
     const int local = it - off[jb];
@@ -599,6 +599,71 @@ __global__ __launch_bounds__(64) void k_ct1d(const DevJob* __restrict__ jobs, in
     if (v < N) {
       dst[base + (size_t)v * stride] = best;
       if (arg) arg[base + (size_t)v * stride] = barg;
+    }
+  }
+}
+
+// The same pass without arg-mins, one wave per (job, line), for power-of-two
+// N in [32, 1024]: lane l takes R consecutive targets v = (l mod TL) R + r
+// (TL = N / R target lanes) and the sources of group l / TL, one of G = 64 / TL
+// equal slices; the groups' minima are combined by lane exchange at the end.
+// Sources go in blocks of R: for a block starting at t0 the costs
+// (v - t)^2 = (D + r - q)^2, D = (l mod TL) R - t0, take only 2R - 1 values,
+// formed exactly as float32 squares of small integers, so a pair costs one
+// subtraction (addition in later passes) and half a v_min3, and the candidate
+// is rounded exactly as in k_ct1d.
+template <int R>
+__global__ __launch_bounds__(64) void k_ct1d_fast(const DevJob* __restrict__ jobs, int njobs,
+                                                  const int* __restrict__ off, int total, int phase, int pass) {
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    if (!J.sep || J.sep_R != R || pass >= J.d) continue;
+    const int N = J.N, P = J.P;
+    const int line = it - off[jb];
+    int stride = 1;
+    for (int q = 0; q < pass; ++q) stride *= N;
+    const int hi = line / stride, lo = line - hi * stride;
+    const int base = hi * stride * N + lo;
+    const float* src = pass == 0 ? (phase == 0 ? J.fhat : J.g) : J.sep_tmp + (size_t)((pass - 1) & 1) * P;
+    float* dst = pass == J.d - 1 ? (phase == 0 ? J.g : J.f) : J.sep_tmp + (size_t)(pass & 1) * P;
+    const int TL = N / R;            // target lanes per line (<= 64)
+    const int SG = N * TL / 64;      // sources per group (a multiple of R)
+    const int lane = threadIdx.x & 63;
+    const int tl = lane & (TL - 1), grp = lane / TL;
+    const float sgn = pass == 0 ? -1.0f : 1.0f;
+    float acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = INFINITY;
+    const int t_begin = grp * SG, t_end = t_begin + SG;
+    for (int t0 = t_begin; t0 < t_end; t0 += R) {
+      float sv[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) sv[q] = sgn * src[base + (size_t)(t0 + q) * stride];
+      // W[k] = (D + k - (R - 1))^2, k = r - q + R - 1
+      const float b0 = (float)(tl * R - t0 - (R - 1));
+      float W[2 * R - 1];
+#pragma unroll
+      for (int k = 0; k < 2 * R - 1; ++k) {
+        const float e = b0 + (float)k;
+        W[k] = e * e;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int q = 0; q < R; q += 2) {
+          const float c0 = W[r - q + R - 1] + sv[q];
+          const float c1 = W[r - q - 1 + R - 1] + sv[q + 1];
+          acc[r] = __builtin_fminf(acc[r], __builtin_fminf(c0, c1));
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      for (int o = TL; o < 64; o <<= 1) acc[r] = __builtin_fminf(acc[r], __shfl_xor(acc[r], o, 64));
+    if (grp == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[base + (size_t)(tl * R + r) * stride] = acc[r];
     }
   }
 }
@@ -2018,6 +2083,15 @@ int launch_tv_prep(const DevJob* jobs, int njobs, void* stream) {
 int launch_ct1d(const DevJob* jobs, int njobs, const int* off, int total, int phase, int pass,
                 void* stream) {
   hipLaunchKernelGGL(k_ct1d, dim3(grid_for(total)), dim3(64), 0, (hipStream_t)stream, jobs, njobs, off, total, phase, pass);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_ct1d_fast(const DevJob* jobs, int njobs, const int* off, int total, int phase, int pass, int R,
+                     void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (R == 16) hipLaunchKernelGGL(k_ct1d_fast<16>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, pass);
+  else if (R == 8) hipLaunchKernelGGL(k_ct1d_fast<8>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, pass);
+  else hipLaunchKernelGGL(k_ct1d_fast<4>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, pass);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

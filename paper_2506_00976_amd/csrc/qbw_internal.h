@@ -110,6 +110,7 @@ struct DevJob {
   double* mom_bs;           // of b_s
   // separable c-transform (p = 2): two float32 ping-pong buffers and d arg-min planes
   int sep;
+  int sep_R;                // 0: k_ct1d (one wave per line chunk, arg-mins); 4, 8, 16: k_ct1d_fast<R>
   float* sep_tmp;           // 2 x P
   int* sep_arg;             // d x P or null
 };
@@ -210,6 +211,13 @@ int launch_grad2(const DevJob* jobs, int njobs, const int* off, int total, const
 int launch_tv_prep(const DevJob* jobs, int njobs, void* stream);
 int launch_ct1d(const DevJob* jobs, int njobs, const int* off, int total, int phase, int pass,
                 void* stream);
+// Targets per lane of the register-window 1-D pass for lines of length N
+// (power of two, 32 <= N <= 1024), 0 where it does not apply.
+constexpr int ct1d_fast_R(int N) {
+  return (N >= 128 && N <= 1024 && (N & (N - 1)) == 0) ? 16 : N == 64 ? 8 : N == 32 ? 4 : 0;
+}
+int launch_ct1d_fast(const DevJob* jobs, int njobs, const int* off, int total, int phase, int pass, int R,
+                     void* stream);
 int launch_sep_argmin(const DevJob* jobs, int njobs, const int* off, int total, int phase,
                       void* stream);
 int launch_reset_counter(int* counter, int n, void* stream);

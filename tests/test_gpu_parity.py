@@ -423,6 +423,16 @@ def test_ctransform_separable_bit_exact(N, d):
     assert np.array_equal(arg.cpu().numpy().astype(np.int64), refarg)
 
 
+@pytest.mark.parametrize("N,d", [(32, 2), (64, 2), (128, 2), (256, 2), (512, 2), (32, 3), (64, 3)])
+def test_ctransform_separable_fast_path_bit_exact(N, d):
+    # without arg-mins, power-of-two N in [32, 1024] takes the register-window
+    # 1-D kernel (R = 4, 8, 16 targets per lane, sources split over lane groups)
+    phi = (si.rng(9750 + N + d).standard_normal(N ** d) * N * N / 4).astype(np.float32)
+    out = qbw.ctransform_separable(dev(phi), N, d, want_argmin=False)
+    ref, _ = lower.ctransform_sep_o32(phi, N, d)
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
 @pytest.mark.parametrize("N,d,k", [(32, 2, 4), (64, 2, 8), (16, 3, 2), (24, 2, 3)])
 def test_bounds_separable(N, d, k):
     mu, nu = pair(N, d, "grf", "cauchy", 9800 + N + k)
