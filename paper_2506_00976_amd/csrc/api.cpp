@@ -556,14 +556,16 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     off[3 * (NJ + 1) + j + 1] = off[3 * (NJ + 1) + j] + D.Q;
     off[4 * (NJ + 1) + j + 1] = off[4 * (NJ + 1) + j] + (int)(((long long)D.Q * D.Q + 255) / 256);
     off[5 * (NJ + 1) + j + 1] = off[5 * (NJ + 1) + j] + (2 * D.Q + 4 * bpw - 1) / (4 * bpw);
-    // p = 1 plan cost: one item per (entry, 64 pixels of its row block)
-    off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + (D.p == 1 ? D.nnz * ((ipow(D.k, D.d) + 63) / 64) : 0);
+    // p = 1 plan cost and upper-bound gradient: one item per (entry, 64 pixels
+    // of its block), or per 64 / reduce_group(k^d) entries when k^d <= 32
+    const int mblk = ipow(D.k, D.d);
+    const int p1_items = mblk <= 32 ? (D.nnz + 64 / reduce_group(mblk) - 1) / (64 / reduce_group(mblk))
+                                    : D.nnz * ((mblk + 63) / 64);
+    off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + (D.p == 1 ? p1_items : 0);
     off[7 * (NJ + 1) + j + 1] = off[7 * (NJ + 1) + j] + (D.p == 2 ? (D.nnz + 255) / 256 : 0);
     // separable passes: one item per line (fast kernel) or per (line, 64 targets)
     off[8 * (NJ + 1) + j + 1] = off[8 * (NJ + 1) + j] + (D.sep ? D.rows * (D.sep_R ? 1 : (D.N + 63) / 64) : 0);
-    // p = 1 upper-bound gradient: one item per (entry, 64 pixels of the block)
-    const int mblk = ipow(D.k, D.d);
-    off[9 * (NJ + 1) + j + 1] = off[9 * (NJ + 1) + j] + (D.p == 1 ? D.nnz * ((mblk + 63) / 64) : 0);
+    off[9 * (NJ + 1) + j + 1] = off[9 * (NJ + 1) + j] + (D.p == 1 ? p1_items : 0);
     if (D.sep) pl.max_sep_d = std::max(pl.max_sep_d, D.d);
     (D.p == 1 ? pl.has_p1 : pl.has_p2) = true;
   }

@@ -988,6 +988,29 @@ __global__ __launch_bounds__(64) void k_plancost(const DevJob* __restrict__ jobs
     const DevJob& J = jobs[jb];
     if (J.p == 2) continue;
     const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    if (m <= 32) {
+      // small blocks: the wave takes 64 / g entries (g = reduce_group(m) lanes
+      // each), lane a of a group holds source a and stages target a of its entry
+      const int gsz = reduce_group(m), sub = threadIdx.x / gsz, a = threadIdx.x - sub * gsz;
+      const int e = (it - off[jb]) * (64 / gsz) + sub;
+      const bool act = e < J.nnz && a < m;
+      int x0 = 0, x1 = 0, x2 = 0;
+      double wa = 0.0;
+      __syncthreads();
+      if (act) {
+        const int i = block_member(J.e_row[e], a, J.N, J.n, J.k, J.d);
+        const int j = block_member(J.e_col[e], a, J.N, J.n, J.k, J.d);
+        pix_coords(i, J.N, J.d, x0, x1, x2);
+        wa = J.a_s[i];
+        sb[threadIdx.x] = J.b_s[j];
+        pix_coords(j, J.N, J.d, sc[threadIdx.x][0], sc[threadIdx.x][1], sc[threadIdx.x][2]);
+      }
+      __syncthreads();
+      double v = act ? wa * dist_dot(x0, x1, x2, sb + sub * gsz, sc + sub * gsz, m) : 0.0;
+      v = group_sum(v, gsz);
+      if (a == 0 && e < J.nnz) J.part1[e] = v;   // one partial per entry
+      continue;
+    }
     const int pcc = (m + 63) / 64;
     const int li = it - off[jb];
     const int e = li / pcc, c = li - e * pcc;
@@ -1418,14 +1441,33 @@ __global__ __launch_bounds__(64) void k_ub_grad(const DevJob* __restrict__ jobs,
     const DevJob& J = jobs[jb];
     double* grad = side == 0 ? J.grad_a : J.grad_b;
     if (!grad || J.p == 2) continue;   // p = 2 jobs: k_grad2
-    // item = (support entry e, 64 pixels of its block on this side)
     const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+    const double* other = side == 0 ? J.nu : J.mu;
+    if (m <= 32) {
+      // small blocks: 64 / g entries per wave, as in k_plancost
+      const int gsz = reduce_group(m), sub = threadIdx.x / gsz, a = threadIdx.x - sub * gsz;
+      const int e = (it - off[jb]) * (64 / gsz) + sub;
+      const bool act = e < J.nnz && a < m;
+      int x0 = 0, x1 = 0, x2 = 0;
+      __syncthreads();
+      if (act) {
+        const int B = side == 0 ? J.e_row[e] : J.e_col[e];
+        const int O = side == 0 ? J.e_col[e] : J.e_row[e];
+        pix_coords(block_member(B, a, J.N, J.n, J.k, J.d), J.N, J.d, x0, x1, x2);
+        const int j = block_member(O, a, J.N, J.n, J.k, J.d);
+        sw[threadIdx.x] = other[j];
+        pix_coords(j, J.N, J.d, sc[threadIdx.x][0], sc[threadIdx.x][1], sc[threadIdx.x][2]);
+      }
+      __syncthreads();
+      if (act) J.part1[(size_t)e * 64 + a] = J.coef[e] * dist_dot(x0, x1, x2, sw + sub * gsz, sc + sub * gsz, m);
+      continue;
+    }
+    // item = (support entry e, 64 pixels of its block on this side)
     const int per = (m + 63) / 64;
     const int li = it - off[jb];
     const int e = li / per, c = li - e * per;
     const int B = side == 0 ? J.e_row[e] : J.e_col[e];
     const int O = side == 0 ? J.e_col[e] : J.e_row[e];
-    const double* other = side == 0 ? J.nu : J.mu;
     const int a = c * 64 + threadIdx.x;
     int x0 = 0, x1 = 0, x2 = 0;
     if (a < m) pix_coords(block_member(B, a, J.N, J.n, J.k, J.d), J.N, J.d, x0, x1, x2);

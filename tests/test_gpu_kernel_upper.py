@@ -254,7 +254,7 @@ def test_kernel_upper_autograd():
     ub = qbw.upper_kernel_bound(a, b, k, p, K, coarse=rec, max_ipf_iter=7)
     (3.0 * ub).backward()
     fwd = qbw.upper_kernel(dev(mu), dev(nu), k, p, K, coarse=rec, max_ipf_iter=7)
-    assert float(ub) == fwd["upper"]
+    assert float(ub.detach()) == fwd["upper"]
     gm, gn, _ = ograd.upper_grad(mu, nu, r, c, v, k, p, fwd["ipf_iters"], kernel=K)
     scale = max(np.abs(gm).max(), np.abs(gn).max())
     assert np.abs(a.grad.cpu().numpy().reshape(-1) - 3.0 * gm).max() <= 3e-9 * scale
