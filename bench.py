@@ -248,7 +248,7 @@ def main():
             b5.run()
         torch.cuda.synchronize()
         ms5 = (time.perf_counter() - t0) * 1e3 / args.steps
-        ev5 = qbw.Batch(J5, coarse=recs5, backward=True, graph=False)
+        ev5 = qbw.Batch(J5, coarse=recs5, backward=True, graph=False, autotune=True)   # same tiling as b5
         ev5.run()
         torch.cuda.synchronize()
         ev5.set_timing(True)

@@ -20,6 +20,7 @@
 #include <mutex>
 #include <set>
 #include <numeric>
+#include <queue>
 #include <sstream>
 #include <string>
 #include <thread>
@@ -299,25 +300,54 @@ struct Plan {
   }
 };
 
+// Relative time of one c-transform pair: p = 1 adds a correctly rounded
+// square root per new window entry (one per source and lane, and R per source
+// row), measured at 1.5x the p = 2 time on long rows and 1.8x on 32-pixel
+// rows; the split sizing balances time, not pairs.
+static double pair_weight(const qbw_grid& g) {
+  return g.p == 1 ? 1.45 + 10.0 / g.N : 1.0;
+}
+
 static int choose_splits(std::vector<JobIn>& in, int target_waves) {
-  double total = 0;
-  for (auto& j : in) total += std::pow((double)j.g.N, 2.0 * j.g.d);
-  for (auto& j : in) {
-    const int P = ipow(j.g.N, j.g.d), rows = ipow(j.g.N, j.g.d - 1);
-    if (j.tiling.R <= 0) j.tiling.R = default_R(j.g.N);
-    const int tiles = (P + 64 * j.tiling.R - 1) / (64 * j.tiling.R);
-    if (j.tiling.S <= 0) {
-      // the job's share of one round of resident waves, rounded down so the
-      // batch never spills a few items into a second round (equal-sized items
-      // then finish together), and at least one split per tile
-      const double share = std::pow((double)j.g.N, 2.0 * j.g.d) / total;
-      j.tiling.S = std::max(1, (int)std::floor(share * target_waves / tiles));
+  // Items (tile, split) of one launch should end together: starting from one
+  // split per tile, the next split goes to the job whose items take longest
+  // (pairs per item times the pair weight) while one round of target_waves
+  // resident waves has room for that job's tiles.  Jobs with a given S keep it.
+  const int nj = (int)in.size();
+  std::vector<int> tiles(nj), rows(nj);
+  std::vector<double> work(nj);
+  std::priority_queue<std::pair<double, int>> heap;   // (time of one item, job)
+  long long used = 0;
+  for (int j = 0; j < nj; ++j) {
+    JobIn& J = in[j];
+    const int P = ipow(J.g.N, J.g.d);
+    rows[j] = ipow(J.g.N, J.g.d - 1);
+    if (J.tiling.R <= 0) J.tiling.R = default_R(J.g.N);
+    tiles[j] = (P + 64 * J.tiling.R - 1) / (64 * J.tiling.R);
+    work[j] = (double)P * (double)P * pair_weight(J.g) / tiles[j];   // per tile
+    if (J.tiling.S > 0) {
+      J.tiling.S = std::min(J.tiling.S, rows[j]);
+    } else {
+      J.tiling.S = 1;
+      heap.push({work[j], j});
     }
-    j.tiling.S = std::max(1, std::min(j.tiling.S, rows));
+    used += (long long)tiles[j] * J.tiling.S;
+  }
+  while (!heap.empty()) {
+    const int j = heap.top().second;
+    JobIn& J = in[j];
+    if (J.tiling.S >= rows[j] || used + tiles[j] > target_waves) break;   // the longest item stays
+    heap.pop();
+    ++J.tiling.S;
+    used += tiles[j];
+    heap.push({work[j] / J.tiling.S, j});
+  }
+  for (int j = 0; j < nj; ++j) {
+    JobIn& J = in[j];
     // splits take whole source rows: with r = ceil(rows / S) rows per split,
     // use no more splits than needed, so no split is longer than r rows
-    const int r = (rows + j.tiling.S - 1) / j.tiling.S;
-    j.tiling.S = (rows + r - 1) / r;
+    const int r = (rows[j] + J.tiling.S - 1) / J.tiling.S;
+    J.tiling.S = (rows[j] + r - 1) / r;
   }
   return QBW_OK;
 }
@@ -1642,7 +1672,8 @@ qbw_status qbw_batch_create(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs, co
     double best_t = 1e30;
     int best_R = 0, best_w = ctx->target_waves;
     for (int R : {32, 16, 8}) {
-      for (int waves : {ctx->num_cu * 4, ctx->num_cu * 8, ctx->num_cu * 16, ctx->num_cu * 32}) {
+      for (int waves : {ctx->num_cu * 4, ctx->num_cu * 8, ctx->num_cu * 16, ctx->num_cu * 32, ctx->num_cu * 48,
+                        ctx->num_cu * 64}) {
         std::vector<JobIn> cand = in;
         for (auto& J : cand) J.tiling = {(J.g.N % R == 0) ? R : default_R(J.g.N), 0};
         const int keep = ctx->target_waves;
