@@ -585,7 +585,10 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     off[2 * (NJ + 1) + j + 1] = off[2 * (NJ + 1) + j] + D.nnz;
     off[3 * (NJ + 1) + j + 1] = off[3 * (NJ + 1) + j] + D.Q;
     off[4 * (NJ + 1) + j + 1] = off[4 * (NJ + 1) + j] + (int)(((long long)D.Q * D.Q + 255) / 256);
-    off[5 * (NJ + 1) + j + 1] = off[5 * (NJ + 1) + j] + (2 * D.Q + 4 * bpw - 1) / (4 * bpw);
+    // block moments: one item per strip of blocks along the last axis (k <= 64),
+    // else per 4 waves of (side, block) lane groups
+    off[5 * (NJ + 1) + j + 1] = off[5 * (NJ + 1) + j] +
+                                (D.k <= 64 ? ipow(D.n, D.d - 1) : (2 * D.Q + 4 * bpw - 1) / (4 * bpw));
     // p = 1 plan cost and upper-bound gradient: one item per (entry, 64 pixels
     // of its block), or per 64 / reduce_group(k^d) entries when k^d <= 32
     const int mblk = ipow(D.k, D.d);

@@ -603,18 +603,20 @@ __global__ __launch_bounds__(64) void k_ct1d(const DevJob* __restrict__ jobs, in
   }
 }
 
-// The same pass without arg-mins, one wave per (job, line), for power-of-two
-// N in [32, 1024]: lane l takes R consecutive targets v = (l mod TL) R + r
-// (TL = N / R target lanes) and the sources of group l / TL, one of G = 64 / TL
-// equal slices; the groups' minima are combined by lane exchange at the end.
-// Sources go in blocks of R: for a block starting at t0 the costs
-// (v - t)^2 = (D + r - q)^2, D = (l mod TL) R - t0, take only 2R - 1 values,
-// formed exactly as float32 squares of small integers, so a pair costs one
-// subtraction (addition in later passes) and half a v_min3, and the candidate
-// is rounded exactly as in k_ct1d.
+// The same pass without arg-mins, for power-of-two N in [32, 1024]: one wave
+// per (job, line).  Lane l takes R consecutive targets v = (l mod TL) R + r
+// (TL = N / R target lanes) and the sources of group l / TL, one of
+// G = 64 / TL equal slices; the groups' minima are combined by lane exchange
+// at the end.  Sources go in blocks of R: for a block starting at t0 the
+// costs (v - t)^2 = (D + r - q)^2, D = (l mod TL) R - t0, take only 2R - 1
+// values, exact float32 squares of small integers, so a pair costs one
+// subtraction (addition in later passes; fused with the exact square) and
+// half a v_min3, and the candidate is rounded exactly as in k_ct1d.  The
+// line's sources are staged in LDS.
 template <int R>
 __global__ __launch_bounds__(64) void k_ct1d_fast(const DevJob* __restrict__ jobs, int njobs,
                                                   const int* __restrict__ off, int total, int phase, int pass) {
+  __shared__ float line_v[1024];   // the line's signed source values
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
@@ -624,7 +626,7 @@ __global__ __launch_bounds__(64) void k_ct1d_fast(const DevJob* __restrict__ job
     int stride = 1;
     for (int q = 0; q < pass; ++q) stride *= N;
     const int hi = line / stride, lo = line - hi * stride;
-    const int base = hi * stride * N + lo;
+    const size_t base = (size_t)hi * stride * N + lo;
     const float* src = pass == 0 ? (phase == 0 ? J.fhat : J.g) : J.sep_tmp + (size_t)((pass - 1) & 1) * P;
     float* dst = pass == J.d - 1 ? (phase == 0 ? J.g : J.f) : J.sep_tmp + (size_t)(pass & 1) * P;
     const int TL = N / R;            // target lanes per line (<= 64)
@@ -632,6 +634,9 @@ __global__ __launch_bounds__(64) void k_ct1d_fast(const DevJob* __restrict__ job
     const int lane = threadIdx.x & 63;
     const int tl = lane & (TL - 1), grp = lane / TL;
     const float sgn = pass == 0 ? -1.0f : 1.0f;
+    __syncthreads();
+    for (int t = lane; t < N; t += 64) line_v[t] = sgn * src[base + (size_t)t * stride];
+    __syncthreads();
     float acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = INFINITY;
@@ -639,7 +644,7 @@ __global__ __launch_bounds__(64) void k_ct1d_fast(const DevJob* __restrict__ job
     for (int t0 = t_begin; t0 < t_end; t0 += R) {
       float sv[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) sv[q] = sgn * src[base + (size_t)(t0 + q) * stride];
+      for (int q = 0; q < R; ++q) sv[q] = line_v[t0 + q];
       // W[k] = (D + k - (R - 1))^2, k = r - q + R - 1
       const float b0 = (float)(tl * R - t0 - (R - 1));
       float W[2 * R - 1];
@@ -655,6 +660,7 @@ __global__ __launch_bounds__(64) void k_ct1d_fast(const DevJob* __restrict__ job
           const float c0 = W[r - q + R - 1] + sv[q];
           const float c1 = W[r - q - 1 + R - 1] + sv[q + 1];
           acc[r] = __builtin_fminf(acc[r], __builtin_fminf(c0, c1));
+          __asm__("" : "+v"(acc[r]));   // keep the running minimum a chain of v_min3
         }
       }
     }
@@ -1195,13 +1201,71 @@ __global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, i
 
 // Block moments about the block centre (5 slots): which = 0 -> (mu, nu) into
 // (mom_mu, mom_nu); which = 1 -> (a_s, b_s) into (mom_as, mom_bs).
+//
+// k <= 64: one work-group per strip of blocks along the last axis (the k or
+// k^2 pixel rows of one block row), both fields.  Thread t takes the strip's
+// columns t, t + W, ... (W = k floor(256 / k), whole blocks per chunk), sums
+// its column over the strip's rows (coalesced row reads), and the k columns
+// of each block are then added in order from LDS.  k > 64: one lane group per
+// (side, block) as in k_pool (block rows are then long enough to coalesce).
 __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs, int njobs,
                                                  const int* __restrict__ off, int total, int which) {
-  // (side, block) pairs reduced by lane groups as in k_pool
+  __shared__ double cs[5][256];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
+    if (J.k <= 64) {
+      const int k = J.k, N = J.N, n = J.n;
+      const int strip = it - off[jb];
+      const int b0 = J.d == 2 ? 0 : strip / n, b1 = J.d == 2 ? strip : strip - (strip / n) * n;
+      const int W = (256 / k) * k;
+      const int nrows = J.d == 2 ? k : k * k;
+      const double h = 0.5 * (k - 1);
+      for (int side = 0; side < 2; ++side) {
+        const double* m = which == 0 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
+        double* mo = which == 0 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs);
+        for (int c0 = 0; c0 < N; c0 += W) {
+          const int x2 = c0 + (int)threadIdx.x;
+          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s4 = 0.0;
+          if ((int)threadIdx.x < W && x2 < N) {
+            for (int r = 0; r < nrows; ++r) {
+              const int u0 = J.d == 2 ? 0 : r / k, u1 = J.d == 2 ? r : r - (r / k) * k;
+              const size_t row = J.d == 2 ? (size_t)(b1 * k + u1)
+                                          : ((size_t)(b0 * k + u0) * N + (size_t)(b1 * k + u1));
+              const double w = m[row * N + x2];
+              const double d0 = J.d == 2 ? 0.0 : u0 - h, d1 = u1 - h;
+              s0 += w;
+              s1 += w * d0;
+              s2 += w * d1;
+              s4 += w * (d0 * d0 + d1 * d1);
+            }
+          }
+          const double d2 = (double)(x2 % k) - h;
+          __syncthreads();
+          cs[0][threadIdx.x] = s0;
+          cs[1][threadIdx.x] = s1;
+          cs[2][threadIdx.x] = s2;
+          cs[3][threadIdx.x] = s0 * d2;
+          cs[4][threadIdx.x] = s4 + s0 * (d2 * d2);
+          __syncthreads();
+          const int nb = min(W, N - c0) / k;   // whole blocks in this chunk
+          if ((int)threadIdx.x < nb) {
+            const int K2 = c0 / k + (int)threadIdx.x;
+            const int K = J.d == 2 ? b1 * n + K2 : (b0 * n + b1) * n + K2;
+            double* o = mo + 5 * (size_t)K;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+              double v = 0.0;
+              for (int c = 0; c < k; ++c) v += cs[q][threadIdx.x * k + c];
+              o[q] = v;
+            }
+          }
+        }
+      }
+      continue;
+    }
+    // k > 64: (side, block) pairs reduced by lane groups as in k_pool
     const int mm = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
     const int g = reduce_group(mm);
     const int idx = ((it - off[jb]) * 4 + wv) * (64 / g) + lane / g;
