@@ -39,15 +39,32 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the kernel source with comments and blank space removed, so that
-    edits to comments do not invalidate counters taken on the same code."""
+    """Hash of the code that decides what one c-transform launch does: the
+    device helpers and the c-transform section of kernels.hip, the shared
+    header, the host planner (item table, splits) and the build flags, with
+    comments and blank space removed.  Edits to comments or to other kernels
+    do not invalidate counters taken on the same c-transform code."""
     import re
-    with open(os.path.join(ROOT, "paper_2506_00976_amd", "csrc", "kernels.hip")) as fh:
+    csrc = os.path.join(ROOT, "paper_2506_00976_amd", "csrc")
+
+    def norm(text):
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        return " ".join(text.split())
+
+    with open(os.path.join(csrc, "kernels.hip")) as fh:
         src = fh.read()
-    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
-    src = re.sub(r"//[^\n]*", " ", src)
-    src = " ".join(src.split())
-    return hashlib.sha256(src.encode()).hexdigest()[:16]
+    mark = "// ------------------------------------------------------------------ "
+    helpers = src[:src.index(mark + "pooling")]
+    ct = src[src.index(mark + "c-transform\n"):src.index(mark + "separable c-transform")]
+    launch = src[src.index("int ctransform_waves_per_cu()"):src.index("int launch_merge(")]
+    parts = [helpers, ct, launch]
+    for name in ("qbw_internal.h", "api.cpp"):
+        with open(os.path.join(csrc, name)) as fh:
+            parts.append(fh.read())
+    with open(os.path.join(ROOT, "paper_2506_00976_amd", "build.py")) as fh:
+        parts.append(fh.read())
+    return hashlib.sha256("\n".join(norm(x) for x in parts).encode()).hexdigest()[:16]
 
 
 def read_traffic():
