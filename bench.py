@@ -118,7 +118,55 @@ def cpu_baseline(N: int, k: int, p: int, budget_s: float = 10.0):
             "sample": f"one 256x256 GRF pair, k=8: {done} random targets of the float32 c-transform "
                       f"(scaled to the 2 x {P} targets of both transforms) + the full upper bound and "
                       f"its gradient; {t_ct + t_ub:.1f} s measured, {per_pair:.1f} s per bound pair",
-            "seconds_measured": t_ct + t_ub}
+            "seconds_measured": t_ct + t_ub, "seconds_upper": t_ub}
+
+
+def _oracle_targets_worker(fh, N, p, targets, budget_s):
+    """One process of the all-cores oracle timing: float32 c-transform targets,
+    128 at a time, until the budget is spent.  Returns (targets done, seconds)."""
+    from oracle import lower
+    t0 = time.perf_counter()
+    done = 0
+    while done < len(targets) and time.perf_counter() - t0 < budget_s:
+        lower.ctransform_o32(fh, N, 2, p, targets=targets[done:done + 128])
+        done += 128
+    return done, time.perf_counter() - t0
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_all_cores(N: int, k: int, p: int, budget_s: float = 10.0):
+    """The same oracle c-transform sample on every host core (up to 16 worker
+    processes, each on its own random targets); the upper bound's share is
+    taken from the single-core run.  Workers are spawned processes that never
+    touch the GPU."""
+    import multiprocessing as mp
+    import concurrent.futures as cf
+    import synth_inputs as si
+    from oracle import lower
+    R = np.load(os.path.join(ROOT, "tests", "golden", "records_256_k8.npz"))
+    fh = lower.upscale_potential(R["grf_f"], N, 2, k).astype(np.float32)
+    P = N * N
+    workers = min(os.cpu_count() or 1, 16)
+    order = np.random.Generator(np.random.PCG64(1)).permutation(P)
+    slices = np.array_split(order, workers)
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        out = list(ex.map(_oracle_targets_worker, [fh] * workers, [N] * workers, [p] * workers, slices,
+                          [budget_s] * workers))
+    done = sum(d for d, _ in out)
+    secs = max(t for _, t in out)
+    rate = done / secs   # targets per second over all workers
+    return {"targets_per_s": rate, "cores": workers, "cpu_model": cpu_model(), "cpu_count": os.cpu_count(),
+            "targets_done": done, "seconds": secs}
 
 
 def main():
@@ -343,6 +391,20 @@ def main():
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(N, k, p)
         log(f"[bench] cpu oracle: {out['cpu_baseline']['value']:.3e} pairs/s")
+        allc = cpu_baseline_all_cores(N, k, p)
+        one = out["cpu_baseline"]
+        # per pair on all cores: the c-transform part scaled by the measured
+        # all-core target rate, the upper-bound part as on one core
+        t_ub = one["seconds_upper"]
+        per_pair = 2 * N * N / allc["targets_per_s"] + t_ub
+        out["cpu_baseline_all_cores"] = {
+            "value": 1.0 / per_pair, "unit": "pairs/s", "cores": allc["cores"], "kind": "oracle",
+            "cpu_model": allc["cpu_model"], "cpu_count": allc["cpu_count"],
+            "sample": f"{allc['targets_done']} random targets of the float32 c-transform on {allc['cores']} "
+                      f"processes in {allc['seconds']:.1f} s, scaled to both transforms, plus the "
+                      f"single-core upper bound and gradient ({t_ub:.1f} s)"}
+        log(f"[bench] cpu oracle, {allc['cores']} cores ({allc['cpu_model']}): "
+            f"{out['cpu_baseline_all_cores']['value']:.3e} pairs/s")
     print(json.dumps(out))
 
 
