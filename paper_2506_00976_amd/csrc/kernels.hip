@@ -1203,10 +1203,11 @@ __global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, i
 // (mom_mu, mom_nu); which = 1 -> (a_s, b_s) into (mom_as, mom_bs).
 //
 // k <= 64: one work-group per strip of blocks along the last axis (the k or
-// k^2 pixel rows of one block row), both fields.  Thread t takes the strip's
-// columns t, t + W, ... (W = k floor(256 / k), whole blocks per chunk), sums
-// its column over the strip's rows (coalesced row reads), and the k columns
-// of each block are then added in order from LDS.  k > 64: one lane group per
+// k^2 pixel rows of one block row), both fields.  The strip goes in chunks of
+// W = k floor(256 / k) columns (whole blocks); a chunk's Wc columns each get
+// 256 / Wc threads that split the strip's rows, every thread sums its share
+// of a column (coalesced row reads), and each block's k columns and their
+// row shares are then added in a fixed order from LDS.  k > 64: one lane group per
 // (side, block) as in k_pool (block rows are then long enough to coalesce).
 __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs, int njobs,
                                                  const int* __restrict__ off, int total, int which) {
@@ -1219,17 +1220,20 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
       const int k = J.k, N = J.N, n = J.n;
       const int strip = it - off[jb];
       const int b0 = J.d == 2 ? 0 : strip / n, b1 = J.d == 2 ? strip : strip - (strip / n) * n;
-      const int W = (256 / k) * k;
+      const int W = (256 / k) * k;            // columns per chunk (whole blocks)
+      const int Wc = min(W, N);               // columns present in a chunk
+      const int RG = 256 / Wc;                // row groups: threads t, t + Wc, ... share a column
+      const int col = (int)threadIdx.x % Wc, rg = (int)threadIdx.x / Wc;
       const int nrows = J.d == 2 ? k : k * k;
       const double h = 0.5 * (k - 1);
       for (int side = 0; side < 2; ++side) {
         const double* m = which == 0 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
         double* mo = which == 0 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs);
         for (int c0 = 0; c0 < N; c0 += W) {
-          const int x2 = c0 + (int)threadIdx.x;
+          const int x2 = c0 + col;
           double s0 = 0.0, s1 = 0.0, s2 = 0.0, s4 = 0.0;
-          if ((int)threadIdx.x < W && x2 < N) {
-            for (int r = 0; r < nrows; ++r) {
+          if (rg < RG && x2 < N) {
+            for (int r = rg; r < nrows; r += RG) {
               const int u0 = J.d == 2 ? 0 : r / k, u1 = J.d == 2 ? r : r - (r / k) * k;
               const size_t row = J.d == 2 ? (size_t)(b1 * k + u1)
                                           : ((size_t)(b0 * k + u0) * N + (size_t)(b1 * k + u1));
@@ -1249,17 +1253,25 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
           cs[3][threadIdx.x] = s0 * d2;
           cs[4][threadIdx.x] = s4 + s0 * (d2 * d2);
           __syncthreads();
-          const int nb = min(W, N - c0) / k;   // whole blocks in this chunk
-          if ((int)threadIdx.x < nb) {
-            const int K2 = c0 / k + (int)threadIdx.x;
-            const int K = J.d == 2 ? b1 * n + K2 : (b0 * n + b1) * n + K2;
-            double* o = mo + 5 * (size_t)K;
+          // column totals over the row groups (in place, in group order) ...
+          if (RG > 1 && (int)threadIdx.x < Wc) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-              double v = 0.0;
-              for (int c = 0; c < k; ++c) v += cs[q][threadIdx.x * k + c];
-              o[q] = v;
+              double v = cs[q][threadIdx.x];
+              for (int g = 1; g < RG; ++g) v += cs[q][g * Wc + threadIdx.x];
+              cs[q][threadIdx.x] = v;
             }
+          }
+          __syncthreads();
+          // ... then each (block, moment) adds its k columns in order
+          const int nb = min(W, N - c0) / k;   // whole blocks in this chunk
+          for (int id = threadIdx.x; id < 5 * nb; id += 256) {
+            const int bq = id / 5, q = id - bq * 5;
+            const int K2 = c0 / k + bq;
+            const int K = J.d == 2 ? b1 * n + K2 : (b0 * n + b1) * n + K2;
+            double v = 0.0;
+            for (int c = 0; c < k; ++c) v += cs[q][bq * k + c];
+            mo[5 * (size_t)K + q] = v;
           }
         }
       }
