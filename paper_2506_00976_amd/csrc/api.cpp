@@ -279,6 +279,7 @@ struct Plan {
       tot_pc1 = 0, tot_pc2 = 0, tot_sep = 0, max_sep_d = 0, tot_ubg = 0;
   bool has_p1 = false, has_p2 = false;  // grid cost exponents present
   unsigned sep_kinds = 0;  // separable passes present: bit 0 k_ct1d, bits 4, 8, 16 k_ct1d_fast<R>
+  P1Items p1_tab{};        // p = 1 plan-cost / gradient items per kernel kind
   CtItem* items = nullptr;
   int n_items = 0;
   int ct_grid = 1;
@@ -409,7 +410,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     O.sep_tmp = sep ? L.add(4 * 2 * (size_t)P) : 0;
     O.sep_arg = (sep && (mode & PM_ARGMIN)) ? L.add(4 * (size_t)d * P) : 0;
   }
-  constexpr int kTables = 10;
+  constexpr int kTables = 12;
   // c-transform work items, grouped per XCD.  Jobs get a home XCD by
   // longest-processing-time assignment of their pair counts; a lone job (or one
   // too big for a single XCD's share) spreads its target tiles over all XCDs.
@@ -592,13 +593,20 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     // p = 1 plan cost and upper-bound gradient: one item per (entry, 64 pixels
     // of its block), or per 64 / reduce_group(k^d) entries when k^d <= 32
     const int mblk = ipow(D.k, D.d);
-    const int p1_items = mblk <= 32 ? (D.nnz + 64 / reduce_group(mblk) - 1) / (64 / reduce_group(mblk))
-                                    : D.nnz * ((mblk + 63) / 64);
-    off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + (D.p == 1 ? p1_items : 0);
+    D.p1_nt = D.p == 1 ? p1_table_nt(D.k, D.d) : 0;
+    // direct kernels (table 6): per (entry, 64 pixels), or 64 / g entries per
+    // item when k^d <= 32; distance-table kernels (tables 10, 11): per
+    // (entry, 64 or 256 pixels)
+    const int p1_items = D.p != 1 || D.p1_nt ? 0
+                         : mblk <= 32 ? (D.nnz + 64 / reduce_group(mblk) - 1) / (64 / reduce_group(mblk))
+                                      : D.nnz * ((mblk + 63) / 64);
+    off[6 * (NJ + 1) + j + 1] = off[6 * (NJ + 1) + j] + p1_items;
+    off[10 * (NJ + 1) + j + 1] = off[10 * (NJ + 1) + j] + (D.p1_nt == 64 ? D.nnz * ((mblk + 63) / 64) : 0);
+    off[11 * (NJ + 1) + j + 1] = off[11 * (NJ + 1) + j] + (D.p1_nt == 256 ? D.nnz * ((mblk + 255) / 256) : 0);
     off[7 * (NJ + 1) + j + 1] = off[7 * (NJ + 1) + j] + (D.p == 2 ? (D.nnz + 255) / 256 : 0);
     // separable passes: one item per line (fast kernel) or per (line, 64 targets)
     off[8 * (NJ + 1) + j + 1] = off[8 * (NJ + 1) + j] + (D.sep ? D.rows * (D.sep_R ? 1 : (D.N + 63) / 64) : 0);
-    off[9 * (NJ + 1) + j + 1] = off[9 * (NJ + 1) + j] + (D.p == 1 ? p1_items : 0);
+    off[9 * (NJ + 1) + j + 1] = off[9 * (NJ + 1) + j] + p1_items;
     if (D.sep) pl.max_sep_d = std::max(pl.max_sep_d, D.d);
     (D.p == 1 ? pl.has_p1 : pl.has_p2) = true;
   }
@@ -618,6 +626,12 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   pl.tot_sep = off[8 * (NJ + 1) + NJ];
   pl.off_ubg = offd + 9 * (NJ + 1);
   pl.tot_ubg = off[9 * (NJ + 1) + NJ];
+  for (int q = 0; q < 2; ++q) {
+    pl.p1_tab.off[1 + q] = offd + (10 + q) * (NJ + 1);
+    pl.p1_tab.total[1 + q] = off[(10 + q) * (NJ + 1) + NJ];
+  }
+  pl.p1_tab.off[0] = pl.off_pc1;
+  pl.p1_tab.total[0] = pl.tot_pc1;
   pl.tot_chunk = off[0 * (NJ + 1) + NJ];
   pl.tot_pool = off[1 * (NJ + 1) + NJ];
   pl.tot_entry = off[2 * (NJ + 1) + NJ];
@@ -728,8 +742,8 @@ static int enqueue_plancost(Plan& pl, hipStream_t st) {
     CHK(launch_moments(pl.djobs, NJ, pl.off_mom, pl.tot_mom, 1, st));
     CHK(launch_plancost2(pl.djobs, NJ, pl.off_pc2, pl.tot_pc2, st));
   }
-  if (pl.tot_pc1) {
-    CHK(launch_plancost(pl.djobs, NJ, pl.off_pc1, pl.tot_pc1, st));
+  if (pl.p1_tab.total[0] + pl.p1_tab.total[1] + pl.p1_tab.total[2]) {
+    CHK(launch_plancost(pl.djobs, NJ, pl.p1_tab, st));
     CHK(launch_pc1_sum(pl.djobs, NJ, st));
   }
   return QBW_OK;
@@ -760,7 +774,10 @@ static int enqueue_backward(Plan& pl, hipStream_t st) {
   CHK(launch_ub_coarse_bwd2(pl.djobs, NJ, pl.bwd_scratch, pl.max_q, st));
   if (pl.has_p1) {
     for (int side = 0; side < 2; ++side) {   // per-entry partials, then per-pixel sums
-      CHK(launch_ub_grad(pl.djobs, NJ, pl.off_ubg, pl.tot_ubg, pl.du, side, st));
+      P1Items ubg = pl.p1_tab;
+      ubg.off[0] = pl.off_ubg;
+      ubg.total[0] = pl.tot_ubg;
+      CHK(launch_ub_grad(pl.djobs, NJ, ubg, pl.du, side, st));
       CHK(launch_ub_grad_sum(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.du, side, st));
     }
   }

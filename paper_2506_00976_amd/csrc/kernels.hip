@@ -992,7 +992,7 @@ __global__ __launch_bounds__(64) void k_plancost(const DevJob* __restrict__ jobs
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
-    if (J.p == 2) continue;
+    if (J.p == 2 || J.p1_nt) continue;   // table-path jobs: k_pc1_tab
     const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
     if (m <= 32) {
       // small blocks: the wave takes 64 / g entries (g = reduce_group(m) lanes
@@ -1043,6 +1043,156 @@ __global__ __launch_bounds__(64) void k_plancost(const DevJob* __restrict__ jobs
     }
     acc = block_sum<64>(acc, sh);
     if (threadIdx.x == 0) J.part1[(size_t)e * pcc + c] = acc;
+  }
+}
+
+// Distance-table kernels (p = 1, blocks of m = k^d pixels with m > 32): for a
+// block pair (B, O) the distance between offset u of B and offset v of O is
+// |k (B - O) + u - v|, and u - v takes only (2k-1)^d values.  Each item builds
+// that table in LDS (float64 square roots of exact integers), stages the
+// other block's weights, and sums weight x table entry over the other block's
+// pixels: the index of u - v is I(u) - I(v) + C with I linear in the offset.
+__device__ __forceinline__ int p1_lin(int a, int k, int d, int w) {
+  if (d == 2) { const int u1 = a / k; return u1 * w + (a - u1 * k); }
+  const int u0 = a / (k * k), r = a - u0 * k * k, u1 = r / k;
+  return (u0 * w + u1) * w + (r - u1 * k);
+}
+
+template <int NT>
+__device__ __forceinline__ void p1_build_table(double* tab, const DevJob& J, int B, int O) {
+  const int k = J.k, w = 2 * k - 1;
+  int b0, b1, b2, o0, o1, o2;
+  pix_coords(B, J.n, J.d, b0, b1, b2);
+  pix_coords(O, J.n, J.d, o0, o1, o2);
+  const int D0 = k * (b0 - o0) - (k - 1), D1 = k * (b1 - o1) - (k - 1), D2 = k * (b2 - o2) - (k - 1);
+  const int size = J.d == 2 ? w * w : w * w * w;
+  for (int q = threadIdx.x; q < size; q += NT) {
+    int e0 = 0, r = q;
+    if (J.d == 3) { e0 = q / (w * w); r = q - e0 * w * w; }
+    const int e1 = r / w, e2 = r - e1 * w;
+    const long long x0 = J.d == 3 ? D0 + e0 : 0, x1 = D1 + e1, x2 = D2 + e2;
+    const long long r2 = x0 * x0 + x1 * x1 + x2 * x2;
+    // the refined float32 root (relative error below 2^-42, inside the upper
+    // bound's allowance) where the squared distance fits its range
+    tab[q] = r2 < (1ll << 24) ? sqrt_int_f64((int)r2) : sqrt((double)r2);
+  }
+}
+
+// sum over the other block's pixels v of wv[v] tab[I(u) - I(v) + C], v in C order
+__device__ __forceinline__ double p1_table_dot(const double* tab, const double* wv, int Iu, int k, int d, int w) {
+  const int C = (k - 1) * (d == 2 ? w + 1 : w * w + w + 1);
+  double s0 = 0.0, s1 = 0.0;
+  int t = 0;
+  const int n0 = d == 2 ? 1 : k;
+  for (int v0 = 0; v0 < n0; ++v0) {
+    for (int v1 = 0; v1 < k; ++v1) {
+      const double* trow = tab + (Iu + C - (v0 * w + v1) * w);
+      int v2 = 0;
+      for (; v2 + 2 <= k; v2 += 2, t += 2) {
+        s0 += wv[t] * trow[-v2];
+        s1 += wv[t + 1] * trow[-v2 - 1];
+      }
+      for (; v2 < k; ++v2, ++t) s0 += wv[t] * trow[-v2];
+    }
+  }
+  return s0 + s1;
+}
+
+// The same sum with k and d known at compile time: fully unrolled, every LDS
+// read at an immediate offset from one base, four partial sums.
+template <int KT, int DT>
+__device__ __forceinline__ double p1_table_dot_fixed(const double* tab, const double* wv, int Iu) {
+  constexpr int w = 2 * KT - 1;
+  constexpr int C = (KT - 1) * (DT == 2 ? w + 1 : w * w + w + 1);
+  const double* base = tab + (Iu + C);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int v0 = 0; v0 < (DT == 2 ? 1 : KT); ++v0)
+#pragma unroll
+    for (int v1 = 0; v1 < KT; ++v1)
+#pragma unroll
+      for (int v2 = 0; v2 < KT; ++v2) {
+        const int t = (v0 * KT + v1) * KT + v2;
+        acc[t & 3] += wv[t] * base[-((v0 * w + v1) * w + v2)];
+      }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+__device__ __forceinline__ double p1_dot_any(const double* tab, const double* wv, int Iu, int k, int d, int w) {
+  if (d == 3 && k == 8) return p1_table_dot_fixed<8, 3>(tab, wv, Iu);
+  if (d == 3 && k == 4) return p1_table_dot_fixed<4, 3>(tab, wv, Iu);
+  if (d == 2 && k == 8) return p1_table_dot_fixed<8, 2>(tab, wv, Iu);
+  if (d == 2 && k == 16) return p1_table_dot_fixed<16, 2>(tab, wv, Iu);
+  return p1_table_dot(tab, wv, Iu, k, d, w);
+}
+
+// p = 1 plan cost, table path: item = (support entry e = (K, L), NT pixels of
+// K); the work-group's partial sum goes to part1 slot e * ceil(m/64) +
+// (NT/64) c, the other slots of its range get 0, and k_pc1_sum adds an
+// entry's slots in order.
+// LDS per table kernel: NT = 64 serves blocks of at most 64 pixels (2D k <= 8,
+// 3D k <= 4: tables of at most 15^2 and 7^3 entries), NT = 256 the rest.
+template <int NT> struct P1Lds {
+  static constexpr int tab = NT == 64 ? 512 : 4096;
+  static constexpr int blk = NT == 64 ? 64 : 1024;
+};
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pc1_tab(const DevJob* __restrict__ jobs, int njobs,
+                                                const int* __restrict__ off, int total) {
+  __shared__ double tab[P1Lds<NT>::tab];
+  __shared__ double sb[P1Lds<NT>::blk];
+  __shared__ double sh[NT];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    if (J.p == 2 || J.p1_nt != NT) continue;
+    const int k = J.k, w = 2 * k - 1;
+    const int m = J.d == 2 ? k * k : k * k * k;
+    const int nch = (m + NT - 1) / NT, pcc = (m + 63) / 64;
+    const int li = it - off[jb];
+    const int e = li / nch, c = li - e * nch;
+    const int K = J.e_row[e], L = J.e_col[e];
+    __syncthreads();
+    p1_build_table<NT>(tab, J, K, L);
+    for (int t = threadIdx.x; t < m; t += NT) sb[t] = J.b_s[block_member(L, t, J.N, J.n, J.k, J.d)];
+    __syncthreads();
+    const int a = c * NT + threadIdx.x;
+    double v = 0.0;
+    if (a < m) v = J.a_s[block_member(K, a, J.N, J.n, J.k, J.d)] * p1_dot_any(tab, sb, p1_lin(a, k, J.d, w), k, J.d, w);
+    v = block_sum<NT>(v, sh);
+    const int s0 = c * (NT / 64);
+    if ((int)threadIdx.x < NT / 64 && s0 + (int)threadIdx.x < pcc)
+      J.part1[(size_t)e * pcc + s0 + threadIdx.x] = threadIdx.x == 0 ? v : 0.0;
+  }
+}
+
+// p = 1 upper-bound gradient, table path: item = (support entry e, NT pixels
+// of the entry's block on this side); part1 layout as in k_ub_grad.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ubg_tab(const DevJob* __restrict__ jobs, int njobs,
+                                                const int* __restrict__ off, int total, int side) {
+  __shared__ double tab[P1Lds<NT>::tab];
+  __shared__ double sb[P1Lds<NT>::blk];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    double* grad = side == 0 ? J.grad_a : J.grad_b;
+    if (!grad || J.p == 2 || J.p1_nt != NT) continue;
+    const int k = J.k, w = 2 * k - 1;
+    const int m = J.d == 2 ? k * k : k * k * k;
+    const int nch = (m + NT - 1) / NT, per = (m + 63) / 64;
+    const int li = it - off[jb];
+    const int e = li / nch, c = li - e * nch;
+    const int B = side == 0 ? J.e_row[e] : J.e_col[e];
+    const int O = side == 0 ? J.e_col[e] : J.e_row[e];
+    const double* other = side == 0 ? J.nu : J.mu;
+    __syncthreads();
+    p1_build_table<NT>(tab, J, B, O);
+    for (int t = threadIdx.x; t < m; t += NT) sb[t] = other[block_member(O, t, J.N, J.n, J.k, J.d)];
+    __syncthreads();
+    const int a = c * NT + threadIdx.x;
+    if (a < m) J.part1[(size_t)e * per * 64 + a] = J.coef[e] * p1_dot_any(tab, sb, p1_lin(a, k, J.d, w), k, J.d, w);
   }
 }
 
@@ -1516,7 +1666,7 @@ __global__ __launch_bounds__(64) void k_ub_grad(const DevJob* __restrict__ jobs,
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
     double* grad = side == 0 ? J.grad_a : J.grad_b;
-    if (!grad || J.p == 2) continue;   // p = 2 jobs: k_grad2
+    if (!grad || J.p == 2 || J.p1_nt) continue;   // p = 2 jobs: k_grad2; table-path jobs: k_ubg_tab
     const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
     const double* other = side == 0 ? J.nu : J.mu;
     if (m <= 32) {
@@ -2122,8 +2272,15 @@ int launch_tv_partial(const DevJob* jobs, int njobs, const int* off, int total, 
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_plancost(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
-  hipLaunchKernelGGL(k_plancost, dim3(grid_for(total)), dim3(64), 0, (hipStream_t)stream, jobs, njobs, off, total);
+int launch_plancost(const DevJob* jobs, int njobs, const P1Items& it, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (it.total[0])
+    hipLaunchKernelGGL(k_plancost, dim3(grid_for(it.total[0])), dim3(64), 0, st, jobs, njobs, it.off[0], it.total[0]);
+  if (it.total[1])
+    hipLaunchKernelGGL(k_pc1_tab<64>, dim3(grid_for(it.total[1])), dim3(64), 0, st, jobs, njobs, it.off[1], it.total[1]);
+  if (it.total[2])
+    hipLaunchKernelGGL(k_pc1_tab<256>, dim3(grid_for(it.total[2])), dim3(256), 0, st, jobs, njobs, it.off[2],
+                       it.total[2]);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
@@ -2158,9 +2315,17 @@ int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int st
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* du, int side,
-                   void* stream) {
-  hipLaunchKernelGGL(k_ub_grad, dim3(grid_for(total)), dim3(64), 0, (hipStream_t)stream, jobs, njobs, off, total, du, side);
+int launch_ub_grad(const DevJob* jobs, int njobs, const P1Items& it, const double* du, int side, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (it.total[0])
+    hipLaunchKernelGGL(k_ub_grad, dim3(grid_for(it.total[0])), dim3(64), 0, st, jobs, njobs, it.off[0], it.total[0],
+                       du, side);
+  if (it.total[1])
+    hipLaunchKernelGGL(k_ubg_tab<64>, dim3(grid_for(it.total[1])), dim3(64), 0, st, jobs, njobs, it.off[1],
+                       it.total[1], side);
+  if (it.total[2])
+    hipLaunchKernelGGL(k_ubg_tab<256>, dim3(grid_for(it.total[2])), dim3(256), 0, st, jobs, njobs, it.off[2],
+                       it.total[2], side);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

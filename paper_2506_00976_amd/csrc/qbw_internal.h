@@ -111,6 +111,7 @@ struct DevJob {
   // separable c-transform (p = 2): two float32 ping-pong buffers and d arg-min planes
   int sep;
   int sep_R;                // 0: k_ct1d (one wave per line chunk, arg-mins); 4, 8, 16: k_ct1d_fast<R>
+  int p1_nt;                // p = 1 plan cost / gradient: 0 direct kernels, 64 or 256 distance-table kernels
   float* sep_tmp;           // 2 x P
   int* sep_arg;             // d x P or null
 };
@@ -187,7 +188,24 @@ int launch_argmin(const DevJob* jobs, int njobs, const int* off, int total, int 
 int launch_ipf(const DevJob* jobs, int njobs, void* stream);
 int launch_scalings(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_tv_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
-int launch_plancost(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+// p = 1 plan cost and upper-bound gradient on blocks of m = k^d pixels: the
+// work-group size of the distance-table kernels (every pair distance of a
+// block pair is one of (2k-1)^d values, tabulated in LDS), or 0 where the
+// direct kernels are used (m <= 32: several entries per wave; table larger
+// than 4096 entries or m > 1024).
+constexpr int p1_table_nt(int k, int d) {
+  return ((d == 2 ? k * k : k * k * k) <= 32 || (d == 2 ? k * k : k * k * k) > 1024 ||
+          (d == 2 ? (2 * k - 1) * (2 * k - 1) : (2 * k - 1) * (2 * k - 1) * (2 * k - 1)) > 4096)
+             ? 0
+             : ((d == 2 ? k * k : k * k * k) <= 64 ? 64 : 256);
+}
+// Item tables of the three p = 1 kernel kinds: [0] direct, [1] table with 64
+// threads, [2] table with 256 threads (device prefix tables and totals).
+struct P1Items {
+  const int* off[3];
+  int total[3];
+};
+int launch_plancost(const DevJob* jobs, int njobs, const P1Items& items, void* stream);
 int launch_finalize(const DevJob* jobs, int njobs, void* stream);
 int launch_moments(const DevJob* jobs, int njobs, const int* off, int total, int which,
                    void* stream);
@@ -197,8 +215,8 @@ int launch_cbar2(const DevJob* jobs, int njobs, const int* off, int total, doubl
 int launch_lb_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
                    void* stream);
 int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int stride, void* stream);
-int launch_ub_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* du,
-                   int side, void* stream);
+int launch_ub_grad(const DevJob* jobs, int njobs, const P1Items& items, const double* du, int side,
+                   void* stream);
 int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
                       double* const* outs, void* stream);
 int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, void* stream);

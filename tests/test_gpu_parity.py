@@ -270,6 +270,28 @@ def test_gradients_against_oracle_and_fd(p):
         assert fd == pytest.approx(an, rel=2e-5, abs=1e-7)
 
 
+# p = 1 on blocks of 36 .. 1024 pixels: plan cost and upper-bound gradient take
+# the distance-table kernels (64- and 256-thread work-groups, tables of up to
+# 63^2 and 15^3 entries); the oracle sums the pair distances directly.
+@pytest.mark.parametrize("N,d,k", [(48, 2, 6), (64, 2, 16), (64, 2, 32), (24, 3, 6), (16, 3, 8), (16, 3, 4)])
+def test_p1_distance_table_paths(N, d, k):
+    p = 1
+    mu, nu = pair(N, d, "grf", "gmm", 7950 + N + k)
+    rec, (r, c, v, ft, gt, obj) = record(mu, nu, k, p)
+    v2 = v * np.exp(0.2 * si.rng(7951).standard_normal(len(v)))    # several IPF iterations
+    rec2 = qbw.Coarse(r, c, v2, ft)
+    res, ga, gb, _ = qbw.bounds_with_grads(dev(mu), dev(nu), k, p, coarse=rec2, dlower=0.0, dupper=1.0)
+    U = upper.upper_bound_o64(mu, nu, r, c, v2, k, p)
+    assert res["ipf_iters"] == U["iters"]
+    assert res["upper_cost"] == pytest.approx(U["plan_cost"], rel=1e-9)
+    assert res["upper_cost"] >= U["plan_cost"]
+    assert U["upper"] <= res["upper"] <= U["upper"] + ub_tol(mu, nu, N, d, p, U["upper"])
+    ugm, ugn, _ = ograd.upper_grad(mu, nu, r, c, v2, k, p, U["iters"])
+    scale = max(np.abs(ugm).max(), np.abs(ugn).max())
+    assert np.allclose(ga.cpu().numpy().reshape(-1), ugm, rtol=1e-9, atol=1e-9 * scale)
+    assert np.allclose(gb.cpu().numpy().reshape(-1), ugn, rtol=1e-9, atol=1e-9 * scale)
+
+
 def test_autograd_function():
     N, d, k, p = 16, 2, 4, 2
     mu, nu = pair(N, d, "grf", "gmm", 7950)
