@@ -214,6 +214,12 @@ qbw_status qbw_upscale_potential(qbw_ctx* ctx, const qbw_grid* grid, const doubl
 qbw_status qbw_upscale_potential_interp(qbw_ctx* ctx, const qbw_grid* grid, uint32_t interp,
                                         const double* ftil, float* fhat, qbw_stream stream);
 
+/* Tiling of the single-pair calls (qbw_bounds*, qbw_ctransform): targets per
+ * lane R come from the environment variable QBW_TILE_R if it is set to one of
+ * 32, 16, 8, 4, 2, 1 dividing N, else from qbw_autotune_ctransform's result for
+ * the grid, else the largest of 32, 16, 8, 4, 2 dividing N (1 otherwise).
+ * Results do not depend on R. */
+
 /* Lazy c-transform (Section 4, eq. of the lazy c-transform):
  * dst[j] = min_i RN32(RN32(|x_i - x_j|^p) - src[i]) over all N^d pixels,
  * float32, exact min; argmin (device int32, may be NULL) = the lowest flat

@@ -301,12 +301,12 @@ struct Plan {
   }
 };
 
-// Relative time of one c-transform pair: p = 1 adds a correctly rounded
-// square root per new window entry (one per source and lane, and R per source
-// row), measured at 1.5x the p = 2 time on long rows and 1.8x on 32-pixel
-// rows; the split sizing balances time, not pairs.
+// Relative time of one c-transform pair: p = 1 builds a row of correctly
+// rounded square roots per source row and target row (R per lane) and reads
+// the window from it, measured at 1.1x the p = 2 time on 256-pixel rows, 1.3x
+// on 128 and 1.55x on 32-pixel rows; the split sizing balances time, not pairs.
 static double pair_weight(const qbw_grid& g) {
-  return g.p == 1 ? 1.45 + 10.0 / g.N : 1.0;
+  return g.p == 1 ? 1.05 + 16.0 / g.N : 1.0;
 }
 
 static int choose_splits(std::vector<JobIn>& in, int target_waves) {
@@ -902,7 +902,14 @@ static int solve_all(const std::vector<qbw_grid>& grids, const std::vector<std::
   return QBW_OK;
 }
 
+// Single-pair tiling: the environment override QBW_TILE_R (targets per lane,
+// one of 32, 16, 8, 4, 2, 1, used where it divides N), else the tuned value,
+// else the default.
 static Tiling lookup_tiling(qbw_ctx* ctx, const qbw_grid& g) {
+  if (const char* e = std::getenv("QBW_TILE_R")) {
+    const int R = std::atoi(e);
+    if ((R == 32 || R == 16 || R == 8 || R == 4 || R == 2 || R == 1) && g.N % R == 0) return {R, 0};
+  }
   auto it = ctx->tuned.find({g.d, g.N, g.p});
   if (it != ctx->tuned.end()) return it->second;
   return {default_R(g.N), 0};

@@ -424,6 +424,135 @@ __device__ __forceinline__ void ct_tile(const float* __restrict__ src, float* __
   }
 }
 
+// p = 1 with a table instead of a square root per step.  For a source row
+// and a target row the costs are RN32(sqrt(A + a^2)), a = |source column -
+// target column| in [0, N], A the squared distance over the other axes.  At
+// every source row the wave writes, for each of its target rows, that row of
+// N values to LDS (R correctly rounded square roots per lane, the same
+// sqrt_rn_int as the direct path), and the sweep then reads each new window
+// value from LDS.  Within a block of R sources the column offset b + m + 1 - v0
+// keeps one sign per lane (blocks and v0 are multiples of R), so its table
+// position moves by one slot per step (+1 on the increasing side's last step
+// where it crosses a multiple of 32): one address multiply-add per step.  Row
+// entries are stored at a + (a >> 5), rows S = (N + N/32) | 1 apart, so lanes
+// whose offsets differ by 32 (or whose rows differ) hit different banks.
+// Applies when the wave's targets cover whole rows (64R a multiple of N, or
+// N a multiple of 64R) and N <= 2048; the table holds at most 2176 floats.
+constexpr int kCtTab = 2176 + 64;
+__device__ __forceinline__ bool ct_p1_table_ok(int N, int R) {
+  return R >= 4 && N <= 2048 && (((64 * R) % N) == 0 || (N % (64 * R)) == 0);
+}
+
+// One table for every tile variant (separate per-variant arrays made the
+// compiler give up the four-waves-per-SIMD register budget).
+__shared__ float ct_tab[kCtTab];
+
+template <int R>
+__device__ __forceinline__ void ct_tile_p1(const float* __restrict__ src, float* __restrict__ out,
+                                           int N, int d, int P, int tile, int r0, int r1) {
+  float* tab = ct_tab;
+  const int lane = threadIdx.x & 63;
+  const int j0 = tile * 64 * R + lane * R;
+  const bool valid = j0 < P;
+  const int wj0 = tile * 64 * R;
+  const int wrow0 = wj0 / N;                       // first target row of the wave
+  const int rpw = 64 * R >= N ? 64 * R / N : 1;    // target rows per wave
+  const int S = (N + (N >> 5)) | 1;                // table row stride
+  const int jj = valid ? j0 : wj0;
+  const int trow = jj / N;
+  const int v0 = jj - trow * N;
+  const int lr = min(max(trow - wrow0, 0), rpw - 1);
+  // the table row this lane fills and its target row's coordinates
+  const int er = lane % rpw, G = 64 / rpw, cnt = N / G;
+  const int erow = wrow0 + er;
+  int eta, etb;
+  if (d == 2) { eta = 0; etb = erow; } else { eta = erow / N; etb = erow - eta * N; }
+  float mn[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) mn[q] = INFINITY;
+  const_fptr cbase = (const_fptr)src;
+  const size_t end = (size_t)r1 * N;
+  float nxt[R];
+  if (r0 < r1) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) nxt[m] = cbase[(size_t)r0 * N + m];
+  }
+  const int rowbase = lr * S;
+  for (int sr = r0; sr < r1; ++sr) {
+    int sa, sb;
+    if (d == 2) { sa = 0; sb = sr; } else { sa = sr / N; sb = sr - sa * N; }
+    {
+      const int da = sa - eta, db = sb - etb;
+      const int A = da * da + db * db;
+      __syncthreads();   // the previous row's reads are done
+      for (int q = 0; q < cnt; ++q) {
+        const int a = lane / rpw + G * q;
+        tab[er * S + a + (a >> 5)] = sqrt_rn_int((float)(A + a * a));
+      }
+      __syncthreads();
+    }
+    // window at source column 0: W[q] = cost(0, v0 + q), one aligned group of R
+    float W[R];
+    {
+      const float* wp = tab + rowbase + v0 + (v0 >> 5);
+#pragma unroll
+      for (int q = 0; q < R; ++q) W[q] = wp[q];
+    }
+    for (int b = 0; b < N; b += R) {
+      float cur[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) cur[m] = nxt[m];
+      {
+        const size_t cb = (size_t)sr * N + b;
+        const size_t nb = cb + R;
+        const_fptr np = cbase + (nb < end ? nb : cb);
+#pragma unroll
+        for (int m = 0; m < R; ++m) nxt[m] = np[m];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // table positions of the new values (source b + m + 1, target v0)
+      const int s = b >= v0 ? 1 : -1;
+      const int a0 = s * (b + 1 - v0);                       // |offset| at m = 0
+      const int lo = s > 0 ? b - v0 : v0 - b - R;            // the block's aligned group
+      int pa = rowbase + a0 + (lo >> 5);   // position of the next new value
+      const int jmp = (s > 0 && ((b - v0 + R) & 31) == 0) ? 1 : 0;
+#pragma unroll
+      for (int m = 0; m < R; m += 2) {
+        // one running position, stepped as the values are consumed (not R
+        // precomputed addresses held across the block)
+        const float nv0 = tab[pa];
+        pa += s;
+        const float nv1 = tab[pa + (m + 1 == R - 1 ? jmp : 0)];
+        pa += s;
+        __asm__ volatile("" : "+v"(pa));
+        float p0 = cur[m], p1 = cur[m + 1];
+        __asm__("" : "+v"(p0));
+        __asm__("" : "+v"(p1));
+        {
+          const float t0 = W[(R - 1 - m + R) % R] - p0;
+          const float t1 = W[(R - 2 - m + 2 * R) % R] - p1;
+          mn[R - 1] = fminf(mn[R - 1], fminf(t0, t1));
+          __asm__("" : "+v"(mn[R - 1]));
+        }
+        W[(R - 1 - m + R) % R] = nv0;
+#pragma unroll
+        for (int q = 0; q < R - 1; ++q) {
+          const float t0 = W[(q - m + R) % R] - p0;
+          const float t1 = W[(q - m - 1 + 2 * R) % R] - p1;
+          mn[q] = fminf(mn[q], fminf(t0, t1));
+          __asm__("" : "+v"(mn[q]));
+        }
+        W[(R - 2 - m + 2 * R) % R] = nv1;
+      }
+    }
+  }
+  if (valid) {
+    float4* o4 = reinterpret_cast<float4*>(out + j0);
+#pragma unroll
+    for (int q = 0; q < R; q += 4) o4[q / 4] = make_float4(mn[q], mn[q + 1], mn[q + 2], mn[q + 3]);
+  }
+}
+
 // Persistent c-transform.  The planner lays the items out so that position
 // b < G (the grid) is work-group b's item for the first round, positions
 // b = q (mod 8) holding XCD q's share: the dispatcher deals work-groups to the
@@ -439,6 +568,14 @@ __device__ __forceinline__ void ct_item(const DevJob* __restrict__ jobs, const C
   float* out = J.part + (size_t)w.split * J.P;
   const int r0 = (int)(((long long)w.split * J.rows) / J.S);
   const int r1 = (int)(((long long)(w.split + 1) * J.rows) / J.S);
+  if (J.p == 1 && J.R >= 4 && ct_p1_table_ok(J.N, J.R)) {
+    switch (J.R) {
+      case 32: ct_tile_p1<32>(src, out, J.N, J.d, J.P, w.tile, r0, r1); return;
+      case 16: ct_tile_p1<16>(src, out, J.N, J.d, J.P, w.tile, r0, r1); return;
+      case 8: ct_tile_p1<8>(src, out, J.N, J.d, J.P, w.tile, r0, r1); return;
+      default: ct_tile_p1<4>(src, out, J.N, J.d, J.P, w.tile, r0, r1); return;
+    }
+  }
   const int key = J.R * 4 + J.p;
   switch (key) {
     case 32 * 4 + 2: ct_tile<32, 2>(src, out, J.N, J.d, J.P, w.tile, r0, r1); break;
