@@ -213,7 +213,8 @@ static int make_coarse(const qbw_grid& g, const qbw_coarse* c, CoarseHost* out) 
   }
   for (int K = 0; K < Q; ++K)
     if (!std::isfinite(c->f[K])) { set_error("coarse potential is not finite"); return QBW_E_INVAL; }
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return c->rows[a] < c->rows[b]; });
+  const auto by_row = [&](int a, int b) { return c->rows[a] < c->rows[b]; };
+  if (!std::is_sorted(ord.begin(), ord.end(), by_row)) std::stable_sort(ord.begin(), ord.end(), by_row);
   out->rows.resize(c->nnz); out->cols.resize(c->nnz); out->vals.resize(c->nnz);
   double obj = 0;
   std::vector<double> Ct;
@@ -453,9 +454,11 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   // (largest first); surplus items of longer queues fill the positions left
   // free by shorter ones, and what exceeds the grid forms the dynamic tail.
   int n_all = 0;
+  const auto larger = [&](const CtItem& x, const CtItem& y) { return item_cost(x) > item_cost(y); };
   for (int q = 0; q < kQueues; ++q) {
-    std::stable_sort(queues[q].begin(), queues[q].end(),
-                     [&](const CtItem& x, const CtItem& y) { return item_cost(x) > item_cost(y); });
+    // items enter in (split, tile) order, usually already by decreasing cost
+    if (!std::is_sorted(queues[q].begin(), queues[q].end(), larger))
+      std::stable_sort(queues[q].begin(), queues[q].end(), larger);
     n_all += (int)queues[q].size();
   }
   // persistent grid: one work-group per item, at most 32 per compute unit
@@ -471,8 +474,8 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     }
     surplus.insert(surplus.end(), queues[q].begin() + used, queues[q].end());
   }
-  std::stable_sort(surplus.begin(), surplus.end(),
-                   [&](const CtItem& x, const CtItem& y) { return item_cost(x) > item_cost(y); });
+  if (!std::is_sorted(surplus.begin(), surplus.end(), larger))
+    std::stable_sort(surplus.begin(), surplus.end(), larger);
   size_t si = 0;
   for (int b : free_pos) items[b] = surplus[si++];
   for (int b = G; b < n_all; ++b) items[b] = surplus[si++];
