@@ -73,13 +73,13 @@ def test_ctransform_bit_exact(N, d, p):
 # 32, 16, 8, 4; several lanes per row, rows per wave, 2D and 3D), and the
 # direct square-root path where the wave does not cover whole rows.
 @pytest.mark.parametrize("R,N,d", [(32, 64, 2), (32, 128, 2), (16, 64, 2), (16, 32, 3), (8, 64, 2), (8, 16, 3),
-                                   (4, 32, 2), (4, 8, 3), (16, 48, 2)])
+                                   (4, 32, 2), (4, 8, 3), (16, 48, 2), (32, 1024, 2), (16, 2048, 2)])
 def test_ctransform_p1_tile_sizes_bit_exact(R, N, d, monkeypatch):
     monkeypatch.setenv("QBW_TILE_R", str(R))
     P = N ** d
     phi = (si.rng(7050 + N + R + d).standard_normal(P) * N).astype(np.float32)
     out, arg = qbw.ctransform(dev(phi), N, d, 1, want_argmin=True)
-    tg = si.rng(7051).choice(P, min(P, 1500), replace=False)
+    tg = si.rng(7051).choice(P, min(P, 1500 if P <= 1 << 16 else 160 if P <= 1 << 20 else 64), replace=False)
     ref, refarg = lower.ctransform_o32(phi, N, d, 1, targets=tg)
     assert np.array_equal(out.cpu().numpy()[tg], ref)
     assert np.array_equal(arg.cpu().numpy()[tg].astype(np.int64), refarg)
