@@ -348,6 +348,26 @@ def main():
                     "workload": "first pair of the batch (256x256, k=8, p=2), Gaussian kernel sigma=1 px, "
                                 "at most 50 fitting iterations, coarse pre-solved, synchronous call"}
 
+    # ---- batch-size sweep: the same workload at 8 and 128 pairs per step
+    # (32 is the timed value above); each batch repeats the 32 pairs' measures
+    sweep = {str(B): value}
+    for Bs in (8, 128):
+        idx = [i % B for i in range(Bs)]
+        js = [(A[i], Bm[i], k, p, torch.zeros_like(A[i]), torch.zeros_like(Bm[i])) for i in idx]
+        bs = qbw.Batch(js, coarse=[recs[i] for i in idx], backward=True, graph=True)
+        for _ in range(args.warmup):
+            bs.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nrep = max(3, args.steps * 32 // Bs)
+        for _ in range(nrep):
+            bs.run()
+        torch.cuda.synchronize()
+        ms_b = (time.perf_counter() - t0) * 1e3 / nrep
+        sweep[str(Bs)] = Bs / (ms_b / 1e3)
+        del bs
+    log("[bench] batch sizes: " + ", ".join(f"{kb} pairs -> {v:.1f} pairs/s" for kb, v in sorted(sweep.items(), key=lambda x: int(x[0]))))
+
     # consistency of the timed results with the single-pair path
     ref = qbw.bounds(A[0], Bm[0], k, p, coarse=recs[0])
     assert ref["lower"] == res[0]["lower"] and ref["upper"] == res[0]["upper"], (ref, res[0])
@@ -387,6 +407,7 @@ def main():
     if uneven is not None:
         out["uneven_batch"] = uneven
     out["upper_kernel"] = upper_kernel
+    out["batch_sizes_pairs_per_s"] = sweep
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(N, k, p)
