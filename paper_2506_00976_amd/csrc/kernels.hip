@@ -1958,18 +1958,44 @@ __global__ __launch_bounds__(1024) void k_tv_prep(const DevJob* __restrict__ job
 // the in-block offsets in C order), so
 //   (pi^ x)_i   = sum_{L: (K,L) in supp} pi~_KL sum_t Kst[s(i), t] x_(L,t),
 //   (pi^T y)_j  = sum_{K: (K,L) in supp} pi~_KL sum_s Kst[s, t(j)] y_(K,s),
-// and the fitting runs on fine vectors.  One work-group handles nt offsets of
-// one block (grid Q x cpb), stages the other side's block in LDS for each
-// coupling entry, and reads the kernel matrix coalesced (Kts for rows, Kst
-// for columns).  Every pass returns at once after the fitting has stopped.
+// and the fitting runs on fine vectors.  Both sums are linear in x (y), so a
+// pass first adds the other side's blocks, weighted by pi~, into one m-vector
+// z in LDS and then takes a single product with the kernel matrix:
+//   (pi^ x)_(K,s) = sum_t Kst[s, t] z_t,  z_t = sum_{L: (K,L) in supp} pi~_KL x_(L,t).
+// One work-group handles nt offsets of one block (grid Q x cpb) and reads the
+// kernel matrix coalesced (Kts for rows, Kst for columns).  Every pass returns
+// at once after the fitting has stopped.
 //
 // Iteration t (t = 1 .. T) of Algorithm 4 is k_kub_col(t) then k_kub_row(t):
 //   col(t): v = pi^T a^t, b^t = nu / v, nu^ = b^t v        (0/0 := 0)
 //   row(t): u = pi^ b^t,  mu^ = a^t u, a^(t+1) = mu / u
 // with a^1 = mu / (pi^ 1) from row(0); k_kub_check(t) then adds the L1
 // residual partials in a fixed order and stops the fitting once it is below
-// xi (or at max_iter).  a^t alternates between a0 (t even) and a1 (t odd), so
-// a^T survives the row pass that follows it.
+// xi (or at max_iter).  a^t alternates
+// between a0 (t even) and a1 (t odd), so a^T survives the row pass that
+// follows it.
+
+// z_q = sum over block blk's coupling entries e (stored order) of
+// pi~_e x_(B_e, q) into xs[0, m), B_e the other side's block (x null: all
+// ones).  ROWS walks the CSR list of a source block, else the CSC list of a
+// target block.  Ends with a barrier.
+template <bool ROWS>
+__device__ __forceinline__ void kub_stage(const KubJob& J, int blk, const double* __restrict__ x, double* xs) {
+  const int m = J.m;
+  const int r0 = ROWS ? J.csr_ptr[blk] : J.csc_ptr[blk];
+  const int r1 = ROWS ? J.csr_ptr[blk + 1] : J.csc_ptr[blk + 1];
+  for (int q = threadIdx.x; q < m; q += 256) {
+    double z = 0.0;
+    for (int r = r0; r < r1; ++r) {
+      const int e = ROWS ? r : J.csc_idx[r];
+      const int B = ROWS ? J.e_col[e] : J.e_row[e];
+      z += J.e_val[e] * (x ? x[block_member(B, q, J.N, J.n, J.k, J.d)] : 1.0);
+    }
+    xs[q] = z;
+  }
+  __syncthreads();
+}
+
 // Thread share g (of S) of sum_q Kmat[q m + o] xs[q], in four independent
 // partial sums so that several loads of the kernel matrix are in flight.
 template <int S>
@@ -2013,20 +2039,13 @@ template <int OFF>
 __global__ __launch_bounds__(256) void k_kub_row(KubJob J, int t) {
   constexpr int S = 256 / OFF;
   if (J.state[0]) return;
-  extern __shared__ double xs[];  // m values of the target block
+  extern __shared__ double xs[];  // z over the target blocks
   __shared__ double sh[256];
   const int K = blockIdx.x, c = blockIdx.y, m = J.m;
   const int g = threadIdx.x / OFF;
   const int s = c * OFF + (threadIdx.x - g * OFF);
-  double acc = 0.0;
-  for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) {
-    const int L = J.e_col[e];
-    __syncthreads();
-    for (int q = threadIdx.x; q < m; q += 256)
-      xs[q] = t == 0 ? 1.0 : J.b[block_member(L, q, J.N, J.n, J.k, J.d)];
-    __syncthreads();
-    if (s < m) acc += J.e_val[e] * kub_dot<S>(J.Kts, xs, m, s, g);
-  }
+  kub_stage<true>(J, K, t == 0 ? nullptr : J.b, xs);
+  double acc = s < m ? kub_dot<S>(J.Kts, xs, m, s, g) : 0.0;
   acc = kub_combine<S, OFF>(acc, sh);
   double part = 0.0;
   if (g == 0 && s < m) {
@@ -2050,21 +2069,13 @@ template <int OFF>
 __global__ __launch_bounds__(256) void k_kub_col(KubJob J, int t) {
   constexpr int S = 256 / OFF;
   if (J.state[0]) return;
-  extern __shared__ double xs[];  // m values of the source block
+  extern __shared__ double xs[];  // z over the source blocks
   __shared__ double sh[256];
   const int L = blockIdx.x, c = blockIdx.y, m = J.m;
   const int g = threadIdx.x / OFF;
   const int o = c * OFF + (threadIdx.x - g * OFF);
-  const double* a = (t & 1) ? J.a1 : J.a0;
-  double acc = 0.0;
-  for (int q0 = J.csc_ptr[L]; q0 < J.csc_ptr[L + 1]; ++q0) {
-    const int e = J.csc_idx[q0];
-    const int K = J.e_row[e];
-    __syncthreads();
-    for (int q = threadIdx.x; q < m; q += 256) xs[q] = a[block_member(K, q, J.N, J.n, J.k, J.d)];
-    __syncthreads();
-    if (o < m) acc += J.e_val[e] * kub_dot<S>(J.Kst, xs, m, o, g);
-  }
+  kub_stage<false>(J, L, (t & 1) ? J.a1 : J.a0, xs);
+  double acc = o < m ? kub_dot<S>(J.Kst, xs, m, o, g) : 0.0;
   acc = kub_combine<S, OFF>(acc, sh);
   double part = 0.0;
   if (g == 0 && o < m) {
@@ -2081,6 +2092,8 @@ __global__ __launch_bounds__(256) void k_kub_col(KubJob J, int t) {
   if (threadIdx.x == 0) J.part_nu[(size_t)L * J.cpb + c] = part;
 }
 
+// Stop test of iteration t after col(t) and row(t): the L1 residual partials
+// of both passes added in a fixed order, then the stop flag.
 __global__ __launch_bounds__(256) void k_kub_check(KubJob J, int t) {
   if (J.state[0]) return;
   __shared__ double sh[256];
@@ -2297,14 +2310,8 @@ __global__ __launch_bounds__(256) void k_kub_rev_row(KubJob J, int t, int T) {
   const int K = blockIdx.x, c = blockIdx.y, m = J.m;
   const int g = threadIdx.x / OFF;
   const int s = c * OFF + (threadIdx.x - g * OFF);
-  double acc = 0.0;
-  for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) {
-    const int L = J.e_col[e];
-    __syncthreads();
-    for (int q = threadIdx.x; q < m; q += 256) xs[q] = J.g_vbar[block_member(L, q, J.N, J.n, J.k, J.d)];
-    __syncthreads();
-    if (s < m) acc += J.e_val[e] * kub_dot<S>(J.Kts, xs, m, s, g);
-  }
+  kub_stage<true>(J, K, J.g_vbar, xs);
+  double acc = s < m ? kub_dot<S>(J.Kts, xs, m, s, g) : 0.0;
   acc = kub_combine<S, OFF>(acc, sh);
   if (g != 0 || s >= m) return;
   const int i = block_member(K, s, J.N, J.n, J.k, J.d);
@@ -2324,15 +2331,8 @@ __global__ __launch_bounds__(256) void k_kub_rev_col(KubJob J, int t) {
   const int L = blockIdx.x, c = blockIdx.y, m = J.m;
   const int g = threadIdx.x / OFF;
   const int o = c * OFF + (threadIdx.x - g * OFF);
-  double acc = 0.0;
-  for (int q0 = J.csc_ptr[L]; q0 < J.csc_ptr[L + 1]; ++q0) {
-    const int e = J.csc_idx[q0];
-    const int K = J.e_row[e];
-    __syncthreads();
-    for (int q = threadIdx.x; q < m; q += 256) xs[q] = J.g_ubar[block_member(K, q, J.N, J.n, J.k, J.d)];
-    __syncthreads();
-    if (o < m) acc += J.e_val[e] * kub_dot<S>(J.Kst, xs, m, o, g);
-  }
+  kub_stage<false>(J, L, J.g_ubar, xs);
+  double acc = o < m ? kub_dot<S>(J.Kst, xs, m, o, g) : 0.0;
   acc = kub_combine<S, OFF>(acc, sh);
   if (g != 0 || o >= m) return;
   const int j = block_member(L, o, J.N, J.n, J.k, J.d);
