@@ -28,6 +28,8 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "qbw_internal.h"
@@ -44,22 +46,42 @@ int64_t row_min(const int64_t* cr, int64_t pk, const int64_t* pl, int len) {
   for (int j = 0; j < len; ++j) v = std::min(v, cr[j] + pk - pl[j]);
   return v;
 }
+// The same with the costs stored in 32 bits (half the bytes streamed).
 __attribute__((target_clones("avx512f", "avx2", "default")))
-double row_min(const double* cr, double pk, const double* pl, int len) {
-  double v = std::numeric_limits<double>::infinity();
-  for (int j = 0; j < len; ++j) {
-    const double r = cr[j] + pk - pl[j];
-    v = r < v ? r : v;
-  }
+int64_t row_min(const int32_t* cr, int64_t pk, const int64_t* pl, int len) {
+  int64_t v = std::numeric_limits<int64_t>::max();
+  for (int j = 0; j < len; ++j) v = std::min(v, (int64_t)cr[j] + pk - pl[j]);
   return v;
 }
+// Eight independent running minima so that the loop vectorises: a minimum
+// is exact, so the grouping cannot change the result.
+__attribute__((target_clones("avx512f", "avx2", "default")))
+double row_min(const double* cr, double pk, const double* pl, int len) {
+  constexpr double inf = std::numeric_limits<double>::infinity();
+  double v[8] = {inf, inf, inf, inf, inf, inf, inf, inf};
+  int j = 0;
+  for (; j + 8 <= len; j += 8)
+    for (int u = 0; u < 8; ++u) {
+      const double r = cr[j + u] + pk - pl[j + u];
+      v[u] = r < v[u] ? r : v[u];
+    }
+  double w = inf;
+  for (; j < len; ++j) {
+    const double r = cr[j] + pk - pl[j];
+    w = r < w ? r : w;
+  }
+  for (int u = 0; u < 8; ++u) w = v[u] < w ? v[u] : w;
+  return w;
+}
 
-template <typename Cost>
+// Cost: arithmetic of costs and potentials; Stored: how the cost matrix is
+// held (32-bit integers when every cost fits, to halve the pricing stream).
+template <typename Cost, typename Stored = Cost>
 struct TransportSimplex {
   // Problem: n sources (supply s_k > 0), m sinks (demand t_l > 0), dense
   // cost c[k*m + l].  Nodes 0..n-1 sources, n..n+m-1 sinks, root = n+m.
   int n, m, root;
-  const Cost* c;
+  const Stored* c;
   std::vector<int64_t> supply;  // +s for sources, -t for sinks, 0 for the root
   Cost art;                     // cost of artificial arcs
 
@@ -74,11 +96,12 @@ struct TransportSimplex {
   // its subtree in that order.  A subtree is a contiguous run of the list.
   std::vector<int> parent, pred, thread, rthread, size, last;
   std::vector<Cost> pi;
-  std::vector<int> path, seq;
+  std::vector<int> path;
+  std::vector<std::pair<int, int>> runs;  // (first, last) node of each run
   int64_t next_arc = 0;
   int64_t pivots = 0;
 
-  Cost arc_cost(const Edge& e) const { return e.arc >= 0 ? c[e.arc] : art; }
+  Cost arc_cost(const Edge& e) const { return e.arc >= 0 ? Cost(c[e.arc]) : art; }
 
   void init() {
     const int N = n + m + 1;
@@ -115,7 +138,7 @@ struct TransportSimplex {
 
   Cost reduced(int64_t arc) const {
     int k = (int)(arc / m), l = (int)(arc % m);
-    return c[arc] + pi[k] - pi[n + l];
+    return Cost(c[arc]) + pi[k] - pi[n + l];
   }
 
   // Block search pricing: scan arcs cyclically in blocks of about sqrt(n m),
@@ -133,12 +156,12 @@ struct TransportSimplex {
       int bk = -1, bl = -1;
       for (int64_t left = len; left > 0;) {
         const int seg = (int)std::min<int64_t>(left, m - l);
-        const Cost* cr = c + (int64_t)k * m;
+        const Stored* cr = c + (int64_t)k * m;
         const Cost pk = pi[k];
         const Cost smin = row_min(cr + l, pk, pl + l, seg);
         if (smin < best) {
           int j = l;
-          while (cr[j] + pk - pl[j] != smin) ++j;   // first arc attaining it
+          while (Cost(cr[j]) + pk - pl[j] != smin) ++j;   // first arc attaining it
           best = smin; bk = k; bl = j;
         }
         left -= seg;
@@ -199,17 +222,19 @@ struct TransportSimplex {
     // path u_in = w_0, w_1, ..., w_k = out
     path.clear();
     for (int x = u_in; ; x = parent[x]) { path.push_back(x); if (x == out) break; }
-    // S in its new preorder: the subtree of w_0, then for each i >= 1 the
-    // run of w_i's subtree with the run of w_{i-1}'s subtree taken out
-    seq.clear();
-    for (int x = u_in; ; x = thread[x]) { seq.push_back(x); if (x == last[u_in]) break; }
+    // S in its new preorder is a sequence of runs of the old list: the
+    // subtree of w_0, then for each i >= 1 the run of w_i's subtree with the
+    // run of w_{i-1}'s subtree taken out (w_i up to just before w_{i-1}, and
+    // what follows w_{i-1}'s subtree up to w_i's last node, if anything).
+    // Each run keeps its inner links; only the run ends are relinked.
+    runs.clear();
+    runs.push_back({u_in, last[u_in]});
     for (size_t i = 1; i < path.size(); ++i) {
       const int w = path[i], wc = path[i - 1];
-      for (int x = w; x != wc; x = thread[x]) seq.push_back(x);
-      if (last[wc] != last[w])
-        for (int x = thread[last[wc]]; ; x = thread[x]) { seq.push_back(x); if (x == last[w]) break; }
+      runs.push_back({w, rthread[wc]});
+      if (last[wc] != last[w]) runs.push_back({thread[last[wc]], last[w]});
     }
-    const int lastS = seq.back();
+    const int lastS = runs.back().second;
     // unlink S's old run from the preorder and fix the subtree ends above it
     {
       const int before = rthread[out], after = thread[last[out]];
@@ -223,7 +248,7 @@ struct TransportSimplex {
     {
       const int after = thread[v_in];
       int prev = v_in;
-      for (int x : seq) { thread[prev] = x; rthread[x] = prev; prev = x; }
+      for (const auto& r : runs) { thread[prev] = r.first; rthread[r.first] = prev; prev = r.second; }
       thread[lastS] = after;
       rthread[after] = lastS;
       for (int a = v_in; a >= 0 && last[a] == v_in; a = parent[a]) last[a] = lastS;
@@ -244,9 +269,18 @@ struct TransportSimplex {
     Edge& E = edges[eid];
     E.a = first; E.b = second; E.arc = in_arc; E.flow = delta;
     // potentials of S shift so that the entering arc has zero reduced cost
-    const Cost rc = c[in_arc] + pi[first] - pi[second];
-    const Cost sigma = out_first ? Cost(-rc) : rc;   // first in S: pi[first] -= rc
-    for (int x : seq) pi[x] += sigma;
+    // (first in S: pi[first] -= rc).  Reduced costs only see differences, and
+    // a constant added to every potential cancels in the returned duals, so
+    // with integer costs the other side is shifted instead when it is the
+    // smaller one (floating-point potentials always shift S, so that their
+    // rounding does not depend on which side is smaller).
+    const Cost rc = Cost(c[in_arc]) + pi[first] - pi[second];
+    const Cost sigma = out_first ? Cost(-rc) : rc;
+    if (std::is_integral<Cost>::value && 2 * nS > n + m + 1) {
+      for (int x = thread[lastS]; x != u_in; x = thread[x]) pi[x] -= sigma;
+    } else {
+      for (int x = u_in; ; x = thread[x]) { pi[x] += sigma; if (x == lastS) break; }
+    }
     ++pivots;
   }
 
@@ -261,11 +295,11 @@ struct TransportSimplex {
   }
 };
 
-template <typename Cost>
-int solve_typed(int n, int m, const Cost* cost, const double* a, const double* b,
+template <typename Cost, typename Stored = Cost>
+int solve_typed(int n, int m, const Stored* cost, const double* a, const double* b,
                 const std::vector<int>& src_ids, const std::vector<int>& dst_ids,
                 CoarseSolution* out, Cost eps) {
-  TransportSimplex<Cost> S;
+  TransportSimplex<Cost, Stored> S;
   S.n = n; S.m = m; S.c = cost;
   // integerise supplies
   const double scale = 4503599627370496.0;  // 2^52
@@ -289,7 +323,7 @@ int solve_typed(int n, int m, const Cost* cost, const double* a, const double* b
   if (sa > sb) S.supply[ia] -= (sa - sb);
   else if (sb > sa) S.supply[n + ib] += (sb - sa);
   Cost cmax = 0;
-  for (int64_t e = 0; e < (int64_t)n * m; ++e) cmax = std::max(cmax, cost[e]);
+  for (int64_t e = 0; e < (int64_t)n * m; ++e) cmax = std::max(cmax, Cost(cost[e]));
   S.art = (cmax + 1) * (Cost)(n + m + 1);
   if (!S.solve(int64_t(200) * (n + m) * (n + m) + 100000, eps)) return QBW_E_LP;
   // every artificial arc must carry no flow
@@ -346,10 +380,21 @@ int coarse_solve(const CoarseProblem& P, CoarseSolution* out) {
   std::vector<char> fset(Q, 0), gset(Q, 0);
   int rc;
   if (P.integer_cost) {
-    std::vector<int64_t> c((size_t)n * m);
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < m; ++j) c[(size_t)i * m + j] = (int64_t)std::llround(P.cost[(size_t)src[i] * Q + dst[j]]);
-    rc = solve_typed<int64_t>(n, m, c.data(), a.data(), b.data(), src, dst, out, 0);
+    // integer costs are held in 32 bits when they all fit (arithmetic stays 64-bit)
+    double cm = 0;
+    for (int i : src)
+      for (int j : dst) cm = std::max(cm, std::fabs(P.cost[(size_t)i * Q + j]));
+    if (std::llround(cm) <= std::numeric_limits<int32_t>::max()) {
+      std::vector<int32_t> c((size_t)n * m);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < m; ++j) c[(size_t)i * m + j] = (int32_t)std::llround(P.cost[(size_t)src[i] * Q + dst[j]]);
+      rc = solve_typed<int64_t, int32_t>(n, m, c.data(), a.data(), b.data(), src, dst, out, 0);
+    } else {
+      std::vector<int64_t> c((size_t)n * m);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < m; ++j) c[(size_t)i * m + j] = (int64_t)std::llround(P.cost[(size_t)src[i] * Q + dst[j]]);
+      rc = solve_typed<int64_t>(n, m, c.data(), a.data(), b.data(), src, dst, out, 0);
+    }
   } else {
     std::vector<double> c((size_t)n * m);
     double cm = 0;
