@@ -166,6 +166,7 @@ struct qbw_ctx {
   qbw::Arena work;      // scratch for single-pair calls that keep nothing
   std::map<std::tuple<int, int, int>, qbw::Tiling> tuned;  // (d, N, p) -> tiling
   int target_waves = 4096;
+  float* sqrt_tab = nullptr;  // kSqrtTab entries, filled at creation, read-only after
   // pinned staging for the planner's one host-to-device copy; `staged` marks
   // a copy in flight (completion recorded in `staged_ev`)
   char* stage = nullptr;
@@ -597,6 +598,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     // of its block), or per 64 / reduce_group(k^d) entries when k^d <= 32
     const int mblk = ipow(D.k, D.d);
     D.p1_nt = D.p == 1 ? p1_table_nt(D.k, D.d) : 0;
+    D.sqrt_tab = (D.p == 1 && (int64_t)D.d * (D.N - 1) * (D.N - 1) < kSqrtTab) ? ctx->sqrt_tab : nullptr;
     // direct kernels (table 6): per (entry, 64 pixels), or 64 / g entries per
     // item when k^d <= 32; distance-table kernels (tables 10, 11): per
     // (entry, 64 or 256 pixels)
@@ -936,6 +938,7 @@ qbw_ctx::~qbw_ctx() {
   }
   if (staged_ev) { (void)hipEventSynchronize(staged_ev); (void)hipEventDestroy(staged_ev); }
   if (stage) (void)hipHostFree(stage);
+  if (sqrt_tab) (void)hipFree(sqrt_tab);
 }
 
 struct qbw_batch {
@@ -979,6 +982,20 @@ qbw_status qbw_create(qbw_ctx** ctx, int32_t device) {
   // finish together instead of leaving a partly filled last round
   const int occ = qbw::ctransform_waves_per_cu();
   c->target_waves = c->num_cu * (occ > 0 ? occ : 16);
+  // the integer square-root table, filled once and never written again, so
+  // plans on any stream (and captured graphs) may read it
+  if (hipMalloc(&c->sqrt_tab, sizeof(float) * qbw::kSqrtTab) != hipSuccess) {
+    c->sqrt_tab = nullptr;
+    delete c;
+    set_error("device allocation of the square-root table failed");
+    return QBW_E_NOMEM;
+  }
+  int rc = qbw::launch_sqrt_table(c->sqrt_tab, qbw::kSqrtTab, nullptr);
+  if (rc == QBW_OK && hipDeviceSynchronize() != hipSuccess) {
+    set_error("filling the square-root table failed");
+    rc = QBW_E_HIP;
+  }
+  if (rc != QBW_OK) { delete c; return (qbw_status)rc; }
   *ctx = c;
   return QBW_OK;
 }

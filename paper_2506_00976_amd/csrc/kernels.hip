@@ -104,6 +104,11 @@ __device__ __forceinline__ float sqrt_rn_int(float x) {
   return s;
 }
 
+// t[n] = sqrt_rn_int(n) for n < count (integers below 2^24 are exact floats).
+__global__ __launch_bounds__(256) void k_sqrt_table(float* __restrict__ t, int count) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) t[i] = sqrt_rn_int((float)i);
+}
+
 // ------------------------------------------------------------------ pooling
 
 // Blocks are reduced by groups of g lanes, g the smallest power of two
@@ -449,7 +454,8 @@ __shared__ float ct_tab[kCtTab];
 
 template <int R>
 __device__ __forceinline__ void ct_tile_p1(const float* __restrict__ src, float* __restrict__ out,
-                                           int N, int d, int P, int tile, int r0, int r1) {
+                                           const float* __restrict__ sq, int N, int d, int P, int tile,
+                                           int r0, int r1) {
   float* tab = ct_tab;
   const int lane = threadIdx.x & 63;
   const int j0 = tile * 64 * R + lane * R;
@@ -464,7 +470,10 @@ __device__ __forceinline__ void ct_tile_p1(const float* __restrict__ src, float*
   const int lr = min(max(trow - wrow0, 0), rpw - 1);
   // the table row this lane fills and its target row's coordinates
   const int er = lane % rpw, G = 64 / rpw, cnt = N / G;
-  const int erow = wrow0 + er;
+  // rows past the grid's end (a last wave covering fewer rows) are filled
+  // from the last row: only lanes without targets read them, and every
+  // squared distance stays within (d - 1)(N - 1)^2
+  const int erow = min(wrow0 + er, P / N - 1);
   int eta, etb;
   if (d == 2) { eta = 0; etb = erow; } else { eta = erow / N; etb = erow - eta * N; }
   float mn[R];
@@ -485,9 +494,19 @@ __device__ __forceinline__ void ct_tile_p1(const float* __restrict__ src, float*
       const int da = sa - eta, db = sb - etb;
       const int A = da * da + db * db;
       __syncthreads();   // the previous row's reads are done
-      for (int q = 0; q < cnt; ++q) {
-        const int a = lane / rpw + G * q;
-        tab[er * S + a + (a >> 5)] = sqrt_rn_int((float)(A + a * a));
+      if (sq) {
+        // the same values from the context's square-root table (small grids,
+        // where the fill is a large share of a row's work)
+#pragma unroll 8
+        for (int q = 0; q < cnt; ++q) {
+          const int a = lane / rpw + G * q;
+          tab[er * S + a + (a >> 5)] = sq[A + a * a];
+        }
+      } else {
+        for (int q = 0; q < cnt; ++q) {
+          const int a = lane / rpw + G * q;
+          tab[er * S + a + (a >> 5)] = sqrt_rn_int((float)(A + a * a));
+        }
       }
       __syncthreads();
     }
@@ -570,10 +589,10 @@ __device__ __forceinline__ void ct_item(const DevJob* __restrict__ jobs, const C
   const int r1 = (int)(((long long)(w.split + 1) * J.rows) / J.S);
   if (J.p == 1 && J.R >= 4 && ct_p1_table_ok(J.N, J.R)) {
     switch (J.R) {
-      case 32: ct_tile_p1<32>(src, out, J.N, J.d, J.P, w.tile, r0, r1); return;
-      case 16: ct_tile_p1<16>(src, out, J.N, J.d, J.P, w.tile, r0, r1); return;
-      case 8: ct_tile_p1<8>(src, out, J.N, J.d, J.P, w.tile, r0, r1); return;
-      default: ct_tile_p1<4>(src, out, J.N, J.d, J.P, w.tile, r0, r1); return;
+      case 32: ct_tile_p1<32>(src, out, J.sqrt_tab, J.N, J.d, J.P, w.tile, r0, r1); return;
+      case 16: ct_tile_p1<16>(src, out, J.sqrt_tab, J.N, J.d, J.P, w.tile, r0, r1); return;
+      case 8: ct_tile_p1<8>(src, out, J.sqrt_tab, J.N, J.d, J.P, w.tile, r0, r1); return;
+      default: ct_tile_p1<4>(src, out, J.sqrt_tab, J.N, J.d, J.P, w.tile, r0, r1); return;
     }
   }
   const int key = J.R * 4 + J.p;
@@ -2380,6 +2399,11 @@ int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int*
                       void* stream) {
   hipLaunchKernelGGL(k_ctransform, dim3(grid), dim3(64), 0, (hipStream_t)stream, jobs, items, n_items, counter,
                      phase);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_sqrt_table(float* t, int n, void* stream) {
+  hipLaunchKernelGGL(k_sqrt_table, dim3(grid_for((n + 255) / 256, 1024)), dim3(256), 0, (hipStream_t)stream, t, n);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

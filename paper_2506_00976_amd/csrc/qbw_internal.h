@@ -113,6 +113,7 @@ struct DevJob {
   int sep_R;                // 0: k_ct1d (one wave per line chunk, arg-mins); 4, 8, 16: k_ct1d_fast<R>
   int p1_nt;                // p = 1 plan cost / gradient: 0 direct kernels, 64 or 256 distance-table kernels
   float* sep_tmp;           // 2 x P
+  const float* sqrt_tab;    // p = 1 c-transform table fill: RN32(sqrt(n)) for n < kSqrtTab, or null
   int* sep_arg;             // d x P or null
 };
 
@@ -181,6 +182,12 @@ int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, voi
 constexpr int kQueues = 8;  // XCDs: the planner groups c-transform items per XCD
 // Waves of k_ctransform resident per compute unit (0 if the runtime cannot say).
 int ctransform_waves_per_cu();
+// Entries of the context's integer square-root table: RN32(sqrt(n)) for
+// 0 <= n < kSqrtTab, filled once with the kernels' own correctly rounded
+// square root.  p = 1 jobs with d (N-1)^2 < kSqrtTab read their table rows
+// from it instead of taking square roots.
+constexpr int kSqrtTab = 65536;
+int launch_sqrt_table(float* t, int n, void* stream);
 int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter, int phase, int grid,
                       void* stream);
 int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);

@@ -71,9 +71,13 @@ def test_ctransform_bit_exact(N, d, p):
 
 # p = 1 costs through the LDS table of each target row (targets per lane R =
 # 32, 16, 8, 4; several lanes per row, rows per wave, 2D and 3D), and the
-# direct square-root path where the wave does not cover whole rows.
+# direct square-root path where the wave does not cover whole rows.  Rows of
+# the table come from the context's square-root table where d (N-1)^2 is
+# small (up to 128^2 and 32^3 here) and are computed above that (1024^2,
+# 2048^2); (16, 16, 2) and (8, 8, 2) give a wave more rows than the grid has.
 @pytest.mark.parametrize("R,N,d", [(32, 64, 2), (32, 128, 2), (16, 64, 2), (16, 32, 3), (8, 64, 2), (8, 16, 3),
-                                   (4, 32, 2), (4, 8, 3), (16, 48, 2), (32, 1024, 2), (16, 2048, 2)])
+                                   (4, 32, 2), (4, 8, 3), (16, 48, 2), (32, 1024, 2), (16, 2048, 2),
+                                   (16, 16, 2), (8, 8, 2)])
 def test_ctransform_p1_tile_sizes_bit_exact(R, N, d, monkeypatch):
     monkeypatch.setenv("QBW_TILE_R", str(R))
     P = N ** d
