@@ -68,6 +68,11 @@ typedef struct qbw_grid {
 #define QBW_SEPARABLE 4u     /* p = 2: evaluate each c-transform as d nested 1-D transforms
                                 (O(N^(d+1)) instead of O(N^(2d)); float32 rounding once per
                                 axis, larger derived shift); ignored for p = 1 */
+#define QBW_SEPARABLE_EXACT 32u /* p = 2: the same values and arg-mins as the all-pairs
+                                   c-transform (Section 4), from exact per-axis minima in
+                                   float64, certified per target against float32 rounding,
+                                   brute force where a target cannot be certified (near or
+                                   exact ties); not with QBW_SEPARABLE; ignored for p = 1 */
 /* Interpolation R of the coarse potential (Section 3.5 admits any; the
  * default is multilinear, as in the paper's experiments).  At most one. */
 #define QBW_INTERP_NEAREST 8u  /* f^ = f~ of the pixel's own block (its nearest centre) */
@@ -81,8 +86,8 @@ typedef struct qbw_grid {
 typedef struct qbw_opts {
   double xi;            /* IPF stop: ||a^ - a||_1 + ||b - b^||_1 < xi (default 1e-12) */
   int32_t max_ipf_iter; /* IPF iteration cap (default 50, >= 1) */
-  uint32_t flags;       /* QBW_WANT_ARGMIN | QBW_SAVE_FOR_BWD | QBW_SEPARABLE |
-                           QBW_INTERP_NEAREST or QBW_INTERP_CUBIC */
+  uint32_t flags;       /* QBW_WANT_ARGMIN | QBW_SAVE_FOR_BWD | QBW_SEPARABLE or
+                           QBW_SEPARABLE_EXACT | QBW_INTERP_NEAREST or QBW_INTERP_CUBIC */
 } qbw_opts;
 
 typedef struct qbw_result {
@@ -234,6 +239,18 @@ qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, 
  * (QBW_E_GRID otherwise). */
 qbw_status qbw_ctransform_separable(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
                                     int32_t* argmin, qbw_stream stream);
+
+/* The lazy c-transform of qbw_ctransform for p = 2, bit for bit (values
+ * and arg-mins), evaluated separably: the exact minimum of |x - y|^2 - src
+ * over the sources is a sum of per-axis minima, taken in float64 (d passes,
+ * last axis first); rounding to float32 is monotone, so dst = RN32 of that
+ * minimum wherever the float64 error bound cannot straddle a rounding
+ * boundary, and the arg-min is the best source wherever every other source
+ * rounds higher.  The other targets are evaluated by brute force.
+ * n_fallback (host int32, may be NULL) receives their number.  grid->p
+ * must be 2 (QBW_E_GRID otherwise); src, dst, argmin as in qbw_ctransform. */
+qbw_status qbw_ctransform_exact(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
+                                int32_t* argmin, int32_t* n_fallback, qbw_stream stream);
 
 /* IPF of Algorithm 4 on the uniformly upscaled coupling: from b_s = 1,
  * repeat a_s = a / (pi^ b_s), b_s = b / (pi^T a_s) until the L1 marginal

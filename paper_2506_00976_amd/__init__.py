@@ -18,12 +18,12 @@ import torch
 
 from . import _lib
 from ._lib import (QBW_BATCH_AUTOTUNE, QBW_BATCH_BACKWARD, QBW_BATCH_GRAPH, QBW_INTERP_CUBIC,
-                   QBW_INTERP_NEAREST, QBW_SAVE_FOR_BWD, QBW_SEPARABLE, QBW_WANT_ARGMIN, QBW_WARN_IPF_NOT_CONVERGED, QBW_WARN_LB_CLIPPED, QbwCoarse,
+                   QBW_INTERP_NEAREST, QBW_SAVE_FOR_BWD, QBW_SEPARABLE, QBW_SEPARABLE_EXACT, QBW_WANT_ARGMIN, QBW_WARN_IPF_NOT_CONVERGED, QBW_WARN_LB_CLIPPED, QbwCoarse,
                    QbwError, QbwGrid, QbwJob, QbwOpts, QbwResult, check, load)
 
 __all__ = ["Context", "Coarse", "Batch", "bounds", "wasserstein_bounds", "BoundsFunction",
            "sumpool", "coarse_cost", "cbar", "coarse_solve", "upscale_potential", "ctransform",
-           "ctransform_separable",
+           "ctransform_separable", "ctransform_exact",
            "ipf", "plan_cost", "tv", "upper_kernel", "upper_kernel_bound", "UpperKernelFunction",
            "plan_kernel_gaussian", "autotune_ctransform", "weighted_cost_upper", "min_cost_lower",
            "bounds_with_grads", "QbwError", "load"]
@@ -141,15 +141,29 @@ def coarse_solve(a_t, b_t, N: int, d: int, k: int, p: int) -> Coarse:
     return Coarse(rows[:n], cols[:n], vals[:n], f, g, obj.value)
 
 
+def _sep_flag(separable) -> int:
+    """separable=False: all-pairs c-transforms; True: axis by axis with float32
+    rounding per axis (QBW_SEPARABLE); "exact": axis by axis in float64 with the
+    all-pairs values and arg-mins (QBW_SEPARABLE_EXACT).  p = 1 jobs ignore it."""
+    if separable is False or separable is None:
+        return 0
+    if separable is True:
+        return QBW_SEPARABLE
+    if separable == "exact":
+        return QBW_SEPARABLE_EXACT
+    raise ValueError(f"separable must be False, True or 'exact' (got {separable!r})")
+
+
 def bounds(a, b, k: int, p: int, coarse: Coarse | None = None, xi: float = 1e-12,
            max_ipf_iter: int = 50, want_argmin: bool = False, separable: bool = False,
            interp: str = "linear") -> dict:
     """Lower and upper bound of W_p(a, b) (no autograd).  Returns the qbw_result fields.
-    separable=True evaluates the p = 2 c-transforms axis by axis (QBW_SEPARABLE);
+    separable=True evaluates the p = 2 c-transforms axis by axis (QBW_SEPARABLE),
+    separable="exact" axis by axis with the all-pairs results (QBW_SEPARABLE_EXACT);
     interp picks the interpolation of the coarse potential ("linear", "nearest", "cubic")."""
     a, b = _dev(a), _dev(b)
     grid = _grid(a, k, p)
-    opts = _opts(xi, max_ipf_iter, (QBW_WANT_ARGMIN if want_argmin else 0) | (QBW_SEPARABLE if separable else 0) |
+    opts = _opts(xi, max_ipf_iter, (QBW_WANT_ARGMIN if want_argmin else 0) | _sep_flag(separable) |
                  _interp(interp))
     res = QbwResult()
     lib = load()
@@ -184,7 +198,7 @@ class BoundsFunction(torch.autograd.Function):
     def forward(ctx, a, b, k, p, coarse, xi, max_ipf_iter, want_argmin, separable=False, interp="linear"):
         a, b = _dev(a), _dev(b)
         grid = _grid(a, k, p)
-        flags = QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_argmin else 0) | (QBW_SEPARABLE if separable else 0) | \
+        flags = QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_argmin else 0) | _sep_flag(separable) | \
             _interp(interp)
         opts = _opts(xi, max_ipf_iter, flags)
         res = QbwResult()
@@ -233,7 +247,7 @@ def bounds_with_grads(a, b, k: int, p: int, coarse: Coarse | None = None, dlower
     a, b = _dev(a), _dev(b)
     grid = _grid(a, k, p)
     opts = _opts(xi, max_ipf_iter, QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_fhat_grad else 0) |
-                 (QBW_SEPARABLE if separable else 0) | _interp(interp))
+                 _sep_flag(separable) | _interp(interp))
     res = QbwResult()
     saved = C.c_void_p()
     lib = load()
@@ -314,6 +328,23 @@ def ctransform_separable(src, N: int, d: int, want_argmin: bool = False):
     check(load().qbw_ctransform_separable(context(src.device.index).handle, C.byref(grid), _ptr(src),
                                           _ptr(dst), _ptr(arg), _stream()), "qbw_ctransform_separable")
     return (dst, arg) if want_argmin else dst
+
+
+def ctransform_exact(src, N: int, d: int, want_argmin: bool = False, return_fallback: bool = False):
+    """p = 2 c-transform with the all-pairs values and arg-mins, from exact
+    per-axis minima (qbw_ctransform_exact); return_fallback also returns how
+    many targets needed the brute-force evaluation."""
+    src = _dev(src, torch.float32)
+    grid = QbwGrid(d, N, 1, 2)
+    dst = torch.empty_like(src)
+    arg = torch.empty(src.shape, dtype=torch.int32, device=src.device) if want_argmin else None
+    nfb = C.c_int32(0)
+    check(load().qbw_ctransform_exact(context(src.device.index).handle, C.byref(grid), _ptr(src), _ptr(dst),
+                                      _ptr(arg), C.byref(nfb), _stream()), "qbw_ctransform_exact")
+    out = (dst, arg) if want_argmin else (dst,)
+    if return_fallback:
+        out = out + (nfb.value,)
+    return out if len(out) > 1 else out[0]
 
 
 def ipf(a, b, k: int, coarse: Coarse, xi: float = 1e-12, max_ipf_iter: int = 50):
@@ -496,7 +527,7 @@ class Batch:
             self._keep.append(coarse)
         flags = (QBW_BATCH_BACKWARD if backward else 0) | (QBW_BATCH_GRAPH if graph else 0) | \
                 (QBW_BATCH_AUTOTUNE if autotune else 0)
-        opts = _opts(xi, max_ipf_iter, (QBW_SEPARABLE if separable else 0) | _interp(interp))
+        opts = _opts(xi, max_ipf_iter, _sep_flag(separable) | _interp(interp))
         h = C.c_void_p()
         self.n = len(jobs)
         self.ctx = context(dev)

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libqbw.so")
 QBW_WANT_ARGMIN = 1
 QBW_SAVE_FOR_BWD = 2
 QBW_SEPARABLE = 4
+QBW_SEPARABLE_EXACT = 32
 QBW_INTERP_NEAREST = 8
 QBW_INTERP_CUBIC = 16
 QBW_WARN_IPF_NOT_CONVERGED = 1
@@ -72,6 +73,7 @@ SIGNATURES = [
     ("qbw_upscale_potential_interp", C.c_int, [_vp, _pg, C.c_uint32, _vp, _vp, _vp]),
     ("qbw_ctransform", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
     ("qbw_ctransform_separable", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
+    ("qbw_ctransform_exact", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp, _vp]),
     ("qbw_ipf", C.c_int, [_vp, _pg, _vp, _vp, _pc, _po, _vp, _vp, _vp, _vp, _vp]),
     ("qbw_plan_cost", C.c_int, [_vp, _pg, _pc, _vp, _vp, _vp, _vp]),
     ("qbw_tv", C.c_int, [_vp, _pg, _vp, _vp, _pc, _vp, _vp, _vp, _vp, _vp]),

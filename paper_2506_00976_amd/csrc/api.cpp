@@ -167,6 +167,7 @@ struct qbw_ctx {
   std::map<std::tuple<int, int, int>, qbw::Tiling> tuned;  // (d, N, p) -> tiling
   int target_waves = 4096;
   float* sqrt_tab = nullptr;  // kSqrtTab entries, filled at creation, read-only after
+  double* xs_sq = nullptr;    // kXsSquares entries (exact separable c-transform), likewise
   // pinned staging for the planner's one host-to-device copy; `staged` marks
   // a copy in flight (completion recorded in `staged_ev`)
   char* stage = nullptr;
@@ -261,7 +262,7 @@ struct JobIn {
 };
 
 enum PlanMode : unsigned {
-  PM_FORWARD = 1, PM_ARGMIN = 2, PM_BACKWARD = 4, PM_CBAR = 8, PM_SEP = 16,
+  PM_FORWARD = 1, PM_ARGMIN = 2, PM_BACKWARD = 4, PM_CBAR = 8, PM_SEP = 16, PM_XS = 32,
 };
 
 struct Plan {
@@ -281,6 +282,13 @@ struct Plan {
       tot_pc1 = 0, tot_pc2 = 0, tot_sep = 0, max_sep_d = 0, tot_ubg = 0;
   bool has_p1 = false, has_p2 = false;  // grid cost exponents present
   unsigned sep_kinds = 0;  // separable passes present: bit 0 k_ct1d, bits 4, 8, 16 k_ct1d_fast<R>
+  // exact separable c-transforms: stage items of all such jobs and of the 3D
+  // ones (third stage), the brute-force queue and its length (all pixels)
+  int *off_xs = nullptr, *off_xs3 = nullptr;
+  int tot_xs = 0, tot_xs3 = 0;
+  int* xs_list = nullptr;
+  int xs_pixels = 0;
+  const double* xs_sq = nullptr;
   P1Items p1_tab{};        // p = 1 plan-cost / gradient items per kernel kind
   CtItem* items = nullptr;
   int n_items = 0;
@@ -369,7 +377,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   struct Offs {
     size_t mu_t, nu_t, ftil, fhat, g, f, part, win, arg_g, arg_f, e_row, e_col, e_val, csr, csc,
         csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, gbar_mu, gbar_nu, coef, gquad, part1, mom_mu, mom_nu,
-        mom_as, mom_bs, sep_tmp, sep_arg;
+        mom_as, mom_bs, sep_tmp, sep_arg, xs_v, xs_i;
   };
   std::vector<Offs> offs(NJ);
   const bool ub = true;
@@ -411,8 +419,13 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     const bool sep = (mode & PM_SEP) && J.g.p == 2;
     O.sep_tmp = sep ? L.add(4 * 2 * (size_t)P) : 0;
     O.sep_arg = (sep && (mode & PM_ARGMIN)) ? L.add(4 * (size_t)d * P) : 0;
+    const bool xs = (mode & PM_XS) && J.g.p == 2;
+    O.xs_v = xs ? L.add(8 * 4 * (size_t)P) : 0;
+    O.xs_i = xs ? L.add(4 * 2 * (size_t)P) : 0;
+    if (xs) pl.xs_pixels += P;
   }
-  constexpr int kTables = 12;
+  const size_t o_xs_list = pl.xs_pixels ? L.add(8 * (size_t)pl.xs_pixels) : 0;
+  constexpr int kTables = 14;
   // c-transform work items, grouped per XCD.  Jobs get a home XCD by
   // longest-processing-time assignment of their pair counts; a lone job (or one
   // too big for a single XCD's share) spreads its target tiles over all XCDs.
@@ -435,7 +448,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
     for (int j : order) {
       const auto& J = pl.in[j];
-      if ((mode & PM_SEP) && J.g.p == 2) continue;   // separable jobs use the 1-D passes
+      if ((mode & (PM_SEP | PM_XS)) && J.g.p == 2) continue;   // separable jobs use the 1-D passes
       const int P = ipow(J.g.N, J.g.d);
       const int tiles = (P + 64 * J.tiling.R - 1) / (64 * J.tiling.R);
       const bool spread = work(j) > total / kQueues;
@@ -481,7 +494,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   for (int b : free_pos) items[b] = surplus[si++];
   for (int b = G; b < n_all; ++b) items[b] = surplus[si++];
   pl.n_items = (int)items.size();
-  pl.n_ints = 2 * kQueues + NJ;
+  pl.n_ints = 2 * kQueues + NJ + 2;   // + the two phases' brute-force queue lengths
   const size_t o_ints = L.add(sizeof(int) * pl.n_ints);
   const size_t o_res = L.add(8 * (size_t)RS_COUNT * NJ);
   size_t maxQ = 1;
@@ -584,6 +597,15 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.sep_arg = (D.sep && (mode & PM_ARGMIN)) ? (int*)(B + O.sep_arg) : nullptr;
     D.sep_R = (D.sep && !(mode & PM_ARGMIN)) ? ct1d_fast_R(D.N) : 0;
     if (D.sep) pl.sep_kinds |= D.sep_R ? (unsigned)D.sep_R : 1u;
+    D.xs = ((mode & PM_XS) && D.p == 2) ? 1 : 0;
+    D.xs_v = D.xs ? (double*)(B + O.xs_v) : nullptr;
+    D.xs_i = D.xs ? (int*)(B + O.xs_i) : nullptr;
+    {
+      // exact separable stages: one wave per (64 lines, 8 targets along the axis)
+      const int xs_items = D.xs ? ((D.rows + 63) / 64) * ((D.N + 7) / 8) : 0;
+      off[12 * (NJ + 1) + j + 1] = off[12 * (NJ + 1) + j] + xs_items;
+      off[13 * (NJ + 1) + j + 1] = off[13 * (NJ + 1) + j] + (D.d == 3 ? xs_items : 0);
+    }
     off[0 * (NJ + 1) + j + 1] = off[0 * (NJ + 1) + j] + D.chunks;
     const int bpw = 64 / reduce_group(ipow(D.k, D.d));   // blocks per wave in pooling / moments
     off[1 * (NJ + 1) + j + 1] = off[1 * (NJ + 1) + j] + (D.Q + 4 * bpw - 1) / (4 * bpw);
@@ -635,6 +657,12 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     pl.p1_tab.off[1 + q] = offd + (10 + q) * (NJ + 1);
     pl.p1_tab.total[1 + q] = off[(10 + q) * (NJ + 1) + NJ];
   }
+  pl.off_xs = offd + 12 * (NJ + 1);
+  pl.tot_xs = off[12 * (NJ + 1) + NJ];
+  pl.off_xs3 = offd + 13 * (NJ + 1);
+  pl.tot_xs3 = off[13 * (NJ + 1) + NJ];
+  pl.xs_list = pl.xs_pixels ? (int*)(B + o_xs_list) : nullptr;
+  pl.xs_sq = ctx->xs_sq;
   pl.p1_tab.off[0] = pl.off_pc1;
   pl.p1_tab.total[0] = pl.tot_pc1;
   pl.tot_chunk = off[0 * (NJ + 1) + NJ];
@@ -717,10 +745,21 @@ static int enqueue_sep(Plan& pl, int phase, hipStream_t st) {
   return QBW_OK;
 }
 
+// The queue lengths sit after the jobs' flags in pl.ints and are cleared with
+// the other counters at the start of a forward pass.
+static int* xs_count(Plan& pl, int phase) { return pl.ints + 2 * kQueues + pl.njobs + phase; }
+
+static int enqueue_xs(Plan& pl, int phase, hipStream_t st) {
+  const int fb_grid = std::max(1, std::min(pl.xs_pixels, 4096));
+  return launch_xs(pl.djobs, pl.njobs, pl.off_xs, pl.tot_xs, pl.off_xs3, pl.tot_xs3, phase, pl.xs_sq, pl.xs_list,
+                   xs_count(pl, phase), fb_grid, st);
+}
+
 static int enqueue_ctransforms(Plan& pl, hipStream_t st) {
   const int NJ = pl.njobs;
   for (int phase = 0; phase < 2; ++phase) {
     if (pl.tot_sep) CHK(enqueue_sep(pl, phase, st));
+    if (pl.tot_xs) CHK(enqueue_xs(pl, phase, st));
     if (!pl.n_items) continue;
     std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
     if (pl.timing) {
@@ -939,6 +978,7 @@ qbw_ctx::~qbw_ctx() {
   if (staged_ev) { (void)hipEventSynchronize(staged_ev); (void)hipEventDestroy(staged_ev); }
   if (stage) (void)hipHostFree(stage);
   if (sqrt_tab) (void)hipFree(sqrt_tab);
+  if (xs_sq) (void)hipFree(xs_sq);
 }
 
 struct qbw_batch {
@@ -982,15 +1022,22 @@ qbw_status qbw_create(qbw_ctx** ctx, int32_t device) {
   // finish together instead of leaving a partly filled last round
   const int occ = qbw::ctransform_waves_per_cu();
   c->target_waves = c->num_cu * (occ > 0 ? occ : 16);
-  // the integer square-root table, filled once and never written again, so
-  // plans on any stream (and captured graphs) may read it
+  // the integer square-root and squares tables, filled once and never
+  // written again, so plans on any stream (and captured graphs) may read them
   if (hipMalloc(&c->sqrt_tab, sizeof(float) * qbw::kSqrtTab) != hipSuccess) {
     c->sqrt_tab = nullptr;
     delete c;
     set_error("device allocation of the square-root table failed");
     return QBW_E_NOMEM;
   }
+  if (hipMalloc(&c->xs_sq, sizeof(double) * qbw::kXsSquares) != hipSuccess) {
+    c->xs_sq = nullptr;
+    delete c;
+    set_error("device allocation of the squares table failed");
+    return QBW_E_NOMEM;
+  }
   int rc = qbw::launch_sqrt_table(c->sqrt_tab, qbw::kSqrtTab, nullptr);
+  if (rc == QBW_OK) rc = qbw::launch_xs_squares(c->xs_sq, nullptr);
   if (rc == QBW_OK && hipDeviceSynchronize() != hipSuccess) {
     set_error("filling the square-root table failed");
     rc = QBW_E_HIP;
@@ -1006,6 +1053,10 @@ static int check_opts(const qbw_opts* o) {
   if (!o) return QBW_OK;
   if (o->max_ipf_iter < 1 || o->max_ipf_iter > 100000) { set_error("max_ipf_iter must be in [1, 1e5]"); return QBW_E_INVAL; }
   if (!(o->xi > 0) && !(o->xi <= 0)) { set_error("xi is NaN"); return QBW_E_INVAL; }
+  if ((o->flags & QBW_SEPARABLE) && (o->flags & QBW_SEPARABLE_EXACT)) {
+    set_error("QBW_SEPARABLE and QBW_SEPARABLE_EXACT are exclusive");
+    return QBW_E_INVAL;
+  }
   if ((o->flags & QBW_INTERP_NEAREST) && (o->flags & QBW_INTERP_CUBIC)) {
     set_error("QBW_INTERP_NEAREST and QBW_INTERP_CUBIC are exclusive");
     return QBW_E_INVAL;
@@ -1019,7 +1070,7 @@ static qbw_status bounds_impl(qbw_ctx* ctx, const qbw_grid* grid, const double* 
   qbw_opts o = opts ? *opts : qbw_default_opts();
   const bool save = (o.flags & QBW_SAVE_FOR_BWD) && saved;
   unsigned mode = PM_FORWARD | ((o.flags & QBW_WANT_ARGMIN) ? PM_ARGMIN : 0u) |
-                  ((o.flags & QBW_SEPARABLE) ? PM_SEP : 0u);
+                  ((o.flags & QBW_SEPARABLE) ? PM_SEP : 0u) | ((o.flags & QBW_SEPARABLE_EXACT) ? PM_XS : 0u);
   JobIn J{*grid, a, b, nullptr, nullptr, nullptr, lookup_tiling(ctx, *grid)};
   hipStream_t st = S(stream);
   if (save) {
@@ -1322,6 +1373,26 @@ qbw_status qbw_ctransform_separable(qbw_ctx* ctx, const qbw_grid* grid, const fl
   if (argmin) pl.hj[0].arg_g = argmin;
   HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
   CHK(enqueue_sep(pl, 0, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
+qbw_status qbw_ctransform_exact(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
+                                int32_t* argmin, int32_t* n_fallback, qbw_stream stream) {
+  if (!ctx || !src || !dst) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  if (grid->p != 2) { set_error("the exact separable c-transform needs p = 2"); return QBW_E_GRID; }
+  Plan pl;
+  hipStream_t st = S(stream);
+  CHK(plan_build(ctx, pl, {stage_job(grid, nullptr, nullptr)}, PM_XS | (argmin ? PM_ARGMIN : 0u),
+                 qbw_default_opts(), false, st));
+  pl.hj[0].fhat = const_cast<float*>(src);
+  pl.hj[0].g = dst;
+  pl.hj[0].arg_g = argmin;
+  HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
+  CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
+  CHK(enqueue_xs(pl, 0, st));
+  if (n_fallback) HIPCHK(hipMemcpyAsync(n_fallback, xs_count(pl, 0), sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   return QBW_OK;
 }
@@ -1711,7 +1782,8 @@ qbw_status qbw_batch_create(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs, co
   for (int j = 0; j < njobs; ++j) in[j].coarse = &B->coarse[j];
   const unsigned mode = PM_FORWARD | ((batch_flags & QBW_BATCH_BACKWARD) ? PM_BACKWARD : 0u) |
                         ((o.flags & QBW_WANT_ARGMIN) ? PM_ARGMIN : 0u) |
-                        ((o.flags & QBW_SEPARABLE) ? PM_SEP : 0u);
+                        ((o.flags & QBW_SEPARABLE) ? PM_SEP : 0u) |
+                        ((o.flags & QBW_SEPARABLE_EXACT) ? PM_XS : 0u);
   load_tune_cache(ctx);
   if (batch_flags & QBW_BATCH_AUTOTUNE) {
     // batch-level tuning: targets per lane and the total number of waves the

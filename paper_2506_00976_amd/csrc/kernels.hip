@@ -644,7 +644,7 @@ __global__ __launch_bounds__(256) void k_merge(const DevJob* __restrict__ jobs, 
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
-    if (J.sep) continue;
+    if (J.sep || J.xs) continue;
     const int j = (it - off[jb]) * kChunk + blockIdx.y * 256 + threadIdx.x;
     if (j >= J.P) continue;
     float* dst = phase == 0 ? J.g : J.f;
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(256) void k_argmin(const DevJob* __restrict__ jobs,
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
-    if (J.sep) continue;
+    if (J.sep || J.xs) continue;
     const int base = (it - off[jb]) * kChunk;
     const float* src = phase == 0 ? J.fhat : J.g;
     const float* dst = phase == 0 ? J.g : J.f;
@@ -700,6 +700,230 @@ __global__ __launch_bounds__(256) void k_argmin(const DevJob* __restrict__ jobs,
         if (c - src[i] == target) found = i;
       }
       arg[j] = found;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ exact separable c-transform (p = 2)
+//
+// The all-pairs reading is psi(y) = min_x RN32(c(x, y) - phi(x)) with c an
+// exact integer, and the arg-min is the lowest x attaining psi.  Rounding is
+// monotone, so psi(y) = RN32(V(y)) with V(y) = min_x (c(x, y) - phi(x)) taken
+// exactly, and for p = 2 that exact minimum separates over the axes:
+//   V(y) = min_{x_0} ((x_0 - y_0)^2 + min_{x_1} ((x_1 - y_1)^2 + ...
+//          min_{x_{d-1}} ((x_{d-1} - y_{d-1})^2 - phi(x)))).
+// Stage k (k = 0 .. d-1) takes axis a = d-1-k from source to target
+// coordinates along every line of the other axes, in float64: per target it
+// keeps the smallest candidate value (lowest source coordinate on equal
+// values), that candidate's flat source index over the axes done so far, and
+// the smallest value over all other sources (the runner-up), which is the
+// smaller of the other candidates' values and the winner's own runner-up.
+// Every float64 operation rounds, so a value is known to within
+// delta(w) = d 2^-51 (|w| + 2 d (N-1)^2 + 1).  The last stage certifies each
+// target: psi = RN32(w1) holds if w1 - delta and w1 + delta round to the same
+// float32, and the arg-min holds if the runner-up minus its delta rounds
+// above psi (no other source can round to psi).  Targets that fail either
+// test (near ties, exact ties, non-finite potentials) are queued and
+// evaluated by brute force exactly as the all-pairs kernel does.
+constexpr int kXsT = 8;        // targets per lane along the processed axis
+constexpr int kXsOff = 2904;   // squares table: xs_sq[i] = (i - kXsOff)^2, 0 <= i <= 2 kXsOff (any valid N)
+
+__global__ __launch_bounds__(256) void k_xs_squares(double* __restrict__ t) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i <= 2 * kXsOff; i += gridDim.x * 256) {
+    const double v = (double)(i - kXsOff);
+    t[i] = v * v;
+  }
+}
+
+typedef const __attribute__((address_space(4))) double* const_dptr;
+
+template <bool FIRST>
+__global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
+                                                 const int* __restrict__ off, int total, int phase, int k,
+                                                 const double* __restrict__ sqt, int2* __restrict__ list,
+                                                 int* __restrict__ count) {
+  const int lane = threadIdx.x;
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    if (!J.xs || k >= J.d) continue;
+    const int N = J.N, P = J.P;
+    const int lines = P / N;
+    const int nchunk = (lines + 63) >> 6;
+    const int local = it - off[jb];
+    const int group = local / nchunk, chunk = local - group * nchunk;
+    const int t0 = group * kXsT;
+    int st = 1;
+    for (int q = 0; q < k; ++q) st *= N;   // stride of axis d-1-k
+    const int e = chunk * 64 + lane;
+    const bool valid = e < lines;
+    const int ee = valid ? e : 0;
+    const int outer = ee / st, inner = ee - outer * st;
+    const int base = outer * N * st + inner;
+    const float* src = phase == 0 ? J.fhat : J.g;
+    const double* v1in = J.xs_v + (size_t)((k + 1) & 1) * 2 * P;   // stage k reads buffer (k+1)&1
+    const double* v2in = v1in + P;
+    const int* ixin = J.xs_i + (size_t)((k + 1) & 1) * P;
+    double m1[kXsT], m2[kXsT];
+    int ix[kXsT];
+#pragma unroll
+    for (int t = 0; t < kXsT; ++t) { m1[t] = INFINITY; m2[t] = INFINITY; ix[t] = -1; }
+    const_dptr sq = (const_dptr)sqt;
+    int pos = base;
+    // unrolled so that loads run ahead and the loop-carried minima are
+    // re-canonicalised (a max with itself, for min/max in IEEE mode) less often
+#pragma unroll 4
+    for (int r = 0; r < N; ++r, pos += st) {
+      const double h = FIRST ? -(double)src[pos] : v1in[pos];
+      // costs (r - t0 - t)^2, the same for every lane: one run of scalar loads
+      const_dptr sr = sq + (r - t0 + kXsOff - (kXsT - 1));
+#pragma unroll
+      for (int t = 0; t < kXsT; ++t) {
+        const double w = h + sr[kXsT - 1 - t];
+        m2[t] = fmin(m2[t], fmax(m1[t], w));
+        ix[t] = w < m1[t] ? r : ix[t];
+        m1[t] = fmin(m1[t], w);
+      }
+    }
+    if (!valid) continue;
+    const bool last = k == J.d - 1;
+    float* dst = phase == 0 ? J.g : J.f;
+    int* arg = phase == 0 ? J.arg_g : J.arg_f;
+    double* v1out = J.xs_v + (size_t)(k & 1) * 2 * P;
+    double* v2out = v1out + P;
+    int* ixout = J.xs_i + (size_t)(k & 1) * P;
+    const double dk = (double)J.d * 4.440892098500626e-16;    // d 2^-51
+    const double c0 = 2.0 * J.d * (double)(N - 1) * (N - 1) + 1.0;
+#pragma unroll
+    for (int t = 0; t < kXsT; ++t) {
+      const int tt = t0 + t;
+      if (tt >= N) break;
+      const int o = base + tt * st;
+      const int rs = ix[t];
+      double s1 = INFINITY;
+      int idx = -1;
+      if (rs >= 0) {
+        const double c = (double)(rs - tt) * (double)(rs - tt);
+        s1 = FIRST ? INFINITY : c + v2in[base + rs * st];
+        idx = rs * st + (FIRST ? 0 : ixin[base + rs * st]);
+      }
+      const double w2 = fmin(m2[t], s1);
+      if (!last) {
+        v1out[o] = m1[t];
+        v2out[o] = w2;
+        ixout[o] = idx;
+        continue;
+      }
+      const double w1 = m1[t];
+      const double del1 = dk * (fabs(w1) + c0);
+      const float lo = (float)(w1 - del1), hi = (float)(w1 + del1);
+      bool ok = lo == hi && idx >= 0;   // false for NaN and infinite values
+      if (ok && arg && w2 != INFINITY) {
+        const double del2 = dk * (fabs(w2) + c0);
+        ok = (float)(w2 - del2) > lo;
+      }
+      if (ok) {
+        dst[o] = lo;
+        if (arg) arg[o] = idx;
+      } else {
+        const int slot = atomicAdd(count, 1);
+        list[slot] = make_int2(jb, o);
+      }
+    }
+  }
+}
+
+// The queued targets, one wave each, with the all-pairs arithmetic:
+// RN32((float)c - phi), smallest value over non-NaN candidates (+inf if there
+// is none), lowest source index attaining it (-1 if none).  Only sources
+// whose value can round to that minimum matter, and the stage buffers bound
+// them from below: a row (2D: one value of the first coordinate; 3D: one
+// (x_0, x_1)) holds no candidate below its stage minimum plus the cost of the
+// remaining axes, less the error bound.  The float64 best w1 gives
+// psi <= hi = RN32(w1 + delta), so every source that can round to psi lies
+// below T = hi + 2^-22 |hi| (beyond the upper end of hi's rounding interval);
+// rows whose bound exceeds T are skipped, the others scanned in index order.
+// NaN or infinite bounds never skip anything.
+__device__ __forceinline__ void xs_take(float v, int i, float& best, int& bi) {
+  if (v < best || (v == best && bi == 0x7fffffff)) { best = v; bi = i; }
+}
+
+__global__ __launch_bounds__(64) void k_xs_fallback(const DevJob* __restrict__ jobs, const int2* __restrict__ list,
+                                                    const int* __restrict__ count, int phase) {
+  const int n = *count;
+  const int lane = threadIdx.x;
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int2 ent = list[q];
+    const DevJob& J = jobs[ent.x];
+    const int y = ent.y, N = J.N, P = J.P, d = J.d;
+    const float* src = phase == 0 ? J.fhat : J.g;
+    int y0, y1, y2;
+    pix_coords(y, N, d, y0, y1, y2);
+    const double* b0 = J.xs_v;           // stage 0: min over x_{d-1} per (x_0.., y_{d-1})
+    const double* b1 = J.xs_v + 2 * P;   // stage 1 (3D): min over (x_1, x_2) per (x_0, y_1, y_2)
+    const double dk = (double)d * 4.440892098500626e-16;
+    const double c0 = 2.0 * d * (double)(N - 1) * (N - 1) + 1.0;
+    // outer index o: 2D the row x_1 (coordinate y1 of the target), 3D the plane x_0
+    const int oy = d == 2 ? y1 : y0;
+    auto outer_bound = [&](int o) -> double {
+      const double c = (double)(o - oy) * (double)(o - oy);
+      return d == 2 ? b0[(size_t)o * N + y2] + c : b1[(size_t)o * N * N + (size_t)y1 * N + y2] + c;
+    };
+    double w1 = INFINITY;
+    for (int o = lane; o < N; o += 64) w1 = fmin(w1, outer_bound(o));
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) w1 = fmin(w1, __shfl_xor(w1, s, 64));
+    const float hi = (float)(w1 + dk * (fabs(w1) + c0));
+    const double T = (double)hi + 2.384185791015625e-07 * fabs((double)hi);   // + 2^-22 |hi|
+    auto skip = [&](double bnd) { return bnd - dk * (fabs(bnd) + c0) > T; };
+    float best = INFINITY;
+    int bi = 0x7fffffff;
+    auto scan_row = [&](int rowbase, int cost_rest, int ya) {
+      // sources rowbase + x, x = 0 .. N-1 along the last axis
+      for (int x = lane; x < N; x += 64) {
+        const int e = x - ya;
+        xs_take((float)(cost_rest + e * e) - src[rowbase + x], rowbase + x, best, bi);
+      }
+    };
+    for (int oc = 0; oc < N; oc += 64) {
+      const int o = oc + lane;
+      unsigned long long m = __ballot(o < N && !skip(outer_bound(o)));
+      while (m) {
+        const int ob = oc + __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const int co = (ob - oy) * (ob - oy);
+        if (d == 2) {
+          scan_row(ob * N, co, y2);
+        } else {
+          // rows (ob, x_1) of the plane, bounded by stage 0
+          for (int rc = 0; rc < N; rc += 64) {
+            const int r1 = rc + lane;
+            bool ok = false;
+            if (r1 < N) {
+              const double bnd = b0[(size_t)ob * N * N + (size_t)r1 * N + y2] +
+                                 (double)(co + (r1 - y1) * (r1 - y1));
+              ok = !skip(bnd);
+            }
+            unsigned long long mr = __ballot(ok);
+            while (mr) {
+              const int rb = rc + __ffsll((long long)mr) - 1;
+              mr &= mr - 1;
+              scan_row(ob * N * N + rb * N, co + (rb - y1) * (rb - y1), y2);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const float ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob < best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) {
+      (phase == 0 ? J.g : J.f)[y] = best;
+      int* arg = phase == 0 ? J.arg_g : J.arg_f;
+      if (arg) arg[y] = bi == 0x7fffffff ? -1 : bi;
     }
   }
 }
@@ -2536,6 +2760,29 @@ int launch_ct1d_fast(const DevJob* jobs, int njobs, const int* off, int total, i
   if (R == 16) hipLaunchKernelGGL(k_ct1d_fast<16>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, pass);
   else if (R == 8) hipLaunchKernelGGL(k_ct1d_fast<8>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, pass);
   else hipLaunchKernelGGL(k_ct1d_fast<4>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, pass);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_xs_squares(double* t, void* stream) {
+  hipLaunchKernelGGL(k_xs_squares, dim3((2 * kXsOff + 256) / 256), dim3(256), 0, (hipStream_t)stream, t);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+int launch_xs(const DevJob* jobs, int njobs, const int* off, int total, const int* off3, int total3, int phase,
+              const double* sqt, int* list, int* count, int fallback_grid, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  int2* l2 = reinterpret_cast<int2*>(list);
+  if (total) {
+    hipLaunchKernelGGL(k_xs_stage<true>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, 0,
+                       sqt, l2, count);
+    hipLaunchKernelGGL(k_xs_stage<false>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, 1,
+                       sqt, l2, count);
+  }
+  if (total3)
+    hipLaunchKernelGGL(k_xs_stage<false>, dim3(grid_for(total3)), dim3(64), 0, st, jobs, njobs, off3, total3, phase,
+                       2, sqt, l2, count);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_xs_fallback, dim3(fallback_grid), dim3(64), 0, st, jobs, l2, count, phase);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -114,6 +114,9 @@ struct DevJob {
   int p1_nt;                // p = 1 plan cost / gradient: 0 direct kernels, 64 or 256 distance-table kernels
   float* sep_tmp;           // 2 x P
   const float* sqrt_tab;    // p = 1 c-transform table fill: RN32(sqrt(n)) for n < kSqrtTab, or null
+  int xs;                   // p = 2 c-transforms by exact separable minima (certified, brute force where not)
+  double* xs_v;             // 2 x (2 P): per stage buffer, best value then runner-up value
+  int* xs_i;                // 2 x P: per stage buffer, flat source index of the best value
   int* sep_arg;             // d x P or null
 };
 
@@ -188,6 +191,15 @@ int ctransform_waves_per_cu();
 // from it instead of taking square roots.
 constexpr int kSqrtTab = 65536;
 int launch_sqrt_table(float* t, int n, void* stream);
+// Exact separable c-transform (p = 2): squares table of kXsSquares doubles
+// ((i - 2904)^2), the d axis stages of every such job of a plan, then the
+// brute-force pass over the targets the last stage could not certify.  `list`
+// holds 2 ints per queued target (capacity: the jobs' total pixel count) and
+// `count` their number (zero on entry).
+constexpr int kXsSquares = 2 * 2904 + 1;
+int launch_xs_squares(double* t, void* stream);
+int launch_xs(const DevJob* jobs, int njobs, const int* off, int total, const int* off3, int total3, int phase,
+              const double* sqt, int* list, int* count, int fallback_grid, void* stream);
 int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter, int phase, int grid,
                       void* stream);
 int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
