@@ -364,14 +364,17 @@ qbw_status qbw_batch_tiling(const qbw_batch* batch, int32_t job, int32_t* target
 void qbw_batch_destroy(qbw_batch* batch);
 
 /* Kernel timing for measurement: while enabled, eager (non-graph) runs record
- * a pair of hipEvents on the run's stream around every c-transform launch.
+ * a pair of hipEvents on the run's stream around every c-transform launch
+ * (the all-pairs kernel, and each stage of the exact separable one).
  * qbw_batch_ctransform_time synchronises on them and returns the mean launch
  * duration (ms) and the number of launches recorded since the last call,
  * then forgets them.  Graph runs record nothing.  Outputs host. */
 qbw_status qbw_batch_set_timing(qbw_batch* batch, int32_t enable);
 qbw_status qbw_batch_ctransform_time(qbw_batch* batch, double* mean_ms, int32_t* launches);
-/* Pair evaluations (sources x targets) one c-transform launch of the batch
- * performs: sum over jobs of (N^d)^2. */
+/* Candidate evaluations (source, target) per timed c-transform launch, over
+ * one phase's launches: an all-pairs launch evaluates (N^d)^2 per job, an
+ * exact separable stage N^d x N per job (d stages per job).  Divided by the
+ * mean launch time it gives evaluations per second. */
 qbw_status qbw_batch_ctransform_pairs(const qbw_batch* batch, double* pairs);
 
 /* Convenience: create, run the forward pass once, fetch results, destroy. */

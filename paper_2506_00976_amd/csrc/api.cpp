@@ -749,10 +749,36 @@ static int enqueue_sep(Plan& pl, int phase, hipStream_t st) {
 // the other counters at the start of a forward pass.
 static int* xs_count(Plan& pl, int phase) { return pl.ints + 2 * kQueues + pl.njobs + phase; }
 
+// Events around a launch when the batch's c-transform timing is on.
+template <typename F>
+static int timed_launch(Plan& pl, hipStream_t st, F launch) {
+  std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+  if (pl.timing) {
+    if (pl.ev_used == pl.ev_pool.size()) {
+      hipEvent_t a, b;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      pl.ev_pool.push_back({a, b});
+    }
+    ev = &pl.ev_pool[pl.ev_used++];
+    HIPCHK(hipEventRecord(ev->first, st));
+  }
+  CHK(launch());
+  if (ev) HIPCHK(hipEventRecord(ev->second, st));
+  return QBW_OK;
+}
+
 static int enqueue_xs(Plan& pl, int phase, hipStream_t st) {
-  const int fb_grid = std::max(1, std::min(pl.xs_pixels, 4096));
-  return launch_xs(pl.djobs, pl.njobs, pl.off_xs, pl.tot_xs, pl.off_xs3, pl.tot_xs3, phase, pl.xs_sq, pl.xs_list,
-                   xs_count(pl, phase), fb_grid, st);
+  int* cnt = xs_count(pl, phase);
+  for (int k = 0; k < 3; ++k) {
+    const int* off = k < 2 ? pl.off_xs : pl.off_xs3;
+    const int total = k < 2 ? pl.tot_xs : pl.tot_xs3;
+    if (!total) continue;
+    CHK(timed_launch(pl, st, [&] {
+      return launch_xs_stage(pl.djobs, pl.njobs, off, total, phase, k, pl.xs_sq, pl.xs_list, cnt, st);
+    }));
+  }
+  return launch_xs_fallback(pl.djobs, pl.xs_list, cnt, phase, std::max(1, std::min(pl.xs_pixels, 4096)), st);
 }
 
 static int enqueue_ctransforms(Plan& pl, hipStream_t st) {
@@ -761,19 +787,9 @@ static int enqueue_ctransforms(Plan& pl, hipStream_t st) {
     if (pl.tot_sep) CHK(enqueue_sep(pl, phase, st));
     if (pl.tot_xs) CHK(enqueue_xs(pl, phase, st));
     if (!pl.n_items) continue;
-    std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
-    if (pl.timing) {
-      if (pl.ev_used == pl.ev_pool.size()) {
-        hipEvent_t a, b;
-        HIPCHK(hipEventCreate(&a));
-        HIPCHK(hipEventCreate(&b));
-        pl.ev_pool.push_back({a, b});
-      }
-      ev = &pl.ev_pool[pl.ev_used++];
-      HIPCHK(hipEventRecord(ev->first, st));
-    }
-    CHK(launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints + phase * kQueues, phase, pl.ct_grid, st));
-    if (ev) HIPCHK(hipEventRecord(ev->second, st));
+    CHK(timed_launch(pl, st, [&] {
+      return launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints + phase * kQueues, phase, pl.ct_grid, st);
+    }));
     CHK(launch_merge(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
     if (pl.mode & PM_ARGMIN) CHK(launch_argmin(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, phase, st));
   }
@@ -1886,9 +1902,21 @@ qbw_status qbw_batch_ctransform_time(qbw_batch* B, double* mean_ms, int32_t* lau
 
 qbw_status qbw_batch_ctransform_pairs(const qbw_batch* B, double* pairs) {
   if (!B || !pairs) { set_error("NULL argument"); return QBW_E_INVAL; }
-  double s = 0;
-  for (const auto& D : B->plan.hj) s += (double)D.P * (double)D.P;
-  *pairs = s;
+  // per phase: one all-pairs launch over the other jobs (P^2 each), and d
+  // exact separable stages (P N candidates per job and stage)
+  double evals = 0, launches = 0, ap = 0, s01 = 0, s2 = 0;
+  for (const auto& D : B->plan.hj) {
+    if (D.xs) {
+      s01 += (double)D.P * D.N;
+      if (D.d == 3) s2 += (double)D.P * D.N;
+    } else {
+      ap += (double)D.P * (double)D.P;
+    }
+  }
+  if (ap > 0) { evals += ap; launches += 1; }
+  if (s01 > 0) { evals += 2 * s01; launches += 2; }
+  if (s2 > 0) { evals += s2; launches += 1; }
+  *pairs = launches > 0 ? evals / launches : 0.0;
   return QBW_OK;
 }
 

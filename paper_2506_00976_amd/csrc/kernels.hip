@@ -769,13 +769,9 @@ __global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs
 #pragma unroll
     for (int t = 0; t < kXsT; ++t) { m1[t] = INFINITY; m2[t] = INFINITY; ix[t] = -1; }
     const_dptr sq = (const_dptr)sqt;
-    int pos = base;
-    // unrolled so that loads run ahead and the loop-carried minima are
-    // re-canonicalised (a max with itself, for min/max in IEEE mode) less often
-#pragma unroll 4
-    for (int r = 0; r < N; ++r, pos += st) {
-      const double h = FIRST ? -(double)src[pos] : v1in[pos];
-      // costs (r - t0 - t)^2, the same for every lane: one run of scalar loads
+    // one source step: candidates h + (r - t0 - t)^2 for the lane's targets,
+    // the costs the same for every lane (one run of scalar loads)
+    auto step = [&](double h, int r) {
       const_dptr sr = sq + (r - t0 + kXsOff - (kXsT - 1));
 #pragma unroll
       for (int t = 0; t < kXsT; ++t) {
@@ -784,6 +780,31 @@ __global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs
         ix[t] = w < m1[t] ? r : ix[t];
         m1[t] = fmin(m1[t], w);
       }
+    };
+    if (FIRST) {
+      // the lines are rows (stride 1): tiles of 64 rows x 32 columns are read
+      // coalesced into LDS, then each lane walks its own row there (stride 33
+      // words, no bank conflicts), instead of 64 rows' cache lines per load
+      __shared__ float tile[64 * 33];
+      const int row0 = chunk * 64;
+      for (int rb = 0; rb < N; rb += 32) {
+        const int nc = min(32, N - rb);
+        __syncthreads();
+#pragma unroll 4
+        for (int i = 0; i < 64; i += 2) {
+          const int row = row0 + i + (lane >> 5), col = rb + (lane & 31);
+          tile[(i + (lane >> 5)) * 33 + (lane & 31)] = (row < lines && col < N) ? src[row * N + col] : 0.0f;
+        }
+        __syncthreads();
+        // unrolled so that the loop-carried minima are re-canonicalised (a
+        // max with itself, for min/max in IEEE mode) once per four steps
+#pragma unroll 4
+        for (int j = 0; j < nc; ++j) step(-(double)tile[lane * 33 + j], rb + j);
+      }
+    } else {
+      int pos = base;
+#pragma unroll 4
+      for (int r = 0; r < N; ++r, pos += st) step(v1in[pos], r);
     }
     if (!valid) continue;
     const bool last = k == J.d - 1;
@@ -2768,21 +2789,22 @@ int launch_xs_squares(double* t, void* stream) {
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_xs(const DevJob* jobs, int njobs, const int* off, int total, const int* off3, int total3, int phase,
-              const double* sqt, int* list, int* count, int fallback_grid, void* stream) {
+int launch_xs_stage(const DevJob* jobs, int njobs, const int* off, int total, int phase, int k, const double* sqt,
+                    int* list, int* count, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   int2* l2 = reinterpret_cast<int2*>(list);
-  if (total) {
+  if (k == 0)
     hipLaunchKernelGGL(k_xs_stage<true>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, 0,
                        sqt, l2, count);
-    hipLaunchKernelGGL(k_xs_stage<false>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, 1,
+  else
+    hipLaunchKernelGGL(k_xs_stage<false>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, k,
                        sqt, l2, count);
-  }
-  if (total3)
-    hipLaunchKernelGGL(k_xs_stage<false>, dim3(grid_for(total3)), dim3(64), 0, st, jobs, njobs, off3, total3, phase,
-                       2, sqt, l2, count);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_xs_fallback, dim3(fallback_grid), dim3(64), 0, st, jobs, l2, count, phase);
+  return QBW_OK;
+}
+int launch_xs_fallback(const DevJob* jobs, const int* list, const int* count, int phase, int grid, void* stream) {
+  hipLaunchKernelGGL(k_xs_fallback, dim3(grid), dim3(64), 0, (hipStream_t)stream, jobs,
+                     reinterpret_cast<const int2*>(list), count, phase);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

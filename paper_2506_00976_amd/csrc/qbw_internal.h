@@ -192,14 +192,15 @@ int ctransform_waves_per_cu();
 constexpr int kSqrtTab = 65536;
 int launch_sqrt_table(float* t, int n, void* stream);
 // Exact separable c-transform (p = 2): squares table of kXsSquares doubles
-// ((i - 2904)^2), the d axis stages of every such job of a plan, then the
-// brute-force pass over the targets the last stage could not certify.  `list`
-// holds 2 ints per queued target (capacity: the jobs' total pixel count) and
-// `count` their number (zero on entry).
+// ((i - 2904)^2); stage k (0 .. d-1) over the items of table `off` (jobs with
+// d > k), then the re-evaluation of the targets the last stage could not
+// certify.  `list` holds 2 ints per queued target (capacity: the jobs' total
+// pixel count) and `count` their number (zero before stage 0).
 constexpr int kXsSquares = 2 * 2904 + 1;
 int launch_xs_squares(double* t, void* stream);
-int launch_xs(const DevJob* jobs, int njobs, const int* off, int total, const int* off3, int total3, int phase,
-              const double* sqt, int* list, int* count, int fallback_grid, void* stream);
+int launch_xs_stage(const DevJob* jobs, int njobs, const int* off, int total, int phase, int k, const double* sqt,
+                    int* list, int* count, void* stream);
+int launch_xs_fallback(const DevJob* jobs, const int* list, const int* count, int phase, int grid, void* stream);
 int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter, int phase, int grid,
                       void* stream);
 int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
