@@ -5,7 +5,9 @@ bound), batched forward + backward, on one MI355X.
 One step = one pass of the whole fine-grid path over a batch of B pairs:
 pooling, potential upscaling, both c-transforms, lower-bound sums and shift,
 IPF, plan cost, TV terms, finalisation, and the backward kernels of both
-bounds, replayed as one hipGraph.  The coarse Kantorovich problems are solved
+bounds, replayed as one hipGraph.  The c-transforms run as exact separable
+minima (the same float32 values and arg-mins as the all-pairs kernel, which
+is timed beside them on the same batch; --all-pairs swaps the two).  The coarse Kantorovich problems are solved
 once before the timed region by the host network simplex (all host cores);
 their cost is reported separately as the end-to-end rate.
 
@@ -32,6 +34,13 @@ sys.path.insert(0, ROOT)
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
 INSTR_PER_PAIR = 1.5               # minimum per (source, target) pair: one v_sub_f32 + half a v_min3_f32
 PEAK_PAIRS = PEAK_LANE_OPS / INSTR_PER_PAIR
+# FP64 vector peak: 78.6 TFLOP/s counts an FMA as two, i.e. 256 CUs x 64 lanes/clk x 2.4 GHz
+# = 39.3 T float64 lane-operations/s.  An exact separable stage needs at least six per
+# (source, target) candidate: v_add_f64, v_cmp_lt_f64 + v_cndmask_b32 (the index), v_min_f64
+# (the best) and v_max_f64 + v_min_f64 (the runner-up).
+PEAK_F64_LANE_OPS = 256 * 64 * 2.4e9
+XS_INSTR_PER_CAND = 6
+PEAK_XS = PEAK_F64_LANE_OPS / XS_INSTR_PER_CAND
 
 
 def log(*a):
@@ -67,15 +76,43 @@ def kernel_source_hash() -> str:
     return hashlib.sha256("\n".join(norm(x) for x in parts).encode()).hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per c-transform launch from the committed counter summary,
-    only if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "ctransform_traffic_256_k8.json")
+def xs_source_hash() -> str:
+    """The same for the exact separable c-transform: the device helpers, its
+    section of kernels.hip and its launchers, the shared header, the host
+    planner and the build flags."""
+    import re
+    csrc = os.path.join(ROOT, "paper_2506_00976_amd", "csrc")
+
+    def norm(text):
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        return " ".join(text.split())
+
+    with open(os.path.join(csrc, "kernels.hip")) as fh:
+        src = fh.read()
+    mark = "// ------------------------------------------------------------------ "
+    helpers = src[:src.index(mark + "pooling")]
+    xs = src[src.index(mark + "exact separable c-transform"):src.index(mark + "separable c-transform (p = 2)")]
+    launch = src[src.index("int launch_xs_squares("):src.index("int launch_sep_argmin(")]
+    parts = [helpers, xs, launch]
+    for name in ("qbw_internal.h", "api.cpp"):
+        with open(os.path.join(csrc, name)) as fh:
+            parts.append(fh.read())
+    with open(os.path.join(ROOT, "paper_2506_00976_amd", "build.py")) as fh:
+        parts.append(fh.read())
+    return hashlib.sha256("\n".join(norm(x) for x in parts).encode()).hexdigest()[:16]
+
+
+def read_traffic(kernel: str = "xs_stage"):
+    """HBM bytes per launch of the kernel ("xs_stage" or "ctransform") from
+    the committed counter summary, only if it was taken on the current source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_256_k8.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+    want = xs_source_hash() if kernel == "xs_stage" else kernel_source_hash()
+    if d.get("kernel_source_sha256_16") != want:
         return None
     return d.get("bytes_per_launch")
 
@@ -182,6 +219,8 @@ def main():
                     help="only the timed steps (for rocprofv3 runs)")
     ap.add_argument("--eager", action="store_true",
                     help="launch the kernels one by one instead of replaying a hipGraph")
+    ap.add_argument("--all-pairs", action="store_true",
+                    help="time the all-pairs c-transform path instead of the exact separable one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of 1 GiB (calibrates FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
@@ -226,7 +265,10 @@ def main():
 
     grads = [(torch.zeros_like(a), torch.zeros_like(b)) for a, b in zip(A, Bm)]
     jobs = [(a, b, k, p, ga, gb) for (a, b), (ga, gb) in zip(zip(A, Bm), grads)]
-    batch = qbw.Batch(jobs, coarse=recs, backward=True, graph=not args.eager)
+    # p = 2 c-transforms: exact separable (the all-pairs float32 values and
+    # arg-mins from per-axis float64 minima), or the all-pairs kernel itself
+    mode = False if args.all_pairs else "exact"
+    batch = qbw.Batch(jobs, coarse=recs, backward=True, graph=not args.eager, separable=mode)
     for _ in range(args.warmup):
         batch.run()
     torch.cuda.synchronize()
@@ -245,33 +287,66 @@ def main():
     log(f"[bench] {ms_step:.3f} ms/step -> {value:.1f} pairs/s")
 
     # ---- the dominant kernel, timed live with HIP events on its stream
-    eager = qbw.Batch(jobs, coarse=recs, backward=True, graph=False)
-    eager.run()
-    torch.cuda.synchronize()
-    eager.set_timing(True)
-    reps = max(3, args.steps // 2)
-    for _ in range(reps):
+    def kernel_timing(sep_mode):
+        eager = qbw.Batch(jobs, coarse=recs, backward=True, graph=False, separable=sep_mode)
         eager.run()
-    mean_ms, launches = eager.ctransform_time()
-    eager.set_timing(False)
-    pairs_per_launch = eager.ctransform_pairs()
-    achieved = pairs_per_launch / (mean_ms / 1e3)
-    log(f"[bench] c-transform: {launches} launches, mean {mean_ms:.3f} ms, "
-        f"{achieved / 1e12:.2f} Tpair/s ({achieved / PEAK_PAIRS:.1%} of {PEAK_PAIRS / 1e12:.1f})")
+        torch.cuda.synchronize()
+        eager.set_timing(True)
+        for _ in range(max(3, args.steps // 2)):
+            eager.run()
+        mean, n = eager.ctransform_time()
+        eager.set_timing(False)
+        return mean, n, eager.ctransform_pairs()
+
+    def roofline(sep_mode, mean, evals):
+        ach = evals / (mean / 1e3)
+        if sep_mode == "exact":
+            return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_XS / 1e12, "unit": "Tcand/s",
+                    "frac": ach / PEAK_XS, "traffic": read_traffic("xs_stage"), "kernel": "k_xs_stage",
+                    "mean_launch_ms": mean, "candidates_per_launch": evals}
+        return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_PAIRS / 1e12, "unit": "Tpair/s",
+                "frac": ach / PEAK_PAIRS, "traffic": read_traffic("ctransform"), "kernel": "k_ctransform",
+                "mean_launch_ms": mean, "pairs_per_launch": evals}
+
+    mean_ms, launches, evals = kernel_timing(mode)
+    roof = roofline(mode, mean_ms, evals)
+    log(f"[bench] {roof['kernel']}: {launches} launches, mean {mean_ms:.3f} ms, "
+        f"{roof['achieved']:.2f} {roof['unit']} ({roof['frac']:.1%} of {roof['peak']:.2f})")
+
+    # ---- the other c-transform path on the same batch
+    other = "exact" if mode is False else False
+    ob = qbw.Batch(jobs, coarse=recs, backward=True, graph=True, separable=other)
+    for _ in range(args.warmup):
+        ob.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nrep_o = args.steps if other == "exact" else max(3, args.steps // 4)
+    for _ in range(nrep_o):
+        ob.run()
+    torch.cuda.synchronize()
+    ms_other = (time.perf_counter() - t0) * 1e3 / nrep_o
+    rother = ob.results()
+    del ob
+    same = all(x[key] == y[key] for x, y in zip(rother, res) for key in ("lower", "upper", "lower_S", "feas_shift"))
+    m_o, n_o, e_o = kernel_timing(other)
+    roof_other = roofline(other, m_o, e_o)
+    log(f"[bench] {'exact separable' if other else 'all-pairs'}: {ms_other:.3f} ms/step -> "
+        f"{B / (ms_other / 1e3):.1f} pairs/s; {roof_other['kernel']} {roof_other['achieved']:.2f} "
+        f"{roof_other['unit']} ({roof_other['frac']:.1%}); bounds identical: {same}")
 
     # ---- plain single-pair path (one pair per call, no graph, same accuracy)
     nplain = min(8, B)
     for i in range(2):
-        qbw.bounds(A[i], Bm[i], k, p, coarse=recs[i])
+        qbw.bounds(A[i], Bm[i], k, p, coarse=recs[i], separable=mode)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(nplain):
-        qbw.bounds(A[i], Bm[i], k, p, coarse=recs[i])
+        qbw.bounds(A[i], Bm[i], k, p, coarse=recs[i], separable=mode)
     torch.cuda.synchronize()
     plain_fwd = nplain / (time.perf_counter() - t0)
     t0 = time.perf_counter()
     for i in range(nplain):
-        qbw.bounds_with_grads(A[i], Bm[i], k, p, coarse=recs[i])
+        qbw.bounds_with_grads(A[i], Bm[i], k, p, coarse=recs[i], separable=mode)
     torch.cuda.synchronize()
     plain_fb = nplain / (time.perf_counter() - t0)
     log(f"[bench] plain: fwd {plain_fwd:.1f} pairs/s, fwd+bwd {plain_fb:.1f} pairs/s")
@@ -288,23 +363,6 @@ def main():
     ms_sep = (time.perf_counter() - t0) * 1e3 / args.steps
     rsep = sep.results()
     log(f"[bench] separable: {ms_sep:.3f} ms/step -> {B / (ms_sep / 1e3):.1f} pairs/s")
-
-    # ---- the same batch with exact separable c-transforms (QBW_SEPARABLE_EXACT):
-    # the all-pairs values and arg-mins from per-axis float64 minima, certified
-    # per target, the rest re-evaluated over the rows that can hold a tie
-    xsb = qbw.Batch(jobs, coarse=recs, backward=True, graph=True, separable="exact")
-    for _ in range(args.warmup):
-        xsb.run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        xsb.run()
-    torch.cuda.synchronize()
-    ms_xs = (time.perf_counter() - t0) * 1e3 / args.steps
-    rxs = xsb.results()
-    xs_same = all(x[key] == y[key] for x, y in zip(rxs, res) for key in ("lower", "upper", "lower_S", "feas_shift"))
-    log(f"[bench] exact separable: {ms_xs:.3f} ms/step -> {B / (ms_xs / 1e3):.1f} pairs/s; "
-        f"bounds identical to the all-pairs batch: {xs_same}")
 
     # ---- uneven batch: 128 jobs over 2D/3D grids, k in {2,4,8}, p in {1,2},
     # one persistent launch per stage in a hipGraph, autotuned tiling
@@ -342,7 +400,7 @@ def main():
             f"c-transform {pairs5 / (m5 / 1e3) / 1e12:.2f} Tpair/s")
         uneven = {"jobs": len(J5), "jobs_per_s": len(J5) / (ms5 / 1e3), "ms_per_step": ms5,
                   "workload": "128 jobs: 32^2, 64^2, 128^2, 16^3, 32^3 grids x k in {2,4,8} x p in {1,2}, "
-                              "GRF measures, forward+backward, hipGraph, autotuned; coarse pre-solved",
+                              "GRF measures, forward+backward, hipGraph, autotuned all-pairs c-transforms; coarse pre-solved",
                   "ctransform_Tpair_per_s": pairs5 / (m5 / 1e3) / 1e12,
                   "ctransform_ms_per_launch": m5, "coarse_seconds": t_c5}
 
@@ -371,7 +429,7 @@ def main():
     for Bs in (8, 128):
         idx = [i % B for i in range(Bs)]
         js = [(A[i], Bm[i], k, p, torch.zeros_like(A[i]), torch.zeros_like(Bm[i])) for i in idx]
-        bs = qbw.Batch(js, coarse=[recs[i] for i in idx], backward=True, graph=True)
+        bs = qbw.Batch(js, coarse=[recs[i] for i in idx], backward=True, graph=True, separable=mode)
         for _ in range(args.warmup):
             bs.run()
         torch.cuda.synchronize()
@@ -386,7 +444,7 @@ def main():
     log("[bench] batch sizes: " + ", ".join(f"{kb} pairs -> {v:.1f} pairs/s" for kb, v in sorted(sweep.items(), key=lambda x: int(x[0]))))
 
     # consistency of the timed results with the single-pair path
-    ref = qbw.bounds(A[0], Bm[0], k, p, coarse=recs[0])
+    ref = qbw.bounds(A[0], Bm[0], k, p, coarse=recs[0], separable=mode)
     assert ref["lower"] == res[0]["lower"] and ref["upper"] == res[0]["upper"], (ref, res[0])
 
     out = {
@@ -405,22 +463,20 @@ def main():
         "config": {"workload": f"batch of {B} pairs of 256x256 measures (GRF and Cauchy families), "
                                "k=8, p=2, forward+backward of both bounds, coarse solutions pre-solved",
                    "N": N, "d": d, "k": k, "p": p, "batch": B,
-                   "precision": "float32 c-transforms, float64 sums/IPF/plan cost"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_PAIRS / 1e12,
-                     "unit": "Tpair/s", "frac": achieved / PEAK_PAIRS, "traffic": read_traffic(),
-                     "kernel": "k_ctransform", "mean_launch_ms": mean_ms,
-                     "pairs_per_launch": pairs_per_launch},
+                   "precision": "float32 c-transforms, float64 sums/IPF/plan cost",
+                   "c_transform": ("exact separable: the all-pairs float32 values and arg-mins from "
+                                   "per-axis float64 minima, certified per target" if mode else
+                                   "all-pairs (lazy) kernel")},
+        "roofline": roof,
+        ("all_pairs" if mode else "exact_separable"): {
+            "pairs_per_s": B / (ms_other / 1e3), "ms_per_step": ms_other,
+            "bounds_identical": same, "roofline": roof_other},
         "plain": {"fwd_pairs_per_s": plain_fwd, "fwd_bwd_pairs_per_s": plain_fb,
                   "batched_over_plain_fwd_bwd": value / plain_fb},
         "separable_p2": {"pairs_per_s": B / (ms_sep / 1e3), "ms_per_step": ms_sep,
                          "note": "same batch, c-transforms as d nested 1-D transforms (O(N^3) here); "
                                  "float32 rounding once per axis, larger derived shift",
                          "lower_sample": rsep[0]["lower"], "upper_sample": rsep[0]["upper"]},
-        "exact_separable_p2": {"pairs_per_s": B / (ms_xs / 1e3), "ms_per_step": ms_xs,
-                               "bounds_identical_to_all_pairs": xs_same,
-                               "note": "same batch, c-transforms from exact per-axis float64 minima "
-                                       "(O(N^3) here), certified against float32 rounding per target, "
-                                       "uncertified targets re-evaluated over the rows that can tie"},
         "end_to_end": {"coarse_seconds": t_coarse, "host_threads": workers,
                        "pairs_per_s_sequential": B / (t_coarse + ms_step / 1e3),
                        "pairs_per_s_pipelined": B / max(t_coarse, ms_step / 1e3)},
