@@ -782,29 +782,53 @@ __global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs
       }
     };
     if (FIRST) {
-      // the lines are rows (stride 1): tiles of 64 rows x 32 columns are read
-      // coalesced into LDS, then each lane walks its own row there (stride 33
-      // words, no bank conflicts), instead of 64 rows' cache lines per load
-      __shared__ float tile[64 * 33];
+      // the lines are rows (stride 1): tiles of 64 rows x 16 columns are read
+      // coalesced (the next tile while the current one is in use) into LDS,
+      // then each lane walks its own row there (stride 17 words, no bank
+      // conflicts), instead of 64 rows' cache lines per load
+      constexpr int TC = 16;
+      __shared__ float tile[64 * (TC + 1)];
       const int row0 = chunk * 64;
-      for (int rb = 0; rb < N; rb += 32) {
-        const int nc = min(32, N - rb);
-        __syncthreads();
-#pragma unroll 4
-        for (int i = 0; i < 64; i += 2) {
-          const int row = row0 + i + (lane >> 5), col = rb + (lane & 31);
-          tile[(i + (lane >> 5)) * 33 + (lane & 31)] = (row < lines && col < N) ? src[row * N + col] : 0.0f;
+      const int sub = lane / TC, cl = lane % TC;   // 4 rows of 16 columns per load
+      float nx[64 / 4];
+      auto fetch = [&](int rb) {
+#pragma unroll
+        for (int i = 0; i < 64 / 4; ++i) {
+          const int row = row0 + 4 * i + sub, col = rb + cl;
+          nx[i] = (row < lines && col < N) ? src[row * N + col] : 0.0f;
         }
+      };
+      fetch(0);
+      for (int rb = 0; rb < N; rb += TC) {
+        const int nc = min(TC, N - rb);
         __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 64 / 4; ++i) tile[(4 * i + sub) * (TC + 1) + cl] = nx[i];
+        __syncthreads();
+        if (rb + TC < N) fetch(rb + TC);
         // unrolled so that the loop-carried minima are re-canonicalised (a
         // max with itself, for min/max in IEEE mode) once per four steps
 #pragma unroll 4
-        for (int j = 0; j < nc; ++j) step(-(double)tile[lane * 33 + j], rb + j);
+        for (int j = 0; j < nc; ++j) step(-(double)tile[lane * (TC + 1) + j], rb + j);
       }
     } else {
-      int pos = base;
-#pragma unroll 4
-      for (int r = 0; r < N; ++r, pos += st) step(v1in[pos], r);
+      // four sources per round, the next four loaded while these are used
+      const int N4 = N & ~3;
+      double hn[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) hn[u] = u < N4 ? v1in[base + u * st] : 0.0;
+      for (int r = 0; r < N4; r += 4) {
+        double hc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) hc[u] = hn[u];
+        if (r + 4 < N4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) hn[u] = v1in[base + (r + 4 + u) * st];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) step(hc[u], r + u);
+      }
+      for (int r = N4; r < N; ++r) step(v1in[base + r * st], r);
     }
     if (!valid) continue;
     const bool last = k == J.d - 1;
