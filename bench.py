@@ -398,11 +398,30 @@ def main():
         pairs5 = ev5.ctransform_pairs()
         log(f"[bench] uneven batch: {ms5:.3f} ms/step -> {len(J5) / (ms5 / 1e3):.1f} jobs/s; "
             f"c-transform {pairs5 / (m5 / 1e3) / 1e12:.2f} Tpair/s")
+        r5 = b5.results()
+        del b5, ev5
+        # the same jobs with the p = 2 c-transforms on the exact separable path
+        # (p = 1 jobs keep the autotuned all-pairs kernel)
+        x5 = qbw.Batch(J5, coarse=recs5, backward=True, graph=True, autotune=True, separable="exact")
+        for _ in range(args.warmup):
+            x5.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x5.run()
+        torch.cuda.synchronize()
+        ms5x = (time.perf_counter() - t0) * 1e3 / args.steps
+        same5 = all(x[key] == y[key] for x, y in zip(x5.results(), r5) for key in ("lower", "upper", "lower_S"))
+        del x5
+        log(f"[bench] uneven batch, exact separable p = 2: {ms5x:.3f} ms/step -> {len(J5) / (ms5x / 1e3):.1f} jobs/s; "
+            f"bounds identical: {same5}")
         uneven = {"jobs": len(J5), "jobs_per_s": len(J5) / (ms5 / 1e3), "ms_per_step": ms5,
                   "workload": "128 jobs: 32^2, 64^2, 128^2, 16^3, 32^3 grids x k in {2,4,8} x p in {1,2}, "
                               "GRF measures, forward+backward, hipGraph, autotuned all-pairs c-transforms; coarse pre-solved",
                   "ctransform_Tpair_per_s": pairs5 / (m5 / 1e3) / 1e12,
-                  "ctransform_ms_per_launch": m5, "coarse_seconds": t_c5}
+                  "ctransform_ms_per_launch": m5, "coarse_seconds": t_c5,
+                  "exact_separable_p2": {"jobs_per_s": len(J5) / (ms5x / 1e3), "ms_per_step": ms5x,
+                                         "bounds_identical": same5}}
 
     # ---- upper bound with a non-uniform coupling-upscaling kernel (Gaussian,
     # sigma = 1 pixel) on the first pair: the fitting runs on fine vectors
