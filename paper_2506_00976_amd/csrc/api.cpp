@@ -535,6 +535,27 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   // host images of the uploaded region
   pl.hj.resize(NJ);
   std::vector<int> off(kTables * (NJ + 1), 0);
+  // exact separable stages: the most targets per lane (fewest instructions per
+  // candidate) that still give a launch about four waves per SIMD
+  int xs_T = 8;
+  {
+    auto waves = [&](int T) {
+      long long w = 0;
+      for (const auto& J : pl.in)
+        if ((mode & PM_XS) && J.g.p == 2) {
+          const long long rows = ipow(J.g.N, J.g.d - 1);
+          w += ((rows + 63) / 64) * ((J.g.N + T - 1) / T);
+        }
+      return w;
+    };
+    const long long want = 4LL * 4 * ctx->num_cu;
+    while (xs_T > 2 && waves(xs_T) < want) xs_T /= 2;
+    // QBW_XS_T (2, 4 or 8) overrides the choice
+    if (const char* e = std::getenv("QBW_XS_T")) {
+      const int v = std::atoi(e);
+      if (v == 2 || v == 4 || v == 8) xs_T = v;
+    }
+  }
   for (int j = 0; j < NJ; ++j) {
     const auto& J = pl.in[j];
     const Offs& O = offs[j];
@@ -601,8 +622,9 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.xs_v = D.xs ? (double*)(B + O.xs_v) : nullptr;
     D.xs_i = D.xs ? (int*)(B + O.xs_i) : nullptr;
     {
-      // exact separable stages: one wave per (64 lines, 8 targets along the axis)
-      const int xs_items = D.xs ? ((D.rows + 63) / 64) * ((D.N + 7) / 8) : 0;
+      // exact separable stages: one wave per (64 lines, xs_T targets along the axis)
+      D.xs_T = xs_T;
+      const int xs_items = D.xs ? ((D.rows + 63) / 64) * ((D.N + xs_T - 1) / xs_T) : 0;
       off[12 * (NJ + 1) + j + 1] = off[12 * (NJ + 1) + j] + xs_items;
       off[13 * (NJ + 1) + j + 1] = off[13 * (NJ + 1) + j] + (D.d == 3 ? xs_items : 0);
     }

@@ -725,7 +725,6 @@ __global__ __launch_bounds__(256) void k_argmin(const DevJob* __restrict__ jobs,
 // above psi (no other source can round to psi).  Targets that fail either
 // test (near ties, exact ties, non-finite potentials) are queued and
 // evaluated by brute force exactly as the all-pairs kernel does.
-constexpr int kXsT = 8;        // targets per lane along the processed axis
 constexpr int kXsOff = 2904;   // squares table: xs_sq[i] = (i - kXsOff)^2, 0 <= i <= 2 kXsOff (any valid N)
 
 __global__ __launch_bounds__(256) void k_xs_squares(double* __restrict__ t) {
@@ -737,20 +736,17 @@ __global__ __launch_bounds__(256) void k_xs_squares(double* __restrict__ t) {
 
 typedef const __attribute__((address_space(4))) double* const_dptr;
 
-template <bool FIRST>
-__global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
-                                                 const int* __restrict__ off, int total, int phase, int k,
-                                                 const double* __restrict__ sqt, int2* __restrict__ list,
-                                                 int* __restrict__ count) {
+// One item of stage k: 64 lines x T targets along the axis.  `tile` is the
+// work-group's LDS staging area of the first stage (64 x 17 floats).
+template <bool FIRST, int kXsT>
+__device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int phase, int k,
+                                        const double* __restrict__ sqt, int2* __restrict__ list,
+                                        int* __restrict__ count, float* tile) {
   const int lane = threadIdx.x;
-  for (int it = blockIdx.x; it < total; it += gridDim.x) {
-    const int jb = find_job(off, njobs, it);
-    const DevJob& J = jobs[jb];
-    if (!J.xs || k >= J.d) continue;
+  {
     const int N = J.N, P = J.P;
     const int lines = P / N;
     const int nchunk = (lines + 63) >> 6;
-    const int local = it - off[jb];
     const int group = local / nchunk, chunk = local - group * nchunk;
     const int t0 = group * kXsT;
     int st = 1;
@@ -787,7 +783,6 @@ __global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs
       // then each lane walks its own row there (stride 17 words, no bank
       // conflicts), instead of 64 rows' cache lines per load
       constexpr int TC = 16;
-      __shared__ float tile[64 * (TC + 1)];
       const int row0 = chunk * 64;
       const int sub = lane / TC, cl = lane % TC;   // 4 rows of 16 columns per load
       float nx[64 / 4];
@@ -830,7 +825,7 @@ __global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs
       }
       for (int r = N4; r < N; ++r) step(v1in[base + r * st], r);
     }
-    if (!valid) continue;
+    if (!valid) return;
     const bool last = k == J.d - 1;
     float* dst = phase == 0 ? J.g : J.f;
     int* arg = phase == 0 ? J.arg_g : J.arg_f;
@@ -875,6 +870,25 @@ __global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs
         list[slot] = make_int2(jb, o);
       }
     }
+  }
+}
+
+// Targets per lane T (8, 4 or 2) is the job's: fewer for small plans, so
+// that a launch still has about four waves per SIMD.
+template <bool FIRST>
+__global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
+                                                 const int* __restrict__ off, int total, int phase, int k,
+                                                 const double* __restrict__ sqt, int2* __restrict__ list,
+                                                 int* __restrict__ count) {
+  __shared__ float tile[64 * 17];
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    const int jb = find_job(off, njobs, it);
+    const DevJob& J = jobs[jb];
+    if (!J.xs || k >= J.d) continue;
+    const int local = it - off[jb];
+    if (J.xs_T == 2) xs_item<FIRST, 2>(J, jb, local, phase, k, sqt, list, count, tile);
+    else if (J.xs_T == 4) xs_item<FIRST, 4>(J, jb, local, phase, k, sqt, list, count, tile);
+    else xs_item<FIRST, 8>(J, jb, local, phase, k, sqt, list, count, tile);
   }
 }
 

@@ -114,7 +114,8 @@ struct DevJob {
   int p1_nt;                // p = 1 plan cost / gradient: 0 direct kernels, 64 or 256 distance-table kernels
   float* sep_tmp;           // 2 x P
   const float* sqrt_tab;    // p = 1 c-transform table fill: RN32(sqrt(n)) for n < kSqrtTab, or null
-  int xs;                   // p = 2 c-transforms by exact separable minima (certified, brute force where not)
+  int xs;                   // p = 2 c-transforms by exact separable minima (certified, re-evaluated where not)
+  int xs_T;                 // targets per lane of its stages (8, 4 or 2)
   double* xs_v;             // 2 x (2 P): per stage buffer, best value then runner-up value
   int* xs_i;                // 2 x P: per stage buffer, flat source index of the best value
   int* sep_arg;             // d x P or null

@@ -1,8 +1,9 @@
 """Exact separable c-transform (p = 2) against the oracle's all-pairs reading.
 
 The path evaluates min_x RN32(|x - y|^2 - phi(x)) from per-axis minima in
-float64, certifies each target against float32 rounding and evaluates the
-rest by brute force, so its values and arg-mins must equal the all-pairs
+float64, certifies each target against float32 rounding and re-evaluates the
+rest with the all-pairs arithmetic over the rows that can hold a tie, so its
+values and arg-mins must equal the all-pairs
 float32 reading (the oracle's ctransform_o32) bit for bit, whatever the
 potential: random, smooth, with exact ties everywhere (linear slope 1), with
 near ties, or constant (every minimum exactly 0).
@@ -77,7 +78,21 @@ def test_ctransform_exact_bit_exact(N, d, kind):
     out2 = qbw.ctransform_exact(dev(phi), N, d)
     assert np.array_equal(out2.cpu().numpy(), ref)
     if kind == "zero":
-        assert nfb == N ** d          # an exact 0 is never certified: all brute force
+        assert nfb == N ** d          # an exact 0 is never certified: all re-evaluated
+
+
+# targets per lane of the stages: small plans get 2; force 8 and 4 (the
+# choice for large batches) on the same grids
+@pytest.mark.parametrize("T", [8, 4])
+@pytest.mark.parametrize("kind", ["normal", "smooth", "ties"])
+@pytest.mark.parametrize("N,d", [(32, 2), (16, 3), (15, 2), (20, 3), (7, 2)])
+def test_ctransform_exact_targets_per_lane(N, d, kind, T, monkeypatch):
+    monkeypatch.setenv("QBW_XS_T", str(T))
+    phi = potential(kind, N, d, 12300 + 7 * N + d + T)
+    out, arg = qbw.ctransform_exact(dev(phi), N, d, want_argmin=True)
+    ref, refarg = lower.ctransform_o32(phi, N, d, 2)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    assert np.array_equal(arg.cpu().numpy().astype(np.int64), refarg)
 
 
 # full-size grids on sampled targets (the oracle evaluates them one by one)
@@ -91,7 +106,7 @@ def test_ctransform_exact_large_sampled(N, d, kind):
     ref, refarg = lower.ctransform_o32(phi, N, d, 2, targets=tg)
     assert np.array_equal(out.cpu().numpy()[tg], ref)
     assert np.array_equal(arg.cpu().numpy()[tg].astype(np.int64), refarg)
-    assert nfb <= 0.05 * P, f"{nfb} of {P} targets needed brute force"
+    assert nfb <= 0.05 * P, f"{nfb} of {P} targets needed the re-evaluation"
 
 
 def test_ctransform_exact_matches_all_pairs_kernel_full():
