@@ -95,6 +95,52 @@ def test_ctransform_exact_targets_per_lane(N, d, kind, T, monkeypatch):
     assert np.array_equal(arg.cpu().numpy().astype(np.int64), refarg)
 
 
+def random_case(rng):
+    """A seeded random grid and potential: normal at magnitudes 1e-6 .. 1e6,
+    integers, multiples of 1/64 (like interpolated integer duals), 30 % exact
+    zeros, magnitudes 1e-30 and 1e30, float32 denormals, and exact linear
+    slopes in half-integers (ties on every axis)."""
+    d = 2 if rng.random() < 0.6 else 3
+    N = int(rng.integers(2, 41)) if d == 2 else int(rng.integers(2, 17))
+    P = N ** d
+    kind = int(rng.integers(0, 8))
+    if kind == 0:
+        phi = rng.standard_normal(P) * 10.0 ** rng.uniform(-6, 6)
+    elif kind == 1:
+        phi = rng.integers(-N * N, N * N, P).astype(np.float64)
+    elif kind == 2:
+        phi = rng.integers(-64 * N * N, 64 * N * N, P) / 64.0
+    elif kind == 3:
+        phi = rng.standard_normal(P) * N
+        phi[rng.random(P) < 0.3] = 0.0
+    elif kind == 4:
+        phi = rng.standard_normal(P) * 1e-30
+    elif kind == 5:
+        phi = rng.standard_normal(P) * 1e30
+    elif kind == 6:
+        phi = rng.standard_normal(P) * 1e-40
+    else:
+        phi = coords(N, d) @ (2 * rng.integers(-3, 4, d) * 0.5) + rng.integers(0, 3) * 0.25
+    return N, d, phi.astype(np.float32)
+
+
+def test_ctransform_exact_random_sweep(monkeypatch):
+    # 120 seeded cases, every targets-per-lane setting, compared bitwise
+    # (float32 bit patterns, so signed zeros and denormals count)
+    rng = np.random.default_rng(20261202)
+    for case in range(120):
+        N, d, phi = random_case(rng)
+        T = ["2", "4", "8", None][case % 4]
+        if T:
+            monkeypatch.setenv("QBW_XS_T", T)
+        else:
+            monkeypatch.delenv("QBW_XS_T", raising=False)
+        out, arg = qbw.ctransform_exact(dev(phi), N, d, want_argmin=True)
+        ref, refarg = lower.ctransform_o32(phi, N, d, 2)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32)), (case, N, d)
+        assert np.array_equal(arg.cpu().numpy().astype(np.int64), refarg), (case, N, d)
+
+
 # full-size grids on sampled targets (the oracle evaluates them one by one)
 @pytest.mark.parametrize("kind", ["normal", "smooth"])
 @pytest.mark.parametrize("N,d", [(256, 2), (32, 3), (128, 2)])
