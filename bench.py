@@ -477,12 +477,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if mode else "f32",
         "data": "synthetic",
         "config": {"workload": f"batch of {B} pairs of 256x256 measures (GRF and Cauchy families), "
                                "k=8, p=2, forward+backward of both bounds, coarse solutions pre-solved",
                    "N": N, "d": d, "k": k, "p": p, "batch": B,
-                   "precision": "float32 c-transforms, float64 sums/IPF/plan cost",
+                   "precision": ("float32 c-transform results (the all-pairs reading) from float64 stage minima, "
+                                 "float64 sums/IPF/plan cost" if mode else
+                                 "float32 c-transforms, float64 sums/IPF/plan cost"),
                    "c_transform": ("exact separable: the all-pairs float32 values and arg-mins from "
                                    "per-axis float64 minima, certified per target" if mode else
                                    "all-pairs (lazy) kernel")},
