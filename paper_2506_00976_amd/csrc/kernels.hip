@@ -737,8 +737,10 @@ __global__ __launch_bounds__(256) void k_xs_squares(double* __restrict__ t) {
 typedef const __attribute__((address_space(4))) double* const_dptr;
 
 // One item of stage k: 64 lines x T targets along the axis.  `tile` is the
-// work-group's LDS staging area of the first stage (64 x 17 floats).
-template <bool FIRST, int kXsT>
+// work-group's LDS staging area of the first stage (64 x 17 floats).  ARG:
+// the job wants arg-mins, so the index and the runner-up are tracked; without
+// them a candidate is one add and one min, and only the value is certified.
+template <bool FIRST, int kXsT, bool ARG>
 __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int phase, int k,
                                         const double* __restrict__ sqt, int2* __restrict__ list,
                                         int* __restrict__ count, float* tile) {
@@ -772,8 +774,10 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
 #pragma unroll
       for (int t = 0; t < kXsT; ++t) {
         const double w = h + sr[kXsT - 1 - t];
-        m2[t] = fmin(m2[t], fmax(m1[t], w));
-        ix[t] = w < m1[t] ? r : ix[t];
+        if (ARG) {
+          m2[t] = fmin(m2[t], fmax(m1[t], w));
+          ix[t] = w < m1[t] ? r : ix[t];
+        }
         m1[t] = fmin(m1[t], w);
       }
     };
@@ -839,6 +843,22 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
       const int tt = t0 + t;
       if (tt >= N) break;
       const int o = base + tt * st;
+      if (!ARG) {
+        if (!last) {
+          v1out[o] = m1[t];
+          continue;
+        }
+        const double w1 = m1[t];
+        const double del1 = dk * (fabs(w1) + c0);
+        const float lo = (float)(w1 - del1), hi = (float)(w1 + del1);
+        if (lo == hi) {   // false for NaN and infinite values
+          dst[o] = lo;
+        } else {
+          const int slot = atomicAdd(count, 1);
+          list[slot] = make_int2(jb, o);
+        }
+        continue;
+      }
       const int rs = ix[t];
       double s1 = INFINITY;
       int idx = -1;
@@ -886,9 +906,15 @@ __global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs
     const DevJob& J = jobs[jb];
     if (!J.xs || k >= J.d) continue;
     const int local = it - off[jb];
-    if (J.xs_T == 2) xs_item<FIRST, 2>(J, jb, local, phase, k, sqt, list, count, tile);
-    else if (J.xs_T == 4) xs_item<FIRST, 4>(J, jb, local, phase, k, sqt, list, count, tile);
-    else xs_item<FIRST, 8>(J, jb, local, phase, k, sqt, list, count, tile);
+    if ((phase == 0 ? J.arg_g : J.arg_f) != nullptr) {
+      if (J.xs_T == 2) xs_item<FIRST, 2, true>(J, jb, local, phase, k, sqt, list, count, tile);
+      else if (J.xs_T == 4) xs_item<FIRST, 4, true>(J, jb, local, phase, k, sqt, list, count, tile);
+      else xs_item<FIRST, 8, true>(J, jb, local, phase, k, sqt, list, count, tile);
+    } else {
+      if (J.xs_T == 2) xs_item<FIRST, 2, false>(J, jb, local, phase, k, sqt, list, count, tile);
+      else if (J.xs_T == 4) xs_item<FIRST, 4, false>(J, jb, local, phase, k, sqt, list, count, tile);
+      else xs_item<FIRST, 8, false>(J, jb, local, phase, k, sqt, list, count, tile);
+    }
   }
 }
 

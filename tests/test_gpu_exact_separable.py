@@ -139,6 +139,9 @@ def test_ctransform_exact_random_sweep(monkeypatch):
         ref, refarg = lower.ctransform_o32(phi, N, d, 2)
         assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32)), (case, N, d)
         assert np.array_equal(arg.cpu().numpy().astype(np.int64), refarg), (case, N, d)
+        # values only: the stages track neither index nor runner-up
+        out2 = qbw.ctransform_exact(dev(phi), N, d)
+        assert np.array_equal(out2.cpu().numpy().view(np.uint32), ref.view(np.uint32)), (case, N, d)
 
 
 # full-size grids on sampled targets (the oracle evaluates them one by one)
