@@ -35,11 +35,13 @@ PEAK_LANE_OPS = 256 * 128 * 2.4e9
 INSTR_PER_PAIR = 1.5               # minimum per (source, target) pair: one v_sub_f32 + half a v_min3_f32
 PEAK_PAIRS = PEAK_LANE_OPS / INSTR_PER_PAIR
 # FP64 vector peak: 78.6 TFLOP/s counts an FMA as two, i.e. 256 CUs x 64 lanes/clk x 2.4 GHz
-# = 39.3 T float64 lane-operations/s.  An exact separable stage needs at least six per
-# (source, target) candidate: v_add_f64, v_cmp_lt_f64 + v_cndmask_b32 (the index), v_min_f64
-# (the best) and v_max_f64 + v_min_f64 (the runner-up).
+# = 39.3 T float64 lane-operations/s.  Per (source, target) candidate an exact separable
+# stage needs at least a v_add_f64 and a v_min_f64 (the best value); with arg-mins also
+# v_cmp_lt_f64 + v_cndmask_b32 (the index) and v_max_f64 + v_min_f64 (the runner-up).  The
+# timed batch asks for no arg-mins (the gradients in a and b are f and g themselves).
 PEAK_F64_LANE_OPS = 256 * 64 * 2.4e9
-XS_INSTR_PER_CAND = 6
+XS_INSTR_PER_CAND = 2
+XS_INSTR_PER_CAND_ARGMIN = 6
 PEAK_XS = PEAK_F64_LANE_OPS / XS_INSTR_PER_CAND
 
 
