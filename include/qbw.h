@@ -249,9 +249,10 @@ qbw_status qbw_ctransform_separable(qbw_ctx* ctx, const qbw_grid* grid, const fl
  * rounds higher.  The other targets are evaluated by brute force.
  * n_fallback (host int32, may be NULL) receives their number.  grid->p
  * must be 2 (QBW_E_GRID otherwise); src, dst, argmin as in qbw_ctransform. */
-/* (Each stage gives a lane 8, 4 or 2 targets along its axis, the most that
- * still leave a launch about four waves per SIMD; the environment variable
- * QBW_XS_T = 2, 4 or 8 overrides the choice, for tests.) */
+/* (Each stage gives a lane 16, 8, 4 or 2 targets along its axis, the most
+ * that still leave a launch about four waves per SIMD; 16 only without
+ * arg-mins and for N <= 2048.  The environment variable QBW_XS_T = 2, 4, 8
+ * or 16 overrides the choice within those limits, for tests.) */
 qbw_status qbw_ctransform_exact(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
                                 int32_t* argmin, int32_t* n_fallback, qbw_stream stream);
 

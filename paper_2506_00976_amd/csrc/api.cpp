@@ -535,9 +535,15 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   // host images of the uploaded region
   pl.hj.resize(NJ);
   std::vector<int> off(kTables * (NJ + 1), 0);
-  // exact separable stages: the most targets per lane (fewest instructions per
-  // candidate) that still give a launch about four waves per SIMD
-  int xs_T = 8;
+  // exact separable stages: the most targets per lane (fewest loads per
+  // candidate) that still give a launch about four waves per SIMD; 16 only
+  // without arg-mins (one running minimum per target) and for N <= 2048 (the
+  // squares table's reach)
+  int xs_max_N = 0;
+  for (const auto& J : pl.in)
+    if ((mode & PM_XS) && J.g.p == 2) xs_max_N = std::max(xs_max_N, J.g.N);
+  const bool xs16 = !(mode & PM_ARGMIN) && xs_max_N <= 2048;
+  int xs_T = xs16 ? 16 : 8;
   {
     auto waves = [&](int T) {
       long long w = 0;
@@ -550,10 +556,10 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     };
     const long long want = 4LL * 4 * ctx->num_cu;
     while (xs_T > 2 && waves(xs_T) < want) xs_T /= 2;
-    // QBW_XS_T (2, 4 or 8) overrides the choice
+    // QBW_XS_T (2, 4, 8, or 16 without arg-mins) overrides the choice
     if (const char* e = std::getenv("QBW_XS_T")) {
       const int v = std::atoi(e);
-      if (v == 2 || v == 4 || v == 8) xs_T = v;
+      if (v == 2 || v == 4 || v == 8 || (v == 16 && xs16)) xs_T = v;
     }
   }
   for (int j = 0; j < NJ; ++j) {

@@ -893,8 +893,9 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
   }
 }
 
-// Targets per lane T (8, 4 or 2) is the job's: fewer for small plans, so
-// that a launch still has about four waves per SIMD.
+// Targets per lane T (16, 8, 4 or 2) is the job's: fewer for small plans,
+// so that a launch still has enough waves per SIMD (16 only without arg-mins,
+// where a target holds one running minimum).
 template <bool FIRST>
 __global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
                                                  const int* __restrict__ off, int total, int phase, int k,
@@ -913,6 +914,7 @@ __global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs
     } else {
       if (J.xs_T == 2) xs_item<FIRST, 2, false>(J, jb, local, phase, k, sqt, list, count, tile);
       else if (J.xs_T == 4) xs_item<FIRST, 4, false>(J, jb, local, phase, k, sqt, list, count, tile);
+      else if (J.xs_T == 16) xs_item<FIRST, 16, false>(J, jb, local, phase, k, sqt, list, count, tile);
       else xs_item<FIRST, 8, false>(J, jb, local, phase, k, sqt, list, count, tile);
     }
   }

@@ -130,7 +130,7 @@ def test_ctransform_exact_random_sweep(monkeypatch):
     rng = np.random.default_rng(20261202)
     for case in range(120):
         N, d, phi = random_case(rng)
-        T = ["2", "4", "8", None][case % 4]
+        T = ["2", "4", "8", None, "16"][case % 5]
         if T:
             monkeypatch.setenv("QBW_XS_T", T)
         else:
@@ -142,6 +142,17 @@ def test_ctransform_exact_random_sweep(monkeypatch):
         # values only: the stages track neither index nor runner-up
         out2 = qbw.ctransform_exact(dev(phi), N, d)
         assert np.array_equal(out2.cpu().numpy().view(np.uint32), ref.view(np.uint32)), (case, N, d)
+
+
+@pytest.mark.parametrize("kind", ["normal", "smooth", "ties", "zero"])
+@pytest.mark.parametrize("N,d", [(32, 2), (16, 3), (15, 2), (20, 3), (7, 2), (64, 2)])
+def test_ctransform_exact_values_16_targets_per_lane(N, d, kind, monkeypatch):
+    # without arg-mins a lane may take 16 targets (large batches)
+    monkeypatch.setenv("QBW_XS_T", "16")
+    phi = potential(kind, N, d, 12400 + 7 * N + d)
+    out = qbw.ctransform_exact(dev(phi), N, d)
+    ref, _ = lower.ctransform_o32(phi, N, d, 2)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32))
 
 
 # full-size grids on sampled targets (the oracle evaluates them one by one)
