@@ -240,8 +240,9 @@ qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, 
 qbw_status qbw_ctransform_separable(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
                                     int32_t* argmin, qbw_stream stream);
 
-/* The lazy c-transform of qbw_ctransform for p = 2, bit for bit (values
- * and arg-mins), evaluated separably: the exact minimum of |x - y|^2 - src
+/* The lazy c-transform of qbw_ctransform (Section 4, eq. of the lazy
+ * c-transform) for p = 2, bit for bit (values and arg-mins), evaluated
+ * separably: the exact minimum of |x - y|^2 - src
  * over the sources is a sum of per-axis minima, taken in float64 (d passes,
  * last axis first); rounding to float32 is monotone, so dst = RN32 of that
  * minimum wherever the float64 error bound cannot straddle a rounding
