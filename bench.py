@@ -228,7 +228,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the method's "
-              "fine-grid path runs on a single MI355X here; see DESIGN.md for how it would shard.",
+              "fine-grid path runs on a single MI355X here (the pairs of a batch are independent, so "
+              "a batch would be split over GPUs, one process each).",
               file=sys.stderr)
         sys.exit(2)
 
