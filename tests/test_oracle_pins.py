@@ -797,3 +797,47 @@ def test_kernel_upper_bound_gradient_matches_fd(p):
         fd = (W(mu * (1 + h * vm), nu * (1 + h * vn)) - W(mu * (1 - h * vm), nu * (1 - h * vn))) / (2 * h)
         an = float((gm * (mu * vm).reshape(-1)).sum() + (gn * (nu * vn).reshape(-1)).sum())
         assert fd == pytest.approx(an, rel=1e-6, abs=1e-9)
+
+
+def _rn32(q):
+    """Correctly rounded float32 of an exact rational (ties to even)."""
+    from fractions import Fraction
+    f = np.float32(float(q))             # within an ulp; fix the last step exactly
+    best = None
+    for c in (np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))):
+        if not np.isfinite(c):
+            continue
+        e = abs(Fraction(float(c)) - q)
+        even = (int(np.array(c, dtype=np.float32).view(np.uint32)) & 1) == 0
+        key = (e, not even)
+        if best is None or key < best[0]:
+            best = (key, c)
+    return best[1]
+
+
+@pytest.mark.parametrize("N,d,kind", [(6, 2, "normal"), (5, 3, "normal"), (7, 2, "lattice"), (4, 3, "lattice")])
+def test_all_pairs_float32_transform_is_rounded_exact_separable_minimum(N, d, kind):
+    # The float32 all-pairs reading min_x RN32(c - phi) equals RN32 of the exact
+    # minimum of c - phi (rounding is monotone), and for p = 2 that exact
+    # minimum is a nest of per-axis minima: the basis of the exact separable
+    # evaluation.  Exact rationals throughout.
+    from fractions import Fraction
+    r = si.rng(31000 + N + d)
+    P = N ** d
+    if kind == "normal":
+        phi = (r.standard_normal(P) * N * N / 4).astype(np.float32)
+    else:
+        phi = (r.integers(-64 * N * N, 64 * N * N, P) / 64.0).astype(np.float32)
+    ref, _ = lower.ctransform_o32(phi, N, d, 2)
+    F = np.array([Fraction(float(v)) for v in phi], dtype=object).reshape((N,) * d)
+    # nested exact minima, last axis first: H = min over x_a of (x_a - y_a)^2 + H
+    H = -F
+    for a in reversed(range(d)):
+        sh = list(H.shape)
+        out = np.empty(sh, dtype=object)
+        for idx in itertools.product(*[range(s) for s in sh]):
+            y = idx[a]
+            out[idx] = min(Fraction((x - y) ** 2) + H[idx[:a] + (x,) + idx[a + 1:]] for x in range(N))
+        H = out
+    got = np.array([_rn32(v) for v in H.reshape(-1)], dtype=np.float32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
