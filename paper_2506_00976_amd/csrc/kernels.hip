@@ -1267,6 +1267,35 @@ __global__ __launch_bounds__(256) void k_scalings(const DevJob* __restrict__ job
 // (written out for the plan cost and the backward pass); the weighted-TV
 // partials of k_tv_partial, with the same arithmetic as those two kernels.
 // Every partial goes to its chunk's slot; k_finalize adds them in order.
+// NS sums and NM maxima of per-thread values over a 256-thread work-group, in
+// a fixed order: a butterfly within each wave, then the four waves' results
+// added in wave order.  Two barriers for all of them.  Results in every thread.
+template <int NS, int NM>
+__device__ __forceinline__ void block_reduce_many(double (&s)[NS], double (&m)[NM], double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) s[i] += __shfl_xor(s[i], o, 64);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) m[i] = fmax(m[i], __shfl_xor(m[i], o, 64));
+  }
+  constexpr int W = NS + NM;
+  const int w = threadIdx.x >> 6;
+  __syncthreads();   // earlier readers of sh are done
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) sh[w * W + i] = s[i];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) sh[w * W + NS + i] = m[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NS; ++i) s[i] = ((sh[i] + sh[W + i]) + sh[2 * W + i]) + sh[3 * W + i];
+#pragma unroll
+  for (int i = 0; i < NM; ++i)
+    m[i] = fmax(fmax(sh[NS + i], sh[W + NS + i]), fmax(sh[2 * W + NS + i], sh[3 * W + NS + i]));
+}
+
 __global__ __launch_bounds__(256) void k_fwd_pixels(const DevJob* __restrict__ jobs, int njobs,
                                                     const int* __restrict__ off, int total) {
   __shared__ double sh[256];
@@ -1313,20 +1342,14 @@ __global__ __launch_bounds__(256) void k_fwd_pixels(const DevJob* __restrict__ j
       wm += w * mu;
       wn += w * nu;
     }
-    sf = block_sum<256>(sf, sh);
-    sg = block_sum<256>(sg, sh);
-    mh = block_max<256>(mh, sh);
-    mg = block_max<256>(mg, sh);
-    mf = block_max<256>(mf, sh);
-    tm = block_sum<256>(tm, sh);
-    tn = block_sum<256>(tn, sh);
-    wm = block_sum<256>(wm, sh);
-    wn = block_sum<256>(wn, sh);
+    double sv[6] = {sf, sg, tm, tn, wm, wn};
+    double mv[3] = {mh, mg, mf};
+    block_reduce_many<6, 3>(sv, mv, sh);
     if (threadIdx.x == 0) {
       double* r = J.red_lb + (size_t)c * kRedSlotsLB;
-      r[0] = sf; r[1] = sg; r[2] = mh; r[3] = mg; r[4] = mf;
+      r[0] = sv[0]; r[1] = sv[1]; r[2] = mv[0]; r[3] = mv[1]; r[4] = mv[2];
       double* t = J.red_tv + (size_t)c * kRedSlotsTV;
-      t[0] = tm; t[1] = tn; t[2] = wm; t[3] = wn;
+      t[0] = sv[2]; t[1] = sv[3]; t[2] = sv[4]; t[3] = sv[5];
     }
   }
 }
