@@ -1712,26 +1712,24 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
     sf += r[0]; sg += r[1];
     mh = fmax(mh, r[2]); mg = fmax(mg, r[3]); mf = fmax(mf, r[4]);
   }
-  sf = block_sum<256>(sf, sh);
-  sg = block_sum<256>(sg, sh);
-  mh = block_max<256>(mh, sh);
-  mg = block_max<256>(mg, sh);
-  mf = block_max<256>(mf, sh);
   // upper bound
   const double kd = J.d == 2 ? (double)J.k * J.k : (double)J.k * J.k * J.k;
   const double cc = 1.0 / (kd * kd);
   double pc = 0;
   for (int e = threadIdx.x; e < J.nnz; e += 256) pc += cc * J.e_val[e] * J.red_pc[e];
-  pc = block_sum<256>(pc, sh);
   double tm = 0, tn = 0, wm = 0, wn = 0;
   for (int c = threadIdx.x; c < J.chunks; c += 256) {
     const double* r = J.red_tv + (size_t)c * kRedSlotsTV;
     tm += r[0]; tn += r[1]; wm += r[2]; wn += r[3];
   }
-  tm = block_sum<256>(tm, sh);
-  tn = block_sum<256>(tn, sh);
-  wm = block_sum<256>(wm, sh);
-  wn = block_sum<256>(wn, sh);
+  // all sums and maxima in one work-group reduction
+  {
+    double sv[7] = {sf, sg, pc, tm, tn, wm, wn};
+    double mv[3] = {mh, mg, mf};
+    block_reduce_many<7, 3>(sv, mv, sh);
+    sf = sv[0]; sg = sv[1]; pc = sv[2]; tm = sv[3]; tn = sv[4]; wm = sv[5]; wn = sv[6];
+    mh = mv[0]; mg = mv[1]; mf = mv[2];
+  }
   if (threadIdx.x != 0) return;
   const double p = J.p;
   // float32 feasibility shift (first order in u = 2^-24; see the oracle's derivation)
