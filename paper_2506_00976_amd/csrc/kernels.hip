@@ -2454,10 +2454,10 @@ __global__ __launch_bounds__(256) void k_kub_check(KubJob J, int t) {
     sm += J.part_mu[q];
     sn += J.part_nu[q];
   }
-  sm = block_sum<256>(sm, sh);
-  sn = block_sum<256>(sn, sh);
+  double sv[2] = {sm, sn}, mv[1] = {0.0};
+  block_reduce_many<2, 1>(sv, mv, sh);
   if (threadIdx.x == 0) {
-    const double err = sm + sn;
+    const double err = sv[0] + sv[1];
     J.result[RS_IPF_RESID] = err;
     J.result[RS_IPF_ITERS] = (double)t;
     const bool conv = err < J.xi;
@@ -2532,13 +2532,11 @@ __global__ __launch_bounds__(256) void k_kub_tv(KubJob J) {
     wm += w * mu;
     wn += w * nu;
   }
-  tm = block_sum<256>(tm, sh);
-  tn = block_sum<256>(tn, sh);
-  wm = block_sum<256>(wm, sh);
-  wn = block_sum<256>(wn, sh);
+  double sv[4] = {tm, tn, wm, wn}, mv[1] = {0.0};
+  block_reduce_many<4, 1>(sv, mv, sh);
   if (threadIdx.x == 0) {
     double* r = J.red_tv + (size_t)c * kRedSlotsTV;
-    r[0] = tm; r[1] = tn; r[2] = wm; r[3] = wn;
+    r[0] = sv[0]; r[1] = sv[1]; r[2] = sv[2]; r[3] = sv[3];
   }
 }
 
@@ -2554,16 +2552,16 @@ __global__ __launch_bounds__(256) void k_kub_finalize(KubJob J) {
     for (int c = 0; c < J.cpb; ++c) s += J.pc_part[(size_t)e * J.cpb + c];
     pc += J.e_val[e] * s;
   }
-  pc = block_sum<256>(pc, sh);
   double tm = 0.0, tn = 0.0, wm = 0.0, wn = 0.0;
   for (int c = threadIdx.x; c < J.chunks; c += 256) {
     const double* r = J.red_tv + (size_t)c * kRedSlotsTV;
     tm += r[0]; tn += r[1]; wm += r[2]; wn += r[3];
   }
-  tm = block_sum<256>(tm, sh);
-  tn = block_sum<256>(tn, sh);
-  wm = block_sum<256>(wm, sh);
-  wn = block_sum<256>(wn, sh);
+  {
+    double sv[5] = {pc, tm, tn, wm, wn}, mv[1] = {0.0};
+    block_reduce_many<5, 1>(sv, mv, sh);
+    pc = sv[0]; tm = sv[1]; tn = sv[2]; wm = sv[3]; wn = sv[4];
+  }
   if (threadIdx.x != 0) return;
   const double mm = (double)J.m * J.m;
   const double rel = 9.094947017729282e-13 + (mm + J.nnz) * 2.220446049250313e-16;
