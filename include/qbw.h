@@ -228,7 +228,9 @@ qbw_status qbw_upscale_potential_interp(qbw_ctx* ctx, const qbw_grid* grid, uint
 /* Lazy c-transform (Section 4, eq. of the lazy c-transform):
  * dst[j] = min_i RN32(RN32(|x_i - x_j|^p) - src[i]) over all N^d pixels,
  * float32, exact min; argmin (device int32, may be NULL) = the lowest flat
- * index attaining it.  src, dst: device float32 (N^d). */
+ * index attaining it.  src, dst: device float32, each exactly N^d elements in
+ * C order (the library cannot see a buffer's size: a shorter one is read or
+ * written past its end); argmin likewise N^d int32.  grid->k is ignored. */
 qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
                           int32_t* argmin, qbw_stream stream);
 
@@ -236,7 +238,8 @@ qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, 
  * c-transforms, last axis first (pass 1 subtracts src, later passes add the
  * previous result), each candidate rounded to float32 once per axis; argmin
  * (may be NULL) = the passes' lowest indices composed.  grid->p must be 2
- * (QBW_E_GRID otherwise). */
+ * (QBW_E_GRID otherwise); src, dst, argmin hold N^d elements each, as in
+ * qbw_ctransform. */
 qbw_status qbw_ctransform_separable(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
                                     int32_t* argmin, qbw_stream stream);
 
@@ -249,7 +252,8 @@ qbw_status qbw_ctransform_separable(qbw_ctx* ctx, const qbw_grid* grid, const fl
  * boundary, and the arg-min is the best source wherever every other source
  * rounds higher.  The other targets are evaluated by brute force.
  * n_fallback (host int32, may be NULL) receives their number.  grid->p
- * must be 2 (QBW_E_GRID otherwise); src, dst, argmin as in qbw_ctransform. */
+ * must be 2 (QBW_E_GRID otherwise); src, dst, argmin as in qbw_ctransform
+ * (N^d elements each). */
 /* (Each stage gives a lane 16, 8, 4 or 2 targets along its axis, the most
  * that still leave a launch about four waves per SIMD; 16 only without
  * arg-mins and for N <= 2048.  The environment variable QBW_XS_T = 2, 4, 8

@@ -77,6 +77,32 @@ def _dev(t, dtype=torch.float64):
     return t.contiguous()
 
 
+def _sized(t, count: int, what: str):
+    """The library reads and writes exactly `count` elements behind each
+    pointer: a shorter tensor would be overrun on the device."""
+    if t.numel() != count:
+        raise QbwError(f"{what} must hold {count} elements, got {t.numel()}")
+    return t
+
+
+def _pair(a, b):
+    """Both measures as contiguous float64 device tensors of one shape."""
+    a, b = _dev(a), _dev(b)
+    if a.shape != b.shape:
+        raise QbwError(f"a and b must have the same shape, got {tuple(a.shape)} and {tuple(b.shape)}")
+    return a, b
+
+
+def _out(t, like, what: str):
+    """A caller-given output buffer: written in place through its pointer, so it
+    must be a contiguous float64 device tensor with as many elements as `like`."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise QbwError(f"{what} must be a float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise QbwError(f"{what} must be contiguous (the library writes through its pointer)")
+    return _sized(t, like.numel(), what)
+
+
 def _grid(a, k, p) -> QbwGrid:
     if a.dim() not in (2, 3) or len(set(a.shape)) != 1:
         raise QbwError(f"measures must have shape (N,)*d with d in {{2,3}}, got {tuple(a.shape)}")
@@ -161,7 +187,7 @@ def bounds(a, b, k: int, p: int, coarse: Coarse | None = None, xi: float = 1e-12
     separable=True evaluates the p = 2 c-transforms axis by axis (QBW_SEPARABLE),
     separable="exact" axis by axis with the all-pairs results (QBW_SEPARABLE_EXACT);
     interp picks the interpolation of the coarse potential ("linear", "nearest", "cubic")."""
-    a, b = _dev(a), _dev(b)
+    a, b = _pair(a, b)
     grid = _grid(a, k, p)
     opts = _opts(xi, max_ipf_iter, (QBW_WANT_ARGMIN if want_argmin else 0) | _sep_flag(separable) |
                  _interp(interp))
@@ -196,7 +222,7 @@ class BoundsFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, a, b, k, p, coarse, xi, max_ipf_iter, want_argmin, separable=False, interp="linear"):
-        a, b = _dev(a), _dev(b)
+        a, b = _pair(a, b)
         grid = _grid(a, k, p)
         flags = QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_argmin else 0) | _sep_flag(separable) | \
             _interp(interp)
@@ -244,7 +270,7 @@ def bounds_with_grads(a, b, k: int, p: int, coarse: Coarse | None = None, dlower
                       dupper: float = 1.0, want_fhat_grad: bool = False, xi: float = 1e-12,
                       max_ipf_iter: int = 50, separable: bool = False, interp: str = "linear"):
     """Forward + backward in one call: returns (result dict, grad_a, grad_b, grad_fhat or None)."""
-    a, b = _dev(a), _dev(b)
+    a, b = _pair(a, b)
     grid = _grid(a, k, p)
     opts = _opts(xi, max_ipf_iter, QBW_SAVE_FOR_BWD | (QBW_WANT_ARGMIN if want_fhat_grad else 0) |
                  _sep_flag(separable) | _interp(interp))
@@ -290,7 +316,7 @@ def coarse_cost(N: int, d: int, k: int, p: int) -> np.ndarray:
 
 
 def cbar(a, b, k: int, p: int):
-    a, b = _dev(a), _dev(b)
+    a, b = _pair(a, b)
     grid = _grid(a, k, p)
     Q = (a.shape[0] // k) ** a.dim()
     out = torch.empty((Q, Q), dtype=torch.float64, device=a.device)
@@ -301,6 +327,8 @@ def cbar(a, b, k: int, p: int):
 
 def upscale_potential(ftil, N: int, d: int, k: int, interp: str = "linear"):
     ftil = _dev(ftil)
+    if 1 <= k <= N and N % k == 0:   # other shapes are the library's QBW_E_GRID
+        _sized(ftil, (N // k) ** d, "ftil")
     grid = QbwGrid(d, N, k, 2)
     out = torch.empty(N ** d, dtype=torch.float32, device=ftil.device)
     check(load().qbw_upscale_potential_interp(context(ftil.device.index).handle, C.byref(grid),
@@ -310,7 +338,7 @@ def upscale_potential(ftil, N: int, d: int, k: int, interp: str = "linear"):
 
 
 def ctransform(src, N: int, d: int, p: int, want_argmin: bool = False):
-    src = _dev(src, torch.float32)
+    src = _sized(_dev(src, torch.float32), N ** d, "src")
     grid = QbwGrid(d, N, 1, p)
     dst = torch.empty_like(src)
     arg = torch.empty(src.shape, dtype=torch.int32, device=src.device) if want_argmin else None
@@ -321,7 +349,7 @@ def ctransform(src, N: int, d: int, p: int, want_argmin: bool = False):
 
 def ctransform_separable(src, N: int, d: int, want_argmin: bool = False):
     """p = 2 c-transform as d nested 1-D transforms (qbw_ctransform_separable)."""
-    src = _dev(src, torch.float32)
+    src = _sized(_dev(src, torch.float32), N ** d, "src")
     grid = QbwGrid(d, N, 1, 2)
     dst = torch.empty_like(src)
     arg = torch.empty(src.shape, dtype=torch.int32, device=src.device) if want_argmin else None
@@ -334,7 +362,7 @@ def ctransform_exact(src, N: int, d: int, want_argmin: bool = False, return_fall
     """p = 2 c-transform with the all-pairs values and arg-mins, from exact
     per-axis minima (qbw_ctransform_exact); return_fallback also returns how
     many targets needed the brute-force evaluation."""
-    src = _dev(src, torch.float32)
+    src = _sized(_dev(src, torch.float32), N ** d, "src")
     grid = QbwGrid(d, N, 1, 2)
     dst = torch.empty_like(src)
     arg = torch.empty(src.shape, dtype=torch.int32, device=src.device) if want_argmin else None
@@ -348,7 +376,7 @@ def ctransform_exact(src, N: int, d: int, want_argmin: bool = False, return_fall
 
 
 def ipf(a, b, k: int, coarse: Coarse, xi: float = 1e-12, max_ipf_iter: int = 50):
-    a, b = _dev(a), _dev(b)
+    a, b = _pair(a, b)
     grid = _grid(a, k, 2)
     opts = _opts(xi, max_ipf_iter, 0)
     a_s = torch.empty(a.numel(), dtype=torch.float64, device=a.device)
@@ -363,7 +391,7 @@ def ipf(a, b, k: int, coarse: Coarse, xi: float = 1e-12, max_ipf_iter: int = 50)
 
 
 def plan_cost(a_s, b_s, N: int, d: int, k: int, p: int, coarse: Coarse) -> float:
-    a_s, b_s = _dev(a_s), _dev(b_s)
+    a_s, b_s = _sized(_dev(a_s), N ** d, "a_s"), _sized(_dev(b_s), N ** d, "b_s")
     grid = QbwGrid(d, N, k, p)
     out = C.c_double()
     cs = coarse.struct()
@@ -373,8 +401,9 @@ def plan_cost(a_s, b_s, N: int, d: int, k: int, p: int, coarse: Coarse) -> float
 
 
 def tv(a, b, k: int, p: int, coarse: Coarse, a_s, b_s):
-    a, b, a_s, b_s = _dev(a), _dev(b), _dev(a_s), _dev(b_s)
+    (a, b), a_s, b_s = _pair(a, b), _dev(a_s), _dev(b_s)
     grid = _grid(a, k, p)
+    _sized(a_s, a.numel(), "a_s"), _sized(b_s, a.numel(), "b_s")
     tm, tn = C.c_double(), C.c_double()
     cs = coarse.struct()
     check(load().qbw_tv(context(a.device.index).handle, C.byref(grid), _ptr(a), _ptr(b), C.byref(cs),
@@ -402,7 +431,7 @@ def upper_kernel(a, b, k: int, p: int, kernel, coarse: Coarse | None = None, xi:
     With ``dupper``, dupper * d upper / d(a, b) is added into ``grad_a`` /
     ``grad_b`` (float64 tensors shaped like a; created as zeros when None and
     returned in the dict)."""
-    a, b = _dev(a), _dev(b)
+    a, b = _pair(a, b)
     if coarse is None:
         coarse = coarse_solve(sumpool(a, k).cpu().numpy(), sumpool(b, k).cpu().numpy(),
                               a.shape[0], a.dim(), k, p)
@@ -417,8 +446,8 @@ def upper_kernel(a, b, k: int, p: int, kernel, coarse: Coarse | None = None, xi:
         a_s = torch.empty(a.numel(), dtype=torch.float64, device=a.device)
         b_s = torch.empty_like(a_s)
     if dupper is not None:
-        grad_a = torch.zeros_like(a) if grad_a is None else grad_a
-        grad_b = torch.zeros_like(b) if grad_b is None else grad_b
+        grad_a = torch.zeros_like(a) if grad_a is None else _out(grad_a, a, "grad_a")
+        grad_b = torch.zeros_like(b) if grad_b is None else _out(grad_b, b, "grad_b")
     cs = coarse.struct()
     check(load().qbw_upper_kernel(context(a.device.index).handle, C.byref(grid), _ptr(a), _ptr(b),
                                   C.byref(cs), kern.ctypes.data, C.byref(opts), C.byref(res),
@@ -441,7 +470,7 @@ class UpperKernelFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, a, b, k, p, kernel, coarse, xi, max_ipf_iter):
-        a, b = _dev(a), _dev(b)
+        a, b = _pair(a, b)
         if coarse is None:
             coarse = coarse_solve(sumpool(a, k).cpu().numpy(), sumpool(b, k).cpu().numpy(),
                                   a.shape[0], a.dim(), k, p)
@@ -468,7 +497,7 @@ def upper_kernel_bound(a, b, k: int, p: int, kernel, coarse: Coarse | None = Non
 
 def weighted_cost_upper(a, b, k: int, p: int):
     """Weighted-cost upper bound (Algorithm 3): (bound, coarse objective on C-bar)."""
-    a, b = _dev(a), _dev(b)
+    a, b = _pair(a, b)
     grid = _grid(a, k, p)
     ub, obj = C.c_double(), C.c_double()
     check(load().qbw_weighted_cost_upper(context(a.device.index).handle, C.byref(grid), _ptr(a), _ptr(b),
@@ -478,7 +507,7 @@ def weighted_cost_upper(a, b, k: int, p: int):
 
 def min_cost_lower(a, b, k: int, p: int):
     """Min-cost lower bound (Section 3.3): (bound, coarse objective on C^min)."""
-    a, b = _dev(a), _dev(b)
+    a, b = _pair(a, b)
     grid = _grid(a, k, p)
     lb, obj = C.c_double(), C.c_double()
     check(load().qbw_min_cost_lower(context(a.device.index).handle, C.byref(grid), _ptr(a), _ptr(b),
@@ -510,11 +539,11 @@ class Batch:
         dev = None
         for i, jb in enumerate(jobs):
             a, b, k, p = jb[:4]
-            a, b = _dev(a), _dev(b)
+            a, b = _pair(a, b)
             ga = gb = None
             if backward:
-                ga = jb[4] if len(jb) > 4 else torch.zeros_like(a)
-                gb = jb[5] if len(jb) > 5 else torch.zeros_like(b)
+                ga = _out(jb[4], a, "grad_a") if len(jb) > 4 else torch.zeros_like(a)
+                gb = _out(jb[5], b, "grad_b") if len(jb) > 5 else torch.zeros_like(b)
             self._keep += [a, b, ga, gb]
             arr[i] = QbwJob(_grid(a, k, p), a.data_ptr(), b.data_ptr(),
                             ga.data_ptr() if ga is not None else None,

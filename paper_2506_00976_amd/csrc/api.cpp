@@ -363,6 +363,81 @@ static int choose_splits(std::vector<JobIn>& in, int target_waves) {
   return QBW_OK;
 }
 
+// c-transform work items of the all-pairs jobs of `in`, laid out for the
+// persistent launch (position b < G is work-group b's item); returns G.
+static int build_ct_items(const qbw_ctx* ctx, const std::vector<JobIn>& in, unsigned mode,
+                          std::vector<CtItem>& items) {
+  const int NJ = (int)in.size();
+  // c-transform work items, grouped per XCD.  Jobs get a home XCD by
+  // longest-processing-time assignment of their pair counts; a lone job (or one
+  // too big for a single XCD's share) spreads its target tiles over all XCDs.
+  // modelled cost of one item of each job (all of a job's items are alike)
+  std::vector<double> job_item_cost(NJ);
+  for (int j = 0; j < NJ; ++j) {
+    const auto& J = in[j];
+    const double rows = std::pow((double)J.g.N, J.g.d - 1);
+    job_item_cost[j] = 64.0 * J.tiling.R * (rows / J.tiling.S) * J.g.N * (J.g.p == 1 ? 1.4 : 1.0);
+  }
+  auto item_cost = [&](const CtItem& w) { return job_item_cost[w.job]; };
+  std::vector<std::vector<CtItem>> queues(kQueues);
+  {
+    std::vector<double> load(kQueues, 0.0);
+    std::vector<int> order(NJ);
+    std::iota(order.begin(), order.end(), 0);
+    auto work = [&](int j) { return std::pow((double)in[j].g.N, 2.0 * in[j].g.d); };
+    double total = 0;
+    for (int j = 0; j < NJ; ++j) total += work(j);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    for (int j : order) {
+      const auto& J = in[j];
+      if ((mode & (PM_SEP | PM_XS)) && J.g.p == 2) continue;   // separable jobs use the 1-D passes
+      const int P = ipow(J.g.N, J.g.d);
+      const int tiles = (P + 64 * J.tiling.R - 1) / (64 * J.tiling.R);
+      const bool spread = work(j) > total / kQueues;
+      int home = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      for (int s = 0; s < J.tiling.S; ++s)
+        for (int t = 0; t < tiles; ++t) {
+          CtItem w{j, t, s, 0};
+          const int q = spread ? (t % kQueues) : home;
+          queues[q].push_back(w);
+          load[q] += item_cost(w);
+        }
+    }
+  }
+  // Item table: position b < G (the grid) is the item work-group b takes in
+  // the static round.  The dispatcher deals work-groups to the XCDs in turn,
+  // so positions b = q (mod kQueues) are XCD q's: they get queue q's items
+  // (largest first); surplus items of longer queues fill the positions left
+  // free by shorter ones, and what exceeds the grid forms the dynamic tail.
+  int n_all = 0;
+  const auto larger = [&](const CtItem& x, const CtItem& y) { return item_cost(x) > item_cost(y); };
+  for (int q = 0; q < kQueues; ++q) {
+    // items enter in (split, tile) order, usually already by decreasing cost
+    if (!std::is_sorted(queues[q].begin(), queues[q].end(), larger))
+      std::stable_sort(queues[q].begin(), queues[q].end(), larger);
+    n_all += (int)queues[q].size();
+  }
+  // persistent grid: one work-group per item, at most 32 per compute unit
+  const int G = std::min(n_all, ctx->num_cu * 4 * 8);
+  items.assign(n_all, CtItem{});
+  std::vector<CtItem> surplus;
+  std::vector<int> free_pos;
+  for (int q = 0; q < kQueues; ++q) {
+    size_t used = 0;
+    for (int b = q; b < G; b += kQueues) {
+      if (used < queues[q].size()) items[b] = queues[q][used++];
+      else free_pos.push_back(b);
+    }
+    surplus.insert(surplus.end(), queues[q].begin() + used, queues[q].end());
+  }
+  if (!std::is_sorted(surplus.begin(), surplus.end(), larger))
+    std::stable_sort(surplus.begin(), surplus.end(), larger);
+  size_t si = 0;
+  for (int b : free_pos) items[b] = surplus[si++];
+  for (int b = G; b < n_all; ++b) items[b] = surplus[si++];
+  return G;
+}
+
 // Build the layout, allocate (or reuse) device memory, upload tables.
 static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mode,
                       const qbw_opts& o, bool own_memory, hipStream_t st) {
@@ -426,73 +501,8 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   }
   const size_t o_xs_list = pl.xs_pixels ? L.add(8 * (size_t)pl.xs_pixels) : 0;
   constexpr int kTables = 14;
-  // c-transform work items, grouped per XCD.  Jobs get a home XCD by
-  // longest-processing-time assignment of their pair counts; a lone job (or one
-  // too big for a single XCD's share) spreads its target tiles over all XCDs.
-  // modelled cost of one item of each job (all of a job's items are alike)
-  std::vector<double> job_item_cost(NJ);
-  for (int j = 0; j < NJ; ++j) {
-    const auto& J = pl.in[j];
-    const double rows = std::pow((double)J.g.N, J.g.d - 1);
-    job_item_cost[j] = 64.0 * J.tiling.R * (rows / J.tiling.S) * J.g.N * (J.g.p == 1 ? 1.4 : 1.0);
-  }
-  auto item_cost = [&](const CtItem& w) { return job_item_cost[w.job]; };
-  std::vector<std::vector<CtItem>> queues(kQueues);
-  {
-    std::vector<double> load(kQueues, 0.0);
-    std::vector<int> order(NJ);
-    std::iota(order.begin(), order.end(), 0);
-    auto work = [&](int j) { return std::pow((double)pl.in[j].g.N, 2.0 * pl.in[j].g.d); };
-    double total = 0;
-    for (int j = 0; j < NJ; ++j) total += work(j);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
-    for (int j : order) {
-      const auto& J = pl.in[j];
-      if ((mode & (PM_SEP | PM_XS)) && J.g.p == 2) continue;   // separable jobs use the 1-D passes
-      const int P = ipow(J.g.N, J.g.d);
-      const int tiles = (P + 64 * J.tiling.R - 1) / (64 * J.tiling.R);
-      const bool spread = work(j) > total / kQueues;
-      int home = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      for (int s = 0; s < J.tiling.S; ++s)
-        for (int t = 0; t < tiles; ++t) {
-          CtItem w{j, t, s, 0};
-          const int q = spread ? (t % kQueues) : home;
-          queues[q].push_back(w);
-          load[q] += item_cost(w);
-        }
-    }
-  }
-  // Item table: position b < G (the grid) is the item work-group b takes in
-  // the static round.  The dispatcher deals work-groups to the XCDs in turn,
-  // so positions b = q (mod kQueues) are XCD q's: they get queue q's items
-  // (largest first); surplus items of longer queues fill the positions left
-  // free by shorter ones, and what exceeds the grid forms the dynamic tail.
-  int n_all = 0;
-  const auto larger = [&](const CtItem& x, const CtItem& y) { return item_cost(x) > item_cost(y); };
-  for (int q = 0; q < kQueues; ++q) {
-    // items enter in (split, tile) order, usually already by decreasing cost
-    if (!std::is_sorted(queues[q].begin(), queues[q].end(), larger))
-      std::stable_sort(queues[q].begin(), queues[q].end(), larger);
-    n_all += (int)queues[q].size();
-  }
-  // persistent grid: one work-group per item, at most 32 per compute unit
-  const int G = std::min(n_all, ctx->num_cu * 4 * 8);
-  std::vector<CtItem> items(n_all);
-  std::vector<CtItem> surplus;
-  std::vector<int> free_pos;
-  for (int q = 0; q < kQueues; ++q) {
-    size_t used = 0;
-    for (int b = q; b < G; b += kQueues) {
-      if (used < queues[q].size()) items[b] = queues[q][used++];
-      else free_pos.push_back(b);
-    }
-    surplus.insert(surplus.end(), queues[q].begin() + used, queues[q].end());
-  }
-  if (!std::is_sorted(surplus.begin(), surplus.end(), larger))
-    std::stable_sort(surplus.begin(), surplus.end(), larger);
-  size_t si = 0;
-  for (int b : free_pos) items[b] = surplus[si++];
-  for (int b = G; b < n_all; ++b) items[b] = surplus[si++];
+  std::vector<CtItem> items;
+  const int G = build_ct_items(ctx, pl.in, mode, items);
   pl.n_items = (int)items.size();
   pl.n_ints = 2 * kQueues + NJ + 2;   // + the two phases' brute-force queue lengths
   const size_t o_ints = L.add(sizeof(int) * pl.n_ints);
@@ -1034,6 +1044,11 @@ struct qbw_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   double* pinned = nullptr;  // 2 * njobs upstream gradients
+  // completion of the last copy out of `pinned`: a run waits for it before it
+  // rewrites the staging memory, so back-to-back runs cannot change the
+  // upstream gradients of a copy that is still pending
+  hipEvent_t pinned_ev = nullptr;
+  bool pinned_busy = false;
 };
 
 extern "C" {
@@ -1082,6 +1097,7 @@ qbw_status qbw_create(qbw_ctx** ctx, int32_t device) {
   }
   int rc = qbw::launch_sqrt_table(c->sqrt_tab, qbw::kSqrtTab, nullptr);
   if (rc == QBW_OK) rc = qbw::launch_xs_squares(c->xs_sq, nullptr);
+
   if (rc == QBW_OK && hipDeviceSynchronize() != hipSuccess) {
     set_error("filling the square-root table failed");
     rc = QBW_E_HIP;
@@ -1884,12 +1900,19 @@ qbw_status qbw_batch_run(qbw_batch* B, const double* dlower, const double* duppe
   hipStream_t st = S(stream);
   const int NJ = B->plan.njobs;
   if (B->flags & QBW_BATCH_BACKWARD) {
+    if (B->pinned_busy) {
+      HIPCHK(hipEventSynchronize(B->pinned_ev));
+      B->pinned_busy = false;
+    }
     for (int j = 0; j < NJ; ++j) {
       B->pinned[j] = dlower ? dlower[j] : 1.0;
       B->pinned[NJ + j] = dupper ? dupper[j] : 1.0;
     }
     HIPCHK(hipMemcpyAsync(B->plan.dl, B->pinned, 8 * NJ, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(B->plan.du, B->pinned + NJ, 8 * NJ, hipMemcpyHostToDevice, st));
+    if (!B->pinned_ev) HIPCHK(hipEventCreateWithFlags(&B->pinned_ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(B->pinned_ev, st));
+    B->pinned_busy = true;
   }
   if (B->exec) {
     HIPCHK(hipGraphLaunch(B->exec, st));
@@ -1960,6 +1983,7 @@ void qbw_batch_destroy(qbw_batch* B) {
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+  if (B->pinned_ev) { (void)hipEventSynchronize(B->pinned_ev); (void)hipEventDestroy(B->pinned_ev); }
   if (B->pinned) (void)hipHostFree(B->pinned);
   delete B;
 }
