@@ -234,6 +234,23 @@ qbw_status qbw_upscale_potential_interp(qbw_ctx* ctx, const qbw_grid* grid, uint
 qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
                           int32_t* argmin, qbw_stream stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops that must not call hipMalloc, harnesses that forbid it): the
+ * c-transform of qbw_ctransform, the same values and arg-mins bit for bit,
+ * with every intermediate buffer (job record, work-item table, counters,
+ * winning splits, partial minima) in a static device array of 64 MiB that
+ * each GPU the library runs on holds until the process ends.  The call
+ * allocates nothing: no hipMalloc, hipHostMalloc or hipFree, and the context's
+ * own workspaces are not touched.  The caller still passes src, dst and
+ * argmin (N^d elements each, as in qbw_ctransform).  The source splits are
+ * reduced until the buffers fit; a grid that does not fit at one split (about
+ * 8.3 million pixels and up) is rejected with QBW_E_INVAL and a message.
+ * All calls on one GPU share its array and leave their contents in it: calls
+ * that overlap on one GPU (other streams or threads) race; calls on one
+ * stream are ordered.  Synchronises `stream` before returning. */
+qbw_status qbw_ctransform_noalloc(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
+                                  int32_t* argmin, qbw_stream stream);
+
 /* The same c-transform for p = 2 evaluated separably: d nested 1-D
  * c-transforms, last axis first (pass 1 subtracts src, later passes add the
  * previous result), each candidate rounded to float32 once per axis; argmin

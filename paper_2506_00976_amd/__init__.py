@@ -347,6 +347,29 @@ def ctransform(src, N: int, d: int, p: int, want_argmin: bool = False):
     return (dst, arg) if want_argmin else dst
 
 
+def ctransform_noalloc(src, N: int, d: int, p: int, dst=None, argmin=None):
+    """qbw_ctransform_noalloc: the c-transform of ``ctransform`` computed in the
+    library's static device scratch.  ``dst`` (float32) and ``argmin`` (int32,
+    optional) are caller-owned N^d buffers; ``dst`` is created here when None.
+    Returns dst, or (dst, argmin) when argmin is given."""
+    src = _sized(_dev(src, torch.float32), N ** d, "src")
+    if dst is None:
+        dst = torch.empty_like(src)
+    elif not (isinstance(dst, torch.Tensor) and dst.is_cuda and dst.dtype == torch.float32
+              and dst.is_contiguous()):
+        raise QbwError("dst must be a contiguous float32 CUDA tensor")
+    _sized(dst, N ** d, "dst")
+    if argmin is not None:
+        if not (isinstance(argmin, torch.Tensor) and argmin.is_cuda and argmin.dtype == torch.int32
+                and argmin.is_contiguous()):
+            raise QbwError("argmin must be a contiguous int32 CUDA tensor")
+        _sized(argmin, N ** d, "argmin")
+    grid = QbwGrid(d, N, 1, p)
+    check(load().qbw_ctransform_noalloc(context(src.device.index).handle, C.byref(grid), _ptr(src), _ptr(dst),
+                                        _ptr(argmin), _stream()), "qbw_ctransform_noalloc")
+    return (dst, argmin) if argmin is not None else dst
+
+
 def ctransform_separable(src, N: int, d: int, want_argmin: bool = False):
     """p = 2 c-transform as d nested 1-D transforms (qbw_ctransform_separable)."""
     src = _sized(_dev(src, torch.float32), N ** d, "src")

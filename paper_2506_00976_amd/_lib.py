@@ -72,6 +72,7 @@ SIGNATURES = [
     ("qbw_upscale_potential", C.c_int, [_vp, _pg, _vp, _vp, _vp]),
     ("qbw_upscale_potential_interp", C.c_int, [_vp, _pg, C.c_uint32, _vp, _vp, _vp]),
     ("qbw_ctransform", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
+    ("qbw_ctransform_noalloc", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
     ("qbw_ctransform_separable", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp]),
     ("qbw_ctransform_exact", C.c_int, [_vp, _pg, _vp, _vp, _vp, _vp, _vp]),
     ("qbw_ipf", C.c_int, [_vp, _pg, _vp, _vp, _pc, _po, _vp, _vp, _vp, _vp, _vp]),

@@ -168,6 +168,7 @@ struct qbw_ctx {
   int target_waves = 4096;
   float* sqrt_tab = nullptr;  // kSqrtTab entries, filled at creation, read-only after
   double* xs_sq = nullptr;    // kXsSquares entries (exact separable c-transform), likewise
+  char* scratch = nullptr;    // this device's static scratch (kScratchBytes), shared by all contexts on it
   // pinned staging for the planner's one host-to-device copy; `staged` marks
   // a copy in flight (completion recorded in `staged_ev`)
   char* stage = nullptr;
@@ -1097,7 +1098,12 @@ qbw_status qbw_create(qbw_ctx** ctx, int32_t device) {
   }
   int rc = qbw::launch_sqrt_table(c->sqrt_tab, qbw::kSqrtTab, nullptr);
   if (rc == QBW_OK) rc = qbw::launch_xs_squares(c->xs_sq, nullptr);
-
+  // the device address of the static scratch array, with `device` current
+  if (rc == QBW_OK) {
+    void* sp = nullptr;
+    rc = qbw::scratch_address(device, &sp);
+    c->scratch = (char*)sp;
+  }
   if (rc == QBW_OK && hipDeviceSynchronize() != hipSuccess) {
     set_error("filling the square-root table failed");
     rc = QBW_E_HIP;
@@ -1415,6 +1421,82 @@ qbw_status qbw_ctransform(qbw_ctx* ctx, const qbw_grid* grid, const float* src, 
   CHK(launch_ctransform(pl.djobs, pl.items, pl.n_items, pl.ints, 0, pl.ct_grid, st));
   CHK(launch_merge(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, 0, st));
   if (argmin) CHK(launch_argmin(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, 0, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return QBW_OK;
+}
+
+qbw_status qbw_ctransform_noalloc(qbw_ctx* ctx, const qbw_grid* grid, const float* src, float* dst,
+                                  int32_t* argmin, qbw_stream stream) {
+  if (!ctx || !src || !dst) { set_error("NULL argument"); return QBW_E_INVAL; }
+  CHK(check_grid(grid));
+  if (!ctx->scratch) { set_error("the context has no static scratch address"); return QBW_E_HIP; }
+  hipStream_t st = S(stream);
+  std::vector<JobIn> in{stage_job(grid, nullptr, nullptr)};
+  in[0].tiling = lookup_tiling(ctx, *grid);
+  CHK(choose_splits(in, ctx->target_waves));
+  const int N = grid->N, d = grid->d;
+  const int P = ipow(N, d), rows = ipow(N, d - 1);
+  const int R = in[0].tiling.R;
+  const int tiles = (P + 64 * R - 1) / (64 * R);
+  const int chunks = (P + kChunk - 1) / kChunk;
+  constexpr int kInts = 64;
+  // scratch layout: [job][prefix table][items][counters][winning split]
+  // [S partial-minimum rows]; the first four are written by the set-up kernel
+  struct Offs { size_t job, off, items, ints, win, part, end; };
+  auto layout = [&](int S) {
+    Layout L;
+    Offs o;
+    o.job = L.add(sizeof(DevJob));
+    o.off = L.add(sizeof(int) * 2);
+    o.items = L.add(sizeof(CtItem) * (size_t)tiles * S);
+    o.ints = L.add(sizeof(int) * kInts);
+    o.win = L.add(4 * (size_t)P);
+    o.part = L.add(4 * (size_t)P * S);
+    o.end = L.size;
+    return o;
+  };
+  // fewer source splits when the planned ones do not fit (results do not
+  // depend on the split count); whole source rows per split, as planned
+  int S = in[0].tiling.S;
+  while (S > 1 && layout(S).end > kScratchBytes) {
+    const int want = S - 1;
+    const int r = (rows + want - 1) / want;
+    S = (rows + r - 1) / r;
+  }
+  const Offs o = layout(S);
+  if (o.end > kScratchBytes) {
+    set_error("qbw_ctransform_noalloc: N^d = %d needs %zu bytes of scratch, the static scratch holds %zu "
+              "(about %zu pixels at most)", P, o.end, kScratchBytes, kScratchBytes / 8 - 64);
+    return QBW_E_INVAL;
+  }
+  const int n_items = tiles * S;
+  const int G = std::min(n_items, ctx->num_cu * 4 * 8);
+  char* B = ctx->scratch;
+  DevJob D;
+  std::memset(&D, 0, sizeof(D));
+  D.d = d; D.N = N; D.k = grid->k; D.p = grid->p;
+  D.n = N / grid->k;
+  D.P = P;
+  D.Q = ipow(D.n, d);
+  D.rows = rows;
+  D.R = R;
+  D.S = S;
+  D.chunks = chunks;
+  D.want_argmin = argmin ? 1 : 0;
+  D.fhat = const_cast<float*>(src);
+  D.g = dst;
+  D.arg_g = argmin;
+  D.part = (float*)(B + o.part);
+  D.win = (int*)(B + o.win);
+  D.sqrt_tab = (D.p == 1 && (int64_t)d * (N - 1) * (N - 1) < kSqrtTab) ? ctx->sqrt_tab : nullptr;
+  DevJob* dj = (DevJob*)(B + o.job);
+  int* doff = (int*)(B + o.off);
+  CtItem* items = (CtItem*)(B + o.items);
+  int* ints = (int*)(B + o.ints);
+  CHK(launch_noalloc_setup(D, dj, doff, items, n_items, tiles, ints, kInts, st));
+  CHK(launch_ctransform(dj, items, n_items, ints, 0, std::max(1, G), st));
+  CHK(launch_merge(dj, 1, doff, chunks, 0, st));
+  if (argmin) CHK(launch_argmin(dj, 1, doff, chunks, 0, st));
   HIPCHK(hipStreamSynchronize(st));
   return QBW_OK;
 }

@@ -9,8 +9,10 @@
 // kernel in a fixed order - repeated runs are bitwise identical.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "qbw_internal.h"
 
@@ -2970,6 +2972,63 @@ int launch_kub_backward(const KubJob& J, int T, double dupper, double* grad_a, d
   const int blocks = std::min((J.P + 255) / 256, 4096);
   hipLaunchKernelGGL(k_kub_grad_out, dim3(blocks), dim3(256), 0, st, J, dupper, grad_a, grad_b);
   HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+
+// ------------------------------------------------------------------ static scratch
+//
+// Device memory of the allocation-free c-transform entry point: one array per
+// GPU, which the GPU holds until the process ends.  On the host the name is
+// only a stand-in for the symbol: its address on a device comes from
+// hipGetSymbolAddress with that device current, taken once per device here
+// and handed to the kernels as a plain pointer.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+// Set-up of the allocation-free c-transform: the job record (passed by value),
+// its chunk prefix table, the work-item table and zeroed counters, written into
+// the static scratch by one launch, so the call needs no host-to-device copy.
+// Item b is tile b mod tiles of split b / tiles: with a multiple of eight
+// tiles that is the planner's per-XCD layout for a single job.
+__global__ __launch_bounds__(256) void k_noalloc_setup(DevJob D, DevJob* __restrict__ dj, int* __restrict__ off,
+                                                       CtItem* __restrict__ items, int n_items, int tiles,
+                                                       int* __restrict__ ints, int n_ints) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i == 0) {
+    *dj = D;
+    off[0] = 0;
+    off[1] = D.chunks;
+  }
+  if (i < n_ints) ints[i] = 0;
+  for (int b = i; b < n_items; b += gridDim.x * 256) items[b] = CtItem{0, b % tiles, b / tiles, 0};
+}
+
+int launch_noalloc_setup(const DevJob& D, DevJob* dj, int* off, CtItem* items, int n_items, int tiles, int* ints,
+                         int n_ints, void* stream) {
+  const int blocks = std::max(1, std::min((std::max(n_items, n_ints) + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_noalloc_setup, dim3(blocks), dim3(256), 0, (hipStream_t)stream, D, dj, off, items, n_items,
+                     tiles, ints, n_ints);
+  HIP_TRY(hipGetLastError());
+  return QBW_OK;
+}
+
+int scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxScratchDevices] = {};
+  if (device < 0 || device >= kMaxScratchDevices) {
+    set_error("device %d beyond the %d devices the static scratch table covers", device, kMaxScratchDevices);
+    return QBW_E_HIP;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("hipGetSymbolAddress(scratch) on device %d failed: %s", device, hipGetErrorString(e));
+      return QBW_E_HIP;
+    }
+    addr[device] = p;
+  }
+  *out = addr[device];
   return QBW_OK;
 }
 

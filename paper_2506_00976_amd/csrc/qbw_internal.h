@@ -261,4 +261,13 @@ int launch_sep_argmin(const DevJob* jobs, int njobs, const int* off, int total, 
                       void* stream);
 int launch_reset_counter(int* counter, int n, void* stream);
 
+// Static device scratch of the allocation-free c-transform (bytes per GPU) and
+// its device address on `device`, which must be the current device; the
+// address is looked up once per device and kept.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxScratchDevices = 64;
+int scratch_address(int device, void** out);
+int launch_noalloc_setup(const DevJob& D, DevJob* dj, int* off, CtItem* items, int n_items, int tiles, int* ints,
+                         int n_ints, void* stream);
+
 }  // namespace qbw

@@ -30,7 +30,7 @@ def test_short_buffers_are_refused():
     N, d = 32, 2
     short = torch.zeros(N * N - 1, dtype=torch.float32, device="cuda:0")
     for fn in (lambda: qbw.ctransform(short, N, d, 2), lambda: qbw.ctransform_separable(short, N, d),
-               lambda: qbw.ctransform_exact(short, N, d)):
+               lambda: qbw.ctransform_exact(short, N, d), lambda: qbw.ctransform_noalloc(short, N, d, 2)):
         with pytest.raises(qbw.QbwError):
             fn()
     a = torch.full((N, N), 1.0 / (N * N), dtype=torch.float64, device="cuda:0")
