@@ -461,6 +461,80 @@ def test_tv_terms_bounded_and_upper_bound_valid_when_not_converged(p):
     assert U["upper"] >= W
 
 
+def _dist_to_grid_mean(i, N, d):
+    """|x_i - x-bar| for the C-order flat index i, x-bar = ((N-1)/2, ...),
+    written out here from the index arithmetic (not through the oracle)."""
+    u = np.array(np.unravel_index(int(i), (N,) * d), dtype=np.float64)
+    return math.sqrt(float(((u - (N - 1) / 2.0) ** 2).sum()))
+
+
+@pytest.mark.parametrize("N,d", [(9, 2), (8, 2), (5, 3), (6, 3)])
+@pytest.mark.parametrize("p", [1, 2])
+def test_tv_of_two_moved_masses_closed_form(N, d, p):
+    # Equation of the weighted total variation with the weights of Algorithm 4,
+    # w_i = rho(x-bar, x_i)^p: when mu^ - mu = eps (delta_x - delta_y),
+    # TV_p^w(mu^, mu) = 2^(1-1/p) (eps (|x - x-bar|^p + |y - x-bar|^p))^(1/p).
+    # Weights without the power p, or a missing 2^(1-1/p), change the value.
+    g = si.rng(9900 + 10 * N + d + p)
+    P = N ** d
+    w = upper.tv_weights(N, d, p)
+    for _ in range(6):
+        i, j = (int(t) for t in g.choice(P, 2, replace=False))
+        base = np.floor(g.random(P) * 2 ** 20) / 2 ** 20       # dyadic: the differences below are exact
+        eps = float(g.integers(1, 2 ** 20)) / 2 ** 30
+        mu_hat = base.copy()
+        mu_hat[i] += eps
+        mu_hat[j] -= eps
+        ri, rj = _dist_to_grid_mean(i, N, d), _dist_to_grid_mean(j, N, d)
+        ref = 2.0 ** (1 - 1 / p) * (eps * (ri ** p + rj ** p)) ** (1 / p)
+        assert upper.weighted_tv(w, mu_hat, base, p) == pytest.approx(ref, rel=1e-13, abs=0)
+        assert upper.weighted_tv(w, base, mu_hat, p) == pytest.approx(ref, rel=1e-13, abs=0)
+
+
+@pytest.mark.parametrize("N,d", [(7, 2), (5, 3)])
+@pytest.mark.parametrize("p", [1, 2])
+def test_tv_is_tight_for_diracs_opposite_about_the_grid_mean(N, d, p):
+    # Odd N puts x-bar on a pixel.  For y and z = 2 x-bar - y,
+    # W_p(delta_y, delta_z) = |y - z| = 2 r and TV_p^w = 2^(1-1/p) (r^p + r^p)^(1/p)
+    # = 2 r: the bound W_p <= TV_p^w holds with equality (exact LP on the full
+    # grid), which fixes both the power p in the weights and 2^(1-1/p).  For a
+    # Dirac at x-bar itself TV_p^w(delta_x, delta_x-bar) = 2^(1-1/p) |x - x-bar|.
+    P = N ** d
+    g = si.rng(9950 + N + d + p)
+    w = upper.tv_weights(N, d, p)
+    c = (N - 1) // 2
+    for _ in range(3):
+        y = g.integers(0, N, size=d)
+        if np.all(y == c):
+            y[0] = 0
+        z = 2 * c - y
+        iy, iz = np.ravel_multi_index(tuple(y), (N,) * d), np.ravel_multi_index(tuple(z), (N,) * d)
+        my, mz = np.zeros(P), np.zeros(P)
+        my[iy] = 1.0
+        mz[iz] = 1.0
+        r = _dist_to_grid_mean(iy, N, d)
+        W = lp.wasserstein_exact(my.reshape((N,) * d), mz.reshape((N,) * d), p)
+        tv = upper.weighted_tv(w, my, mz, p)
+        assert W == pytest.approx(2 * r, rel=1e-12)
+        assert tv == pytest.approx(2 * r, rel=1e-12)
+        mc = np.zeros(P)
+        mc[np.ravel_multi_index((c,) * d, (N,) * d)] = 1.0
+        assert upper.weighted_tv(w, my, mc, p) == pytest.approx(2.0 ** (1 - 1 / p) * r, rel=1e-12)
+
+
+@pytest.mark.parametrize("N,d", [(8, 2), (4, 3)])
+@pytest.mark.parametrize("p", [1, 2])
+def test_wasserstein_below_weighted_tv_by_exact_lp(N, d, p):
+    # The property behind the equation of the weighted total variation:
+    # W_p(mu, nu) <= TV_p^w(mu, nu) for any pair, here by the exact LP.
+    w = upper.tv_weights(N, d, p)
+    for s, (fa, fb) in enumerate([("grf", "gmm"), ("white_noise", "cauchy"), ("shapes", "grf")]):
+        mu, nu = pair(N, d, fa, fb, 9970 + 10 * s + d + p)
+        W = lp.wasserstein_exact(mu, nu, p)
+        tv = upper.weighted_tv(w, mu.reshape(-1), nu.reshape(-1), p)
+        assert W <= tv * (1 + 1e-12)
+
+
 def test_ordering_of_the_four_bounds():
     N, d, k, p = 16, 2, 4, 2
     mu, nu = pair(N, d, "gmm", "gmm", 120)
