@@ -72,8 +72,22 @@ def plan_kernel_gaussian(k: int, d: int, sigma: float) -> np.ndarray:
     return w / w.sum()
 
 
+# x86 extended precision (64-bit significand) for the sums of the fitting
+# passes; the oracle refuses to run where numpy's long double is narrower.
+_EXT = np.longdouble
+assert np.finfo(_EXT).nmant >= 63, "the oracle needs an 80-bit long double for its IPF sums"
+
+
 def _matvec(I, J, V, x, n):
-    return np.bincount(I, weights=V * x[J], minlength=n)
+    """(pi^ x)_i = sum over the entries (i, j) of pi^_ij x_j.  Each product is
+    rounded to float64; the products are added in extended precision and the
+    sum rounded once to float64, so each entry is within about one float64
+    rounding of the exact sum of the rounded products, whatever the number of
+    terms (up to k^d times a row's coupling entries): the fitted marginals of
+    Algorithm 4 then carry only the roundings of the scalings themselves."""
+    acc = np.zeros(n, dtype=_EXT)
+    np.add.at(acc, I, (V * x[J]).astype(_EXT))
+    return acc.astype(np.float64)
 
 
 def _safe_div(x, y):
