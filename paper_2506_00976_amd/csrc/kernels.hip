@@ -1703,6 +1703,48 @@ __global__ __launch_bounds__(256) void k_pc1_sum(const DevJob* __restrict__ jobs
 
 // ------------------------------------------------------------------ finalize
 
+// gamma(n) = n u / (1 - n u), u = 2^-53: a float64 evaluation n roundings deep
+// (a sum of nonnegative terms along any tree of that height, a chain of
+// products and quotients) is within a relative gamma(n) of its exact value.
+__device__ __forceinline__ double gam(double n) {
+  const double t = n * 1.1102230246251565e-16;
+  return t / (1.0 - t);
+}
+
+__device__ __forceinline__ int ilog2(int g) {
+  int l = 0;
+  while ((1 << l) < g) ++l;
+  return l;
+}
+
+// Outward allowances of the emitted upper bound.  The lemma on the triangle
+// inequality upper bound holds for the coupling the kernels formed, diag(a_s)
+// pi^ diag(b_s) with the float64 scalings as computed, so the emitted value must
+// dominate that coupling's exact plan cost and the exact weighted TV of its
+// exact marginals; it also dominates the exact-arithmetic value of Algorithm 4
+// on the same inputs and any float64 evaluation of it whose sums stay within
+// about one rounding of exact (such an evaluation's fitted marginals carry at
+// most 14 T u of relative error after T iterations).  With r, c the longest
+// row and column of the coarse coupling and s_p the depth of the pooled block
+// sums, each fitting step of the coarse iteration (row sum, pooled-mass
+// quotient, column sum, pooled-mass quotient) adds at most
+//   D = gamma(r+1) + gamma(c+1) + 2 gamma(s_p) + 4u
+// of relative error to the iterates against exact arithmetic, starting from
+// gamma(r+1) + u, so the fitted mu^ = a_s (pi^ b_s) is within
+//   e_G = 2 (gamma(r+1) + u) + (2T - 1) D + 2u
+// of the exact iterate's, and within gamma(r+1) + gamma(s_p) + 4u <= e_G of the
+// exact marginal of the formed coupling; nu^ is within
+//   e_nu = gamma(c+1) + gamma(s_p) + 4u
+// of nu on both counts (the column update fits nu exactly in exact
+// arithmetic).  A weighted TV sum T computed over pixels n_s additions deep
+// then satisfies T_exact <= Z + e (W + Z) / (1 - e_G), with Z = T (1 +
+// gamma(n_s + 3)), W = <w, mu> (1 + gamma(n_s + 2)) and e = e_G + 14 T u (resp.
+// e_nu).  The plan cost: p = 2 sums block moments, each entry within
+// (2 gamma(k^d + 3) + gamma(16)) M_e of exact, M_e = A0 B0 (|D_KL| + 2 rho)^2
+// bounding the absolute values of its terms (rho the largest offset of a pixel
+// from its block centre); p = 1 sums nonnegative terms (gamma(k^2d + nnz + 8)
+// plus 2^-41 for the refined square roots).  Both are then widened by the
+// scalings' e_G + 14 T u.
 __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ jobs, int njobs) {
   __shared__ double sh[256];
   const DevJob& J = jobs[blockIdx.x];
@@ -1715,10 +1757,27 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
     mh = fmax(mh, r[2]); mg = fmax(mg, r[3]); mf = fmax(mf, r[4]);
   }
   // upper bound
-  const double kd = J.d == 2 ? (double)J.k * J.k : (double)J.k * J.k * J.k;
+  const int kdi = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
+  const double kd = (double)kdi;
   const double cc = 1.0 / (kd * kd);
-  double pc = 0;
-  for (int e = threadIdx.x; e < J.nnz; e += 256) pc += cc * J.e_val[e] * J.red_pc[e];
+  const double rho2 = sqrt((double)J.d) * (double)(J.k - 1);   // twice the largest in-block offset
+  double pc = 0, mm = 0;
+  for (int e = threadIdx.x; e < J.nnz; e += 256) {
+    pc += cc * J.e_val[e] * J.red_pc[e];
+    if (J.p == 2) {
+      const int K = J.e_row[e], L = J.e_col[e];
+      double D0, D1, D2;
+      block_delta(K, L, J, D0, D1, D2);
+      const double dn = sqrt(D0 * D0 + D1 * D1 + D2 * D2) + rho2;
+      mm += cc * J.e_val[e] * (J.mom_as[5 * (size_t)K] * J.mom_bs[5 * (size_t)L]) * (dn * dn);
+    }
+  }
+  double rmax = 0, cmax = 0;
+  if (J.nnz > 0)
+    for (int K = threadIdx.x; K < J.Q; K += 256) {
+      rmax = fmax(rmax, (double)(J.csr_ptr[K + 1] - J.csr_ptr[K]));
+      cmax = fmax(cmax, (double)(J.csc_ptr[K + 1] - J.csc_ptr[K]));
+    }
   double tm = 0, tn = 0, wm = 0, wn = 0;
   for (int c = threadIdx.x; c < J.chunks; c += 256) {
     const double* r = J.red_tv + (size_t)c * kRedSlotsTV;
@@ -1726,14 +1785,13 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   }
   // all sums and maxima in one work-group reduction
   {
-    double sv[7] = {sf, sg, pc, tm, tn, wm, wn};
-    double mv[3] = {mh, mg, mf};
-    block_reduce_many<7, 3>(sv, mv, sh);
-    sf = sv[0]; sg = sv[1]; pc = sv[2]; tm = sv[3]; tn = sv[4]; wm = sv[5]; wn = sv[6];
-    mh = mv[0]; mg = mv[1]; mf = mv[2];
+    double sv[8] = {sf, sg, pc, tm, tn, wm, wn, mm};
+    double mv[5] = {mh, mg, mf, rmax, cmax};
+    block_reduce_many<8, 5>(sv, mv, sh);
+    sf = sv[0]; sg = sv[1]; pc = sv[2]; tm = sv[3]; tn = sv[4]; wm = sv[5]; wn = sv[6]; mm = sv[7];
+    mh = mv[0]; mg = mv[1]; mf = mv[2]; rmax = mv[3]; cmax = mv[4];
   }
   if (threadIdx.x != 0) return;
-  const double p = J.p;
   // float32 feasibility shift (first order in u = 2^-24; see the oracle's derivation)
   const double u = 5.9604644775390625e-08;
   const double up = J.p == 1 ? u : 0.0;
@@ -1755,17 +1813,34 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   double lower = 0.0;
   if (Se > 0.0) lower = J.p == 2 ? sqrt(Se) : Se;
   else warn |= QBW_WARN_LB_CLIPPED;
-  // upper bound with outward rounding allowances: relative 2^-40 on the plan
-  // cost (p = 1: plus (k^2d + nnz) 2^-52, the linear bound for the float64 sums
-  // of nonnegative terms, which also covers the 2^-42 of the refined square
-  // roots), absolute 2^-40 <w, mu> (resp. nu) on each TV sum
-  const double rel = 9.094947017729282e-13 + (J.p == 1 ? (kd * kd + J.nnz) * 2.220446049250313e-16 : 0.0);
-  const double pe = pc * (1.0 + rel);
-  const double c1 = J.p == 2 ? 1.4142135623730951 : 1.0;
+  // upper bound with the outward allowances derived above
+  const double u53 = 1.1102230246251565e-16;
+  const double T = fmax(1.0, res[RS_IPF_ITERS]);
+  const int gp = reduce_group(kdi);
+  const double s_pool = (double)((kdi + gp - 1) / gp - 1 + ilog2(gp));
+  const double n_s = 4 + 6 + 3 + (J.chunks + 255) / 256 + 9;   // pixel sums: thread, wave, work-group, chunks
+  const double n_e = (J.nnz + 255) / 256 + 9;                   // entry sums
+  const double a1 = gam(rmax + 1) + u53;
+  const double Dg = gam(rmax + 1) + gam(cmax + 1) + 2.0 * gam(s_pool) + 4.0 * u53;
+  const double eG = 2.0 * a1 + (2.0 * T - 1.0) * Dg + 2.0 * u53;
+  const double eO = 14.0 * T * u53;
+  const double emu = (eG + eO) * (1.0 + 0x1p-40);
+  const double enu = (gam(cmax + 1) + gam(s_pool) + 4.0 * u53) * (1.0 + 0x1p-40);
+  const double Zm = tm * (1.0 + gam(n_s + 3)), Zn = tn * (1.0 + gam(n_s + 3));
+  const double Wm = wm * (1.0 + gam(n_s + 2)), Wn = wn * (1.0 + gam(n_s + 2));
+  const double Tm = (Zm + emu * (Wm + Zm) / (1.0 - eG)) * (1.0 + 8.0 * u53);
+  const double Tn = (Zn + enu * (Wn + Zn) / (1.0 - enu)) * (1.0 + 8.0 * u53);
+  double Pv;
+  if (J.p == 2)
+    Pv = pc + (2.0 * gam(kd + 3) + gam(16) + 2.0 * gam(n_e + 4)) * mm * (1.0 + gam(n_e + 8));
+  else
+    Pv = pc * (1.0 + gam(kd * kd + J.nnz + 8) + 0x1p-41);
+  const double pe = Pv * (1.0 + eG + eO + 6.0 * u53) * (1.0 + 4.0 * u53);
+  const double c1 = J.p == 2 ? 1.4142135623730951 : 1.0;   // RN(sqrt 2) > sqrt 2
   auto root = [&](double x) { return J.p == 2 ? sqrt(x) : x; };
-  const double tvm = c1 * root(tm + 9.094947017729282e-13 * wm);
-  const double tvn = c1 * root(tn + 9.094947017729282e-13 * wn);
-  const double upper = root(pe) + tvm + tvn;
+  const double tvm = c1 * root(Tm) * (1.0 + 2.0 * u53);
+  const double tvn = c1 * root(Tn) * (1.0 + 2.0 * u53);
+  const double upper = (root(pe) * (1.0 + u53) + tvm + tvn) * (1.0 + 2.0 * u53);
   res[RS_LOWER] = lower;
   res[RS_UPPER] = upper;
   res[RS_LOWER_S] = Se;
@@ -1786,7 +1861,6 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   res[RS_MW_NU] = wn;
   res[RS_TV_RAW_MU] = c1 * root(tm);
   res[RS_TV_RAW_NU] = c1 * root(tn);
-  (void)p;
 }
 
 // ------------------------------------------------------------------ C-bar (Section 3.2)
@@ -2542,10 +2616,17 @@ __global__ __launch_bounds__(256) void k_kub_tv(KubJob J) {
   }
 }
 
-// The bound with outward rounding allowances: relative 2^-40 + (m^2 + nnz) 2^-52
-// on the plan cost (the linear bound for float64 sums of m^2 nonnegative
-// terms per entry and nnz entries, with room for the square roots of p = 1),
-// absolute 2^-40 <w, mu> (resp. nu) on each TV sum.
+// The bound with outward allowances derived as for the uniform kernel (see
+// k_finalize), for fitting on fine vectors: a row pass forms, per pixel, the
+// pi~-weighted sum of r entries' blocks (gamma(r+1)) and its product with a
+// kernel row of m nonnegative weights (gamma(m+2)); a column pass likewise with
+// c entries.  Each iteration then adds D = gamma(r+1) + gamma(c+1) +
+// 2 gamma(m+2) + 2u to the iterates' relative error against exact arithmetic,
+// from gamma(r+1) + gamma(m+2) at the first row pass, so the fitted
+// mu^ is within e_G = 2 (gamma(r+1) + gamma(m+2)) + (2T - 1) D + 2u and nu^ within
+// e_nu = gamma(c+1) + gamma(m+2) + 4u.  The plan cost sums nonnegative terms
+// m + cpb + ceil(nnz/256) + 24 additions deep (plus 2^-41 for p = 1's roots),
+// widened by the scalings' e_G + 14 T u.
 __global__ __launch_bounds__(256) void k_kub_finalize(KubJob J) {
   __shared__ double sh[256];
   double pc = 0.0;
@@ -2554,26 +2635,46 @@ __global__ __launch_bounds__(256) void k_kub_finalize(KubJob J) {
     for (int c = 0; c < J.cpb; ++c) s += J.pc_part[(size_t)e * J.cpb + c];
     pc += J.e_val[e] * s;
   }
+  double rmax = 0, cmax = 0;
+  if (J.nnz > 0)
+    for (int K = threadIdx.x; K < J.Q; K += 256) {
+      rmax = fmax(rmax, (double)(J.csr_ptr[K + 1] - J.csr_ptr[K]));
+      cmax = fmax(cmax, (double)(J.csc_ptr[K + 1] - J.csc_ptr[K]));
+    }
   double tm = 0.0, tn = 0.0, wm = 0.0, wn = 0.0;
   for (int c = threadIdx.x; c < J.chunks; c += 256) {
     const double* r = J.red_tv + (size_t)c * kRedSlotsTV;
     tm += r[0]; tn += r[1]; wm += r[2]; wn += r[3];
   }
   {
-    double sv[5] = {pc, tm, tn, wm, wn}, mv[1] = {0.0};
-    block_reduce_many<5, 1>(sv, mv, sh);
+    double sv[5] = {pc, tm, tn, wm, wn}, mv[2] = {rmax, cmax};
+    block_reduce_many<5, 2>(sv, mv, sh);
     pc = sv[0]; tm = sv[1]; tn = sv[2]; wm = sv[3]; wn = sv[4];
+    rmax = mv[0]; cmax = mv[1];
   }
   if (threadIdx.x != 0) return;
-  const double mm = (double)J.m * J.m;
-  const double rel = 9.094947017729282e-13 + (mm + J.nnz) * 2.220446049250313e-16;
-  const double pe = pc * (1.0 + rel);
+  double* res = J.result;
+  const double u53 = 1.1102230246251565e-16;
+  const double T = fmax(1.0, res[RS_IPF_ITERS]);
+  const double m = (double)J.m;
+  const double n_s = 4 + 9 + (J.chunks + 255) / 256 + 9;
+  const double a1 = gam(rmax + 1) + gam(m + 2);
+  const double Dg = gam(rmax + 1) + gam(cmax + 1) + 2.0 * gam(m + 2) + 2.0 * u53;
+  const double eG = 2.0 * a1 + (2.0 * T - 1.0) * Dg + 2.0 * u53;
+  const double eO = 14.0 * T * u53;
+  const double emu = (eG + eO) * (1.0 + 0x1p-40);
+  const double enu = (gam(cmax + 1) + gam(m + 2) + 4.0 * u53) * (1.0 + 0x1p-40);
+  const double Zm = tm * (1.0 + gam(n_s + 3)), Zn = tn * (1.0 + gam(n_s + 3));
+  const double Wm = wm * (1.0 + gam(n_s + 2)), Wn = wn * (1.0 + gam(n_s + 2));
+  const double Tm = (Zm + emu * (Wm + Zm) / (1.0 - eG)) * (1.0 + 8.0 * u53);
+  const double Tn = (Zn + enu * (Wn + Zn) / (1.0 - enu)) * (1.0 + 8.0 * u53);
+  const double Pv = pc * (1.0 + gam(m + J.cpb + (J.nnz + 255) / 256 + 24) + (J.p == 1 ? 0x1p-41 : 0.0));
+  const double pe = Pv * (1.0 + eG + eO + 6.0 * u53) * (1.0 + 4.0 * u53);
   const double c1 = J.p == 2 ? 1.4142135623730951 : 1.0;
   auto root = [&](double x) { return J.p == 2 ? sqrt(x) : x; };
-  const double tvm = c1 * root(tm + 9.094947017729282e-13 * wm);
-  const double tvn = c1 * root(tn + 9.094947017729282e-13 * wn);
-  double* res = J.result;
-  res[RS_UPPER] = root(pe) + tvm + tvn;
+  const double tvm = c1 * root(Tm) * (1.0 + 2.0 * u53);
+  const double tvn = c1 * root(Tn) * (1.0 + 2.0 * u53);
+  res[RS_UPPER] = (root(pe) * (1.0 + u53) + tvm + tvn) * (1.0 + 2.0 * u53);
   res[RS_UPPER_COST] = pe;
   res[RS_TV_MU] = tvm;
   res[RS_TV_NU] = tvn;

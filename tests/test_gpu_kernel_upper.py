@@ -36,11 +36,22 @@ def dev(x):
     return torch.tensor(np.ascontiguousarray(x), device="cuda:0")
 
 
-def ub_tol(mu, nu, N, d, p, ub):
+def ub_tol(mu, nu, N, d, p, k, ub, rows, cols, iters):
+    """Room above the oracle's upper bound with a coupling kernel: inside each
+    weighted-TV term the library adds e u (<w, mu> + T), e bounding the fitted
+    marginals' relative error after `iters` fine-vector iterations (coupling
+    rows of r entries, columns of c, kernel rows of m = k^d weights) plus a
+    float64 reference's (14 T); allowed here: twice that inside the root, on
+    top of 1e-9 relative for the float64 sums."""
     w = upper.tv_weights(N, d, p)
     Mw = max(float(w @ mu.reshape(-1)), float(w @ nu.reshape(-1)))
+    r = int(np.bincount(np.asarray(rows)).max())
+    c = int(np.bincount(np.asarray(cols)).max())
+    m = k ** d
+    T = max(1, int(iters))
+    e = 2 * (r + m + 3) + (2 * T - 1) * (r + c + 2 * m + 8) + 2 + 14 * T
     c1 = 2.0 ** (1 - 1 / p)
-    return 1e-9 * ub + 2 * 2 * c1 * (2.0 ** -39 * Mw) ** (1 / p)
+    return 1e-9 * ub + 2 * c1 * (2 * e * 2.0 ** -53 * Mw) ** (1 / p)
 
 
 def make_kernel(kind, k, d, seed):
@@ -75,7 +86,7 @@ def check_against_oracle(mu, nu, k, p, K, max_iter, xi=1e-12):
     assert np.abs(b_s - U["b"]).max() <= 1e-9 * sb
     assert res["upper_cost"] >= U["plan_cost"]
     assert res["upper_cost"] == pytest.approx(U["plan_cost"], rel=1e-9)
-    assert U["upper"] <= res["upper"] <= U["upper"] + ub_tol(mu, nu, N, d, p, U["upper"])
+    assert U["upper"] <= res["upper"] <= U["upper"] + ub_tol(mu, nu, N, d, p, k, U["upper"], r, c, U["iters"])
     assert res["lower"] == 0.0
     return res, U
 
@@ -124,7 +135,12 @@ def test_uniform_kernel_equals_the_built_in_upper_bound(p):
     assert res["ipf_iters"] == 1
     r, c, v, ft, gt, obj = upper.coarse_record_lp(mu, nu, k, p)
     base = qbw.bounds(dev(mu), dev(nu), k, p, coarse=qbw.Coarse(r, c, v, ft, gt, obj))
-    assert res["upper"] == pytest.approx(base["upper"], rel=1e-9)
+    # the same fitted plan; the two paths' rounding allowances differ (fine
+    # vectors and kernel rows here, coarse vectors and pooled sums there), so
+    # the emitted bounds agree to within the larger allowance
+    assert res["upper_cost"] == pytest.approx(base["upper_cost"], rel=1e-9)
+    assert base["upper"] >= U["upper"]
+    assert abs(res["upper"] - base["upper"]) <= ub_tol(mu, nu, N, d, p, k, U["upper"], r, c, 1)
 
 
 def _permuted_translation(N, d, k, shift_blocks, g):
