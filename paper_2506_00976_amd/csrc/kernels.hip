@@ -737,6 +737,42 @@ __global__ __launch_bounds__(256) void k_xs_squares(double* __restrict__ t) {
 }
 
 typedef const __attribute__((address_space(4))) double* const_dptr;
+typedef const __attribute__((address_space(1))) double* gdptr;
+
+// min of two doubles with quiet NaN operands ignored (IEEE mode), as one
+// v_min_f64: the asm keeps the compiler from re-canonicalising the
+// loop-carried minima (a max of each with itself) at every unrolled block.
+__device__ __forceinline__ double vmin_f64(double a, double b) {
+  double r;
+  __asm__("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// Value-only stage candidates for one block of T sources r0 .. r0+T-1 and the
+// lane's T targets t0 .. t0+T-1: h + (r - t0 - t)^2.  The squares of the T
+// offsets a - t a source meets (a = r - t0) sit in a window of T registers;
+// from one source to the next the window moves by one offset, so each step
+// writes one new square, (a)^2 = (a-1)^2 + (2a-1), exact in float64, into the
+// slot the last step's target T-1 no longer needs, and the slots' roles
+// rotate through the unrolled block (target t at step j reads slot
+// (t - j) mod T).  Every candidate is then one all-VGPR add and one min.
+// On entry W[1] holds (r0 - t0 - 1)^2 and W[q] = (r0 - t0 - q)^2 for q >= 1;
+// inc = 2 (r0 - t0) - 1.  H(j) gives the line's value at source r0 + j.
+template <int T, typename H>
+__device__ __forceinline__ void xs_window_block(double (&m1)[T], double (&W)[T], double& inc, H&& hval) {
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const int s = (T - j) % T, sp = (T - j + 1) % T;
+    W[s] = W[sp] + inc;
+    inc += 2.0;
+    const double h = hval(j);
+#pragma unroll
+    for (int t = 0; t < T; ++t) m1[t] = vmin_f64(m1[t], h + W[(t - j + T) % T]);
+    // one step at a time: without this the scheduler pulls later steps'
+    // work (and so the waits for their sources' loads) up into this one
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
 
 // One item of stage k: 64 lines x T targets along the axis.  `tile` is the
 // work-group's LDS staging area of the first stage (64 x 17 floats).  ARG:
@@ -783,6 +819,17 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
         m1[t] = fmin(m1[t], w);
       }
     };
+    // value-only: squares from a rotating register window (all-VGPR adds)
+    // over whole blocks of kXsT sources; the last N mod kXsT sources take
+    // them from the table
+    double W[kXsT];
+    double inc = 2.0 * (double)(-t0) - 1.0;
+    if constexpr (!ARG) {
+#pragma unroll
+      for (int q = 1; q < kXsT; ++q) W[q] = (double)(-t0 - q) * (double)(-t0 - q);
+      W[0] = 0.0;
+    }
+    const int NB = ARG ? 0 : N - N % kXsT;   // sources in whole window blocks
     if (FIRST) {
       // the lines are rows (stride 1): tiles of 64 rows x 16 columns are read
       // coalesced (the next tile while the current one is in use) into LDS,
@@ -792,11 +839,16 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
       const int row0 = chunk * 64;
       const int sub = lane / TC, cl = lane % TC;   // 4 rows of 16 columns per load
       float nx[64 / 4];
+      // a wave-uniform base per group of four rows plus the lane's 32-bit
+      // offset inside the group: the loads take the scalar-base form and no
+      // per-row 64-bit addresses stay live across the tiles
+      const unsigned loff = (unsigned)(sub * N + cl);
       auto fetch = [&](int rb) {
 #pragma unroll
         for (int i = 0; i < 64 / 4; ++i) {
           const int row = row0 + 4 * i + sub, col = rb + cl;
-          nx[i] = (row < lines && col < N) ? src[row * N + col] : 0.0f;
+          const float* ub = src + ((size_t)(row0 + 4 * i) * N + rb);
+          nx[i] = (row < lines && col < N) ? ub[loff] : 0.0f;
         }
       };
       fetch(0);
@@ -807,11 +859,67 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
         for (int i = 0; i < 64 / 4; ++i) tile[(4 * i + sub) * (TC + 1) + cl] = nx[i];
         __syncthreads();
         if (rb + TC < N) fetch(rb + TC);
-        // unrolled so that the loop-carried minima are re-canonicalised (a
-        // max with itself, for min/max in IEEE mode) once per four steps
+        if constexpr (!ARG) {
+          static_assert(TC % kXsT == 0, "window blocks must tile the LDS tile");
+          int j0 = 0;
+          for (; j0 + kXsT <= nc && rb + j0 + kXsT <= NB; j0 += kXsT) {
+            // the block's sources read from LDS up front (one wait, not one per step)
+            const float* row = tile + lane * (TC + 1) + j0;
+            float hv[kXsT];
+#pragma unroll
+            for (int j = 0; j < kXsT; ++j) hv[j] = row[j];
+            xs_window_block<kXsT>(m1, W, inc, [&](int j) { return -(double)hv[j]; });
+          }
+          for (int j = j0; j < nc; ++j) step(-(double)tile[lane * (TC + 1) + j], rb + j);
+        } else {
+          // unrolled so that the loop-carried minima are re-canonicalised (a
+          // max with itself, for min/max in IEEE mode) once per four steps
 #pragma unroll 4
-        for (int j = 0; j < nc; ++j) step(-(double)tile[lane * (TC + 1) + j], rb + j);
+          for (int j = 0; j < nc; ++j) step(-(double)tile[lane * (TC + 1) + j], rb + j);
+        }
       }
+    } else if constexpr (!ARG) {
+      // whole window blocks; each source is loaded four steps before its use
+      // into a ring of eight (a block of 8 or 16 sources starts at a multiple
+      // of 8, so the ring slots are fixed), or for 2 and 4 targets per lane a
+      // block's sources while the previous block is in use
+      if constexpr (kXsT >= 8) {
+        // global loads from a wave-uniform base (the source's row of lines)
+        // plus the lane's 32-bit offset: no per-load address arithmetic
+        const gdptr vg = (gdptr)v1in;
+        const unsigned lob = (unsigned)base * 8u;   // the lane's byte offset
+        auto at = [&](int r) {
+          return *(gdptr)((const __attribute__((address_space(1))) char*)(vg + (size_t)r * st) + lob);
+        };
+        double hb[8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) hb[u] = u < NB ? at(u) : 0.0;
+        for (int r0 = 0; r0 < NB; r0 += kXsT) {
+          xs_window_block<kXsT>(m1, W, inc, [&](int j) {
+            // past the last whole block the load repeats a valid source and
+            // goes unused (no branch inside the unrolled block)
+            const int ra = min(r0 + j + 4, NB - 1);
+            hb[(j + 4) & 7] = at(ra);
+            return hb[j & 7];
+          });
+        }
+      } else {
+        double hc[kXsT], hn[kXsT];
+        if (NB > 0) {
+#pragma unroll
+          for (int u = 0; u < kXsT; ++u) hn[u] = v1in[base + u * st];
+        }
+        for (int r0 = 0; r0 < NB; r0 += kXsT) {
+#pragma unroll
+          for (int u = 0; u < kXsT; ++u) hc[u] = hn[u];
+          if (r0 + kXsT < NB) {
+#pragma unroll
+            for (int u = 0; u < kXsT; ++u) hn[u] = v1in[base + (r0 + kXsT + u) * st];
+          }
+          xs_window_block<kXsT>(m1, W, inc, [&](int j) { return hc[j]; });
+        }
+      }
+      for (int r = NB; r < N; ++r) step(v1in[base + r * st], r);
     } else {
       // four sources per round, the next four loaded while these are used
       const int N4 = N & ~3;
@@ -899,6 +1007,7 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
 // so that a launch still has enough waves per SIMD (16 only without arg-mins,
 // where a target holds one running minimum).
 template <bool FIRST>
+__attribute__((amdgpu_waves_per_eu(4)))
 __global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
                                                  const int* __restrict__ off, int total, int phase, int k,
                                                  const double* __restrict__ sqt, int2* __restrict__ list,
