@@ -955,7 +955,11 @@ static int solve_coarse_host(const qbw_grid& g, const std::vector<double>& mt, c
   std::vector<double> C((size_t)Q * Q);
   centre_cost(g, C.data());
   CoarseProblem P{Q, mt.data(), nt.data(), C.data(), g.p == 2};
-  int rc = coarse_solve(P, sol);
+  // multiscale start by default; QBW_COARSE_SOLVER=dense prices every block
+  // pair from the first pivot (the same optimum either way)
+  const char* e = std::getenv("QBW_COARSE_SOLVER");
+  const bool dense = e && std::strcmp(e, "dense") == 0;
+  int rc = dense ? coarse_solve(P, sol) : coarse_solve_multiscale(P, g.N / g.k, g.d, g.p, sol);
   if (rc != QBW_OK) set_error("coarse network simplex failed (Q=%d)", Q);
   return rc;
 }

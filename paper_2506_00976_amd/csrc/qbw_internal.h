@@ -24,9 +24,16 @@ struct CoarseSolution {
   std::vector<double> vals, f, g;
   double objective = 0;
   int64_t pivots = 0;
+  int rounds = 0;          // pricing rounds of a multiscale solve (candidates, then checks of every pair)
 };
 
 int coarse_solve(const CoarseProblem& P, CoarseSolution* out);
+// The same optimum from a multiscale start: P's blocks form an n^d grid (C
+// order); its half-resolution problem is solved first and its support's
+// children are priced first.  Below kMultiscaleMinQ blocks, or for odd n,
+// the plain solve.
+constexpr int kMultiscaleMinQ = 256;
+int coarse_solve_multiscale(const CoarseProblem& P, int n, int d, int p, CoarseSolution* out);
 void centre_cost(const qbw_grid& g, double* out);  // C~, host
 void set_error(const char* fmt, ...);
 

@@ -293,14 +293,78 @@ struct TransportSimplex {
       pivot(e);
     }
   }
+
+  // Pricing over a candidate subset of the arcs (source k, sink l), cyclic
+  // blocks of about sqrt(size) candidates, most negative reduced cost of the
+  // first block that has one (first in scan order on ties).
+  std::vector<int> ck, cl;
+  size_t next_cand = 0;
+  int64_t find_entering_sparse(Cost eps) {
+    const size_t A = ck.size();
+    if (!A) return -1;
+    const size_t block = std::max<size_t>(64, (size_t)std::sqrt((double)A));
+    size_t pos = next_cand % A;
+    for (size_t scanned = 0; scanned < A;) {
+      const size_t len = std::min(block, A - scanned);
+      Cost best = -eps;
+      int64_t barc = -1;
+      for (size_t q = 0; q < len; ++q) {
+        const int k = ck[pos], l = cl[pos];
+        const int64_t a = (int64_t)k * m + l;
+        const Cost r = Cost(c[a]) + pi[k] - pi[n + l];
+        if (r < best) { best = r; barc = a; }
+        if (++pos == A) pos = 0;
+      }
+      scanned += len;
+      if (barc >= 0) { next_cand = pos; return barc; }
+    }
+    return -1;
+  }
+
+  // Arcs of the whole dense set with a reduced cost below -eps, appended to
+  // the candidates; returns how many.
+  int64_t add_violators(Cost eps) {
+    const Cost* pl = pi.data() + n;
+    int64_t added = 0;
+    for (int k = 0; k < n; ++k) {
+      const Stored* cr = c + (int64_t)k * m;
+      const Cost pk = pi[k];
+      if (!(row_min(cr, pk, pl, m) < -eps)) continue;
+      for (int l = 0; l < m; ++l)
+        if (Cost(cr[l]) + pk - pl[l] < -eps) { ck.push_back(k); cl.push_back(l); ++added; }
+    }
+    return added;
+  }
+
+  // Optimal on the candidate arcs, then checked against every arc: arcs with
+  // a negative reduced cost join the candidates and pivoting continues from
+  // the current tree, until no arc of the dense set prices out (the basis is
+  // then optimal for the whole problem, whatever the first candidates were).
+  bool solve_sparse(int64_t max_pivots, Cost eps, int* rounds) {
+    init();
+    for (*rounds = 1;; ++*rounds) {
+      for (;;) {
+        const int64_t e = find_entering_sparse(eps);
+        if (e < 0) break;
+        if (pivots >= max_pivots) return false;
+        pivot(e);
+      }
+      if (add_violators(eps) == 0) return true;
+    }
+  }
 };
 
 template <typename Cost, typename Stored = Cost>
 int solve_typed(int n, int m, const Stored* cost, const double* a, const double* b,
                 const std::vector<int>& src_ids, const std::vector<int>& dst_ids,
-                CoarseSolution* out, Cost eps) {
+                CoarseSolution* out, Cost eps, const std::vector<std::pair<int, int>>* cand = nullptr) {
   TransportSimplex<Cost, Stored> S;
   S.n = n; S.m = m; S.c = cost;
+  if (cand) {
+    S.ck.reserve(cand->size());
+    S.cl.reserve(cand->size());
+    for (const auto& kl : *cand) { S.ck.push_back(kl.first); S.cl.push_back(kl.second); }
+  }
   // integerise supplies
   const double scale = 4503599627370496.0;  // 2^52
   double ta = 0, tb = 0;
@@ -325,7 +389,14 @@ int solve_typed(int n, int m, const Stored* cost, const double* a, const double*
   Cost cmax = 0;
   for (int64_t e = 0; e < (int64_t)n * m; ++e) cmax = std::max(cmax, Cost(cost[e]));
   S.art = (cmax + 1) * (Cost)(n + m + 1);
-  if (!S.solve(int64_t(200) * (n + m) * (n + m) + 100000, eps)) return QBW_E_LP;
+  const int64_t max_pivots = int64_t(200) * (n + m) * (n + m) + 100000;
+  if (cand) {
+    int rounds = 0;
+    if (!S.solve_sparse(max_pivots, eps, &rounds)) return QBW_E_LP;
+    out->rounds = rounds;
+  } else if (!S.solve(max_pivots, eps)) {
+    return QBW_E_LP;
+  }
   // every artificial arc must carry no flow
   for (const auto& e : S.edges)
     if (e.arc < 0 && e.flow != 0) return QBW_E_LP;
@@ -365,7 +436,10 @@ int solve_typed(int n, int m, const Stored* cost, const double* a, const double*
 
 }  // namespace
 
-int coarse_solve(const CoarseProblem& P, CoarseSolution* out) {
+// `cand` (may be null): candidate block pairs (source block, target block) for
+// pricing first; the solve still ends optimal for every pair.
+static int coarse_solve_cand(const CoarseProblem& P, const std::vector<std::pair<int, int>>* cand_blocks,
+                             CoarseSolution* out) {
   const int Q = P.Q;
   std::vector<int> src, dst;
   for (int i = 0; i < Q; ++i) if (P.mu[i] > 0) src.push_back(i);
@@ -375,6 +449,18 @@ int coarse_solve(const CoarseProblem& P, CoarseSolution* out) {
   std::vector<double> a(n), b(m);
   for (int i = 0; i < n; ++i) a[i] = P.mu[src[i]];
   for (int j = 0; j < m; ++j) b[j] = P.nu[dst[j]];
+  // candidates in the solver's numbering (blocks of zero mass are not in the LP)
+  std::vector<std::pair<int, int>> cand;
+  const std::vector<std::pair<int, int>>* cp = nullptr;
+  if (cand_blocks) {
+    std::vector<int> si(Q, -1), di(Q, -1);
+    for (int i = 0; i < n; ++i) si[src[i]] = i;
+    for (int j = 0; j < m; ++j) di[dst[j]] = j;
+    cand.reserve(cand_blocks->size());
+    for (const auto& kl : *cand_blocks)
+      if (si[kl.first] >= 0 && di[kl.second] >= 0) cand.push_back({si[kl.first], di[kl.second]});
+    cp = &cand;
+  }
   out->f.assign(Q, 0.0);
   out->g.assign(Q, 0.0);
   std::vector<char> fset(Q, 0), gset(Q, 0);
@@ -388,12 +474,12 @@ int coarse_solve(const CoarseProblem& P, CoarseSolution* out) {
       std::vector<int32_t> c((size_t)n * m);
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < m; ++j) c[(size_t)i * m + j] = (int32_t)std::llround(P.cost[(size_t)src[i] * Q + dst[j]]);
-      rc = solve_typed<int64_t, int32_t>(n, m, c.data(), a.data(), b.data(), src, dst, out, 0);
+      rc = solve_typed<int64_t, int32_t>(n, m, c.data(), a.data(), b.data(), src, dst, out, 0, cp);
     } else {
       std::vector<int64_t> c((size_t)n * m);
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < m; ++j) c[(size_t)i * m + j] = (int64_t)std::llround(P.cost[(size_t)src[i] * Q + dst[j]]);
-      rc = solve_typed<int64_t>(n, m, c.data(), a.data(), b.data(), src, dst, out, 0);
+      rc = solve_typed<int64_t>(n, m, c.data(), a.data(), b.data(), src, dst, out, 0, cp);
     }
   } else {
     std::vector<double> c((size_t)n * m);
@@ -403,7 +489,7 @@ int coarse_solve(const CoarseProblem& P, CoarseSolution* out) {
         c[(size_t)i * m + j] = P.cost[(size_t)src[i] * Q + dst[j]];
         cm = std::max(cm, c[(size_t)i * m + j]);
       }
-    rc = solve_typed<double>(n, m, c.data(), a.data(), b.data(), src, dst, out, 1e-11 * (cm + 1.0));
+    rc = solve_typed<double>(n, m, c.data(), a.data(), b.data(), src, dst, out, 1e-11 * (cm + 1.0), cp);
   }
   if (rc != QBW_OK) return rc;
   for (int i : src) fset[i] = 1;
@@ -433,6 +519,86 @@ int coarse_solve(const CoarseProblem& P, CoarseSolution* out) {
     obj += out->vals[e] * P.cost[(size_t)out->rows[e] * Q + out->cols[e]];
   out->objective = obj;
   return QBW_OK;
+}
+
+int coarse_solve(const CoarseProblem& P, CoarseSolution* out) { return coarse_solve_cand(P, nullptr, out); }
+
+// Multiscale start (coarse-to-fine, as the paper suggests for the coarse solve
+// itself): the problem on the n^d blocks is pooled once more, 2^d blocks to
+// one, and solved (recursively, down to a few hundred blocks); the pairs of
+// children of that solution's support are priced first.  (Widening each
+// target to its 3^d neighbours made the first set larger and the solve
+// slower: the arcs the start set lacks come in through the checks.)  The result is optimal for the whole
+// dense problem: the solve only stops when no block pair has a negative
+// reduced cost (solve_sparse), so the start set affects the time, not the
+// objective.
+int coarse_solve_multiscale(const CoarseProblem& P, int n, int d, int p, CoarseSolution* out) {
+  const int Q = P.Q;
+  if (n % 2 != 0 || Q <= kMultiscaleMinQ) return coarse_solve(P, out);
+  const int h = n / 2;
+  const int Q2 = d == 2 ? h * h : h * h * h;
+  auto coords = [&](int K, int side, int* x) {
+    for (int a = d - 1; a >= 0; --a) { x[a] = K % side; K /= side; }
+  };
+  auto index = [&](const int* x, int side) {
+    int K = 0;
+    for (int a = 0; a < d; ++a) K = K * side + x[a];
+    return K;
+  };
+  // pooled masses and a cost of the same form on the half-resolution blocks
+  std::vector<double> mu2(Q2, 0.0), nu2(Q2, 0.0);
+  for (int K = 0; K < Q; ++K) {
+    int x[3];
+    coords(K, n, x);
+    for (int a = 0; a < d; ++a) x[a] /= 2;
+    const int K2 = index(x, h);
+    mu2[K2] += P.mu[K];
+    nu2[K2] += P.nu[K];
+  }
+  std::vector<double> C2((size_t)Q2 * Q2);
+  for (int K = 0; K < Q2; ++K) {
+    int x[3];
+    coords(K, h, x);
+    for (int L = 0; L < Q2; ++L) {
+      int y[3];
+      coords(L, h, y);
+      long long d2 = 0;
+      for (int a = 0; a < d; ++a) d2 += (long long)(x[a] - y[a]) * (x[a] - y[a]);
+      C2[(size_t)K * Q2 + L] = p == 2 ? (double)d2 : std::sqrt((double)d2);
+    }
+  }
+  CoarseProblem P2{Q2, mu2.data(), nu2.data(), C2.data(), p == 2};
+  CoarseSolution s2;
+  int rc = coarse_solve_multiscale(P2, h, d, p, &s2);
+  if (rc != QBW_OK) return coarse_solve(P, out);
+  // candidate pairs: the children of the support's block pairs
+  const int nc = 1 << d;
+  std::vector<std::vector<int>> tg(Q);
+  for (size_t e = 0; e < s2.vals.size(); ++e) {
+    int xs[3], xt[3];
+    coords(s2.rows[e], h, xs);
+    coords(s2.cols[e], h, xt);
+    for (int cs = 0; cs < nc; ++cs) {
+      int u[3];
+      for (int a = 0; a < d; ++a) u[a] = 2 * xs[a] + ((cs >> a) & 1);
+      std::vector<int>& T = tg[index(u, n)];
+      for (int ct = 0; ct < nc; ++ct) {
+        int v[3];
+        for (int a = 0; a < d; ++a) v[a] = 2 * xt[a] + ((ct >> a) & 1);
+        T.push_back(index(v, n));
+      }
+    }
+  }
+  std::vector<std::pair<int, int>> cand;
+  for (int K = 0; K < Q; ++K) {
+    std::vector<int>& T = tg[K];
+    std::sort(T.begin(), T.end());
+    T.erase(std::unique(T.begin(), T.end()), T.end());
+    for (int L : T) cand.push_back({K, L});
+  }
+  rc = coarse_solve_cand(P, &cand, out);
+  if (rc == QBW_OK) out->pivots += s2.pivots;
+  return rc;
 }
 
 }  // namespace qbw

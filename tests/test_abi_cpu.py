@@ -74,6 +74,71 @@ def test_host_simplex_certified_against_highs(lib, N, d, k, p, fa, fb):
         assert np.array_equal(rec.f, np.round(rec.f))   # integer costs -> integer duals
 
 
+def _certified_optimal(rec, mt, nt, Ct, p):
+    cert = lp.certify(rec.rows, rec.cols, rec.vals, rec.f, rec.g, mt, nt, Ct)
+    assert len(rec.vals) <= 2 * len(mt) - 1
+    assert cert["min_entry"] > 0
+    assert cert["row_err"] <= 1e-15 and cert["col_err"] <= 1e-15
+    tol = 0.0 if p == 2 else 1e-9 * Ct.max()
+    assert cert["dual_viol"] <= tol and cert["slack_on_support"] <= max(tol, 1e-12 * Ct.max())
+    assert cert["dual"] == pytest.approx(rec.objective, rel=1e-12)
+
+
+def _dense_start(mt, nt, N, d, k, p):
+    import paper_2506_00976_amd as qbw
+    os.environ["QBW_COARSE_SOLVER"] = "dense"
+    try:
+        return qbw.coarse_solve(mt, nt, N, d, k, p)
+    finally:
+        del os.environ["QBW_COARSE_SOLVER"]
+
+
+@pytest.mark.parametrize("fam", ["grf", "cauchy"])
+def test_multiscale_coarse_solve_q1024_against_highs(lib, fam):
+    # 256^2 pairs, k = 8: the multiscale start (the library's default) reaches
+    # the optimum HiGHS found for the same pooled masses (stored objective),
+    # with an optimality certificate, and the dense start's objective
+    import paper_2506_00976_amd as qbw
+    N, d, k, p = 256, 2, 8, 2
+    mu, nu = si.config3_pair(N, fam)
+    mt, nt = coarse.sumpool(mu, k), coarse.sumpool(nu, k)
+    rec = qbw.coarse_solve(mt, nt, N, d, k, p)
+    golden = np.load(os.path.join(ROOT, "tests", "golden", "records_256_k8.npz"))
+    assert rec.objective == pytest.approx(float(golden[f"{fam}_obj"][0]), rel=1e-12)
+    _certified_optimal(rec, mt, nt, coarse.centre_cost(N, d, k, p), p)
+    assert rec.objective == pytest.approx(_dense_start(mt, nt, N, d, k, p).objective, rel=1e-13)
+
+
+@pytest.mark.parametrize("N,d,k,p", [(256, 2, 8, 1), (32, 3, 2, 2), (32, 3, 2, 1), (48, 2, 2, 2), (64, 3, 4, 1)])
+def test_multiscale_coarse_solve_certified(lib, N, d, k, p):
+    # Q = 1024 (p = 1), 4096 (32^3, k = 2), 576 (n = 24: its half level has
+    # 144 blocks, solved densely) and 4096 (64^3, k = 4): certificate of
+    # optimality and the dense start's objective
+    import paper_2506_00976_amd as qbw
+    mu = si.family("grf", N, d, si.rng(9200 + N + d + p))
+    nu = si.family("cauchy" if d == 2 else "gmm", N, d, si.rng(9201 + N + d + p))
+    mt, nt = coarse.sumpool(mu, k), coarse.sumpool(nu, k)
+    rec = qbw.coarse_solve(mt, nt, N, d, k, p)
+    _certified_optimal(rec, mt, nt, coarse.centre_cost(N, d, k, p), p)
+    assert rec.objective == pytest.approx(_dense_start(mt, nt, N, d, k, p).objective, rel=1e-12)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_multiscale_coarse_solve_with_empty_blocks(lib, p):
+    # shapes: most blocks carry no mass and are left out of the LP, at both levels
+    import paper_2506_00976_amd as qbw
+    N, d, k = 128, 2, 4
+    mu = si.shapes(N, d, si.rng(9300 + p))
+    nu = si.shapes(N, d, si.rng(9301 + p))
+    mt, nt = coarse.sumpool(mu, k), coarse.sumpool(nu, k)
+    assert (mt == 0).sum() > 100 and (nt == 0).sum() > 100
+    rec = qbw.coarse_solve(mt, nt, N, d, k, p)
+    Ct = coarse.centre_cost(N, d, k, p)
+    *_, obj = lp.solve_ot(mt, nt, Ct)
+    assert rec.objective == pytest.approx(obj, rel=1e-9)
+    _certified_optimal(rec, mt, nt, Ct, p)
+
+
 def test_host_simplex_degenerate_and_identical(lib):
     import paper_2506_00976_amd as qbw
     N, d, k, p = 16, 2, 4, 2
