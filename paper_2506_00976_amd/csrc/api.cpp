@@ -289,6 +289,9 @@ struct Plan {
   int tot_xs = 0, tot_xs3 = 0;
   int* xs_list = nullptr;
   int xs_pixels = 0;
+  int xs_T = 8, xs_W = 1;  // targets per lane and waves per work-group of the stages
+  size_t ipf_lds = 0;      // dynamic LDS of the coarse fitting kernel (jobs that do not fit use global memory)
+  size_t bwd_lds = 0;      // the same for the coarse backward kernel
   const double* xs_sq = nullptr;
   P1Items p1_tab{};        // p = 1 plan-cost / gradient items per kernel kind
   CtItem* items = nullptr;
@@ -452,7 +455,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   Layout L;
   struct Offs {
     size_t mu_t, nu_t, ftil, fhat, g, f, part, win, arg_g, arg_f, e_row, e_col, e_val, csr, csc,
-        csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, gbar_mu, gbar_nu, coef, gquad, part1, mom_mu, mom_nu,
+        csc_idx, ipf_u, ipf_v, a_s, b_s, red_lb, red_tv, red_pc, red_pm, gbar_mu, gbar_nu, coef, gquad, part1, mom_mu, mom_nu,
         mom_as, mom_bs, sep_tmp, sep_arg, xs_v, xs_i;
   };
   std::vector<Offs> offs(NJ);
@@ -480,6 +483,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     O.red_lb = L.add(8 * (size_t)chunks * kRedSlotsLB);
     O.red_tv = L.add(8 * (size_t)chunks * kRedSlotsTV);
     O.red_pc = L.add(8 * (size_t)nnz);
+    O.red_pm = L.add(8 * (size_t)nnz);
     O.gbar_mu = L.add(8 * (size_t)Q);
     O.gbar_nu = L.add(8 * (size_t)Q);
     O.coef = L.add(8 * (size_t)nnz);
@@ -566,12 +570,26 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
       return w;
     };
     const long long want = 4LL * 4 * ctx->num_cu;
-    while (xs_T > 2 && waves(xs_T) < want) xs_T /= 2;
+    // without arg-mins a work-group's waves can split an item's sources
+    // (up to four), which counts toward the waves a launch has
+    const int max_split = (mode & PM_ARGMIN) ? 1 : 4;
+    while (xs_T > 2 && waves(xs_T) * max_split < want) xs_T /= 2;
     // QBW_XS_T (2, 4, 8, or 16 without arg-mins) overrides the choice
     if (const char* e = std::getenv("QBW_XS_T")) {
       const int v = std::atoi(e);
       if (v == 2 || v == 4 || v == 8 || (v == 16 && xs16)) xs_T = v;
     }
+    // splits up to about eight waves per SIMD requested (fewer fit at 16
+    // targets per lane; the surplus queues behind, which still measured
+    // faster than stopping at four)
+    pl.xs_W = 1;
+    while (pl.xs_W < max_split && waves(xs_T) * pl.xs_W < 2 * want) pl.xs_W *= 2;
+    // QBW_XS_W (1, 2 or 4 without arg-mins) overrides the split
+    if (const char* e = std::getenv("QBW_XS_W")) {
+      const int v = std::atoi(e);
+      if (v == 1 || ((v == 2 || v == 4) && max_split == 4)) pl.xs_W = v;
+    }
+    pl.xs_T = xs_T;
   }
   for (int j = 0; j < NJ; ++j) {
     const auto& J = pl.in[j];
@@ -617,6 +635,14 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     D.red_lb = (double*)(B + O.red_lb);
     D.red_tv = (double*)(B + O.red_tv);
     D.red_pc = (double*)(B + O.red_pc);
+    D.red_pm = (double*)(B + O.red_pm);
+    if (J.coarse) {
+      const CoarseHost& C = *J.coarse;
+      for (int K = 0; K < C.Q; ++K) {
+        D.row_max = std::max(D.row_max, C.csr_ptr[K + 1] - C.csr_ptr[K]);
+        D.col_max = std::max(D.col_max, C.csc_ptr[K + 1] - C.csc_ptr[K]);
+      }
+    }
     D.result = (double*)(B + o_res) + (size_t)RS_COUNT * j;
     D.flags = (int*)(B + o_ints) + 2 * kQueues + j;
     D.grad_a = J.ga;
@@ -720,6 +746,11 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   pl.cbar_out = ptrs;
   pl.fhat_grad_out = ptrs + 3 * NJ;
   pl.ct_grid = std::max(1, G);
+  for (const auto& D : pl.hj) {   // jobs that do not fit keep their coarse data in global memory
+    const size_t ni = coarse_lds_need(D.Q, D.nnz, 6), nb = coarse_lds_need(D.Q, D.nnz, 4);
+    if (ni <= kCoarseLdsMax) pl.ipf_lds = std::max(pl.ipf_lds, ni);
+    if (nb <= kCoarseLdsMax) pl.bwd_lds = std::max(pl.bwd_lds, nb);
+  }
 
   // uploads: the previous staged copy must have landed before the staging
   // memory is rewritten
@@ -814,7 +845,8 @@ static int enqueue_xs(Plan& pl, int phase, hipStream_t st) {
     const int total = k < 2 ? pl.tot_xs : pl.tot_xs3;
     if (!total) continue;
     CHK(timed_launch(pl, st, [&] {
-      return launch_xs_stage(pl.djobs, pl.njobs, off, total, phase, k, pl.xs_sq, pl.xs_list, cnt, st);
+      return launch_xs_stage(pl.djobs, pl.njobs, off, total, phase, k, pl.xs_sq, pl.xs_list, cnt, pl.xs_T,
+                             (pl.mode & PM_ARGMIN) ? 1 : 0, pl.xs_W, st);
     }));
   }
   return launch_xs_fallback(pl.djobs, pl.xs_list, cnt, phase, std::max(1, std::min(pl.xs_pixels, 4096)), st);
@@ -851,13 +883,13 @@ static int enqueue_plancost(Plan& pl, hipStream_t st) {
 static int enqueue_forward(Plan& pl, hipStream_t st) {
   const int NJ = pl.njobs;
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, NJ, pl.off_pool, pl.tot_pool, st));
+  CHK(launch_pool(pl.djobs, NJ, pl.off_mom, pl.tot_mom, st));
   // lower bound (Algorithm 5)
   CHK(launch_upscale(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
   CHK(enqueue_ctransforms(pl, st));
   // upper bound (Algorithm 4): coarse IPF, then one sweep over the pixels for
   // the lower-bound sums, the fine scalings and the weighted-TV sums
-  CHK(launch_ipf(pl.djobs, NJ, st));
+  CHK(launch_ipf(pl.djobs, NJ, pl.ipf_lds, st));
   CHK(launch_fwd_pixels(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
   CHK(enqueue_plancost(pl, st));
   CHK(launch_finalize(pl.djobs, NJ, st));
@@ -869,8 +901,7 @@ static int enqueue_backward(Plan& pl, hipStream_t st) {
   // p = 1 jobs: separate lower- and upper-bound passes (the latter over
   // support blocks); p = 2 jobs: one fused pass over pixels after the moments
   if (pl.has_p1) CHK(launch_lb_grad(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, st));
-  if (pl.tot_pc2) CHK(launch_moments(pl.djobs, NJ, pl.off_mom, pl.tot_mom, 0, st));
-  CHK(launch_ub_coarse_bwd2(pl.djobs, NJ, pl.bwd_scratch, pl.max_q, st));
+  CHK(launch_ub_coarse_bwd2(pl.djobs, NJ, pl.bwd_scratch, pl.max_q, pl.bwd_lds, st));
   if (pl.has_p1) {
     for (int side = 0; side < 2; ++side) {   // per-entry partials, then per-pixel sums
       P1Items ubg = pl.p1_tab;
@@ -880,10 +911,7 @@ static int enqueue_backward(Plan& pl, hipStream_t st) {
       CHK(launch_ub_grad_sum(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.du, side, st));
     }
   }
-  if (pl.has_p2) {
-    CHK(launch_grad2_quad(pl.djobs, NJ, pl.off_block, pl.tot_block, st));
-    CHK(launch_grad2(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, pl.du, st));
-  }
+  if (pl.has_p2) CHK(launch_grad2(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, pl.du, st));
   return QBW_OK;
 }
 
@@ -917,7 +945,7 @@ static int pool_and_check(qbw_ctx* ctx, const std::vector<JobIn>& jobs, std::vec
   o.max_ipf_iter = 1;
   CHK(plan_build(ctx, pl, jobs, 0, o, true, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, pl.njobs, pl.off_pool, pl.tot_pool, st));
+  CHK(launch_pool(pl.djobs, pl.njobs, pl.off_mom, pl.tot_mom, st));
   std::vector<int> flags(pl.n_ints);
   mt->resize(pl.njobs);
   nt->resize(pl.njobs);
@@ -1249,7 +1277,7 @@ qbw_status qbw_sumpool(qbw_ctx* ctx, const qbw_grid* grid, const double* m, doub
   pl.hj[0].mu_t = out;
   HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, 1, pl.off_pool, pl.tot_pool, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, st));
   HIPCHK(hipStreamSynchronize(st));
   return QBW_OK;
 }
@@ -1270,8 +1298,7 @@ qbw_status qbw_cbar(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const d
   CHK(plan_build(ctx, pl, {stage_job(grid, a, b)}, PM_CBAR, qbw_default_opts(), false, st));
   HIPCHK(hipMemcpyAsync(pl.cbar_out, &out, sizeof(double*), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, 1, pl.off_pool, pl.tot_pool, st));
-  CHK(launch_moments(pl.djobs, 1, pl.off_mom, pl.tot_mom, 0, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, st));
   CHK(launch_cbar2(pl.djobs, 1, pl.off_cbar, pl.tot_cbar, pl.cbar_out, st));
   HIPCHK(hipStreamSynchronize(st));
   return QBW_OK;
@@ -1314,8 +1341,7 @@ qbw_status qbw_weighted_cost_upper(qbw_ctx* ctx, const qbw_grid* grid, const dou
   std::unique_ptr<double, void (*)(double*)> guard(dC, [](double* p) { (void)hipFree(p); });
   HIPCHK(hipMemcpyAsync(pl.cbar_out, &dC, sizeof(double*), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, 1, pl.off_pool, pl.tot_pool, st));
-  CHK(launch_moments(pl.djobs, 1, pl.off_mom, pl.tot_mom, 0, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, st));
   CHK(launch_cbar2(pl.djobs, 1, pl.off_cbar, pl.tot_cbar, pl.cbar_out, st));
   std::vector<double> C((size_t)Q * Q);
   HIPCHK(hipMemcpyAsync(C.data(), dC, 8 * C.size(), hipMemcpyDeviceToHost, st));
@@ -1567,8 +1593,8 @@ qbw_status qbw_ipf(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const do
   pl.hj[0].b_s = b_s;
   HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, 1, pl.off_pool, pl.tot_pool, st));
-  CHK(launch_ipf(pl.djobs, 1, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, st));
+  CHK(launch_ipf(pl.djobs, 1, pl.ipf_lds, st));
   CHK(launch_scalings(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, st));
   CHK(fetch_results(pl, st));
   if (iters) *iters = (int32_t)pl.host_results[RS_IPF_ITERS];
@@ -1611,6 +1637,7 @@ qbw_status qbw_tv(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const dou
   HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(D.red_lb, 0, 8 * (size_t)D.chunks * kRedSlotsLB, st));
   HIPCHK(hipMemsetAsync(D.red_pc, 0, 8 * (size_t)std::max(1, D.nnz), st));
+  HIPCHK(hipMemsetAsync(D.red_pm, 0, 8 * (size_t)std::max(1, D.nnz), st));
   HIPCHK(hipMemsetAsync(D.result, 0, 8 * RS_COUNT, st));
   CHK(launch_tv_prep(pl.djobs, 1, st));
   CHK(launch_tv_partial(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, st));

@@ -122,41 +122,6 @@ __device__ __forceinline__ double group_sum(double v, int g) {
   return v;
 }
 
-// Block sums (SumPool) of a and b, four waves per work-group; negative and NaN
-// entries raise the job's flags.
-__global__ __launch_bounds__(256) void k_pool(const DevJob* __restrict__ jobs, int njobs,
-                                              const int* __restrict__ off, int total) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int it = blockIdx.x; it < total; it += gridDim.x) {
-    const int jb = find_job(off, njobs, it);
-    const DevJob& J = jobs[jb];
-    const int m = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
-    const int g = reduce_group(m);
-    const int K = ((it - off[jb]) * 4 + wv) * (64 / g) + lane / g;
-    const int sub = lane & (g - 1);
-    const bool ok = K < J.Q;
-    double sm = 0.0, sn = 0.0;
-    int bad = 0;
-    if (ok) {
-      for (int t = sub; t < m; t += g) {
-        const int i = block_member(K, t, J.N, J.n, J.k, J.d);
-        const double x = J.mu[i], y = J.nu[i];
-        sm += x;
-        sn += y;
-        bad |= (x < 0.0 || y < 0.0) ? 1 : 0;
-        bad |= (x != x || y != y) ? 2 : 0;
-      }
-    }
-    sm = group_sum(sm, g);
-    sn = group_sum(sn, g);
-    for (int o = g >> 1; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
-    if (ok && sub == 0) {
-      J.mu_t[K] = sm;
-      J.nu_t[K] = sn;
-      if (bad) atomicOr(J.flags, bad);
-    }
-  }
-}
 
 // ------------------------------------------------------------------ upscaling
 
@@ -169,7 +134,9 @@ __device__ __forceinline__ void axis_weight(int x, int k, int n, int& K0, int& K
   if (q >= n - 1) { K0 = n - 1; K1 = n - 1; w = 0.0; return; }
   K0 = q;
   K1 = q + 1;
-  w = (double)(t - den * q) / (double)den;
+  // a power-of-two denominator divides exactly as a product with its reciprocal
+  const double r = (double)(t - den * q);
+  w = (den & (den - 1)) == 0 ? r * (1.0 / (double)den) : r / (double)den;
 }
 
 __device__ __forceinline__ double lerp_nc(double a, double b, double w) {
@@ -194,7 +161,7 @@ __device__ __forceinline__ void axis_cubic(int x, int k, int n, int (&K)[4], dou
     if (i >= n - 1) { i = n - 1; r = 0; }
   }
   for (int o = 0; o < 4; ++o) K[o] = min(max(i + o - 1, 0), n - 1);
-  const double s = (double)r / (double)den;
+  const double s = (den & (den - 1)) == 0 ? (double)r * (1.0 / (double)den) : (double)r / (double)den;
   const double s2 = s * s;
   const double s3 = s2 * s;
   w[0] = 0.5 * ((2.0 * s2 - s3) - s);
@@ -781,17 +748,34 @@ __device__ __forceinline__ void xs_window_block(double (&m1)[T], double (&W)[T],
 template <bool FIRST, int kXsT, bool ARG>
 __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int phase, int k,
                                         const double* __restrict__ sqt, int2* __restrict__ list,
-                                        int* __restrict__ count, float* tile) {
-  const int lane = threadIdx.x;
+                                        int* __restrict__ count, float* tile, int wv, int SW,
+                                        double* red) {
+  const int lane = threadIdx.x & 63;
   {
     const int N = J.N, P = J.P;
     const int lines = P / N;
     const int nchunk = (lines + 63) >> 6;
-    const int group = local / nchunk, chunk = local - group * nchunk;
-    const int t0 = group * kXsT;
+    // Lanes are (line, target group) pairs.  Later stages: 64 consecutive
+    // lines of one target group per wave (their loads are coalesced along
+    // the last axis).  First stage without arg-mins: the lanes run along the
+    // rows, G groups per row, so the lanes of a row read the same source
+    // values (a few distinct addresses per load, no staging); with arg-mins
+    // it keeps the line-per-lane layout and its LDS tiles.  Either way a
+    // launch has nchunk x G items of 64 lanes.
+    constexpr bool ROWLANES = FIRST && !ARG;
+    const int G = (N + kXsT - 1) / kXsT;
+    int e, t0;
+    if constexpr (ROWLANES) {
+      const int gi = local * 64 + lane;
+      e = gi / G;
+      t0 = (gi - e * G) * kXsT;
+    } else {
+      const int group = local / nchunk, chunk = local - group * nchunk;
+      t0 = group * kXsT;
+      e = chunk * 64 + lane;
+    }
     int st = 1;
     for (int q = 0; q < k; ++q) st *= N;   // stride of axis d-1-k
-    const int e = chunk * 64 + lane;
     const bool valid = e < lines;
     const int ee = valid ? e : 0;
     const int outer = ee / st, inner = ee - outer * st;
@@ -819,24 +803,63 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
         m1[t] = fmin(m1[t], w);
       }
     };
+    // The SW waves of the work-group split the sources: wave wv takes
+    // [rlo, rhi), a multiple of 16 long (the first stage's tile width, so
+    // also of kXsT), and the minima meet in LDS at the end.  Arg-mins keep
+    // one wave per item (SW = 1).
+    const int chunkS = ((N + 16 * SW - 1) / (16 * SW)) * 16;
+    const int rlo = min(N, wv * chunkS), rhi = min(N, rlo + chunkS);
     // value-only: squares from a rotating register window (all-VGPR adds)
-    // over whole blocks of kXsT sources; the last N mod kXsT sources take
-    // them from the table
+    // over whole blocks of kXsT sources; the last (rhi - rlo) mod kXsT
+    // sources take them from the table
     double W[kXsT];
-    double inc = 2.0 * (double)(-t0) - 1.0;
+    double inc = 2.0 * (double)(rlo - t0) - 1.0;
     if constexpr (!ARG) {
 #pragma unroll
-      for (int q = 1; q < kXsT; ++q) W[q] = (double)(-t0 - q) * (double)(-t0 - q);
+      for (int q = 1; q < kXsT; ++q) W[q] = (double)(rlo - t0 - q) * (double)(rlo - t0 - q);
       W[0] = 0.0;
     }
-    const int NB = ARG ? 0 : N - N % kXsT;   // sources in whole window blocks
-    if (FIRST) {
+    const int NB = ARG ? rlo : rhi - (rhi - rlo) % kXsT;   // sources in whole window blocks end here
+    if constexpr (ROWLANES) {
+      // the lane's row, loaded one source at a time four steps ahead (all
+      // lanes of a row load the same address), converted to -phi in float64
+      typedef const __attribute__((address_space(1))) float* gfptr;
+      const gfptr rp = (gfptr)(src + (size_t)ee * N);
+      if constexpr (kXsT >= 8) {
+        float hb[8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) hb[u] = rlo + u < NB ? rp[rlo + u] : 0.0f;
+        for (int r0 = rlo; r0 < NB; r0 += kXsT) {
+          xs_window_block<kXsT>(m1, W, inc, [&](int j) {
+            hb[(j + 4) & 7] = rp[min(r0 + j + 4, NB - 1)];
+            return -(double)hb[j & 7];
+          });
+        }
+      } else {
+        for (int r0 = rlo; r0 < NB; r0 += kXsT) {
+          float hc[kXsT];
+#pragma unroll
+          for (int u = 0; u < kXsT; ++u) hc[u] = rp[r0 + u];
+          xs_window_block<kXsT>(m1, W, inc, [&](int j) { return -(double)hc[j]; });
+        }
+      }
+      // the remaining sources: per-lane targets, so the squares are formed
+      // here (exact small integers) rather than read as wave-uniform values
+      for (int r = NB; r < rhi; ++r) {
+        const double h = -(double)rp[r];
+#pragma unroll
+        for (int t = 0; t < kXsT; ++t) {
+          const double dd = (double)(r - t0 - t);
+          m1[t] = vmin_f64(m1[t], h + dd * dd);
+        }
+      }
+    } else if (FIRST) {
       // the lines are rows (stride 1): tiles of 64 rows x 16 columns are read
       // coalesced (the next tile while the current one is in use) into LDS,
       // then each lane walks its own row there (stride 17 words, no bank
       // conflicts), instead of 64 rows' cache lines per load
       constexpr int TC = 16;
-      const int row0 = chunk * 64;
+      const int row0 = e - lane;   // the chunk's first line
       const int sub = lane / TC, cl = lane % TC;   // 4 rows of 16 columns per load
       float nx[64 / 4];
       // a wave-uniform base per group of four rows plus the lane's 32-bit
@@ -851,32 +874,24 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
           nx[i] = (row < lines && col < N) ? ub[loff] : 0.0f;
         }
       };
-      fetch(0);
-      for (int rb = 0; rb < N; rb += TC) {
-        const int nc = min(TC, N - rb);
-        __syncthreads();
+      // each wave has its own tile: ordering its LDS writes and reads needs
+      // only a wave-level barrier
+      auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      };
+      if (rlo < rhi) fetch(rlo);
+      for (int rb = rlo; rb < rhi; rb += TC) {
+        const int nc = min(TC, rhi - rb);
+        wave_sync();
 #pragma unroll
         for (int i = 0; i < 64 / 4; ++i) tile[(4 * i + sub) * (TC + 1) + cl] = nx[i];
-        __syncthreads();
-        if (rb + TC < N) fetch(rb + TC);
-        if constexpr (!ARG) {
-          static_assert(TC % kXsT == 0, "window blocks must tile the LDS tile");
-          int j0 = 0;
-          for (; j0 + kXsT <= nc && rb + j0 + kXsT <= NB; j0 += kXsT) {
-            // the block's sources read from LDS up front (one wait, not one per step)
-            const float* row = tile + lane * (TC + 1) + j0;
-            float hv[kXsT];
-#pragma unroll
-            for (int j = 0; j < kXsT; ++j) hv[j] = row[j];
-            xs_window_block<kXsT>(m1, W, inc, [&](int j) { return -(double)hv[j]; });
-          }
-          for (int j = j0; j < nc; ++j) step(-(double)tile[lane * (TC + 1) + j], rb + j);
-        } else {
-          // unrolled so that the loop-carried minima are re-canonicalised (a
-          // max with itself, for min/max in IEEE mode) once per four steps
+        wave_sync();
+        if (rb + TC < rhi) fetch(rb + TC);
+        // unrolled so that the loop-carried minima are re-canonicalised (a
+        // max with itself, for min/max in IEEE mode) once per four steps
 #pragma unroll 4
-          for (int j = 0; j < nc; ++j) step(-(double)tile[lane * (TC + 1) + j], rb + j);
-        }
+        for (int j = 0; j < nc; ++j) step(-(double)tile[lane * (TC + 1) + j], rb + j);
       }
     } else if constexpr (!ARG) {
       // whole window blocks; each source is loaded four steps before its use
@@ -893,8 +908,8 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
         };
         double hb[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) hb[u] = u < NB ? at(u) : 0.0;
-        for (int r0 = 0; r0 < NB; r0 += kXsT) {
+        for (int u = 0; u < 4; ++u) hb[u] = rlo + u < NB ? at(rlo + u) : 0.0;
+        for (int r0 = rlo; r0 < NB; r0 += kXsT) {
           xs_window_block<kXsT>(m1, W, inc, [&](int j) {
             // past the last whole block the load repeats a valid source and
             // goes unused (no branch inside the unrolled block)
@@ -905,11 +920,11 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
         }
       } else {
         double hc[kXsT], hn[kXsT];
-        if (NB > 0) {
+        if (NB > rlo) {
 #pragma unroll
-          for (int u = 0; u < kXsT; ++u) hn[u] = v1in[base + u * st];
+          for (int u = 0; u < kXsT; ++u) hn[u] = v1in[base + (rlo + u) * st];
         }
-        for (int r0 = 0; r0 < NB; r0 += kXsT) {
+        for (int r0 = rlo; r0 < NB; r0 += kXsT) {
 #pragma unroll
           for (int u = 0; u < kXsT; ++u) hc[u] = hn[u];
           if (r0 + kXsT < NB) {
@@ -919,7 +934,7 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
           xs_window_block<kXsT>(m1, W, inc, [&](int j) { return hc[j]; });
         }
       }
-      for (int r = NB; r < N; ++r) step(v1in[base + r * st], r);
+      for (int r = NB; r < rhi; ++r) step(v1in[base + r * st], r);
     } else {
       // four sources per round, the next four loaded while these are used
       const int N4 = N & ~3;
@@ -938,6 +953,23 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
         for (int u = 0; u < 4; ++u) step(hc[u], r + u);
       }
       for (int r = N4; r < N; ++r) step(v1in[base + r * st], r);
+    }
+    if constexpr (!ARG) {
+      if (SW > 1) {
+        // the other waves' minima into wave 0 (the barrier before the writes
+        // also keeps them behind wave 0's reads for the previous item)
+        __syncthreads();
+        if (wv > 0) {
+#pragma unroll
+          for (int t = 0; t < kXsT; ++t) red[((wv - 1) * kXsT + t) * 64 + lane] = m1[t];
+        }
+        __syncthreads();
+        if (wv > 0) return;
+        for (int w = 1; w < SW; ++w) {
+#pragma unroll
+          for (int t = 0; t < kXsT; ++t) m1[t] = vmin_f64(m1[t], red[((w - 1) * kXsT + t) * 64 + lane]);
+        }
+      }
     }
     if (!valid) return;
     const bool last = k == J.d - 1;
@@ -1003,32 +1035,40 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
   }
 }
 
-// Targets per lane T (16, 8, 4 or 2) is the job's: fewer for small plans,
-// so that a launch still has enough waves per SIMD (16 only without arg-mins,
-// where a target holds one running minimum).
-template <bool FIRST>
+// One instance per (stage kind, targets per lane T, arg-mins): each has its
+// own register budget.  T (16, 8, 4 or 2) is the plan's: fewer for small
+// plans, so that a launch still has enough waves (16 only without arg-mins,
+// where a target holds one running minimum).  A work-group of SW = blockDim / 64
+// waves takes one item, its waves splitting the sources.
+template <bool FIRST, int T, bool ARG>
 __attribute__((amdgpu_waves_per_eu(4)))
-__global__ __launch_bounds__(64) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
-                                                 const int* __restrict__ off, int total, int phase, int k,
-                                                 const double* __restrict__ sqt, int2* __restrict__ list,
-                                                 int* __restrict__ count) {
-  __shared__ float tile[64 * 17];
+__global__ __launch_bounds__(256) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
+                                                  const int* __restrict__ off, int total, int phase, int k,
+                                                  const double* __restrict__ sqt, int2* __restrict__ list,
+                                                  int* __restrict__ count) {
+  // dynamic LDS, sized by the launcher (xs_lds_bytes): the first stage's
+  // per-wave tiles (64 x 17 floats, with arg-mins only), then (SW - 1) x 64 x T
+  // doubles for the other waves' minima
+  extern __shared__ double xs_lds[];
+  const int SW = blockDim.x >> 6;
+  // the wave index, known wave-uniform: source ranges and load addresses
+  // derived from it stay in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float* tiles = reinterpret_cast<float*>(xs_lds);
+  double* red = xs_lds + (FIRST && ARG ? (SW * 64 * 17 + 1) / 2 : 0);
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
     if (!J.xs || k >= J.d) continue;
-    const int local = it - off[jb];
-    if ((phase == 0 ? J.arg_g : J.arg_f) != nullptr) {
-      if (J.xs_T == 2) xs_item<FIRST, 2, true>(J, jb, local, phase, k, sqt, list, count, tile);
-      else if (J.xs_T == 4) xs_item<FIRST, 4, true>(J, jb, local, phase, k, sqt, list, count, tile);
-      else xs_item<FIRST, 8, true>(J, jb, local, phase, k, sqt, list, count, tile);
-    } else {
-      if (J.xs_T == 2) xs_item<FIRST, 2, false>(J, jb, local, phase, k, sqt, list, count, tile);
-      else if (J.xs_T == 4) xs_item<FIRST, 4, false>(J, jb, local, phase, k, sqt, list, count, tile);
-      else if (J.xs_T == 16) xs_item<FIRST, 16, false>(J, jb, local, phase, k, sqt, list, count, tile);
-      else xs_item<FIRST, 8, false>(J, jb, local, phase, k, sqt, list, count, tile);
-    }
+    xs_item<FIRST, T, ARG>(J, jb, it - off[jb], phase, k, sqt, list, count, tiles + wv * 64 * 17, wv, SW, red);
   }
+}
+
+// LDS bytes of one k_xs_stage work-group (matches the kernel's carving).
+static size_t xs_lds_bytes(bool first, int T, bool arg, int waves) {
+  const size_t tiles = first && arg ? 8 * (size_t)((waves * 64 * 17 + 1) / 2) : 0;
+  const size_t red = arg ? 0 : 8 * (size_t)(waves - 1) * 64 * T;
+  return std::max<size_t>(8, tiles + red);
 }
 
 // The queued targets, one wave each, with the all-pairs arithmetic:
@@ -1287,7 +1327,56 @@ __global__ __launch_bounds__(256) void k_sep_argmin(const DevJob* __restrict__ j
 // b = nu / v (v = pi^T a) the block sums are A_K = mu~_K / u_K and
 // B_L = nu~_L / v_L; b = 1 at the start gives B^0 = k^d.  Every iterate u^t,
 // v^t is kept for the backward pass.  One work-group per job.
-__global__ __launch_bounds__(1024) void k_ipf(const DevJob* __restrict__ jobs, int njobs) {
+// The coarse coupling and per-block vectors a coarse kernel reads, in LDS
+// when they fit the launch's dynamic allocation (lds_bytes), else in global
+// memory; the arithmetic and its order are the same either way.
+struct CoarseView {
+  const int *csr, *csc, *cidx, *erow, *ecol;
+  const double* ev;
+  double* vec;   // nvec x Q doubles of scratch vectors (LDS), or null
+  bool in_lds;
+};
+
+__device__ CoarseView coarse_view(const DevJob& J, double* lds, size_t lds_bytes, int nvec) {
+  CoarseView c;
+  const int Q = J.Q, nnz = J.nnz;
+  c.in_lds = lds_bytes > 0 && coarse_lds_need(Q, nnz, nvec) <= lds_bytes;
+  if (!c.in_lds) {
+    c.csr = J.csr_ptr; c.csc = J.csc_ptr; c.cidx = J.csc_idx; c.erow = J.e_row; c.ecol = J.e_col;
+    c.ev = J.e_val; c.vec = nullptr;
+    return c;
+  }
+  double* ev = lds + (size_t)nvec * Q;
+  int* ip = reinterpret_cast<int*>(ev + nnz);
+  int* csr = ip;
+  int* csc = csr + Q + 1;
+  int* cidx = csc + Q + 1;
+  int* erow = cidx + nnz;
+  int* ecol = erow + nnz;
+  for (int i = threadIdx.x; i < nnz; i += blockDim.x) {
+    ev[i] = J.e_val[i];
+    cidx[i] = J.csc_idx[i];
+    erow[i] = J.e_row[i];
+    ecol[i] = J.e_col[i];
+  }
+  for (int i = threadIdx.x; i <= Q; i += blockDim.x) {
+    csr[i] = J.csr_ptr[i];
+    csc[i] = J.csc_ptr[i];
+  }
+  c.csr = csr; c.csc = csc; c.cidx = cidx; c.erow = erow; c.ecol = ecol; c.ev = ev;
+  c.vec = lds;
+  __syncthreads();
+  return c;
+}
+
+// Iterative proportional fitting on coarse vectors (uniform kernel): with
+// b-block sums B (B^0 = k^d), u^t = cc pi~ B^{t-1}, A^t = mu~ / u^t,
+// v^t = cc pi~^T A^t, B^t = nu~ / v^t (0/0 := 0); the residual after
+// iteration t is ||mu^ - mu||_1 (from u^{t+1} / u^t per block) plus the mass
+// of unmatched target blocks.  One work-group per job; u^t and v^t are
+// written out for the backward pass and the fine sweeps.
+__global__ __launch_bounds__(1024) void k_ipf(const DevJob* __restrict__ jobs, int njobs, size_t lds_bytes) {
+  extern __shared__ double lds[];
   __shared__ double sh[1024];
   const DevJob& J = jobs[blockIdx.x];
   const int Q = J.Q;
@@ -1295,52 +1384,75 @@ __global__ __launch_bounds__(1024) void k_ipf(const DevJob* __restrict__ jobs, i
   const double cc = 1.0 / (kd * kd);
   double* U = J.ipf_u;  // row t holds u^t, t = 1 .. T+1
   double* V = J.ipf_v;  // row t holds v^t
-  double* Bprev = J.gbar_nu;  // scratch: B^{t-1}
-  double* Acur = J.gbar_mu;   // scratch: A^t
-  for (int L = threadIdx.x; L < Q; L += 1024) Bprev[L] = kd;
+  const CoarseView C = coarse_view(J, lds, lds_bytes, 6);
+  // scratch vectors: LDS, or the job's global scratch and checkpoint rows
+  double* Bprev = C.in_lds ? C.vec : J.gbar_nu;            // B^{t-1}
+  double* Acur = C.in_lds ? C.vec + Q : J.gbar_mu;         // A^t
+  double* ucur = C.in_lds ? C.vec + 2 * Q : nullptr;       // u^t (else row t of U)
+  double* vcur = C.in_lds ? C.vec + 3 * Q : nullptr;       // v^t (else row t of V)
+  double* muL = C.in_lds ? C.vec + 4 * Q : nullptr;
+  double* nuL = C.in_lds ? C.vec + 5 * Q : nullptr;
+  const double* mu_t = C.in_lds ? muL : J.mu_t;
+  const double* nu_t = C.in_lds ? nuL : J.nu_t;
+  for (int L = threadIdx.x; L < Q; L += 1024) {
+    Bprev[L] = kd;
+    if (C.in_lds) { muL[L] = J.mu_t[L]; nuL[L] = J.nu_t[L]; }
+  }
+  __syncthreads();
+  // u^1
+  {
+    double* u = C.in_lds ? ucur : U + (size_t)1 * Q;
+    for (int K = threadIdx.x; K < Q; K += 1024) {
+      double s = 0.0;
+      for (int e = C.csr[K]; e < C.csr[K + 1]; ++e) s += C.ev[e] * Bprev[C.ecol[e]];
+      u[K] = cc * s;
+      if (C.in_lds) U[(size_t)1 * Q + K] = u[K];
+    }
+  }
   __syncthreads();
   int T = 0;
   double resid = INFINITY;
   for (int t = 1; t <= J.max_iter; ++t) {
-    double* u = U + (size_t)t * Q;
-    double* v = V + (size_t)t * Q;
-    for (int K = threadIdx.x; K < Q; K += 1024) {
-      double s = 0.0;
-      for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) s += J.e_val[e] * Bprev[J.e_col[e]];
-      u[K] = cc * s;
-    }
-    __syncthreads();
-    for (int K = threadIdx.x; K < Q; K += 1024) Acur[K] = u[K] > 0.0 ? J.mu_t[K] / u[K] : 0.0;
+    const double* u = C.in_lds ? ucur : U + (size_t)t * Q;
+    double* v = C.in_lds ? vcur : V + (size_t)t * Q;
+    for (int K = threadIdx.x; K < Q; K += 1024) Acur[K] = u[K] > 0.0 ? mu_t[K] / u[K] : 0.0;
     __syncthreads();
     for (int L = threadIdx.x; L < Q; L += 1024) {
       double s = 0.0;
-      for (int q = J.csc_ptr[L]; q < J.csc_ptr[L + 1]; ++q) {
-        const int e = J.csc_idx[q];
-        s += J.e_val[e] * Acur[J.e_row[e]];
+      for (int q = C.csc[L]; q < C.csc[L + 1]; ++q) {
+        const int e = C.cidx[q];
+        s += C.ev[e] * Acur[C.erow[e]];
       }
       v[L] = cc * s;
+      if (C.in_lds) V[(size_t)t * Q + L] = v[L];
+      Bprev[L] = v[L] > 0.0 ? nu_t[L] / v[L] : 0.0;
     }
     __syncthreads();
-    for (int L = threadIdx.x; L < Q; L += 1024) Bprev[L] = v[L] > 0.0 ? J.nu_t[L] / v[L] : 0.0;
-    __syncthreads();
-    double* un = U + (size_t)(t + 1) * Q;
+    // u^{t+1} (also the next iteration's u^t) and the residual of iteration t
     double part = 0.0;
     for (int K = threadIdx.x; K < Q; K += 1024) {
       double s = 0.0;
-      for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) s += J.e_val[e] * Bprev[J.e_col[e]];
-      un[K] = cc * s;
+      for (int e = C.csr[K]; e < C.csr[K + 1]; ++e) s += C.ev[e] * Bprev[C.ecol[e]];
+      const double un = cc * s;
+      U[(size_t)(t + 1) * Q + K] = un;
       // ||mu^ - mu||_1 on block K: mu^_i = mu_i u^{t+1}_K / u^t_K
-      const double m = J.mu_t[K];
-      if (u[K] > 0.0) part += m * fabs(un[K] / u[K] - 1.0);
+      const double m = mu_t[K];
+      const double uk = u[K];
+      if (uk > 0.0) part += m * fabs(un / uk - 1.0);
       else part += m;
+      if (C.in_lds) Acur[K] = un;   // staged; copied into ucur below (Acur is free here)
     }
     for (int L = threadIdx.x; L < Q; L += 1024) {
       // nu^_j = b_j (pi^T a)_j = nu_j exactly when v^t_L > 0
-      if (!(v[L] > 0.0)) part += J.nu_t[L];
+      if (!(v[L] > 0.0)) part += nu_t[L];
     }
-    resid = block_sum<1024>(part, sh);
+    resid = block_sum<1024>(part, sh);   // its barriers also order the writes above
     T = t;
     if (resid < J.xi) break;
+    if (C.in_lds) {
+      for (int K = threadIdx.x; K < Q; K += 1024) ucur[K] = Acur[K];
+      __syncthreads();
+    }
   }
   if (threadIdx.x == 0) {
     J.result[RS_IPF_ITERS] = (double)T;
@@ -1545,7 +1657,14 @@ __global__ __launch_bounds__(256) void k_plancost2(const DevJob* __restrict__ jo
     const int K = J.e_row[e], L = J.e_col[e];
     double D0, D1, D2;
     block_delta(K, L, J, D0, D1, D2);
-    J.red_pc[e] = moment_pair_sq(J.mom_as + 5 * (size_t)K, J.mom_bs + 5 * (size_t)L, D0, D1, D2);
+    const double* A = J.mom_as + 5 * (size_t)K;
+    const double* Bm = J.mom_bs + 5 * (size_t)L;
+    J.red_pc[e] = moment_pair_sq(A, Bm, D0, D1, D2);
+    // A0 B0 (|D| + 2 rho)^2 bounds the absolute values of the moment form's
+    // terms (rho the largest offset of a pixel from its block centre): the
+    // scale of this entry's rounding error, summed by k_finalize
+    const double dn = sqrt(D0 * D0 + D1 * D1 + D2 * D2) + sqrt((double)J.d) * (double)(J.k - 1);
+    J.red_pm[e] = (A[0] * Bm[0]) * (dn * dn);
   }
 }
 
@@ -1812,18 +1931,30 @@ __global__ __launch_bounds__(256) void k_pc1_sum(const DevJob* __restrict__ jobs
 
 // ------------------------------------------------------------------ finalize
 
+// Additions on the longest path of a pooled block sum in k_moments (the
+// accumulators start at zero, so the first term adds exactly): k <= 64, a
+// thread's share of a column (ceil(rows / RG) terms), the RG row groups, the
+// block's k columns; k > 64, every g-th pixel in a lane, then the butterfly.
+__device__ __forceinline__ int pool_depth(const DevJob& J) {
+  const int k = J.k;
+  if (k <= 64) {
+    const int W = (256 / k) * k, Wc = min(W, J.N), RG = 256 / Wc;
+    const int nrows = J.d == 2 ? k : k * k;
+    return (nrows + RG - 1) / RG - 1 + (RG - 1) + (k - 1);
+  }
+  const int m = J.d == 2 ? k * k : k * k * k;
+  const int g = reduce_group(m);
+  int lg = 0;
+  while ((1 << lg) < g) ++lg;
+  return (m + g - 1) / g - 1 + lg;
+}
+
 // gamma(n) = n u / (1 - n u), u = 2^-53: a float64 evaluation n roundings deep
 // (a sum of nonnegative terms along any tree of that height, a chain of
 // products and quotients) is within a relative gamma(n) of its exact value.
 __device__ __forceinline__ double gam(double n) {
   const double t = n * 1.1102230246251565e-16;
   return t / (1.0 - t);
-}
-
-__device__ __forceinline__ int ilog2(int g) {
-  int l = 0;
-  while ((1 << l) < g) ++l;
-  return l;
 }
 
 // Outward allowances of the emitted upper bound.  The lemma on the triangle
@@ -1869,24 +2000,13 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   const int kdi = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
   const double kd = (double)kdi;
   const double cc = 1.0 / (kd * kd);
-  const double rho2 = sqrt((double)J.d) * (double)(J.k - 1);   // twice the largest in-block offset
   double pc = 0, mm = 0;
   for (int e = threadIdx.x; e < J.nnz; e += 256) {
-    pc += cc * J.e_val[e] * J.red_pc[e];
-    if (J.p == 2) {
-      const int K = J.e_row[e], L = J.e_col[e];
-      double D0, D1, D2;
-      block_delta(K, L, J, D0, D1, D2);
-      const double dn = sqrt(D0 * D0 + D1 * D1 + D2 * D2) + rho2;
-      mm += cc * J.e_val[e] * (J.mom_as[5 * (size_t)K] * J.mom_bs[5 * (size_t)L]) * (dn * dn);
-    }
+    const double ce = cc * J.e_val[e];
+    pc += ce * J.red_pc[e];
+    if (J.p == 2) mm += ce * J.red_pm[e];
   }
-  double rmax = 0, cmax = 0;
-  if (J.nnz > 0)
-    for (int K = threadIdx.x; K < J.Q; K += 256) {
-      rmax = fmax(rmax, (double)(J.csr_ptr[K + 1] - J.csr_ptr[K]));
-      cmax = fmax(cmax, (double)(J.csc_ptr[K + 1] - J.csc_ptr[K]));
-    }
+  const double rmax = (double)J.row_max, cmax = (double)J.col_max;
   double tm = 0, tn = 0, wm = 0, wn = 0;
   for (int c = threadIdx.x; c < J.chunks; c += 256) {
     const double* r = J.red_tv + (size_t)c * kRedSlotsTV;
@@ -1895,10 +2015,10 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   // all sums and maxima in one work-group reduction
   {
     double sv[8] = {sf, sg, pc, tm, tn, wm, wn, mm};
-    double mv[5] = {mh, mg, mf, rmax, cmax};
-    block_reduce_many<8, 5>(sv, mv, sh);
+    double mv[3] = {mh, mg, mf};
+    block_reduce_many<8, 3>(sv, mv, sh);
     sf = sv[0]; sg = sv[1]; pc = sv[2]; tm = sv[3]; tn = sv[4]; wm = sv[5]; wn = sv[6]; mm = sv[7];
-    mh = mv[0]; mg = mv[1]; mf = mv[2]; rmax = mv[3]; cmax = mv[4];
+    mh = mv[0]; mg = mv[1]; mf = mv[2];
   }
   if (threadIdx.x != 0) return;
   // float32 feasibility shift (first order in u = 2^-24; see the oracle's derivation)
@@ -1925,8 +2045,7 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   // upper bound with the outward allowances derived above
   const double u53 = 1.1102230246251565e-16;
   const double T = fmax(1.0, res[RS_IPF_ITERS]);
-  const int gp = reduce_group(kdi);
-  const double s_pool = (double)((kdi + gp - 1) / gp - 1 + ilog2(gp));
+  const double s_pool = (double)pool_depth(J);
   const double n_s = 4 + 6 + 3 + (J.chunks + 255) / 256 + 9;   // pixel sums: thread, wave, work-group, chunks
   const double n_e = (J.nnz + 255) / 256 + 9;                   // entry sums
   const double a1 = gam(rmax + 1) + u53;
@@ -1941,7 +2060,7 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   const double Tn = (Zn + enu * (Wn + Zn) / (1.0 - enu)) * (1.0 + 8.0 * u53);
   double Pv;
   if (J.p == 2)
-    Pv = pc + (2.0 * gam(kd + 3) + gam(16) + 2.0 * gam(n_e + 4)) * mm * (1.0 + gam(n_e + 8));
+    Pv = pc + (2.0 * gam(kd + 3) + gam(16) + 2.0 * gam(n_e + 4)) * mm * (1.0 + gam(n_e + 10));
   else
     Pv = pc * (1.0 + gam(kd * kd + J.nnz + 8) + 0x1p-41);
   const double pe = Pv * (1.0 + eG + eO + 6.0 * u53) * (1.0 + 4.0 * u53);
@@ -2023,7 +2142,9 @@ __global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, i
 }
 
 // Block moments about the block centre (5 slots): which = 0 -> (mu, nu) into
-// (mom_mu, mom_nu); which = 1 -> (a_s, b_s) into (mom_as, mom_bs).
+// (mom_mu, mom_nu); which = 1 -> (a_s, b_s) into (mom_as, mom_bs); which = 2
+// -> as 0, and also the pooled masses (SumPool: the block sums, slot 0) into
+// (mu_t, nu_t) and the input checks (negative entry, NaN) into the job's flags.
 //
 // k <= 64: one work-group per strip of blocks along the last axis (the k or
 // k^2 pixel rows of one block row), both fields.  The strip goes in chunks of
@@ -2031,7 +2152,9 @@ __global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, i
 // 256 / Wc threads that split the strip's rows, every thread sums its share
 // of a column (coalesced row reads), and each block's k columns and their
 // row shares are then added in a fixed order from LDS.  k > 64: one lane group per
-// (side, block) as in k_pool (block rows are then long enough to coalesce).
+// (side, block), g lanes summing every g-th pixel, then a butterfly (block
+// rows are then long enough to coalesce).  pool_depth gives the additions a
+// block sum takes.
 __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs, int njobs,
                                                  const int* __restrict__ off, int total, int which) {
   __shared__ double cs[5][256];
@@ -2050,17 +2173,20 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
       const int nrows = J.d == 2 ? k : k * k;
       const double h = 0.5 * (k - 1);
       for (int side = 0; side < 2; ++side) {
-        const double* m = which == 0 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
-        double* mo = which == 0 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs);
+        const double* m = which != 1 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
+        double* mo = which != 1 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs);
+        double* pooled = which == 2 ? (side == 0 ? J.mu_t : J.nu_t) : nullptr;
         for (int c0 = 0; c0 < N; c0 += W) {
           const int x2 = c0 + col;
           double s0 = 0.0, s1 = 0.0, s2 = 0.0, s4 = 0.0;
+          int bad = 0;
           if (rg < RG && x2 < N) {
             for (int r = rg; r < nrows; r += RG) {
               const int u0 = J.d == 2 ? 0 : r / k, u1 = J.d == 2 ? r : r - (r / k) * k;
               const size_t row = J.d == 2 ? (size_t)(b1 * k + u1)
                                           : ((size_t)(b0 * k + u0) * N + (size_t)(b1 * k + u1));
               const double w = m[row * N + x2];
+              bad |= (w < 0.0 ? 1 : 0) | (w != w ? 2 : 0);
               const double d0 = J.d == 2 ? 0.0 : u0 - h, d1 = u1 - h;
               s0 += w;
               s1 += w * d0;
@@ -2068,6 +2194,7 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
               s4 += w * (d0 * d0 + d1 * d1);
             }
           }
+          if (bad && which == 2) atomicOr(J.flags, bad);
           const double d2 = (double)(x2 % k) - h;
           __syncthreads();
           cs[0][threadIdx.x] = s0;
@@ -2095,6 +2222,7 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
             double v = 0.0;
             for (int c = 0; c < k; ++c) v += cs[q][bq * k + c];
             mo[5 * (size_t)K + q] = v;
+            if (q == 0 && pooled) pooled[K] = v;
           }
         }
       }
@@ -2107,9 +2235,10 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
     const int sub = lane & (g - 1);
     const bool ok = idx < 2 * J.Q;
     const int side = ok ? idx / J.Q : 0, K = ok ? idx - side * J.Q : 0;
-    const double* m = which == 0 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
+    const double* m = which != 1 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
     const double h = 0.5 * (J.k - 1);
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+    int bad = 0;
     if (ok) {
       for (int a = sub; a < mm; a += g) {
         const int i = block_member(K, a, J.N, J.n, J.k, J.d);
@@ -2117,6 +2246,7 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
         pix_coords(a, J.k, J.d, u0, u1, u2);
         const double d0 = J.d == 2 ? 0.0 : u0 - h, d1 = u1 - h, d2 = u2 - h;
         const double w = m[i];
+        bad |= (w < 0.0 ? 1 : 0) | (w != w ? 2 : 0);
         s0 += w;
         s1 += w * d0; s2 += w * d1; s3 += w * d2;
         s4 += w * (d0 * d0 + d1 * d1 + d2 * d2);
@@ -2124,9 +2254,11 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
     }
     s0 = group_sum(s0, g); s1 = group_sum(s1, g); s2 = group_sum(s2, g);
     s3 = group_sum(s3, g); s4 = group_sum(s4, g);
+    if (bad && which == 2) atomicOr(J.flags, bad);
     if (ok && sub == 0) {
-      double* o = (which == 0 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs)) + 5 * (size_t)K;
+      double* o = (which != 1 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs)) + 5 * (size_t)K;
       o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3; o[4] = s4;
+      if (which == 2) (side == 0 ? J.mu_t : J.nu_t)[K] = s0;
     }
   }
 }
@@ -2156,15 +2288,49 @@ __global__ __launch_bounds__(256) void k_lb_grad(const DevJob* __restrict__ jobs
 // Produces d P / d mu~ (gbar_mu), d P / d nu~ (gbar_nu) and, per support
 // entry, coef_e = k^(-2d) pi~_e / (u^T_K v^T_L), the weight of
 // S_e = sum mu_i nu_j c_ij in P.
+// Quadratic coefficients of the direct upper-bound gradient term for p = 2
+// at block K: both sides' h(x) = A |z|^2 + B.z + C, z = x - centre of K, from
+// the other side's block moments and the entries' coefficients.
+__device__ void grad2_quad_block(const DevJob& J, const CoarseView& C, int K) {
+  const int n = J.n;
+  int k0, k1, k2;
+  pix_coords(K, n, J.d, k0, k1, k2);
+  for (int side = 0; side < 2; ++side) {
+    const double* omom = side == 0 ? J.mom_nu : J.mom_mu;
+    const int e0 = side == 0 ? C.csr[K] : C.csc[K];
+    const int e1 = side == 0 ? C.csr[K + 1] : C.csc[K + 1];
+    double A = 0.0, B0 = 0.0, B1 = 0.0, B2 = 0.0, Cc = 0.0;
+    for (int q = e0; q < e1; ++q) {
+      const int e = side == 0 ? q : C.cidx[q];
+      const int O = side == 0 ? C.ecol[e] : C.erow[e];
+      int o0, o1, o2;
+      pix_coords(O, n, J.d, o0, o1, o2);
+      const double D0 = J.d == 2 ? 0.0 : (double)(J.k * (k0 - o0));
+      const double D1 = (double)(J.k * (k1 - o1)), D2 = (double)(J.k * (k2 - o2));
+      const double* W = omom + 5 * (size_t)O;
+      const double cf = J.coef[e];
+      A += cf * W[0];
+      B0 += cf * (2.0 * W[0] * D0 - 2.0 * W[1]);
+      B1 += cf * (2.0 * W[0] * D1 - 2.0 * W[2]);
+      B2 += cf * (2.0 * W[0] * D2 - 2.0 * W[3]);
+      Cc += cf * (W[0] * (D0 * D0 + D1 * D1 + D2 * D2) - 2.0 * (D0 * W[1] + D1 * W[2] + D2 * W[3]) + W[4]);
+    }
+    double* o = J.gquad + (size_t)10 * K + 5 * side;
+    o[0] = A; o[1] = B0; o[2] = B1; o[3] = B2; o[4] = Cc;
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict__ jobs, int njobs,
                                                         double* __restrict__ scratch_all,
-                                                        int stride) {
+                                                        int stride, size_t lds_bytes) {
+  extern __shared__ double lds[];
   const DevJob& J = jobs[blockIdx.x];
   const int Q = J.Q;
   const int T = (int)J.result[RS_IPF_ITERS];
   const double kd = J.d == 2 ? (double)J.k * J.k : (double)J.k * J.k * J.k;
   const double cc = 1.0 / (kd * kd);
-  double* sc = scratch_all + (size_t)blockIdx.x * 4 * stride;  // stride >= every job's Q
+  const CoarseView C = coarse_view(J, lds, lds_bytes, 4);
+  double* sc = C.in_lds ? C.vec : scratch_all + (size_t)blockIdx.x * 4 * stride;  // stride >= every job's Q
   double* ub = sc;          // adjoint of u^t
   double* vb = sc + Q;      // adjoint of v^t
   double* Ab = sc + 2 * Q;  // adjoint of A^t
@@ -2172,22 +2338,25 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
   const double* uT = J.ipf_u + (size_t)T * Q;
   const double* vT = J.ipf_v + (size_t)T * Q;
   for (int e = threadIdx.x; e < J.nnz; e += 1024) {
-    const int K = J.e_row[e], L = J.e_col[e];
-    J.coef[e] = (uT[K] > 0.0 && vT[L] > 0.0) ? cc * J.e_val[e] / (uT[K] * vT[L]) : 0.0;
+    const int K = C.erow[e], L = C.ecol[e];
+    J.coef[e] = (uT[K] > 0.0 && vT[L] > 0.0) ? cc * C.ev[e] / (uT[K] * vT[L]) : 0.0;
   }
   for (int K = threadIdx.x; K < Q; K += 1024) { J.gbar_mu[K] = 0.0; J.gbar_nu[K] = 0.0; }
   __syncthreads();
+  // p = 2: the direct term's per-block quadratic (needs the coefficients above)
+  if (J.p == 2)
+    for (int K = threadIdx.x; K < Q; K += 1024) grad2_quad_block(J, C, K);
   // direct terms: P = sum_e cc val_e red_pc[e], red_pc = S_e / (u_K v_L)
   for (int K = threadIdx.x; K < Q; K += 1024) {
     double s = 0.0;
-    for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) s += cc * J.e_val[e] * J.red_pc[e];
+    for (int e = C.csr[K]; e < C.csr[K + 1]; ++e) s += cc * C.ev[e] * J.red_pc[e];
     ub[K] = uT[K] > 0.0 ? -s / uT[K] : 0.0;
   }
   for (int L = threadIdx.x; L < Q; L += 1024) {
     double s = 0.0;
-    for (int q = J.csc_ptr[L]; q < J.csc_ptr[L + 1]; ++q) {
-      const int e = J.csc_idx[q];
-      s += cc * J.e_val[e] * J.red_pc[e];
+    for (int q = C.csc[L]; q < C.csc[L + 1]; ++q) {
+      const int e = C.cidx[q];
+      s += cc * C.ev[e] * J.red_pc[e];
     }
     vb[L] = vT[L] > 0.0 ? -s / vT[L] : 0.0;
   }
@@ -2197,7 +2366,7 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
     // v^t = cc pi^T A^t  ->  Ab
     for (int K = threadIdx.x; K < Q; K += 1024) {
       double s = 0.0;
-      for (int e = J.csr_ptr[K]; e < J.csr_ptr[K + 1]; ++e) s += J.e_val[e] * vb[J.e_col[e]];
+      for (int e = C.csr[K]; e < C.csr[K + 1]; ++e) s += C.ev[e] * vb[C.ecol[e]];
       Ab[K] = cc * s;
     }
     __syncthreads();
@@ -2214,9 +2383,9 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
     // u^t = cc pi B^{t-1}  ->  Bb
     for (int L = threadIdx.x; L < Q; L += 1024) {
       double s = 0.0;
-      for (int q = J.csc_ptr[L]; q < J.csc_ptr[L + 1]; ++q) {
-        const int e = J.csc_idx[q];
-        s += J.e_val[e] * ub[J.e_row[e]];
+      for (int q = C.csc[L]; q < C.csc[L + 1]; ++q) {
+        const int e = C.cidx[q];
+        s += C.ev[e] * ub[C.erow[e]];
       }
       Bb[L] = cc * s;
     }
@@ -2252,41 +2421,6 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
 //   A = sum coef_e W0,  B = sum coef_e (2 W0 D_e - 2 W1),
 //   C = sum coef_e (W0 |D_e|^2 - 2 D_e.W1 + W2).
 // One thread per coarse block and side writes (A, B0, B1, B2, C).
-__global__ __launch_bounds__(256) void k_grad2_quad(const DevJob* __restrict__ jobs, int njobs,
-                                                    const int* __restrict__ off, int total) {
-  for (int gi = blockIdx.x * blockDim.x + threadIdx.x; gi < total; gi += gridDim.x * blockDim.x) {
-    const int jb = find_job(off, njobs, gi);
-    const DevJob& J = jobs[jb];
-    if (J.p != 2) continue;
-    const int K = gi - off[jb];
-    const int n = J.n;
-    int k0, k1, k2;
-    pix_coords(K, n, J.d, k0, k1, k2);
-    for (int side = 0; side < 2; ++side) {
-      const double* omom = side == 0 ? J.mom_nu : J.mom_mu;
-      const int e0 = side == 0 ? J.csr_ptr[K] : J.csc_ptr[K];
-      const int e1 = side == 0 ? J.csr_ptr[K + 1] : J.csc_ptr[K + 1];
-      double A = 0.0, B0 = 0.0, B1 = 0.0, B2 = 0.0, C = 0.0;
-      for (int q = e0; q < e1; ++q) {
-        const int e = side == 0 ? q : J.csc_idx[q];
-        const int O = side == 0 ? J.e_col[e] : J.e_row[e];
-        int o0, o1, o2;
-        pix_coords(O, n, J.d, o0, o1, o2);
-        const double D0 = J.d == 2 ? 0.0 : (double)(J.k * (k0 - o0));
-        const double D1 = (double)(J.k * (k1 - o1)), D2 = (double)(J.k * (k2 - o2));
-        const double* W = omom + 5 * (size_t)O;
-        const double cf = J.coef[e];
-        A += cf * W[0];
-        B0 += cf * (2.0 * W[0] * D0 - 2.0 * W[1]);
-        B1 += cf * (2.0 * W[0] * D1 - 2.0 * W[2]);
-        B2 += cf * (2.0 * W[0] * D2 - 2.0 * W[3]);
-        C += cf * (W[0] * (D0 * D0 + D1 * D1 + D2 * D2) - 2.0 * (D0 * W[1] + D1 * W[2] + D2 * W[3]) + W[4]);
-      }
-      double* o = J.gquad + (size_t)10 * K + 5 * side;
-      o[0] = A; o[1] = B0; o[2] = B1; o[3] = B2; o[4] = C;
-    }
-  }
-}
 
 // Gradients of dl * lower + du * upper for p = 2 jobs, one thread per pixel
 // (coalesced): the lower-bound term s_L f_i (resp. s_L g_j), then the
@@ -2917,11 +3051,6 @@ __global__ __launch_bounds__(256) void k_kub_grad_out(KubJob J, double dupper, d
 
 static inline int grid_for(int total, int cap = 65535) { return total < 1 ? 1 : (total < cap ? total : cap); }
 
-int launch_pool(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
-  hipLaunchKernelGGL(k_pool, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
-  HIP_TRY(hipGetLastError());
-  return QBW_OK;
-}
 int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
   hipLaunchKernelGGL(k_upscale, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
   HIP_TRY(hipGetLastError());
@@ -2960,8 +3089,8 @@ int launch_argmin(const DevJob* jobs, int njobs, const int* off, int total, int 
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_ipf(const DevJob* jobs, int njobs, void* stream) {
-  hipLaunchKernelGGL(k_ipf, dim3(njobs), dim3(1024), 0, (hipStream_t)stream, jobs, njobs);
+int launch_ipf(const DevJob* jobs, int njobs, size_t lds_bytes, void* stream) {
+  hipLaunchKernelGGL(k_ipf, dim3(njobs), dim3(1024), lds_bytes, (hipStream_t)stream, jobs, njobs, lds_bytes);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
@@ -2997,6 +3126,9 @@ int launch_finalize(const DevJob* jobs, int njobs, void* stream) {
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
+int launch_pool(const DevJob* jobs, int njobs, const int* off_mom, int total_mom, void* stream) {
+  return launch_moments(jobs, njobs, off_mom, total_mom, 2, stream);
+}
 int launch_moments(const DevJob* jobs, int njobs, const int* off, int total, int which, void* stream) {
   hipLaunchKernelGGL(k_moments, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, which);
   HIP_TRY(hipGetLastError());
@@ -3013,8 +3145,10 @@ int launch_lb_grad(const DevJob* jobs, int njobs, const int* off, int total, con
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int stride, void* stream) {
-  hipLaunchKernelGGL(k_ub_coarse_bwd, dim3(njobs), dim3(1024), 0, (hipStream_t)stream, jobs, njobs, scratch, stride);
+int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int stride, size_t lds_bytes,
+                          void* stream) {
+  hipLaunchKernelGGL(k_ub_coarse_bwd, dim3(njobs), dim3(1024), lds_bytes, (hipStream_t)stream, jobs, njobs, scratch,
+                     stride, lds_bytes);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
@@ -3049,12 +3183,6 @@ int launch_ub_grad_sum(const DevJob* jobs, int njobs, const int* off, int total,
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_grad2_quad(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
-  const int blocks = total < 1 ? 1 : std::min((total + 255) / 256, 65535);
-  hipLaunchKernelGGL(k_grad2_quad, dim3(blocks), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
-  HIP_TRY(hipGetLastError());
-  return QBW_OK;
-}
 int launch_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl, const double* du,
                  void* stream) {
   hipLaunchKernelGGL(k_grad2, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, dl, du);
@@ -3086,16 +3214,30 @@ int launch_xs_squares(double* t, void* stream) {
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
+template <bool FIRST>
+static void launch_xs_kind(int T, bool arg, int waves, const DevJob* jobs, int njobs, const int* off, int total,
+                           int phase, int k, const double* sqt, int2* list, int* count, hipStream_t st) {
+  const dim3 g(grid_for(total)), b(64 * waves);
+  const size_t lds = xs_lds_bytes(FIRST, T, arg, waves);
+  if (arg) {
+    if (T == 2) hipLaunchKernelGGL((k_xs_stage<FIRST, 2, true>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
+    else if (T == 4) hipLaunchKernelGGL((k_xs_stage<FIRST, 4, true>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
+    else hipLaunchKernelGGL((k_xs_stage<FIRST, 8, true>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
+  } else {
+    if (T == 2) hipLaunchKernelGGL((k_xs_stage<FIRST, 2, false>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
+    else if (T == 4) hipLaunchKernelGGL((k_xs_stage<FIRST, 4, false>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
+    else if (T == 16) hipLaunchKernelGGL((k_xs_stage<FIRST, 16, false>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
+    else hipLaunchKernelGGL((k_xs_stage<FIRST, 8, false>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
+  }
+}
+
 int launch_xs_stage(const DevJob* jobs, int njobs, const int* off, int total, int phase, int k, const double* sqt,
-                    int* list, int* count, void* stream) {
+                    int* list, int* count, int T, int argmin, int waves, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   int2* l2 = reinterpret_cast<int2*>(list);
-  if (k == 0)
-    hipLaunchKernelGGL(k_xs_stage<true>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, 0,
-                       sqt, l2, count);
-  else
-    hipLaunchKernelGGL(k_xs_stage<false>, dim3(grid_for(total)), dim3(64), 0, st, jobs, njobs, off, total, phase, k,
-                       sqt, l2, count);
+  if (argmin) waves = 1;
+  if (k == 0) launch_xs_kind<true>(T, argmin != 0, waves, jobs, njobs, off, total, phase, 0, sqt, l2, count, st);
+  else launch_xs_kind<false>(T, argmin != 0, waves, jobs, njobs, off, total, phase, k, sqt, l2, count, st);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -98,6 +98,8 @@ struct DevJob {
   double* red_lb;           // chunks x kRedSlotsLB
   double* red_tv;           // chunks x kRedSlotsTV
   double* red_pc;           // nnz: per-entry sum of a_s b_s c
+  double* red_pm;           // nnz (p = 2): per-entry bound on the absolute values of the moment form's terms
+  int row_max, col_max;     // longest row and column of the coarse coupling (entries)
   double* result;           // RS_COUNT doubles
   int* flags;               // bit 0: negative entry, bit 1: NaN (pool kernel)
   // backward
@@ -188,7 +190,9 @@ struct Launch {
   int total;           // total items
 };
 
-int launch_pool(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+// SumPool of both measures with their block moments and the input checks
+// (k_moments, which = 2), over the plan's moment items.
+int launch_pool(const DevJob* jobs, int njobs, const int* off_mom, int total_mom, void* stream);
 int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 constexpr int kQueues = 8;  // XCDs: the planner groups c-transform items per XCD
 // Waves of k_ctransform resident per compute unit (0 if the runtime cannot say).
@@ -206,14 +210,23 @@ int launch_sqrt_table(float* t, int n, void* stream);
 // pixel count) and `count` their number (zero before stage 0).
 constexpr int kXsSquares = 2 * 2904 + 1;
 int launch_xs_squares(double* t, void* stream);
+// T: the plan's targets per lane (every job's xs_T); argmin: the plan wants
+// arg-mins; waves: waves per work-group splitting an item's sources (1, 2, 4;
+// 1 with arg-mins).
 int launch_xs_stage(const DevJob* jobs, int njobs, const int* off, int total, int phase, int k, const double* sqt,
-                    int* list, int* count, void* stream);
+                    int* list, int* count, int T, int argmin, int waves, void* stream);
 int launch_xs_fallback(const DevJob* jobs, const int* list, const int* count, int phase, int grid, void* stream);
 int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter, int phase, int grid,
                       void* stream);
 int launch_merge(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
 int launch_argmin(const DevJob* jobs, int njobs, const int* off, int total, int phase, void* stream);
-int launch_ipf(const DevJob* jobs, int njobs, void* stream);
+// Coarse kernels (one work-group per job) stage the coupling and nvec
+// per-block vectors in LDS when the job's bytes fit the launch's allocation.
+constexpr size_t kCoarseLdsMax = 160 * 1024;
+constexpr size_t coarse_lds_need(int Q, int nnz, int nvec) {
+  return 8 * ((size_t)nvec * Q + (size_t)nnz) + 4 * (2 * (size_t)(Q + 1) + 3 * (size_t)nnz) + 16;
+}
+int launch_ipf(const DevJob* jobs, int njobs, size_t lds_bytes, void* stream);
 int launch_scalings(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_tv_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 // p = 1 plan cost and upper-bound gradient on blocks of m = k^d pixels: the
@@ -242,7 +255,11 @@ int launch_cbar2(const DevJob* jobs, int njobs, const int* off, int total, doubl
                  void* stream);
 int launch_lb_grad(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
                    void* stream);
-int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int stride, void* stream);
+// The coarse reverse pass of the fitting; for p = 2 jobs it also writes the
+// per-block quadratics of the direct gradient term (block moments of mu, nu
+// must be current).
+int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int stride, size_t lds_bytes,
+                          void* stream);
 int launch_ub_grad(const DevJob* jobs, int njobs, const P1Items& items, const double* du, int side,
                    void* stream);
 int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
@@ -251,7 +268,6 @@ int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, 
 int launch_pc1_sum(const DevJob* jobs, int njobs, void* stream);
 int launch_ub_grad_sum(const DevJob* jobs, int njobs, const int* off, int total, const double* du, int side,
                        void* stream);
-int launch_grad2_quad(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl, const double* du,
                  void* stream);
 int launch_tv_prep(const DevJob* jobs, int njobs, void* stream);

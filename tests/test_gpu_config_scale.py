@@ -59,10 +59,13 @@ def ub_tol(mu, nu, N, d, p, k, ub, rows, cols, iters):
     r = int(np.bincount(np.asarray(rows)).max())
     c = int(np.bincount(np.asarray(cols)).max())
     m = k ** d
-    g = 1
-    while g < min(m, 64):
-        g *= 2
-    s_pool = -(-m // g) - 1 + int(math.log2(g))
+    if k <= 64:   # the pooled block sums' depth (strips of blocks, row groups, the block's columns)
+        Wc = min((256 // k) * k, N)
+        RG = 256 // Wc
+        s_pool = -(-k ** (d - 1) // RG) - 1 + (RG - 1) + (k - 1)
+    else:         # lane groups: every g-th pixel, then a butterfly
+        g = 64
+        s_pool = -(-m // g) - 1 + 6
     T = max(1, int(iters))
     e = 2 * (r + 2) + (2 * T - 1) * (r + c + 2 * s_pool + 6) + 2 + 14 * T
     c1 = 2.0 ** (1 - 1 / p)

@@ -50,7 +50,7 @@ def ub_tol(mu, nu, N, d, p, k, ub, rows, cols, iters):
     """Room above the oracle's upper bound.  Inside each weighted-TV term the
     library adds e u (<w, mu> + T), e bounding the relative error of the fitted
     marginals after `iters` iterations against exact arithmetic, for its own
-    iteration (longest coupling row r and column c, pooled block sums s_p deep)
+    iteration (longest coupling row r and column c, pooled block sums s_p additions deep)
     plus a float64 reference's (14 T); allowed here: twice that inside the
     root, on top of 1e-9 relative for the float64 sums."""
     w = upper.tv_weights(N, d, p)
@@ -58,10 +58,13 @@ def ub_tol(mu, nu, N, d, p, k, ub, rows, cols, iters):
     r = int(np.bincount(np.asarray(rows)).max())
     c = int(np.bincount(np.asarray(cols)).max())
     m = k ** d
-    g = 1
-    while g < min(m, 64):
-        g *= 2
-    s_pool = -(-m // g) - 1 + int(math.log2(g))
+    if k <= 64:   # the pooled block sums' depth (strips of blocks, row groups, the block's columns)
+        Wc = min((256 // k) * k, N)
+        RG = 256 // Wc
+        s_pool = -(-k ** (d - 1) // RG) - 1 + (RG - 1) + (k - 1)
+    else:         # lane groups: every g-th pixel, then a butterfly
+        g = 64
+        s_pool = -(-m // g) - 1 + 6
     T = max(1, int(iters))
     e = 2 * (r + 2) + (2 * T - 1) * (r + c + 2 * s_pool + 6) + 2 + 14 * T
     c1 = 2.0 ** (1 - 1 / p)
