@@ -45,6 +45,47 @@ XS_INSTR_PER_CAND_ARGMIN = 6
 PEAK_XS = PEAK_F64_LANE_OPS / XS_INSTR_PER_CAND
 
 
+# The paper's own figures (Section 5, NVIDIA L40 GPU + AMD EPYC 9654 CPU, JAX
+# for the bounds, an exact network-simplex solver for the reference), as
+# percentages, each pair [kappa = 2, kappa = 4]: relative errors against the
+# exact distance (accuracy table, DOTmark classes at 128x128) and computation
+# time relative to the exact solver (DOTmark time table; 3D cryo-EM time
+# table at 32^3).  Other hardware, other data: context, not a target.
+PAPER_CONTEXT = {
+    "hardware": "NVIDIA L40 GPU + AMD EPYC 9654 CPU; bounds in JAX, exact OT by network simplex (Section 5)",
+    "units": "percent; each entry [kappa=2, kappa=4]",
+    "relative_error_dotmark_128": {
+        "dual_upscaling_lower": {"classic": {"p1": [0.3, 0.7], "p2": [0.7, 2.4]},
+                                 "microscopy": {"p1": [0.4, 0.9], "p2": [0.2, 0.7]},
+                                 "shapes": {"p1": [0.5, 1.0], "p2": [0.9, 1.7]}},
+        "primal_upscaling_upper": {"classic": {"p1": [9.6, 23.0], "p2": [2.2, 8.8]},
+                                   "microscopy": {"p1": [2.4, 6.5], "p2": [0.7, 2.7]},
+                                   "shapes": {"p1": [3.2, 7.8], "p2": [1.4, 3.6]}},
+        "weighted_cost_upper": {"classic": {"p1": [3.1, 11.0], "p2": [1.6, 7.9]},
+                                "microscopy": {"p1": [0.9, 3.4], "p2": [0.5, 2.2]},
+                                "shapes": {"p1": [1.1, 3.6], "p2": [1.2, 3.2]}},
+        "min_cost_lower": {"classic": {"p1": [10.0, 27.0], "p2": [13.0, 33.0]},
+                           "microscopy": {"p1": [6.2, 17.0], "p2": [5.5, 16.0]},
+                           "shapes": {"p1": [7.3, 20.0], "p2": [7.7, 20.0]}}},
+    "relative_time_dotmark": {
+        "dual_upscaling_lower": {"classic": {"p1": [4.9, 0.2], "p2": [6.1, 0.3]},
+                                 "microscopy": {"p1": [14.4, 2.2], "p2": [15.6, 2.0]},
+                                 "shapes": {"p1": [7.8, 1.5], "p2": [7.4, 1.2]}},
+        "primal_upscaling_upper": {"classic": {"p1": [5.0, 0.3], "p2": [6.1, 0.3]},
+                                   "microscopy": {"p1": [20.7, 6.6], "p2": [17.4, 3.0]},
+                                   "shapes": {"p1": [15.1, 10.8], "p2": [9.6, 4.2]}},
+        "weighted_cost_upper": {"classic": {"p1": [4.4, 0.3], "p2": [6.1, 0.4]},
+                                "microscopy": {"p1": [16.7, 2.3], "p2": [15.4, 1.9]},
+                                "shapes": {"p1": [10.2, 1.9], "p2": [7.9, 1.5]}}},
+    "relative_time_cryoem_32cubed": {
+        "dual_upscaling_lower": {"p1": [0.55, 0.33], "p2": [0.19, 0.04]},
+        "primal_upscaling_upper": {"p1": [1.09, 27.23], "p2": [0.30, 0.16]},
+        "weighted_cost_upper": {"p1": [0.22, 0.12], "p2": [0.22, 0.06]},
+        "min_cost_lower": {"p1": [0.20, 0.11], "p2": [0.21, 0.04]}},
+    "absolute_throughput": None,
+}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -260,11 +301,34 @@ def main():
     t0 = time.perf_counter()
     mts = [qbw.sumpool(a, k).cpu().numpy() for a in A]
     nts = [qbw.sumpool(b, k).cpu().numpy() for b in Bm]
+    t_pool = time.perf_counter() - t0
     workers = min(os.cpu_count() or 1, 16)
-    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
-        recs = list(ex.map(lambda t: qbw.coarse_solve(t[0], t[1], N, d, k, p), zip(mts, nts)))
-    t_coarse = time.perf_counter() - t0
-    log(f"[bench] coarse solves: {t_coarse:.2f} s for {B} pairs on {workers} threads")
+
+    def solve_all(dense: bool):
+        if dense:
+            os.environ["QBW_COARSE_SOLVER"] = "dense"
+        try:
+            t = time.perf_counter()
+            with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+                rs = list(ex.map(lambda t: qbw.coarse_solve(t[0], t[1], N, d, k, p), zip(mts, nts)))
+            return rs, time.perf_counter() - t
+        finally:
+            os.environ.pop("QBW_COARSE_SOLVER", None)
+
+    # the library's multiscale start against pricing every block pair from the
+    # first pivot, on the same pooled masses, each the best of two rounds
+    runs = {False: [], True: []}
+    for _ in range(2):
+        for dense in (True, False):
+            runs[dense].append(solve_all(dense))
+    recs = runs[False][-1][0]
+    recs_d = runs[True][-1][0]
+    t_solve = min(t for _, t in runs[False])
+    t_coarse_dense = min(t for _, t in runs[True])
+    t_coarse = t_pool + t_solve
+    same_obj = all(abs(x.objective - y.objective) <= 1e-12 * abs(y.objective) for x, y in zip(recs, recs_d))
+    log(f"[bench] coarse: pooling + transfer {t_pool:.3f} s, solves {t_solve:.3f} s (multiscale start), "
+        f"{t_coarse_dense:.3f} s (dense start) for {B} pairs on {workers} threads; same objectives: {same_obj}")
 
     grads = [(torch.zeros_like(a), torch.zeros_like(b)) for a, b in zip(A, Bm)]
     jobs = [(a, b, k, p, ga, gb) for (a, b), (ga, gb) in zip(zip(A, Bm), grads)]
@@ -492,6 +556,9 @@ def main():
                                    "per-axis float64 minima, certified per target" if mode else
                                    "all-pairs (lazy) kernel")},
         "roofline": roof,
+        "roofline_note": ("the c-transform roofline target is judged on the timed path's kernel, "
+                          + ("k_xs_stage (exact separable stages); the all-pairs k_ctransform is reported "
+                             "beside it under all_pairs" if mode else "k_ctransform (all-pairs)")),
         ("all_pairs" if mode else "exact_separable"): {
             "pairs_per_s": B / (ms_other / 1e3), "ms_per_step": ms_other,
             "bounds_identical": same, "roofline": roof_other},
@@ -502,10 +569,16 @@ def main():
                                  "float32 rounding once per axis, larger derived shift",
                          "lower_sample": rsep[0]["lower"], "upper_sample": rsep[0]["upper"]},
         "end_to_end": {"coarse_seconds": t_coarse, "host_threads": workers,
+                       "coarse_solver": "host network simplex, multiscale start (half-resolution problem "
+                                        "solved first, its support's children priced first, optimality "
+                                        "checked over every block pair)",
+                       "coarse_pool_seconds": t_pool, "coarse_solve_seconds": t_solve,
+                       "coarse_solve_seconds_dense_start": t_coarse_dense, "same_objectives": same_obj,
                        "pairs_per_s_sequential": B / (t_coarse + ms_step / 1e3),
                        "pairs_per_s_pipelined": B / max(t_coarse, ms_step / 1e3)},
         "bounds_sample": {"lower": res[0]["lower"], "upper": res[0]["upper"]},
     }
+    out["paper_context"] = PAPER_CONTEXT
     if uneven is not None:
         out["uneven_batch"] = uneven
     out["upper_kernel"] = upper_kernel
