@@ -292,12 +292,16 @@ struct Plan {
   int xs_T = 8, xs_W = 1;  // targets per lane and waves per work-group of the stages
   size_t ipf_lds = 0;      // dynamic LDS of the coarse fitting kernel (jobs that do not fit use global memory)
   size_t bwd_lds = 0;      // the same for the coarse backward kernel
+  bool fwd_rev = false;    // a backward pass follows: the forward's coarse kernel runs its p = 2 reverse pass
   const double* xs_sq = nullptr;
   P1Items p1_tab{};        // p = 1 plan-cost / gradient items per kernel kind
   CtItem* items = nullptr;
   int n_items = 0;
   int ct_grid = 1;
-  int* ints = nullptr;   // ints[0], ints[kQueues]: the two phases' tail counters; from 2 kQueues: njobs flags
+  // ints[0], ints[kQueues]: the two phases' tail counters; ints[2 kQueues + 0,
+  // 1]: the phases' brute-force queue lengths (all zeroed by the pixel sweep
+  // for the next step); then njobs input flags
+  int* ints = nullptr;
   int n_ints = 0;
   double* dl = nullptr;  // per-job upstream gradients
   double* du = nullptr;
@@ -448,6 +452,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   pl.in = std::move(in);
   pl.njobs = (int)pl.in.size();
   pl.mode = mode;
+  pl.fwd_rev = (mode & PM_BACKWARD) != 0;
   pl.max_iter = o.max_ipf_iter;
   pl.xi = o.xi;
   const int NJ = pl.njobs;
@@ -509,8 +514,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   std::vector<CtItem> items;
   const int G = build_ct_items(ctx, pl.in, mode, items);
   pl.n_items = (int)items.size();
-  pl.n_ints = 2 * kQueues + NJ + 2;   // + the two phases' brute-force queue lengths
-  const size_t o_ints = L.add(sizeof(int) * pl.n_ints);
+  pl.n_ints = 2 * kQueues + 2 + NJ;
   const size_t o_res = L.add(8 * (size_t)RS_COUNT * NJ);
   size_t maxQ = 1;
   for (auto& J : pl.in) maxQ = std::max<size_t>(maxQ, ipow(J.g.N / J.g.k, J.g.d));
@@ -524,6 +528,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   const size_t o_items = L.add(sizeof(CtItem) * std::max(1, pl.n_items));
   const size_t o_dl = L.add(8 * NJ), o_du = L.add(8 * NJ);
   const size_t o_ptrs = L.add(sizeof(double*) * 4 * NJ);
+  const size_t o_ints = L.add(sizeof(int) * pl.n_ints);   // zero at the start
   for (int j = 0; j < NJ; ++j) {
     const auto& J = pl.in[j];
     const int Q = ipow(J.g.N / J.g.k, J.g.d);
@@ -644,7 +649,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
       }
     }
     D.result = (double*)(B + o_res) + (size_t)RS_COUNT * j;
-    D.flags = (int*)(B + o_ints) + 2 * kQueues + j;
+    D.flags = (int*)(B + o_ints) + 2 * kQueues + 2 + j;
     D.grad_a = J.ga;
     D.grad_b = J.gb;
     D.gbar_mu = (double*)(B + O.gbar_mu);
@@ -781,6 +786,7 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   put(o_offs, off.data(), sizeof(int) * off.size());
   put(o_items, items.data(), sizeof(CtItem) * items.size());
   std::memset(at(o_ptrs), 0, sizeof(double*) * 4 * NJ);
+  std::memset(at(o_ints), 0, sizeof(int) * pl.n_ints);
   {
     const std::vector<double> ones(NJ, 1.0);
     put(o_dl, ones.data(), 8 * (size_t)NJ);
@@ -817,7 +823,7 @@ static int enqueue_sep(Plan& pl, int phase, hipStream_t st) {
 
 // The queue lengths sit after the jobs' flags in pl.ints and are cleared with
 // the other counters at the start of a forward pass.
-static int* xs_count(Plan& pl, int phase) { return pl.ints + 2 * kQueues + pl.njobs + phase; }
+static int* xs_count(Plan& pl, int phase) { return pl.ints + 2 * kQueues + phase; }
 
 // Events around a launch when the batch's c-transform timing is on.
 template <typename F>
@@ -852,6 +858,15 @@ static int enqueue_xs(Plan& pl, int phase, hipStream_t st) {
   return launch_xs_fallback(pl.djobs, pl.xs_list, cnt, phase, std::max(1, std::min(pl.xs_pixels, 4096)), st);
 }
 
+static int enqueue_plancost_p1(Plan& pl, hipStream_t st) {
+  const int NJ = pl.njobs;
+  if (pl.p1_tab.total[0] + pl.p1_tab.total[1] + pl.p1_tab.total[2]) {
+    CHK(launch_plancost(pl.djobs, NJ, pl.p1_tab, st));
+    CHK(launch_pc1_sum(pl.djobs, NJ, st));
+  }
+  return QBW_OK;
+}
+
 static int enqueue_ctransforms(Plan& pl, hipStream_t st) {
   const int NJ = pl.njobs;
   for (int phase = 0; phase < 2; ++phase) {
@@ -867,31 +882,52 @@ static int enqueue_ctransforms(Plan& pl, hipStream_t st) {
   return QBW_OK;
 }
 
+// Plan cost from caller-supplied scalings: their block moments, then the
+// entries (p = 2); the pixel-pair sums (p = 1).
 static int enqueue_plancost(Plan& pl, hipStream_t st) {
   const int NJ = pl.njobs;
   if (pl.tot_pc2) {
     CHK(launch_moments(pl.djobs, NJ, pl.off_mom, pl.tot_mom, 1, st));
     CHK(launch_plancost2(pl.djobs, NJ, pl.off_pc2, pl.tot_pc2, st));
   }
-  if (pl.p1_tab.total[0] + pl.p1_tab.total[1] + pl.p1_tab.total[2]) {
-    CHK(launch_plancost(pl.djobs, NJ, pl.p1_tab, st));
-    CHK(launch_pc1_sum(pl.djobs, NJ, st));
-  }
-  return QBW_OK;
+  return enqueue_plancost_p1(pl, st);
 }
 
-static int enqueue_forward(Plan& pl, hipStream_t st) {
+// A second stream for the coarse kernel of a step: it depends only on the
+// pooled measures and overlaps the c-transforms.  Null members: one stream.
+struct SideStream {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+// The plan's counters are zero when it is built and the pixel sweep zeroes
+// the c-transform counters again for the next step.
+static int enqueue_forward(Plan& pl, hipStream_t st, const SideStream* side = nullptr) {
   const int NJ = pl.njobs;
-  CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, NJ, pl.off_mom, pl.tot_mom, st));
-  // lower bound (Algorithm 5)
-  CHK(launch_upscale(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
+  // SumPool, block moments and f^ (Algorithm 5's upscaled potential) in one
+  // pass over the block strips
+  bool big_k = false;
+  for (const auto& D : pl.hj) big_k |= D.k > 64;
+  CHK(launch_pool(pl.djobs, NJ, pl.off_mom, pl.tot_mom, 1, st));
+  if (big_k) CHK(launch_upscale(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, 1, st));
+  // upper bound (Algorithm 4), coarse part: the fitting, the p = 2 plan-cost
+  // entries from the pooled moments and, when a backward pass follows, its
+  // coarse reverse pass, all in one launch that needs only the pooled measures
+  hipStream_t cs = st;
+  if (side && side->st) {
+    HIPCHK(hipEventRecord(side->fork, st));
+    HIPCHK(hipStreamWaitEvent(side->st, side->fork, 0));
+    cs = side->st;
+  }
+  CHK(launch_ipf(pl.djobs, NJ, pl.ipf_lds, 1 | (pl.fwd_rev ? 2 : 0), pl.bwd_scratch, pl.max_q, cs));
+  if (cs != st) HIPCHK(hipEventRecord(side->join, cs));
+  // lower bound (Algorithm 5): the c-transforms of f^
   CHK(enqueue_ctransforms(pl, st));
-  // upper bound (Algorithm 4): coarse IPF, then one sweep over the pixels for
-  // the lower-bound sums, the fine scalings and the weighted-TV sums
-  CHK(launch_ipf(pl.djobs, NJ, pl.ipf_lds, st));
-  CHK(launch_fwd_pixels(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, st));
-  CHK(enqueue_plancost(pl, st));
+  if (cs != st) HIPCHK(hipStreamWaitEvent(st, side->join, 0));
+  // one sweep over the pixels for the lower-bound sums, the fine scalings and
+  // the weighted-TV sums; the p = 1 plan cost; the bounds
+  CHK(launch_fwd_pixels(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.ints, 2 * kQueues + 2, st));
+  CHK(enqueue_plancost_p1(pl, st));
   CHK(launch_finalize(pl.djobs, NJ, st));
   return QBW_OK;
 }
@@ -901,7 +937,9 @@ static int enqueue_backward(Plan& pl, hipStream_t st) {
   // p = 1 jobs: separate lower- and upper-bound passes (the latter over
   // support blocks); p = 2 jobs: one fused pass over pixels after the moments
   if (pl.has_p1) CHK(launch_lb_grad(pl.djobs, NJ, pl.off_chunk, pl.tot_chunk, pl.dl, st));
-  CHK(launch_ub_coarse_bwd2(pl.djobs, NJ, pl.bwd_scratch, pl.max_q, pl.bwd_lds, st));
+  // the coarse reverse pass, unless the forward's coarse kernel ran it (p = 2)
+  if (pl.has_p1 || !pl.fwd_rev)
+    CHK(launch_ub_coarse_bwd2(pl.djobs, NJ, pl.bwd_scratch, pl.max_q, pl.bwd_lds, pl.fwd_rev ? 1 : 0, st));
   if (pl.has_p1) {
     for (int side = 0; side < 2; ++side) {   // per-entry partials, then per-pixel sums
       P1Items ubg = pl.p1_tab;
@@ -945,7 +983,7 @@ static int pool_and_check(qbw_ctx* ctx, const std::vector<JobIn>& jobs, std::vec
   o.max_ipf_iter = 1;
   CHK(plan_build(ctx, pl, jobs, 0, o, true, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, pl.njobs, pl.off_mom, pl.tot_mom, st));
+  CHK(launch_pool(pl.djobs, pl.njobs, pl.off_mom, pl.tot_mom, 0, st));
   std::vector<int> flags(pl.n_ints);
   mt->resize(pl.njobs);
   nt->resize(pl.njobs);
@@ -959,7 +997,7 @@ static int pool_and_check(qbw_ctx* ctx, const std::vector<JobIn>& jobs, std::vec
   HIPCHK(hipMemcpyAsync(flags.data(), pl.ints, 4 * pl.n_ints, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   for (int j = 0; j < pl.njobs; ++j) {
-    const int fl = flags[2 * kQueues + j];
+    const int fl = flags[2 * kQueues + 2 + j];
     if (fl & 2) { set_error("job %d: a measure contains NaN", j); return QBW_E_MASS; }
     if (fl & 1) { set_error("job %d: a measure has a negative entry", j); return QBW_E_MASS; }
     double sa = 0, sb = 0;
@@ -1011,8 +1049,13 @@ static int solve_all(const std::vector<qbw_grid>& grids, const std::vector<std::
   std::vector<int> rcs(NJ, QBW_OK);
   std::vector<std::string> errs(NJ);
   std::atomic<int> next{0};
-  unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const int nthreads = std::max(1, std::min<int>(NJ, (int)hw));
+  // one host thread per core (QBW_HOST_THREADS overrides), at most one per job
+  int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  if (const char* e = std::getenv("QBW_HOST_THREADS")) {
+    const int t = std::atoi(e);
+    if (t > 0) hw = t;
+  }
+  const int nthreads = std::max(1, std::min(NJ, hw));
   auto worker = [&]() {
     for (;;) {
       int j = next.fetch_add(1);
@@ -1082,6 +1125,7 @@ struct qbw_batch {
   // upstream gradients of a copy that is still pending
   hipEvent_t pinned_ev = nullptr;
   bool pinned_busy = false;
+  SideStream side;   // the coarse kernel's stream and its fork / join events
 };
 
 extern "C" {
@@ -1277,7 +1321,7 @@ qbw_status qbw_sumpool(qbw_ctx* ctx, const qbw_grid* grid, const double* m, doub
   pl.hj[0].mu_t = out;
   HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, 0, st));
   HIPCHK(hipStreamSynchronize(st));
   return QBW_OK;
 }
@@ -1298,7 +1342,7 @@ qbw_status qbw_cbar(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const d
   CHK(plan_build(ctx, pl, {stage_job(grid, a, b)}, PM_CBAR, qbw_default_opts(), false, st));
   HIPCHK(hipMemcpyAsync(pl.cbar_out, &out, sizeof(double*), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, 0, st));
   CHK(launch_cbar2(pl.djobs, 1, pl.off_cbar, pl.tot_cbar, pl.cbar_out, st));
   HIPCHK(hipStreamSynchronize(st));
   return QBW_OK;
@@ -1341,7 +1385,7 @@ qbw_status qbw_weighted_cost_upper(qbw_ctx* ctx, const qbw_grid* grid, const dou
   std::unique_ptr<double, void (*)(double*)> guard(dC, [](double* p) { (void)hipFree(p); });
   HIPCHK(hipMemcpyAsync(pl.cbar_out, &dC, sizeof(double*), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, 0, st));
   CHK(launch_cbar2(pl.djobs, 1, pl.off_cbar, pl.tot_cbar, pl.cbar_out, st));
   std::vector<double> C((size_t)Q * Q);
   HIPCHK(hipMemcpyAsync(C.data(), dC, 8 * C.size(), hipMemcpyDeviceToHost, st));
@@ -1429,7 +1473,7 @@ qbw_status qbw_upscale_potential_interp(qbw_ctx* ctx, const qbw_grid* grid, uint
   pl.hj[0].ftil = ftil;
   pl.hj[0].fhat = fhat;
   HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
-  CHK(launch_upscale(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, st));
+  CHK(launch_upscale(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, 0, st));
   HIPCHK(hipStreamSynchronize(st));
   return QBW_OK;
 }
@@ -1593,8 +1637,8 @@ qbw_status qbw_ipf(qbw_ctx* ctx, const qbw_grid* grid, const double* a, const do
   pl.hj[0].b_s = b_s;
   HIPCHK(hipMemcpyAsync(pl.djobs, pl.hj.data(), sizeof(DevJob), hipMemcpyHostToDevice, st));
   CHK(launch_reset_counter(pl.ints, pl.n_ints, st));
-  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, st));
-  CHK(launch_ipf(pl.djobs, 1, pl.ipf_lds, st));
+  CHK(launch_pool(pl.djobs, 1, pl.off_mom, pl.tot_mom, 0, st));
+  CHK(launch_ipf(pl.djobs, 1, pl.ipf_lds, 0, nullptr, 0, st));
   CHK(launch_scalings(pl.djobs, 1, pl.off_chunk, pl.tot_chunk, st));
   CHK(fetch_results(pl, st));
   if (iters) *iters = (int32_t)pl.host_results[RS_IPF_ITERS];
@@ -1841,7 +1885,7 @@ qbw_status qbw_plan_kernel_gaussian(int32_t k, int32_t d, double sigma, double* 
 // ---------------------------------------------------------------- batches
 
 static qbw_status batch_enqueue(qbw_batch* B, hipStream_t st) {
-  CHK(enqueue_forward(B->plan, st));
+  CHK(enqueue_forward(B->plan, st, &B->side));
   if (B->flags & QBW_BATCH_BACKWARD) CHK(enqueue_backward(B->plan, st));
   return QBW_OK;
 }
@@ -1993,6 +2037,13 @@ qbw_status qbw_batch_create(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs, co
     CHK(plan_build(ctx, B->plan, in, mode, o, true, st));
   }
   HIPCHK(hipHostMalloc((void**)&B->pinned, 16 * (size_t)njobs, hipHostMallocDefault));
+  // the coarse kernel's own stream (QBW_COARSE_STREAM=main: the batch's stream)
+  const char* cse = std::getenv("QBW_COARSE_STREAM");
+  if (!(cse && std::strcmp(cse, "main") == 0)) {
+    HIPCHK(hipStreamCreateWithFlags(&B->side.st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&B->side.fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&B->side.join, hipEventDisableTiming));
+  }
   if (batch_flags & QBW_BATCH_GRAPH) {
     HIPCHK(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -2096,6 +2147,9 @@ void qbw_batch_destroy(qbw_batch* B) {
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+  if (B->side.st) { (void)hipStreamSynchronize(B->side.st); (void)hipStreamDestroy(B->side.st); }
+  if (B->side.fork) (void)hipEventDestroy(B->side.fork);
+  if (B->side.join) (void)hipEventDestroy(B->side.join);
   if (B->pinned_ev) { (void)hipEventSynchronize(B->pinned_ev); (void)hipEventDestroy(B->pinned_ev); }
   if (B->pinned) (void)hipHostFree(B->pinned);
   delete B;

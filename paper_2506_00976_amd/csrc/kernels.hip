@@ -175,75 +175,84 @@ __device__ __forceinline__ double cubic_sum(const double (&w)[4], double v0, dou
   return ((w[0] * v0 + w[1] * v1) + w[2] * v2) + w[3] * v3;
 }
 
+// f^ at pixel (x0, x1, x2) (2D: x1 row, x2 column) from the job's coarse
+// potential, by its interpolation rule.
+__device__ __forceinline__ float upscale_value(const DevJob& J, int x0, int x1, int x2) {
+  const double* __restrict__ F = J.ftil;
+  const int n = J.n;
+  double val;
+  if (J.interp == 1) {
+    // nearest centre = the centre of the pixel's own block
+    const int b1 = x1 / J.k, b2 = x2 / J.k;
+    val = J.d == 2 ? F[b1 * n + b2] : F[((x0 / J.k) * n + b1) * n + b2];
+  } else if (J.interp == 2) {
+    int B[4], C[4];
+    double wb[4], wc[4];
+    axis_cubic(x1, J.k, n, B, wb);
+    axis_cubic(x2, J.k, n, C, wc);
+    if (J.d == 2) {
+      double r[4];
+      for (int u = 0; u < 4; ++u) {
+        const double* row = F + B[u] * n;
+        r[u] = cubic_sum(wc, row[C[0]], row[C[1]], row[C[2]], row[C[3]]);
+      }
+      val = cubic_sum(wb, r[0], r[1], r[2], r[3]);
+    } else {
+      int A[4];
+      double wa[4];
+      axis_cubic(x0, J.k, n, A, wa);
+      double sa[4];
+      for (int t = 0; t < 4; ++t) {
+        double r[4];
+        for (int u = 0; u < 4; ++u) {
+          const double* row = F + (A[t] * n + B[u]) * n;
+          r[u] = cubic_sum(wc, row[C[0]], row[C[1]], row[C[2]], row[C[3]]);
+        }
+        sa[t] = cubic_sum(wb, r[0], r[1], r[2], r[3]);
+      }
+      val = cubic_sum(wa, sa[0], sa[1], sa[2], sa[3]);
+    }
+  } else if (J.d == 2) {
+    int A0, A1, B0, B1;
+    double wa, wb;
+    axis_weight(x1, J.k, n, A0, A1, wa);
+    axis_weight(x2, J.k, n, B0, B1, wb);
+    const double r0 = lerp_nc(F[A0 * n + B0], F[A0 * n + B1], wb);
+    const double r1 = lerp_nc(F[A1 * n + B0], F[A1 * n + B1], wb);
+    val = lerp_nc(r0, r1, wa);
+  } else {
+    int A0, A1, B0, B1, C0, C1;
+    double wa, wb, wc;
+    axis_weight(x0, J.k, n, A0, A1, wa);
+    axis_weight(x1, J.k, n, B0, B1, wb);
+    axis_weight(x2, J.k, n, C0, C1, wc);
+    auto at = [&](int a, int b, int c) { return F[(a * n + b) * n + c]; };
+    const double s00 = lerp_nc(at(A0, B0, C0), at(A0, B0, C1), wc);
+    const double s01 = lerp_nc(at(A0, B1, C0), at(A0, B1, C1), wc);
+    const double s10 = lerp_nc(at(A1, B0, C0), at(A1, B0, C1), wc);
+    const double s11 = lerp_nc(at(A1, B1, C0), at(A1, B1, C1), wc);
+    const double t0 = lerp_nc(s00, s01, wb);
+    const double t1 = lerp_nc(s10, s11, wb);
+    val = lerp_nc(t0, t1, wa);
+  }
+  return (float)val;
+}
+
+// f^ over chunks of pixels.  skip_small: only jobs with k > 64 (the pooling
+// launch upscales the others along with its block strips).
 __global__ __launch_bounds__(256) void k_upscale(const DevJob* __restrict__ jobs, int njobs,
-                                                 const int* __restrict__ off, int total) {
+                                                 const int* __restrict__ off, int total, int skip_small) {
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
+    if (skip_small && J.k <= 64) continue;
     const int base = (it - off[jb]) * kChunk;
-    const double* __restrict__ F = J.ftil;
-    const int n = J.n;
     for (int q = threadIdx.x; q < kChunk; q += 256) {
       const int i = base + q;
       if (i >= J.P) break;
       int x0, x1, x2;
       pix_coords(i, J.N, J.d, x0, x1, x2);
-      double val;
-      if (J.interp == 1) {
-        // nearest centre = the centre of the pixel's own block
-        const int b1 = x1 / J.k, b2 = x2 / J.k;
-        val = J.d == 2 ? F[b1 * n + b2] : F[((x0 / J.k) * n + b1) * n + b2];
-      } else if (J.interp == 2) {
-        int B[4], C[4];
-        double wb[4], wc[4];
-        axis_cubic(x1, J.k, n, B, wb);
-        axis_cubic(x2, J.k, n, C, wc);
-        if (J.d == 2) {
-          double r[4];
-          for (int u = 0; u < 4; ++u) {
-            const double* row = F + B[u] * n;
-            r[u] = cubic_sum(wc, row[C[0]], row[C[1]], row[C[2]], row[C[3]]);
-          }
-          val = cubic_sum(wb, r[0], r[1], r[2], r[3]);
-        } else {
-          int A[4];
-          double wa[4];
-          axis_cubic(x0, J.k, n, A, wa);
-          double sa[4];
-          for (int t = 0; t < 4; ++t) {
-            double r[4];
-            for (int u = 0; u < 4; ++u) {
-              const double* row = F + (A[t] * n + B[u]) * n;
-              r[u] = cubic_sum(wc, row[C[0]], row[C[1]], row[C[2]], row[C[3]]);
-            }
-            sa[t] = cubic_sum(wb, r[0], r[1], r[2], r[3]);
-          }
-          val = cubic_sum(wa, sa[0], sa[1], sa[2], sa[3]);
-        }
-      } else if (J.d == 2) {
-        int A0, A1, B0, B1;
-        double wa, wb;
-        axis_weight(x1, J.k, n, A0, A1, wa);
-        axis_weight(x2, J.k, n, B0, B1, wb);
-        const double r0 = lerp_nc(F[A0 * n + B0], F[A0 * n + B1], wb);
-        const double r1 = lerp_nc(F[A1 * n + B0], F[A1 * n + B1], wb);
-        val = lerp_nc(r0, r1, wa);
-      } else {
-        int A0, A1, B0, B1, C0, C1;
-        double wa, wb, wc;
-        axis_weight(x0, J.k, n, A0, A1, wa);
-        axis_weight(x1, J.k, n, B0, B1, wb);
-        axis_weight(x2, J.k, n, C0, C1, wc);
-        auto at = [&](int a, int b, int c) { return F[(a * n + b) * n + c]; };
-        const double s00 = lerp_nc(at(A0, B0, C0), at(A0, B0, C1), wc);
-        const double s01 = lerp_nc(at(A0, B1, C0), at(A0, B1, C1), wc);
-        const double s10 = lerp_nc(at(A1, B0, C0), at(A1, B0, C1), wc);
-        const double s11 = lerp_nc(at(A1, B1, C0), at(A1, B1, C1), wc);
-        const double t0 = lerp_nc(s00, s01, wb);
-        const double t1 = lerp_nc(s10, s11, wb);
-        val = lerp_nc(t0, t1, wa);
-      }
-      J.fhat[i] = (float)val;
+      J.fhat[i] = upscale_value(J, x0, x1, x2);
     }
   }
 }
@@ -1369,13 +1378,20 @@ __device__ CoarseView coarse_view(const DevJob& J, double* lds, size_t lds_bytes
   return c;
 }
 
+__device__ void coarse_reverse(const DevJob& J, const CoarseView& C, double* sc);
+__device__ void coarse_plancost2(const DevJob& J, const CoarseView& C, int T);
+
 // Iterative proportional fitting on coarse vectors (uniform kernel): with
 // b-block sums B (B^0 = k^d), u^t = cc pi~ B^{t-1}, A^t = mu~ / u^t,
 // v^t = cc pi~^T A^t, B^t = nu~ / v^t (0/0 := 0); the residual after
 // iteration t is ||mu^ - mu||_1 (from u^{t+1} / u^t per block) plus the mass
 // of unmatched target blocks.  One work-group per job; u^t and v^t are
-// written out for the backward pass and the fine sweeps.
-__global__ __launch_bounds__(1024) void k_ipf(const DevJob* __restrict__ jobs, int njobs, size_t lds_bytes) {
+// written out for the backward pass and the fine sweeps.  For p = 2 jobs the
+// same work-group then forms the plan-cost entries (flags bit 0) and runs the
+// reverse pass of the backward (bit 1, which needs bit 0), on the coupling it
+// already holds: the whole coarse part of a step in one launch.
+__global__ __launch_bounds__(1024) void k_ipf(const DevJob* __restrict__ jobs, int njobs, size_t lds_bytes,
+                                              int flags, double* __restrict__ scratch_all, int stride) {
   extern __shared__ double lds[];
   __shared__ double sh[1024];
   const DevJob& J = jobs[blockIdx.x];
@@ -1459,6 +1475,12 @@ __global__ __launch_bounds__(1024) void k_ipf(const DevJob* __restrict__ jobs, i
     J.result[RS_IPF_RESID] = resid;
     J.result[RS_WARN] = (resid < J.xi) ? 0.0 : (double)QBW_WARN_IPF_NOT_CONVERGED;
   }
+  if (J.p != 2 || !(flags & 1)) return;
+  __syncthreads();   // the iterates and the results above, for the whole work-group
+  coarse_plancost2(J, C, T);
+  if (!(flags & 2)) return;
+  __syncthreads();
+  coarse_reverse(J, C, C.in_lds ? C.vec : scratch_all + (size_t)blockIdx.x * 4 * stride);
 }
 
 // Fine scalings of the last iterate: a_s = mu / u^T, b_s = nu / v^T (0/0 := 0).
@@ -1487,7 +1509,8 @@ __global__ __launch_bounds__(256) void k_scalings(const DevJob* __restrict__ job
 // The forward pass's pixel sweep after IPF (one read of f, g, f^, mu, nu for
 // three jobs): per chunk the lower-bound sums <f, mu>, <g, nu> and the maxima
 // |f^|, |g|, |f| of the feasibility shift; the fine scalings of k_scalings
-// (written out for the plan cost and the backward pass); the weighted-TV
+// (written out for p = 1 jobs, whose plan cost and gradient sum pixel pairs;
+// p = 2 jobs take block moments instead); the weighted-TV
 // partials of k_tv_partial, with the same arithmetic as those two kernels.
 // Every partial goes to its chunk's slot; k_finalize adds them in order.
 // NS sums and NM maxima of per-thread values over a 256-thread work-group, in
@@ -1519,9 +1542,14 @@ __device__ __forceinline__ void block_reduce_many(double (&s)[NS], double (&m)[N
     m[i] = fmax(fmax(sh[NS + i], sh[W + NS + i]), fmax(sh[2 * W + NS + i], sh[3 * W + NS + i]));
 }
 
+// clear[0 .. nclear): counters of the step's c-transforms, done with here,
+// zeroed for the next step.
 __global__ __launch_bounds__(256) void k_fwd_pixels(const DevJob* __restrict__ jobs, int njobs,
-                                                    const int* __restrict__ off, int total) {
+                                                    const int* __restrict__ off, int total,
+                                                    int* __restrict__ clear, int nclear) {
   __shared__ double sh[256];
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < nclear; i += 256) clear[i] = 0;
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
@@ -1552,8 +1580,10 @@ __global__ __launch_bounds__(256) void k_fwd_pixels(const DevJob* __restrict__ j
       const int K = J.d == 2 ? (x1 / k) * n + x2 / k : ((x0 / k) * n + x1 / k) * n + x2 / k;
       const double as = u[K] > 0.0 ? mu / u[K] : 0.0;
       const double bs = v[K] > 0.0 ? nu / v[K] : 0.0;
-      J.a_s[i] = as;
-      J.b_s[i] = bs;
+      if (J.p == 1) {   // the p = 1 plan cost and gradient read them; p = 2 uses block moments
+        J.a_s[i] = as;
+        J.b_s[i] = bs;
+      }
       // weighted TV
       const double d0 = J.d == 2 ? 0.0 : x0 - hN, d1 = x1 - hN, d2 = x2 - hN;
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
@@ -1664,6 +1694,34 @@ __global__ __launch_bounds__(256) void k_plancost2(const DevJob* __restrict__ jo
     // terms (rho the largest offset of a pixel from its block centre): the
     // scale of this entry's rounding error, summed by k_finalize
     const double dn = sqrt(D0 * D0 + D1 * D1 + D2 * D2) + sqrt((double)J.d) * (double)(J.k - 1);
+    J.red_pm[e] = (A[0] * Bm[0]) * (dn * dn);
+  }
+}
+
+// The same entries from the pooled moments of mu and nu (k_moments) and the
+// last iterates: on block K the scaling a_s = mu / u^T_K has one divisor, so
+// its block moments are those of mu divided by u^T_K (and those of b_s are
+// nu's divided by v^T_L); 0 where the divisor is 0, as a_s and b_s are.  The
+// work-group of the coarse fitting, one thread per entry.
+__device__ void coarse_plancost2(const DevJob& J, const CoarseView& C, int T) {
+  const double* uT = J.ipf_u + (size_t)T * J.Q;
+  const double* vT = J.ipf_v + (size_t)T * J.Q;
+  const double rho2 = sqrt((double)J.d) * (double)(J.k - 1);
+  for (int e = threadIdx.x; e < J.nnz; e += blockDim.x) {
+    const int K = C.erow[e], L = C.ecol[e];
+    double D0, D1, D2;
+    block_delta(K, L, J, D0, D1, D2);
+    const double uk = uT[K], vl = vT[L];
+    const double* Mm = J.mom_mu + 5 * (size_t)K;
+    const double* Mn = J.mom_nu + 5 * (size_t)L;
+    double A[5], Bm[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      A[q] = uk > 0.0 ? Mm[q] / uk : 0.0;
+      Bm[q] = vl > 0.0 ? Mn[q] / vl : 0.0;
+    }
+    J.red_pc[e] = moment_pair_sq(A, Bm, D0, D1, D2);
+    const double dn = sqrt(D0 * D0 + D1 * D1 + D2 * D2) + rho2;
     J.red_pm[e] = (A[0] * Bm[0]) * (dn * dn);
   }
 }
@@ -1980,14 +2038,17 @@ __device__ __forceinline__ double gam(double n) {
 // then satisfies T_exact <= Z + e (W + Z) / (1 - e_G), with Z = T (1 +
 // gamma(n_s + 3)), W = <w, mu> (1 + gamma(n_s + 2)) and e = e_G + 14 T u (resp.
 // e_nu).  The plan cost: p = 2 sums block moments, each entry within
-// (2 gamma(k^d + 3) + gamma(16)) M_e of exact, M_e = A0 B0 (|D_KL| + 2 rho)^2
+// (2 gamma(s_m + 4) + gamma(16)) M_e of exact, M_e = A0 B0 (|D_KL| + 2 rho)^2
 // bounding the absolute values of its terms (rho the largest offset of a pixel
-// from its block centre); p = 1 sums nonnegative terms (gamma(k^2d + nnz + 8)
-// plus 2^-41 for the refined square roots).  Both are then widened by the
-// scalings' e_G + 14 T u.
-__global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ jobs, int njobs) {
-  __shared__ double sh[256];
-  const DevJob& J = jobs[blockIdx.x];
+// from its block centre) and s_m = max(k^d, s_p): a moment of the scalings is
+// a pooled moment of the measure (at most s_p + 2 roundings deep, the offset
+// products included) divided by u^T_K (one more), against the sum of the
+// scalings as rounded (one more), or the same moments summed from the scalings
+// themselves; p = 1 sums nonnegative terms (gamma(k^2d + nnz + 8) plus 2^-41
+// for the refined square roots).  Both are then widened by the scalings'
+// e_G + 14 T u.
+// One job's bounds by a 256-thread work-group (sh: 256 doubles of LDS).
+__device__ void finalize_job(const DevJob& J, double* sh) {
   double* res = J.result;
   // lower bound
   double sf = 0, sg = 0, mh = 0, mg = 0, mf = 0;
@@ -2001,6 +2062,9 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   const double kd = (double)kdi;
   const double cc = 1.0 / (kd * kd);
   double pc = 0, mm = 0;
+  // unrolled so that several entries' loads are in flight at once (the sums
+  // keep their order)
+#pragma unroll 4
   for (int e = threadIdx.x; e < J.nnz; e += 256) {
     const double ce = cc * J.e_val[e];
     pc += ce * J.red_pc[e];
@@ -2060,7 +2124,7 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   const double Tn = (Zn + enu * (Wn + Zn) / (1.0 - enu)) * (1.0 + 8.0 * u53);
   double Pv;
   if (J.p == 2)
-    Pv = pc + (2.0 * gam(kd + 3) + gam(16) + 2.0 * gam(n_e + 4)) * mm * (1.0 + gam(n_e + 10));
+    Pv = pc + (2.0 * gam(fmax(kd, s_pool) + 4) + gam(16) + 2.0 * gam(n_e + 4)) * mm * (1.0 + gam(n_e + 10));
   else
     Pv = pc * (1.0 + gam(kd * kd + J.nnz + 8) + 0x1p-41);
   const double pe = Pv * (1.0 + eG + eO + 6.0 * u53) * (1.0 + 4.0 * u53);
@@ -2089,6 +2153,12 @@ __global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ job
   res[RS_MW_NU] = wn;
   res[RS_TV_RAW_MU] = c1 * root(tm);
   res[RS_TV_RAW_NU] = c1 * root(tn);
+}
+
+// The bounds of every job, one work-group per job.
+__global__ __launch_bounds__(256) void k_finalize(const DevJob* __restrict__ jobs, int njobs) {
+  __shared__ double sh[256];
+  finalize_job(jobs[blockIdx.x], sh);
 }
 
 // ------------------------------------------------------------------ C-bar (Section 3.2)
@@ -2144,7 +2214,9 @@ __global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, i
 // Block moments about the block centre (5 slots): which = 0 -> (mu, nu) into
 // (mom_mu, mom_nu); which = 1 -> (a_s, b_s) into (mom_as, mom_bs); which = 2
 // -> as 0, and also the pooled masses (SumPool: the block sums, slot 0) into
-// (mu_t, nu_t) and the input checks (negative entry, NaN) into the job's flags.
+// (mu_t, nu_t) and the input checks (negative entry, NaN) into the job's flags;
+// which = 3 -> as 2, and for k <= 64 also f^ on the strip's pixels (the
+// upscaled coarse potential, which depends on neither measure).
 //
 // k <= 64: one work-group per strip of blocks along the last axis (the k or
 // k^2 pixel rows of one block row), both fields.  The strip goes in chunks of
@@ -2175,7 +2247,7 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
       for (int side = 0; side < 2; ++side) {
         const double* m = which != 1 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
         double* mo = which != 1 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs);
-        double* pooled = which == 2 ? (side == 0 ? J.mu_t : J.nu_t) : nullptr;
+        double* pooled = which >= 2 ? (side == 0 ? J.mu_t : J.nu_t) : nullptr;
         for (int c0 = 0; c0 < N; c0 += W) {
           const int x2 = c0 + col;
           double s0 = 0.0, s1 = 0.0, s2 = 0.0, s4 = 0.0;
@@ -2194,7 +2266,7 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
               s4 += w * (d0 * d0 + d1 * d1);
             }
           }
-          if (bad && which == 2) atomicOr(J.flags, bad);
+          if (bad && which >= 2) atomicOr(J.flags, bad);
           const double d2 = (double)(x2 % k) - h;
           __syncthreads();
           cs[0][threadIdx.x] = s0;
@@ -2226,6 +2298,19 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
           }
         }
       }
+      if (which == 3) {
+        // f^ of the strip's pixels, each by the thread that read them above
+        for (int c0 = 0; c0 < N; c0 += W) {
+          const int x2 = c0 + col;
+          if (rg >= RG || x2 >= N) continue;
+          for (int r = rg; r < nrows; r += RG) {
+            const int u0 = J.d == 2 ? 0 : r / k, u1 = J.d == 2 ? r : r - (r / k) * k;
+            const int X0 = J.d == 2 ? 0 : b0 * k + u0, X1 = b1 * k + u1;
+            const size_t row = J.d == 2 ? (size_t)X1 : ((size_t)X0 * N + (size_t)X1);
+            J.fhat[row * N + x2] = upscale_value(J, X0, X1, x2);
+          }
+        }
+      }
       continue;
     }
     // k > 64: (side, block) pairs reduced by lane groups as in k_pool
@@ -2254,11 +2339,11 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
     }
     s0 = group_sum(s0, g); s1 = group_sum(s1, g); s2 = group_sum(s2, g);
     s3 = group_sum(s3, g); s4 = group_sum(s4, g);
-    if (bad && which == 2) atomicOr(J.flags, bad);
+    if (bad && which >= 2) atomicOr(J.flags, bad);
     if (ok && sub == 0) {
       double* o = (which != 1 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs)) + 5 * (size_t)K;
       o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3; o[4] = s4;
-      if (which == 2) (side == 0 ? J.mu_t : J.nu_t)[K] = s0;
+      if (which >= 2) (side == 0 ? J.mu_t : J.nu_t)[K] = s0;
     }
   }
 }
@@ -2320,39 +2405,35 @@ __device__ void grad2_quad_block(const DevJob& J, const CoarseView& C, int K) {
   }
 }
 
-__global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict__ jobs, int njobs,
-                                                        double* __restrict__ scratch_all,
-                                                        int stride, size_t lds_bytes) {
-  extern __shared__ double lds[];
-  const DevJob& J = jobs[blockIdx.x];
+// The reverse pass of one job, by its work-group: the four adjoint vectors
+// live in sc (LDS or the job's global scratch).
+__device__ void coarse_reverse(const DevJob& J, const CoarseView& C, double* sc) {
   const int Q = J.Q;
   const int T = (int)J.result[RS_IPF_ITERS];
   const double kd = J.d == 2 ? (double)J.k * J.k : (double)J.k * J.k * J.k;
   const double cc = 1.0 / (kd * kd);
-  const CoarseView C = coarse_view(J, lds, lds_bytes, 4);
-  double* sc = C.in_lds ? C.vec : scratch_all + (size_t)blockIdx.x * 4 * stride;  // stride >= every job's Q
   double* ub = sc;          // adjoint of u^t
   double* vb = sc + Q;      // adjoint of v^t
   double* Ab = sc + 2 * Q;  // adjoint of A^t
   double* Bb = sc + 3 * Q;  // adjoint of B^{t-1}
   const double* uT = J.ipf_u + (size_t)T * Q;
   const double* vT = J.ipf_v + (size_t)T * Q;
-  for (int e = threadIdx.x; e < J.nnz; e += 1024) {
+  for (int e = threadIdx.x; e < J.nnz; e += blockDim.x) {
     const int K = C.erow[e], L = C.ecol[e];
     J.coef[e] = (uT[K] > 0.0 && vT[L] > 0.0) ? cc * C.ev[e] / (uT[K] * vT[L]) : 0.0;
   }
-  for (int K = threadIdx.x; K < Q; K += 1024) { J.gbar_mu[K] = 0.0; J.gbar_nu[K] = 0.0; }
+  for (int K = threadIdx.x; K < Q; K += blockDim.x) { J.gbar_mu[K] = 0.0; J.gbar_nu[K] = 0.0; }
   __syncthreads();
   // p = 2: the direct term's per-block quadratic (needs the coefficients above)
   if (J.p == 2)
-    for (int K = threadIdx.x; K < Q; K += 1024) grad2_quad_block(J, C, K);
+    for (int K = threadIdx.x; K < Q; K += blockDim.x) grad2_quad_block(J, C, K);
   // direct terms: P = sum_e cc val_e red_pc[e], red_pc = S_e / (u_K v_L)
-  for (int K = threadIdx.x; K < Q; K += 1024) {
+  for (int K = threadIdx.x; K < Q; K += blockDim.x) {
     double s = 0.0;
     for (int e = C.csr[K]; e < C.csr[K + 1]; ++e) s += cc * C.ev[e] * J.red_pc[e];
     ub[K] = uT[K] > 0.0 ? -s / uT[K] : 0.0;
   }
-  for (int L = threadIdx.x; L < Q; L += 1024) {
+  for (int L = threadIdx.x; L < Q; L += blockDim.x) {
     double s = 0.0;
     for (int q = C.csc[L]; q < C.csc[L + 1]; ++q) {
       const int e = C.cidx[q];
@@ -2364,14 +2445,14 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
   for (int t = T; t >= 1; --t) {
     const double* u = J.ipf_u + (size_t)t * Q;
     // v^t = cc pi^T A^t  ->  Ab
-    for (int K = threadIdx.x; K < Q; K += 1024) {
+    for (int K = threadIdx.x; K < Q; K += blockDim.x) {
       double s = 0.0;
       for (int e = C.csr[K]; e < C.csr[K + 1]; ++e) s += C.ev[e] * vb[C.ecol[e]];
       Ab[K] = cc * s;
     }
     __syncthreads();
     // A^t = mu~ / u^t
-    for (int K = threadIdx.x; K < Q; K += 1024) {
+    for (int K = threadIdx.x; K < Q; K += blockDim.x) {
       if (u[K] > 0.0) {
         J.gbar_mu[K] += Ab[K] / u[K];
         ub[K] += -Ab[K] * J.mu_t[K] / (u[K] * u[K]);
@@ -2381,7 +2462,7 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
     if (t == 1) break;
     const double* vp = J.ipf_v + (size_t)(t - 1) * Q;
     // u^t = cc pi B^{t-1}  ->  Bb
-    for (int L = threadIdx.x; L < Q; L += 1024) {
+    for (int L = threadIdx.x; L < Q; L += blockDim.x) {
       double s = 0.0;
       for (int q = C.csc[L]; q < C.csc[L + 1]; ++q) {
         const int e = C.cidx[q];
@@ -2391,7 +2472,7 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
     }
     __syncthreads();
     // B^{t-1} = nu~ / v^{t-1}
-    for (int L = threadIdx.x; L < Q; L += 1024) {
+    for (int L = threadIdx.x; L < Q; L += blockDim.x) {
       if (vp[L] > 0.0) {
         J.gbar_nu[L] += Bb[L] / vp[L];
         vb[L] = -Bb[L] * J.nu_t[L] / (vp[L] * vp[L]);
@@ -2399,9 +2480,22 @@ __global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict
         vb[L] = 0.0;
       }
     }
-    for (int K = threadIdx.x; K < Q; K += 1024) ub[K] = 0.0;
+    for (int K = threadIdx.x; K < Q; K += blockDim.x) ub[K] = 0.0;
     __syncthreads();
   }
+}
+
+// The reverse pass as a launch of its own (one work-group per job), for jobs
+// whose forward did not run it: with skip_p2, p = 2 jobs are left alone (their
+// forward coarse kernel ran it).
+__global__ __launch_bounds__(1024) void k_ub_coarse_bwd(const DevJob* __restrict__ jobs, int njobs,
+                                                        double* __restrict__ scratch_all,
+                                                        int stride, size_t lds_bytes, int skip_p2) {
+  extern __shared__ double lds[];
+  const DevJob& J = jobs[blockIdx.x];
+  if (skip_p2 && J.p == 2) return;
+  const CoarseView C = coarse_view(J, lds, lds_bytes, 4);
+  coarse_reverse(J, C, C.in_lds ? C.vec : scratch_all + (size_t)blockIdx.x * 4 * stride);  // stride >= every job's Q
 }
 
 // d upper / d mu (side 0) or d nu (side 1).  For a member x of block B the
@@ -3051,8 +3145,9 @@ __global__ __launch_bounds__(256) void k_kub_grad_out(KubJob J, double dupper, d
 
 static inline int grid_for(int total, int cap = 65535) { return total < 1 ? 1 : (total < cap ? total : cap); }
 
-int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
-  hipLaunchKernelGGL(k_upscale, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, int skip_small, void* stream) {
+  hipLaunchKernelGGL(k_upscale, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total,
+                     skip_small);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
@@ -3089,8 +3184,10 @@ int launch_argmin(const DevJob* jobs, int njobs, const int* off, int total, int 
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_ipf(const DevJob* jobs, int njobs, size_t lds_bytes, void* stream) {
-  hipLaunchKernelGGL(k_ipf, dim3(njobs), dim3(1024), lds_bytes, (hipStream_t)stream, jobs, njobs, lds_bytes);
+int launch_ipf(const DevJob* jobs, int njobs, size_t lds_bytes, int flags, double* scratch, int stride,
+               void* stream) {
+  hipLaunchKernelGGL(k_ipf, dim3(njobs), dim3(1024), lds_bytes, (hipStream_t)stream, jobs, njobs, lds_bytes, flags,
+                     scratch, stride);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
@@ -3126,8 +3223,8 @@ int launch_finalize(const DevJob* jobs, int njobs, void* stream) {
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_pool(const DevJob* jobs, int njobs, const int* off_mom, int total_mom, void* stream) {
-  return launch_moments(jobs, njobs, off_mom, total_mom, 2, stream);
+int launch_pool(const DevJob* jobs, int njobs, const int* off_mom, int total_mom, int upscale, void* stream) {
+  return launch_moments(jobs, njobs, off_mom, total_mom, upscale ? 3 : 2, stream);
 }
 int launch_moments(const DevJob* jobs, int njobs, const int* off, int total, int which, void* stream) {
   hipLaunchKernelGGL(k_moments, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total, which);
@@ -3146,9 +3243,9 @@ int launch_lb_grad(const DevJob* jobs, int njobs, const int* off, int total, con
   return QBW_OK;
 }
 int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int stride, size_t lds_bytes,
-                          void* stream) {
+                          int skip_p2, void* stream) {
   hipLaunchKernelGGL(k_ub_coarse_bwd, dim3(njobs), dim3(1024), lds_bytes, (hipStream_t)stream, jobs, njobs, scratch,
-                     stride, lds_bytes);
+                     stride, lds_bytes, skip_p2);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
@@ -3166,8 +3263,10 @@ int launch_ub_grad(const DevJob* jobs, int njobs, const P1Items& it, const doubl
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }
-int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, void* stream) {
-  hipLaunchKernelGGL(k_fwd_pixels, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total);
+int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, int* clear, int nclear,
+                      void* stream) {
+  hipLaunchKernelGGL(k_fwd_pixels, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)stream, jobs, njobs, off, total,
+                     clear, nclear);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -192,8 +192,10 @@ struct Launch {
 
 // SumPool of both measures with their block moments and the input checks
 // (k_moments, which = 2), over the plan's moment items.
-int launch_pool(const DevJob* jobs, int njobs, const int* off_mom, int total_mom, void* stream);
-int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+// SumPool with the block moments and input checks; upscale: also f^ for the
+// jobs with k <= 64 (launch_upscale with skip_small does the others).
+int launch_pool(const DevJob* jobs, int njobs, const int* off_mom, int total_mom, int upscale, void* stream);
+int launch_upscale(const DevJob* jobs, int njobs, const int* off, int total, int skip_small, void* stream);
 constexpr int kQueues = 8;  // XCDs: the planner groups c-transform items per XCD
 // Waves of k_ctransform resident per compute unit (0 if the runtime cannot say).
 int ctransform_waves_per_cu();
@@ -226,7 +228,11 @@ constexpr size_t kCoarseLdsMax = 160 * 1024;
 constexpr size_t coarse_lds_need(int Q, int nnz, int nvec) {
   return 8 * ((size_t)nvec * Q + (size_t)nnz) + 4 * (2 * (size_t)(Q + 1) + 3 * (size_t)nnz) + 16;
 }
-int launch_ipf(const DevJob* jobs, int njobs, size_t lds_bytes, void* stream);
+// flags: bit 0 p = 2 plan-cost entries, bit 1 also the reverse pass (the
+// coarse part of the backward; scratch holds 4 x stride doubles per job for
+// jobs whose coupling is not staged in LDS).
+int launch_ipf(const DevJob* jobs, int njobs, size_t lds_bytes, int flags, double* scratch, int stride,
+               void* stream);
 int launch_scalings(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 int launch_tv_partial(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
 // p = 1 plan cost and upper-bound gradient on blocks of m = k^d pixels: the
@@ -259,12 +265,15 @@ int launch_lb_grad(const DevJob* jobs, int njobs, const int* off, int total, con
 // per-block quadratics of the direct gradient term (block moments of mu, nu
 // must be current).
 int launch_ub_coarse_bwd2(const DevJob* jobs, int njobs, double* scratch, int stride, size_t lds_bytes,
-                          void* stream);
+                          int skip_p2, void* stream);
 int launch_ub_grad(const DevJob* jobs, int njobs, const P1Items& items, const double* du, int side,
                    void* stream);
 int launch_fhat_grad2(const DevJob* jobs, int njobs, const int* off, int total, const double* dl,
                       double* const* outs, void* stream);
-int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, void* stream);
+// The forward pixel sweep; it also zeroes clear[0 .. nclear) (the c-transform
+// counters, for the next step).
+int launch_fwd_pixels(const DevJob* jobs, int njobs, const int* off, int total, int* clear, int nclear,
+                      void* stream);
 int launch_pc1_sum(const DevJob* jobs, int njobs, void* stream);
 int launch_ub_grad_sum(const DevJob* jobs, int njobs, const int* off, int total, const double* du, int side,
                        void* stream);
