@@ -750,6 +750,32 @@ __device__ __forceinline__ void xs_window_block(double (&m1)[T], double (&W)[T],
   }
 }
 
+// The same block when the lane's targets are the wave's (t0 wave-uniform):
+// the squares (a0 + q)^2, a0 = r0 - t0, |q| < T, are the same in every lane,
+// so they are read once per block from the table into scalar registers and
+// each candidate is one add with a scalar operand and one min, with no
+// per-lane window.  sqa points at the table entry of a0.
+template <int T, int PARTS, typename H>
+__device__ __forceinline__ void xs_sq_block(double (&m1)[T], const_dptr sqa, H&& hval) {
+  // in PARTS runs of T / PARTS steps, each with the T + T / PARTS - 1 squares
+  // it uses, so that fewer scalar registers hold squares at a time
+  constexpr int TP = T / PARTS, NS = T + TP - 1;
+#pragma unroll
+  for (int hf = 0; hf < PARTS; ++hf) {
+    double sq[NS];   // offsets hf TP - (T - 1) ... hf TP + TP - 1
+#pragma unroll
+    for (int q = 0; q < NS; ++q) sq[q] = sqa[hf * TP + q - (T - 1)];
+#pragma unroll
+    for (int jj = 0; jj < TP; ++jj) {
+      const int j = hf * TP + jj;
+      const double h = hval(j);
+#pragma unroll
+      for (int t = 0; t < T; ++t) m1[t] = vmin_f64(m1[t], h + sq[jj - t + T - 1]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 // One item of stage k: 64 lines x T targets along the axis.  `tile` is the
 // work-group's LDS staging area of the first stage (64 x 17 floats).  ARG:
 // the job wants arg-mins, so the index and the runner-up are tracked; without
@@ -766,11 +792,12 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
     const int nchunk = (lines + 63) >> 6;
     // Lanes are (line, target group) pairs.  Later stages: 64 consecutive
     // lines of one target group per wave (their loads are coalesced along
-    // the last axis).  First stage without arg-mins: the lanes run along the
-    // rows, G groups per row, so the lanes of a row read the same source
-    // values (a few distinct addresses per load, no staging); with arg-mins
-    // it keeps the line-per-lane layout and its LDS tiles.  Either way a
-    // launch has nchunk x G items of 64 lanes.
+    // the last axis, and the wave's targets, so the squares its candidates
+    // add, are the same in every lane).  First stage without arg-mins: the
+    // lanes run along the rows, G groups per row, so the lanes of a row read
+    // the same source values (a few distinct addresses per load, no
+    // staging); with arg-mins it keeps the line-per-lane layout and its LDS
+    // tiles.  Either way a launch has nchunk x G items of 64 lanes.
     constexpr bool ROWLANES = FIRST && !ARG;
     const int G = (N + kXsT - 1) / kXsT;
     int e, t0;
@@ -908,22 +935,27 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
       // of 8, so the ring slots are fixed), or for 2 and 4 targets per lane a
       // block's sources while the previous block is in use
       if constexpr (kXsT >= 8) {
-        // global loads from a wave-uniform base (the source's row of lines)
-        // plus the lane's 32-bit offset: no per-load address arithmetic
-        const gdptr vg = (gdptr)v1in;
-        const unsigned lob = (unsigned)base * 8u;   // the lane's byte offset
+        // buffer loads: the lane's byte offset in a vector register, the
+        // source's (r st 8 bytes) in a scalar one, so a load takes no vector
+        // address arithmetic.  The resource spans this stage's two input
+        // halves (v1in, v2in: 2P doubles); the loads four steps ahead of the
+        // last whole block stay inside it and go unused.
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(v1in), 0, 16 * P, 0x00020000);
+        const int lob = base * 8;   // the lane's byte offset
+        const int st8 = st * 8;
         auto at = [&](int r) {
-          return *(gdptr)((const __attribute__((address_space(1))) char*)(vg + (size_t)r * st) + lob);
+          const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lob, r * st8, 0);
+          double x;
+          __builtin_memcpy(&x, &w, 8);
+          return x;
         };
         double hb[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) hb[u] = rlo + u < NB ? at(rlo + u) : 0.0;
+        for (int u = 0; u < 4; ++u) hb[u] = at(rlo + u);
         for (int r0 = rlo; r0 < NB; r0 += kXsT) {
-          xs_window_block<kXsT>(m1, W, inc, [&](int j) {
-            // past the last whole block the load repeats a valid source and
-            // goes unused (no branch inside the unrolled block)
-            const int ra = min(r0 + j + 4, NB - 1);
-            hb[(j + 4) & 7] = at(ra);
+          xs_sq_block<kXsT, 4>(m1, sq + (r0 - t0 + kXsOff), [&](int j) {
+            hb[(j + 4) & 7] = at(r0 + j + 4);
             return hb[j & 7];
           });
         }
@@ -964,21 +996,24 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
       for (int r = N4; r < N; ++r) step(v1in[base + r * st], r);
     }
     if constexpr (!ARG) {
-      if (SW > 1) {
-        // the other waves' minima into wave 0 (the barrier before the writes
-        // also keeps them behind wave 0's reads for the previous item)
+      // the waves' minima meet in wave 0 as a tree: the upper half of the
+      // waves hands its minima to the lower half, which halves again (the
+      // barrier before each round's writes also keeps them behind the reads
+      // of the round before, and of the previous item's last round), so the
+      // LDS holds SW / 2 waves' minima at most and more work-groups fit a CU
+      for (int half = SW >> 1; half > 0; half >>= 1) {
         __syncthreads();
-        if (wv > 0) {
+        if (wv >= half && wv < 2 * half) {
 #pragma unroll
-          for (int t = 0; t < kXsT; ++t) red[((wv - 1) * kXsT + t) * 64 + lane] = m1[t];
+          for (int t = 0; t < kXsT; ++t) red[((wv - half) * kXsT + t) * 64 + lane] = m1[t];
         }
         __syncthreads();
-        if (wv > 0) return;
-        for (int w = 1; w < SW; ++w) {
+        if (wv < half) {
 #pragma unroll
-          for (int t = 0; t < kXsT; ++t) m1[t] = vmin_f64(m1[t], red[((w - 1) * kXsT + t) * 64 + lane]);
+          for (int t = 0; t < kXsT; ++t) m1[t] = vmin_f64(m1[t], red[(wv * kXsT + t) * 64 + lane]);
         }
       }
+      if (wv > 0) return;
     }
     if (!valid) return;
     const bool last = k == J.d - 1;
@@ -1056,8 +1091,8 @@ __global__ __launch_bounds__(256) void k_xs_stage(const DevJob* __restrict__ job
                                                   const double* __restrict__ sqt, int2* __restrict__ list,
                                                   int* __restrict__ count) {
   // dynamic LDS, sized by the launcher (xs_lds_bytes): the first stage's
-  // per-wave tiles (64 x 17 floats, with arg-mins only), then (SW - 1) x 64 x T
-  // doubles for the other waves' minima
+  // per-wave tiles (64 x 17 floats, with arg-mins only), then SW / 2 x 64 x T
+  // doubles for the waves' minima on their way to wave 0
   extern __shared__ double xs_lds[];
   const int SW = blockDim.x >> 6;
   // the wave index, known wave-uniform: source ranges and load addresses
@@ -1076,7 +1111,7 @@ __global__ __launch_bounds__(256) void k_xs_stage(const DevJob* __restrict__ job
 // LDS bytes of one k_xs_stage work-group (matches the kernel's carving).
 static size_t xs_lds_bytes(bool first, int T, bool arg, int waves) {
   const size_t tiles = first && arg ? 8 * (size_t)((waves * 64 * 17 + 1) / 2) : 0;
-  const size_t red = arg ? 0 : 8 * (size_t)(waves - 1) * 64 * T;
+  const size_t red = arg ? 0 : 8 * (size_t)(waves / 2) * 64 * T;
   return std::max<size_t>(8, tiles + red);
 }
 
