@@ -290,6 +290,7 @@ struct Plan {
   int* xs_list = nullptr;
   int xs_pixels = 0;
   int xs_T = 8, xs_W = 1;  // targets per lane and waves per work-group of the stages
+  int xs_W0 = 1;           // waves per work-group of the first stage
   size_t ipf_lds = 0;      // dynamic LDS of the coarse fitting kernel (jobs that do not fit use global memory)
   size_t bwd_lds = 0;      // the same for the coarse backward kernel
   bool fwd_rev = false;    // a backward pass follows: the forward's coarse kernel runs its p = 2 reverse pass
@@ -594,6 +595,11 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
       const int v = std::atoi(e);
       if (v == 1 || ((v == 2 || v == 4) && max_split == 4)) pl.xs_W = v;
     }
+    pl.xs_W0 = pl.xs_W;
+    if (const char* e = std::getenv("QBW_XS_W0")) {   // the first stage's alone
+      const int v = std::atoi(e);
+      if (v == 1 || ((v == 2 || v == 4) && max_split == 4)) pl.xs_W0 = v;
+    }
     pl.xs_T = xs_T;
   }
   for (int j = 0; j < NJ; ++j) {
@@ -852,7 +858,7 @@ static int enqueue_xs(Plan& pl, int phase, hipStream_t st) {
     if (!total) continue;
     CHK(timed_launch(pl, st, [&] {
       return launch_xs_stage(pl.djobs, pl.njobs, off, total, phase, k, pl.xs_sq, pl.xs_list, cnt, pl.xs_T,
-                             (pl.mode & PM_ARGMIN) ? 1 : 0, pl.xs_W, st);
+                             (pl.mode & PM_ARGMIN) ? 1 : 0, k == 0 ? pl.xs_W0 : pl.xs_W, st);
     }));
   }
   return launch_xs_fallback(pl.djobs, pl.xs_list, cnt, phase, std::max(1, std::min(pl.xs_pixels, 4096)), st);

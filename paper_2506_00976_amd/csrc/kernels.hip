@@ -835,8 +835,12 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
         if (ARG) {
           m2[t] = fmin(m2[t], fmax(m1[t], w));
           ix[t] = w < m1[t] ? r : ix[t];
+          m1[t] = fmin(m1[t], w);
+        } else {
+          // each candidate's add next to its min, so that the scheduler does
+          // not hold all T candidates in registers at once
+          m1[t] = vmin_f64(m1[t], w);
         }
-        m1[t] = fmin(m1[t], w);
       }
     };
     // The SW waves of the work-group split the sources: wave wv takes
@@ -944,18 +948,25 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
             __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(v1in), 0, 16 * P, 0x00020000);
         const int lob = base * 8;   // the lane's byte offset
         const int st8 = st * 8;
-        auto at = [&](int r) {
-          const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lob, r * st8, 0);
+        // the next load's source offset, advanced by one source per load; the
+        // empty asm keeps it one running scalar (rather than sixteen
+        // precomputed per-step offsets that would not fit the scalar
+        // registers)
+        int soff = rlo * st8;
+        auto next = [&]() {
+          const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lob, soff, 0);
+          soff += st8;
+          __asm__ volatile("" : "+s"(soff));
           double x;
           __builtin_memcpy(&x, &w, 8);
           return x;
         };
         double hb[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) hb[u] = at(rlo + u);
+        for (int u = 0; u < 4; ++u) hb[u] = next();
         for (int r0 = rlo; r0 < NB; r0 += kXsT) {
           xs_sq_block<kXsT, 4>(m1, sq + (r0 - t0 + kXsOff), [&](int j) {
-            hb[(j + 4) & 7] = at(r0 + j + 4);
+            hb[(j + 4) & 7] = next();   // source r0 + j + 4
             return hb[j & 7];
           });
         }
@@ -1085,7 +1096,7 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
 // where a target holds one running minimum).  A work-group of SW = blockDim / 64
 // waves takes one item, its waves splitting the sources.
 template <bool FIRST, int T, bool ARG>
-__attribute__((amdgpu_waves_per_eu(4)))
+__attribute__((amdgpu_waves_per_eu((ARG || FIRST) ? 4 : 8)))
 __global__ __launch_bounds__(256) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
                                                   const int* __restrict__ off, int total, int phase, int k,
                                                   const double* __restrict__ sqt, int2* __restrict__ list,
