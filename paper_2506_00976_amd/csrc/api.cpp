@@ -291,6 +291,7 @@ struct Plan {
   int xs_pixels = 0;
   int xs_T = 8, xs_W = 1;  // targets per lane and waves per work-group of the stages
   int xs_W0 = 1;           // waves per work-group of the first stage
+  bool xs_has_xt = false, xs_has_std = false;   // jobs on xs_item_xt (2D, axis 0 first) / on xs_item
   size_t ipf_lds = 0;      // dynamic LDS of the coarse fitting kernel (jobs that do not fit use global memory)
   size_t bwd_lds = 0;      // the same for the coarse backward kernel
   bool fwd_rev = false;    // a backward pass follows: the forward's coarse kernel runs its p = 2 reverse pass
@@ -564,6 +565,9 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   for (const auto& J : pl.in)
     if ((mode & PM_XS) && J.g.p == 2) xs_max_N = std::max(xs_max_N, J.g.N);
   const bool xs16 = !(mode & PM_ARGMIN) && xs_max_N <= 2048;
+  // QBW_XS_XT=0 keeps two-dimensional jobs on the last-axis-first order
+  const char* xte = std::getenv("QBW_XS_XT");
+  const bool xs_xt_on = !(xte && std::strcmp(xte, "0") == 0);
   int xs_T = xs16 ? 16 : 8;
   {
     auto waves = [&](int T) {
@@ -678,6 +682,8 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     {
       // exact separable stages: one wave per (64 lines, xs_T targets along the axis)
       D.xs_T = xs_T;
+      D.xs_xt = (D.xs && D.d == 2 && !(mode & PM_ARGMIN) && xs_T >= 8 && xs_xt_on) ? 1 : 0;
+      if (D.xs) (D.xs_xt ? pl.xs_has_xt : pl.xs_has_std) = true;
       const int xs_items = D.xs ? ((D.rows + 63) / 64) * ((D.N + xs_T - 1) / xs_T) : 0;
       off[12 * (NJ + 1) + j + 1] = off[12 * (NJ + 1) + j] + xs_items;
       off[13 * (NJ + 1) + j + 1] = off[13 * (NJ + 1) + j] + (D.d == 3 ? xs_items : 0);
@@ -856,10 +862,15 @@ static int enqueue_xs(Plan& pl, int phase, hipStream_t st) {
     const int* off = k < 2 ? pl.off_xs : pl.off_xs3;
     const int total = k < 2 ? pl.tot_xs : pl.tot_xs3;
     if (!total) continue;
-    CHK(timed_launch(pl, st, [&] {
-      return launch_xs_stage(pl.djobs, pl.njobs, off, total, phase, k, pl.xs_sq, pl.xs_list, cnt, pl.xs_T,
-                             (pl.mode & PM_ARGMIN) ? 1 : 0, k == 0 ? pl.xs_W0 : pl.xs_W, st);
-    }));
+    // two-dimensional value-only jobs take axis 0 first (their own kernel
+    // instance), the others axis d-1 first; a plan may hold both
+    for (int xt = 0; xt < 2; ++xt) {
+      if (!(xt ? pl.xs_has_xt && k < 2 : pl.xs_has_std)) continue;
+      CHK(timed_launch(pl, st, [&] {
+        return launch_xs_stage(pl.djobs, pl.njobs, off, total, phase, k, pl.xs_sq, pl.xs_list, cnt, pl.xs_T,
+                               (pl.mode & PM_ARGMIN) ? 1 : 0, k == 0 ? pl.xs_W0 : pl.xs_W, xt, st);
+      }));
+    }
   }
   return launch_xs_fallback(pl.djobs, pl.xs_list, cnt, phase, std::max(1, std::min(pl.xs_pixels, 4096)), st);
 }

@@ -8,6 +8,7 @@
 // per-work-group partials in a fixed tree order, combined by a finalize
 // kernel in a fixed order - repeated runs are bitwise identical.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 #include <cmath>
@@ -1090,13 +1091,125 @@ __device__ __forceinline__ void xs_item(const DevJob& J, int jb, int local, int 
   }
 }
 
+// Two-dimensional jobs without arg-mins, 8 or 16 targets per lane: axis 0
+// first, then axis 1.  Both stages give a wave 64 consecutive lines (the
+// columns x_1 in the first, the target rows y_0 in the second) whose sources
+// lie N apart, so every load is coalesced across the lanes and the wave's
+// targets, hence the squares its candidates add, are common to its lanes
+// (scalar registers, as in the later stages above).  The first stage writes
+// its minima line by line, [x_1][y_0], the layout the second reads along its
+// lanes.  Each candidate still takes one float64 rounding per axis, of the
+// same magnitudes, so the error bound and the certification are those of the
+// other order, and so are the certified values.
+template <bool FIRST, int kXsT>
+__device__ __forceinline__ void xs_item_xt(const DevJob& J, int jb, int local, int phase,
+                                           const double* __restrict__ sqt, int2* __restrict__ list,
+                                           int* __restrict__ count, int wv, int SW, double* red) {
+  const int lane = threadIdx.x & 63;
+  const int N = J.N, P = J.P;
+  const int nchunk = (N + 63) >> 6;
+  const int group = local / nchunk, chunk = local - group * nchunk;
+  const int t0 = group * kXsT;
+  const int e = chunk * 64 + lane;   // the lane's line
+  const bool valid = e < N;
+  const int ee = valid ? e : 0;
+  double m1[kXsT];
+#pragma unroll
+  for (int t = 0; t < kXsT; ++t) m1[t] = INFINITY;
+  const_dptr sq = (const_dptr)sqt;
+  const int chunkS = ((N + 16 * SW - 1) / (16 * SW)) * 16;
+  const int rlo = min(N, wv * chunkS), rhi = min(N, rlo + chunkS);
+  const int NB = rhi - (rhi - rlo) % kXsT;   // sources in whole blocks end here
+  // source r of line e at r N + e: the first stage reads the potential
+  // (float32, negated), the second the first stage's minima (buffer 0);
+  // buffer loads with the lane's byte offset in a vector register and the
+  // source's in a scalar one, clamped to the last source (the loads four
+  // steps ahead of the last block go unused)
+  constexpr int EB = FIRST ? 4 : 8;
+  const void* base = FIRST ? (const void*)(phase == 0 ? J.fhat : J.g) : (const void*)J.xs_v;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, EB * P, 0x00020000);
+  const int lob = ee * EB;
+  const int st8 = N * EB, last_off = (N - 1) * st8;
+  int soff = rlo * st8;
+  // a ring of eight raw loads (float32 or float64 bits), each converted only
+  // when its step uses it
+  typedef typename std::conditional<FIRST, float, double>::type HT;
+  auto next = [&]() {
+    HT x;
+    if constexpr (FIRST) {
+      x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lob, soff, 0));
+    } else {
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lob, soff, 0);
+      __builtin_memcpy(&x, &w, 8);
+    }
+    soff = min(soff + st8, last_off);
+    __asm__ volatile("" : "+s"(soff));
+    return x;
+  };
+  HT hb[8];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) hb[u] = next();
+  for (int r0 = rlo; r0 < NB; r0 += kXsT) {
+    xs_sq_block<kXsT, 4>(m1, sq + (r0 - t0 + kXsOff), [&](int j) {
+      hb[(j + 4) & 7] = next();   // source r0 + j + 4
+      return FIRST ? -(double)hb[j & 7] : (double)hb[j & 7];
+    });
+  }
+  // the last (rhi - rlo) mod kXsT sources: squares from the table per step
+  for (int r = NB; r < rhi; ++r) {
+    const double h = FIRST ? -(double)(phase == 0 ? J.fhat : J.g)[(size_t)r * N + ee]
+                           : J.xs_v[(size_t)r * N + ee];
+    const_dptr sr = sq + (r - t0 + kXsOff - (kXsT - 1));
+#pragma unroll
+    for (int t = 0; t < kXsT; ++t) m1[t] = vmin_f64(m1[t], h + sr[kXsT - 1 - t]);
+  }
+  // the waves' minima meet in wave 0 (as in xs_item)
+  for (int half = SW >> 1; half > 0; half >>= 1) {
+    __syncthreads();
+    if (wv >= half && wv < 2 * half) {
+#pragma unroll
+      for (int t = 0; t < kXsT; ++t) red[((wv - half) * kXsT + t) * 64 + lane] = m1[t];
+    }
+    __syncthreads();
+    if (wv < half) {
+#pragma unroll
+      for (int t = 0; t < kXsT; ++t) m1[t] = vmin_f64(m1[t], red[(wv * kXsT + t) * 64 + lane]);
+    }
+  }
+  if (wv > 0 || !valid) return;
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int t = 0; t < kXsT; ++t)
+      if (t0 + t < N) J.xs_v[(size_t)e * N + t0 + t] = m1[t];
+  } else {
+    float* dst = phase == 0 ? J.g : J.f;
+    const double dk = 2.0 * 4.440892098500626e-16;    // d 2^-51, d = 2
+    const double c0 = 4.0 * (double)(N - 1) * (N - 1) + 1.0;
+#pragma unroll
+    for (int t = 0; t < kXsT; ++t) {
+      if (t0 + t >= N) break;
+      const int o = e * N + t0 + t;   // target (y_0 = e, y_1 = t0 + t)
+      const double w1 = m1[t];
+      const double del1 = dk * (fabs(w1) + c0);
+      const float lo = (float)(w1 - del1), hi = (float)(w1 + del1);
+      if (lo == hi) {   // false for NaN and infinite values
+        dst[o] = lo;
+      } else {
+        const int slot = atomicAdd(count, 1);
+        list[slot] = make_int2(jb, o);
+      }
+    }
+  }
+}
+
 // One instance per (stage kind, targets per lane T, arg-mins): each has its
 // own register budget.  T (16, 8, 4 or 2) is the plan's: fewer for small
 // plans, so that a launch still has enough waves (16 only without arg-mins,
 // where a target holds one running minimum).  A work-group of SW = blockDim / 64
 // waves takes one item, its waves splitting the sources.
-template <bool FIRST, int T, bool ARG>
-__attribute__((amdgpu_waves_per_eu((ARG || FIRST) ? 4 : 8)))
+template <bool FIRST, int T, bool ARG, bool XT>
+__attribute__((amdgpu_waves_per_eu((ARG || (FIRST && !XT)) ? 4 : 8)))
 __global__ __launch_bounds__(256) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
                                                   const int* __restrict__ off, int total, int phase, int k,
                                                   const double* __restrict__ sqt, int2* __restrict__ list,
@@ -1115,7 +1228,11 @@ __global__ __launch_bounds__(256) void k_xs_stage(const DevJob* __restrict__ job
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
     if (!J.xs || k >= J.d) continue;
-    xs_item<FIRST, T, ARG>(J, jb, it - off[jb], phase, k, sqt, list, count, tiles + wv * 64 * 17, wv, SW, red);
+    if constexpr (XT) {
+      if (J.xs_xt) xs_item_xt<FIRST, T>(J, jb, it - off[jb], phase, sqt, list, count, wv, SW, red);
+    } else {
+      if (!J.xs_xt) xs_item<FIRST, T, ARG>(J, jb, it - off[jb], phase, k, sqt, list, count, tiles + wv * 64 * 17, wv, SW, red);
+    }
   }
 }
 
@@ -1156,11 +1273,14 @@ __global__ __launch_bounds__(64) void k_xs_fallback(const DevJob* __restrict__ j
     const double* b1 = J.xs_v + 2 * P;   // stage 1 (3D): min over (x_1, x_2) per (x_0, y_1, y_2)
     const double dk = (double)d * 4.440892098500626e-16;
     const double c0 = 2.0 * d * (double)(N - 1) * (N - 1) + 1.0;
-    // outer index o: 2D the row x_1 (coordinate y1 of the target), 3D the plane x_0
-    const int oy = d == 2 ? y1 : y0;
+    // outer index o: 2D the row x_1 (coordinate y1 of the target), or the
+    // column x_2 for jobs whose first stage ran along axis 0 (its buffer
+    // [x_2][y_1]); 3D the plane x_0
+    const bool xt = d == 2 && J.xs_xt;
+    const int oy = d == 2 ? (xt ? y2 : y1) : y0;
     auto outer_bound = [&](int o) -> double {
       const double c = (double)(o - oy) * (double)(o - oy);
-      return d == 2 ? b0[(size_t)o * N + y2] + c : b1[(size_t)o * N * N + (size_t)y1 * N + y2] + c;
+      return d == 2 ? b0[(size_t)o * N + (xt ? y1 : y2)] + c : b1[(size_t)o * N * N + (size_t)y1 * N + y2] + c;
     };
     double w1 = INFINITY;
     for (int o = lane; o < N; o += 64) w1 = fmin(w1, outer_bound(o));
@@ -1185,7 +1305,13 @@ __global__ __launch_bounds__(64) void k_xs_fallback(const DevJob* __restrict__ j
         const int ob = oc + __ffsll((long long)m) - 1;
         m &= m - 1;
         const int co = (ob - oy) * (ob - oy);
-        if (d == 2) {
+        if (xt) {
+          // sources (r, ob) of the column, r = 0 .. N-1
+          for (int r = lane; r < N; r += 64) {
+            const int e = r - y1;
+            xs_take((float)(co + e * e) - src[r * N + ob], r * N + ob, best, bi);
+          }
+        } else if (d == 2) {
           scan_row(ob * N, co, y2);
         } else {
           // rows (ob, x_1) of the plane, bounded by stage 0
@@ -3360,29 +3486,36 @@ int launch_xs_squares(double* t, void* stream) {
   return QBW_OK;
 }
 template <bool FIRST>
-static void launch_xs_kind(int T, bool arg, int waves, const DevJob* jobs, int njobs, const int* off, int total,
-                           int phase, int k, const double* sqt, int2* list, int* count, hipStream_t st) {
+static void launch_xs_kind(int T, bool arg, bool xt, int waves, const DevJob* jobs, int njobs, const int* off,
+                           int total, int phase, int k, const double* sqt, int2* list, int* count, hipStream_t st) {
   const dim3 g(grid_for(total)), b(64 * waves);
-  const size_t lds = xs_lds_bytes(FIRST, T, arg, waves);
-  if (arg) {
-    if (T == 2) hipLaunchKernelGGL((k_xs_stage<FIRST, 2, true>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
-    else if (T == 4) hipLaunchKernelGGL((k_xs_stage<FIRST, 4, true>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
-    else hipLaunchKernelGGL((k_xs_stage<FIRST, 8, true>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
+  const size_t lds = xs_lds_bytes(FIRST && !xt, T, arg, waves);
+#define QBW_XS(TT, AA, XX) hipLaunchKernelGGL((k_xs_stage<FIRST, TT, AA, XX>), g, b, lds, st, jobs, njobs, off, total, \
+                                              phase, k, sqt, list, count)
+  if (xt) {
+    if (T == 16) QBW_XS(16, false, true);
+    else QBW_XS(8, false, true);
+  } else if (arg) {
+    if (T == 2) QBW_XS(2, true, false);
+    else if (T == 4) QBW_XS(4, true, false);
+    else QBW_XS(8, true, false);
   } else {
-    if (T == 2) hipLaunchKernelGGL((k_xs_stage<FIRST, 2, false>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
-    else if (T == 4) hipLaunchKernelGGL((k_xs_stage<FIRST, 4, false>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
-    else if (T == 16) hipLaunchKernelGGL((k_xs_stage<FIRST, 16, false>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
-    else hipLaunchKernelGGL((k_xs_stage<FIRST, 8, false>), g, b, lds, st, jobs, njobs, off, total, phase, k, sqt, list, count);
+    if (T == 2) QBW_XS(2, false, false);
+    else if (T == 4) QBW_XS(4, false, false);
+    else if (T == 16) QBW_XS(16, false, false);
+    else QBW_XS(8, false, false);
   }
+#undef QBW_XS
 }
 
 int launch_xs_stage(const DevJob* jobs, int njobs, const int* off, int total, int phase, int k, const double* sqt,
-                    int* list, int* count, int T, int argmin, int waves, void* stream) {
+                    int* list, int* count, int T, int argmin, int waves, int xt, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   int2* l2 = reinterpret_cast<int2*>(list);
   if (argmin) waves = 1;
-  if (k == 0) launch_xs_kind<true>(T, argmin != 0, waves, jobs, njobs, off, total, phase, 0, sqt, l2, count, st);
-  else launch_xs_kind<false>(T, argmin != 0, waves, jobs, njobs, off, total, phase, k, sqt, l2, count, st);
+  if (xt && (argmin || T < 8)) return QBW_E_INVAL;
+  if (k == 0) launch_xs_kind<true>(T, argmin != 0, xt != 0, waves, jobs, njobs, off, total, phase, 0, sqt, l2, count, st);
+  else launch_xs_kind<false>(T, argmin != 0, xt != 0, waves, jobs, njobs, off, total, phase, k, sqt, l2, count, st);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

@@ -125,6 +125,7 @@ struct DevJob {
   const float* sqrt_tab;    // p = 1 c-transform table fill: RN32(sqrt(n)) for n < kSqrtTab, or null
   int xs;                   // p = 2 c-transforms by exact separable minima (certified, re-evaluated where not)
   int xs_T;                 // targets per lane of its stages (8, 4 or 2)
+  int xs_xt;                // 2D, no arg-mins, 8 or 16 targets per lane: axis 0 first (xs_item_xt)
   double* xs_v;             // 2 x (2 P): per stage buffer, best value then runner-up value
   int* xs_i;                // 2 x P: per stage buffer, flat source index of the best value
   int* sep_arg;             // d x P or null
@@ -216,7 +217,7 @@ int launch_xs_squares(double* t, void* stream);
 // arg-mins; waves: waves per work-group splitting an item's sources (1, 2, 4;
 // 1 with arg-mins).
 int launch_xs_stage(const DevJob* jobs, int njobs, const int* off, int total, int phase, int k, const double* sqt,
-                    int* list, int* count, int T, int argmin, int waves, void* stream);
+                    int* list, int* count, int T, int argmin, int waves, int xt, void* stream);
 int launch_xs_fallback(const DevJob* jobs, const int* list, const int* count, int phase, int grid, void* stream);
 int launch_ctransform(const DevJob* jobs, const CtItem* items, int n_items, int* counter, int phase, int grid,
                       void* stream);
