@@ -1150,6 +1150,7 @@ __device__ __forceinline__ void xs_item_xt(const DevJob& J, int jb, int local, i
   HT hb[8];
 #pragma unroll
   for (int u = 0; u < 4; ++u) hb[u] = next();
+#pragma unroll 2
   for (int r0 = rlo; r0 < NB; r0 += kXsT) {
     xs_sq_block<kXsT, 4>(m1, sq + (r0 - t0 + kXsOff), [&](int j) {
       hb[(j + 4) & 7] = next();   // source r0 + j + 4
