@@ -1283,8 +1283,17 @@ __global__ __launch_bounds__(64) void k_xs_fallback(const DevJob* __restrict__ j
       const double c = (double)(o - oy) * (double)(o - oy);
       return d == 2 ? b0[(size_t)o * N + (xt ? y1 : y2)] + c : b1[(size_t)o * N * N + (size_t)y1 * N + y2] + c;
     };
+    // the lane's outer bounds (o = lane + 64 i), kept for the scan below
+    // when N <= 256
+    double obv[4];
     double w1 = INFINITY;
-    for (int o = lane; o < N; o += 64) w1 = fmin(w1, outer_bound(o));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int o = lane + 64 * i;
+      obv[i] = o < N ? outer_bound(o) : INFINITY;
+      w1 = fmin(w1, obv[i]);
+    }
+    for (int o = lane + 256; o < N; o += 64) w1 = fmin(w1, outer_bound(o));
 #pragma unroll
     for (int s = 32; s > 0; s >>= 1) w1 = fmin(w1, __shfl_xor(w1, s, 64));
     const float hi = (float)(w1 + dk * (fabs(w1) + c0));
@@ -1293,7 +1302,9 @@ __global__ __launch_bounds__(64) void k_xs_fallback(const DevJob* __restrict__ j
     float best = INFINITY;
     int bi = 0x7fffffff;
     auto scan_row = [&](int rowbase, int cost_rest, int ya) {
-      // sources rowbase + x, x = 0 .. N-1 along the last axis
+      // sources rowbase + x, x = 0 .. N-1 along the last axis (four loads in
+      // flight per lane)
+#pragma unroll 4
       for (int x = lane; x < N; x += 64) {
         const int e = x - ya;
         xs_take((float)(cost_rest + e * e) - src[rowbase + x], rowbase + x, best, bi);
@@ -1301,13 +1312,16 @@ __global__ __launch_bounds__(64) void k_xs_fallback(const DevJob* __restrict__ j
     };
     for (int oc = 0; oc < N; oc += 64) {
       const int o = oc + lane;
-      unsigned long long m = __ballot(o < N && !skip(outer_bound(o)));
+      const int ci = oc >> 6;
+      const double bo = ci == 0 ? obv[0] : ci == 1 ? obv[1] : ci == 2 ? obv[2] : ci == 3 ? obv[3] : 0.0;
+      unsigned long long m = __ballot(o < N && !skip(ci < 4 ? bo : outer_bound(o)));
       while (m) {
         const int ob = oc + __ffsll((long long)m) - 1;
         m &= m - 1;
         const int co = (ob - oy) * (ob - oy);
         if (xt) {
           // sources (r, ob) of the column, r = 0 .. N-1
+#pragma unroll 4
           for (int r = lane; r < N; r += 64) {
             const int e = r - y1;
             xs_take((float)(co + e * e) - src[r * N + ob], r * N + ob, best, bi);
@@ -2402,7 +2416,7 @@ __global__ __launch_bounds__(256) void k_cbar(const DevJob* __restrict__ jobs, i
 // block sum takes.
 __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs, int njobs,
                                                  const int* __restrict__ off, int total, int which) {
-  __shared__ double cs[5][256];
+  __shared__ double cs[10][256];   // five column sums per side
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     const int jb = find_job(off, njobs, it);
@@ -2417,58 +2431,72 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
       const int col = (int)threadIdx.x % Wc, rg = (int)threadIdx.x / Wc;
       const int nrows = J.d == 2 ? k : k * k;
       const double h = 0.5 * (k - 1);
-      for (int side = 0; side < 2; ++side) {
-        const double* m = which != 1 ? (side == 0 ? J.mu : J.nu) : (side == 0 ? J.a_s : J.b_s);
-        double* mo = which != 1 ? (side == 0 ? J.mom_mu : J.mom_nu) : (side == 0 ? J.mom_as : J.mom_bs);
-        double* pooled = which >= 2 ? (side == 0 ? J.mu_t : J.nu_t) : nullptr;
-        for (int c0 = 0; c0 < N; c0 += W) {
-          const int x2 = c0 + col;
-          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s4 = 0.0;
-          int bad = 0;
-          if (rg < RG && x2 < N) {
-            for (int r = rg; r < nrows; r += RG) {
-              const int u0 = J.d == 2 ? 0 : r / k, u1 = J.d == 2 ? r : r - (r / k) * k;
-              const size_t row = J.d == 2 ? (size_t)(b1 * k + u1)
-                                          : ((size_t)(b0 * k + u0) * N + (size_t)(b1 * k + u1));
-              const double w = m[row * N + x2];
-              bad |= (w < 0.0 ? 1 : 0) | (w != w ? 2 : 0);
-              const double d0 = J.d == 2 ? 0.0 : u0 - h, d1 = u1 - h;
-              s0 += w;
-              s1 += w * d0;
-              s2 += w * d1;
-              s4 += w * (d0 * d0 + d1 * d1);
-            }
+      // both fields in one sweep (each with its own sums, in the same order
+      // as a sweep of its own)
+      const double* ma = which != 1 ? J.mu : J.a_s;
+      const double* mb = which != 1 ? J.nu : J.b_s;
+      double* moa = which != 1 ? J.mom_mu : J.mom_as;
+      double* mob = which != 1 ? J.mom_nu : J.mom_bs;
+      for (int c0 = 0; c0 < N; c0 += W) {
+        const int x2 = c0 + col;
+        double sa0 = 0.0, sa1 = 0.0, sa2 = 0.0, sa4 = 0.0;
+        double sb0 = 0.0, sb1 = 0.0, sb2 = 0.0, sb4 = 0.0;
+        int bad = 0;
+        if (rg < RG && x2 < N) {
+#pragma unroll 4
+          for (int r = rg; r < nrows; r += RG) {
+            const int u0 = J.d == 2 ? 0 : r / k, u1 = J.d == 2 ? r : r - (r / k) * k;
+            const size_t row = J.d == 2 ? (size_t)(b1 * k + u1)
+                                        : ((size_t)(b0 * k + u0) * N + (size_t)(b1 * k + u1));
+            const double wa = ma[row * N + x2], wb = mb[row * N + x2];
+            bad |= (wa < 0.0 ? 1 : 0) | (wa != wa ? 2 : 0) | (wb < 0.0 ? 1 : 0) | (wb != wb ? 2 : 0);
+            const double d0 = J.d == 2 ? 0.0 : u0 - h, d1 = u1 - h;
+            sa0 += wa;
+            sa1 += wa * d0;
+            sa2 += wa * d1;
+            sa4 += wa * (d0 * d0 + d1 * d1);
+            sb0 += wb;
+            sb1 += wb * d0;
+            sb2 += wb * d1;
+            sb4 += wb * (d0 * d0 + d1 * d1);
           }
-          if (bad && which >= 2) atomicOr(J.flags, bad);
-          const double d2 = (double)(x2 % k) - h;
-          __syncthreads();
-          cs[0][threadIdx.x] = s0;
-          cs[1][threadIdx.x] = s1;
-          cs[2][threadIdx.x] = s2;
-          cs[3][threadIdx.x] = s0 * d2;
-          cs[4][threadIdx.x] = s4 + s0 * (d2 * d2);
-          __syncthreads();
-          // column totals over the row groups (in place, in group order) ...
-          if (RG > 1 && (int)threadIdx.x < Wc) {
+        }
+        if (bad && which >= 2) atomicOr(J.flags, bad);
+        const double d2 = (double)(x2 % k) - h;
+        __syncthreads();
+        cs[0][threadIdx.x] = sa0;
+        cs[1][threadIdx.x] = sa1;
+        cs[2][threadIdx.x] = sa2;
+        cs[3][threadIdx.x] = sa0 * d2;
+        cs[4][threadIdx.x] = sa4 + sa0 * (d2 * d2);
+        cs[5][threadIdx.x] = sb0;
+        cs[6][threadIdx.x] = sb1;
+        cs[7][threadIdx.x] = sb2;
+        cs[8][threadIdx.x] = sb0 * d2;
+        cs[9][threadIdx.x] = sb4 + sb0 * (d2 * d2);
+        __syncthreads();
+        // column totals over the row groups (in place, in group order) ...
+        if (RG > 1 && (int)threadIdx.x < Wc) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-              double v = cs[q][threadIdx.x];
-              for (int g = 1; g < RG; ++g) v += cs[q][g * Wc + threadIdx.x];
-              cs[q][threadIdx.x] = v;
-            }
+          for (int q = 0; q < 10; ++q) {
+            double v = cs[q][threadIdx.x];
+            for (int g = 1; g < RG; ++g) v += cs[q][g * Wc + threadIdx.x];
+            cs[q][threadIdx.x] = v;
           }
-          __syncthreads();
-          // ... then each (block, moment) adds its k columns in order
-          const int nb = min(W, N - c0) / k;   // whole blocks in this chunk
-          for (int id = threadIdx.x; id < 5 * nb; id += 256) {
-            const int bq = id / 5, q = id - bq * 5;
-            const int K2 = c0 / k + bq;
-            const int K = J.d == 2 ? b1 * n + K2 : (b0 * n + b1) * n + K2;
-            double v = 0.0;
-            for (int c = 0; c < k; ++c) v += cs[q][bq * k + c];
-            mo[5 * (size_t)K + q] = v;
-            if (q == 0 && pooled) pooled[K] = v;
-          }
+        }
+        __syncthreads();
+        // ... then each (side, block, moment) adds its k columns in order
+        const int nb = min(W, N - c0) / k;   // whole blocks in this chunk
+        for (int id = threadIdx.x; id < 10 * nb; id += 256) {
+          const int side = id >= 5 * nb ? 1 : 0;
+          const int rest = id - side * 5 * nb;
+          const int bq = rest / 5, q = rest - bq * 5;
+          const int K2 = c0 / k + bq;
+          const int K = J.d == 2 ? b1 * n + K2 : (b0 * n + b1) * n + K2;
+          double v = 0.0;
+          for (int c = 0; c < k; ++c) v += cs[side * 5 + q][bq * k + c];
+          (side ? mob : moa)[5 * (size_t)K + q] = v;
+          if (q == 0 && which >= 2) (side ? J.nu_t : J.mu_t)[K] = v;
         }
       }
       if (which == 3) {
