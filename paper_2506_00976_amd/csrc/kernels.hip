@@ -1150,7 +1150,6 @@ __device__ __forceinline__ void xs_item_xt(const DevJob& J, int jb, int local, i
   HT hb[8];
 #pragma unroll
   for (int u = 0; u < 4; ++u) hb[u] = next();
-#pragma unroll 2
   for (int r0 = rlo; r0 < NB; r0 += kXsT) {
     xs_sq_block<kXsT, 4>(m1, sq + (r0 - t0 + kXsOff), [&](int j) {
       hb[(j + 4) & 7] = next();   // source r0 + j + 4
@@ -1225,14 +1224,21 @@ __global__ __launch_bounds__(256) void k_xs_stage(const DevJob* __restrict__ job
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* tiles = reinterpret_cast<float*>(xs_lds);
   double* red = xs_lds + (FIRST && ARG ? (SW * 64 * 17 + 1) / 2 : 0);
-  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+  if constexpr (XT) {
+    // one item per work-group (the launcher's grid is the item count): with
+    // the source loop not nested in an item loop, the wait before each block
+    // is for the load four sources back, not for every load in flight
+    const int it = blockIdx.x;
+    if (it >= total) return;
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
-    if (!J.xs || k >= J.d) continue;
-    if constexpr (XT) {
-      if (J.xs_xt) xs_item_xt<FIRST, T>(J, jb, it - off[jb], phase, sqt, list, count, wv, SW, red);
-    } else {
-      if (!J.xs_xt) xs_item<FIRST, T, ARG>(J, jb, it - off[jb], phase, k, sqt, list, count, tiles + wv * 64 * 17, wv, SW, red);
+    if (J.xs && k < J.d && J.xs_xt) xs_item_xt<FIRST, T>(J, jb, it - off[jb], phase, sqt, list, count, wv, SW, red);
+  } else {
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+      const int jb = find_job(off, njobs, it);
+      const DevJob& J = jobs[jb];
+      if (!J.xs || k >= J.d || J.xs_xt) continue;
+      xs_item<FIRST, T, ARG>(J, jb, it - off[jb], phase, k, sqt, list, count, tiles + wv * 64 * 17, wv, SW, red);
     }
   }
 }
@@ -3517,7 +3523,7 @@ int launch_xs_squares(double* t, void* stream) {
 template <bool FIRST>
 static void launch_xs_kind(int T, bool arg, bool xt, int waves, const DevJob* jobs, int njobs, const int* off,
                            int total, int phase, int k, const double* sqt, int2* list, int* count, hipStream_t st) {
-  const dim3 g(grid_for(total)), b(64 * waves);
+  const dim3 g(xt ? total : grid_for(total)), b(64 * waves);
   const size_t lds = xs_lds_bytes(FIRST && !xt, T, arg, waves);
 #define QBW_XS(TT, AA, XX) hipLaunchKernelGGL((k_xs_stage<FIRST, TT, AA, XX>), g, b, lds, st, jobs, njobs, off, total, \
                                               phase, k, sqt, list, count)
@@ -3543,6 +3549,10 @@ int launch_xs_stage(const DevJob* jobs, int njobs, const int* off, int total, in
   int2* l2 = reinterpret_cast<int2*>(list);
   if (argmin) waves = 1;
   if (xt && (argmin || T < 8)) return QBW_E_INVAL;
+  if (xt && total > (1 << 23)) {   // one work-group per item: the grid's threads must stay below 2^32
+    set_error("launch_xs_stage: %d items exceed one work-group per item", total);
+    return QBW_E_INVAL;
+  }
   if (k == 0) launch_xs_kind<true>(T, argmin != 0, xt != 0, waves, jobs, njobs, off, total, phase, 0, sqt, l2, count, st);
   else launch_xs_kind<false>(T, argmin != 0, xt != 0, waves, jobs, njobs, off, total, phase, k, sqt, l2, count, st);
   HIP_TRY(hipGetLastError());
