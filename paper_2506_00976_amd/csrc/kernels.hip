@@ -29,6 +29,14 @@ namespace qbw {
   } while (0)
 
 __device__ __forceinline__ int find_job(const int* __restrict__ off, int njobs, int item) {
+  // a batch of equal jobs: the quotient by the first job's count, checked
+  // against its two prefix entries (two dependent loads, not log2 njobs);
+  // otherwise the last job whose prefix entry is at most the item
+  const int per = off[1] - off[0];
+  if (per > 0) {
+    const int g = min(item / per, njobs - 1);
+    if (off[g] <= item && item < off[g + 1]) return g;
+  }
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
@@ -2243,12 +2251,16 @@ __device__ __forceinline__ double gam(double n) {
 // One job's bounds by a 256-thread work-group (sh: 256 doubles of LDS).
 __device__ void finalize_job(const DevJob& J, double* sh) {
   double* res = J.result;
-  // lower bound
+  // the pixel chunks' partials of the lower bound (sums and maxima) and of
+  // the TV terms, one loop so that both rows' loads are in flight together
   double sf = 0, sg = 0, mh = 0, mg = 0, mf = 0;
+  double tm = 0, tn = 0, wm = 0, wn = 0;
   for (int c = threadIdx.x; c < J.chunks; c += 256) {
     const double* r = J.red_lb + (size_t)c * kRedSlotsLB;
+    const double* t = J.red_tv + (size_t)c * kRedSlotsTV;
     sf += r[0]; sg += r[1];
     mh = fmax(mh, r[2]); mg = fmax(mg, r[3]); mf = fmax(mf, r[4]);
+    tm += t[0]; tn += t[1]; wm += t[2]; wn += t[3];
   }
   // upper bound
   const int kdi = J.d == 2 ? J.k * J.k : J.k * J.k * J.k;
@@ -2257,18 +2269,13 @@ __device__ void finalize_job(const DevJob& J, double* sh) {
   double pc = 0, mm = 0;
   // unrolled so that several entries' loads are in flight at once (the sums
   // keep their order)
-#pragma unroll 4
+#pragma unroll 8
   for (int e = threadIdx.x; e < J.nnz; e += 256) {
     const double ce = cc * J.e_val[e];
     pc += ce * J.red_pc[e];
     if (J.p == 2) mm += ce * J.red_pm[e];
   }
   const double rmax = (double)J.row_max, cmax = (double)J.col_max;
-  double tm = 0, tn = 0, wm = 0, wn = 0;
-  for (int c = threadIdx.x; c < J.chunks; c += 256) {
-    const double* r = J.red_tv + (size_t)c * kRedSlotsTV;
-    tm += r[0]; tn += r[1]; wm += r[2]; wn += r[3];
-  }
   // all sums and maxima in one work-group reduction
   {
     double sv[8] = {sf, sg, pc, tm, tn, wm, wn, mm};
