@@ -292,6 +292,8 @@ struct Plan {
   int xs_T = 8, xs_W = 1;  // targets per lane and waves per work-group of the stages
   int xs_W0 = 1;           // waves per work-group of the first stage
   bool xs_has_xt = false, xs_has_std = false;   // jobs on xs_item_xt (2D, axis 0 first) / on xs_item
+  int xs_xt_kind = 2;   // the axis-0-first jobs' kind: 2 argmin windows (xs_item_win), 1 every source
+  int xs_wg = 2;        // argmin windows: targets and waves of a work-group, in multiples of xs_T, xs_W
   size_t ipf_lds = 0;      // dynamic LDS of the coarse fitting kernel (jobs that do not fit use global memory)
   size_t bwd_lds = 0;      // the same for the coarse backward kernel
   bool fwd_rev = false;    // a backward pass follows: the forward's coarse kernel runs its p = 2 reverse pass
@@ -568,6 +570,17 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
   // QBW_XS_XT=0 keeps two-dimensional jobs on the last-axis-first order
   const char* xte = std::getenv("QBW_XS_XT");
   const bool xs_xt_on = !(xte && std::strcmp(xte, "0") == 0);
+  // QBW_XS_WIN=0 scans every source of those jobs (no argmin windows)
+  const char* xwe = std::getenv("QBW_XS_WIN");
+  const bool xs_win_on = !(xwe && std::strcmp(xwe, "0") == 0);
+  // QBW_XS_WG (1 or 2): an argmin-window item spans that many target groups
+  // of xs_T targets, on as many times the waves (one scan of the item's
+  // lines serves all of its targets' windows)
+  int xs_wg = 2;
+  if (const char* e = std::getenv("QBW_XS_WG")) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2) xs_wg = v;
+  }
   int xs_T = xs16 ? 16 : 8;
   {
     auto waves = [&](int T) {
@@ -682,9 +695,12 @@ static int plan_build(qbw_ctx* ctx, Plan& pl, std::vector<JobIn> in, unsigned mo
     {
       // exact separable stages: one wave per (64 lines, xs_T targets along the axis)
       D.xs_T = xs_T;
-      D.xs_xt = (D.xs && D.d == 2 && !(mode & PM_ARGMIN) && xs_T >= 8 && xs_xt_on) ? 1 : 0;
+      D.xs_xt = (D.xs && D.d == 2 && !(mode & PM_ARGMIN) && xs_T >= 8 && xs_xt_on) ? (xs_win_on ? 2 : 1) : 0;
+      pl.xs_xt_kind = xs_win_on ? 2 : 1;
+      pl.xs_wg = xs_wg;
       if (D.xs) (D.xs_xt ? pl.xs_has_xt : pl.xs_has_std) = true;
-      const int xs_items = D.xs ? ((D.rows + 63) / 64) * ((D.N + xs_T - 1) / xs_T) : 0;
+      const int Tj = D.xs_xt == 2 ? xs_T * xs_wg : xs_T;   // targets per item
+      const int xs_items = D.xs ? ((D.rows + 63) / 64) * ((D.N + Tj - 1) / Tj) : 0;
       off[12 * (NJ + 1) + j + 1] = off[12 * (NJ + 1) + j] + xs_items;
       off[13 * (NJ + 1) + j + 1] = off[13 * (NJ + 1) + j] + (D.d == 3 ? xs_items : 0);
     }
@@ -867,8 +883,10 @@ static int enqueue_xs(Plan& pl, int phase, hipStream_t st) {
     for (int xt = 0; xt < 2; ++xt) {
       if (!(xt ? pl.xs_has_xt && k < 2 : pl.xs_has_std)) continue;
       CHK(timed_launch(pl, st, [&] {
-        return launch_xs_stage(pl.djobs, pl.njobs, off, total, phase, k, pl.xs_sq, pl.xs_list, cnt, pl.xs_T,
-                               (pl.mode & PM_ARGMIN) ? 1 : 0, k == 0 ? pl.xs_W0 : pl.xs_W, xt, st);
+        const int kind = xt ? pl.xs_xt_kind : 0;
+        const int f = kind == 2 ? pl.xs_wg : 1;
+        return launch_xs_stage(pl.djobs, pl.njobs, off, total, phase, k, pl.xs_sq, pl.xs_list, cnt, pl.xs_T * f,
+                               (pl.mode & PM_ARGMIN) ? 1 : 0, (k == 0 ? pl.xs_W0 : pl.xs_W) * f, kind, st);
       }));
     }
   }

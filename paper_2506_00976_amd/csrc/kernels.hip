@@ -1211,20 +1211,245 @@ __device__ __forceinline__ void xs_item_xt(const DevJob& J, int jb, int local, i
   }
 }
 
+// The same stage by windows (the default for these jobs).  Along one axis the
+// candidate matrix a[r] + (r - t)^2 is Monge, so the first exact minimiser of
+// a target never lies left of the first one of a smaller target, nor the last
+// one right of the last one of a larger target.  Rounding is monotone: every
+// exact minimiser of t attains the rounded minimum of t, and the rounded
+// minimum is the rounding of the exact one.  Hence, for the targets t0 <= t <=
+// t1 of an item, the sources from the first one attaining the rounded minimum
+// of t0 to the last one attaining that of t1 hold a minimiser of each t, and
+// the minimum over that window equals the minimum over all sources, bit for
+// bit (no source whose value is NaN ever bounds a window; a line without a
+// finite candidate keeps +inf).  Phase 1: the item's waves split the sources
+// and scan the two boundary targets, keeping each one's rounded minimum and
+// the start of the first, or the end of the last, block of eight sources
+// attaining it (bounds on the first and last sources attaining it); the
+// waves' partials meet through LDS.
+// Phase 2: each wave scans the window (the union over its 64 lines, so that
+// loads stay coalesced and the squares wave-uniform) for T / SW of the
+// item's targets, and certifies and stores them as above.
+template <bool FIRST, int TPW>
+__device__ __forceinline__ void xs_win_scan(const DevJob& J, int jb, int phase, const_dptr sq,
+                                            int2* __restrict__ list, int* __restrict__ count, int e,
+                                            bool valid, int tw0, int wlo, int whi,
+                                            __amdgpu_buffer_rsrc_t rs, int lob, int st8) {
+  const int N = J.N;
+  double m[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) m[j] = INFINITY;
+  typedef typename std::conditional<FIRST, float, double>::type HT;
+  auto load = [&](int off) {   // the source at byte offset off (a scalar)
+    HT x;
+    if constexpr (FIRST) {
+      x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lob, off, 0));
+    } else {
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lob, off, 0);
+      __builtin_memcpy(&x, &w, 8);
+    }
+    return x;
+  };
+  if (wlo <= whi) {
+    // blocks of sixteen through a ring of loads eight ahead; in the last
+    // block the sources past the window load the window's last source and
+    // count as +inf
+    const int whi8 = whi * st8;
+    int soff = wlo * st8;
+    auto next = [&]() {
+      const HT x = load(soff);
+      soff = min(soff + st8, whi8);
+      __asm__ volatile("" : "+s"(soff));
+      return x;
+    };
+    HT hb[16];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) hb[u] = next();
+    auto block = [&](int r0, auto partial) {   // sixteen sources
+#pragma unroll
+      for (int bk = 0; bk < 2; ++bk) {
+        // sb[j + TPW - 1 - t] = (r0 + 8 bk + j - tw0 - t)^2
+        const_dptr sb = sq + (r0 + 8 * bk - tw0 + kXsOff - (TPW - 1));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          hb[(8 * bk + j + 8) & 15] = next();   // source r0 + 8 bk + j + 8
+          double h = FIRST ? -(double)hb[8 * bk + j] : (double)hb[8 * bk + j];
+          if constexpr (decltype(partial)::value) h = r0 + 8 * bk + j <= whi ? h : INFINITY;
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) m[t] = vmin_f64(m[t], h + sb[j + TPW - 1 - t]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    int r0 = wlo;
+    for (; r0 + 15 <= whi; r0 += 16) block(r0, std::false_type());
+    if (r0 <= whi) block(r0, std::true_type());
+  }
+  if (!valid) return;
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+      if (tw0 + j < N) J.xs_v[(size_t)e * N + tw0 + j] = m[j];
+  } else {
+    float* dst = phase == 0 ? J.g : J.f;
+    const double dk = 2.0 * 4.440892098500626e-16;    // d 2^-51, d = 2
+    const double c0 = 4.0 * (double)(N - 1) * (N - 1) + 1.0;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      if (tw0 + j >= N) break;
+      const int o = e * N + tw0 + j;   // target (y_0 = e, y_1 = tw0 + j)
+      const double w1 = m[j];
+      const double del1 = dk * (fabs(w1) + c0);
+      const float lo = (float)(w1 - del1), hi = (float)(w1 + del1);
+      if (lo == hi) {   // false for NaN and infinite values
+        dst[o] = lo;
+      } else {
+        const int slot = atomicAdd(count, 1);
+        list[slot] = make_int2(jb, o);
+      }
+    }
+  }
+}
+
+template <bool FIRST, int kXsT>
+__device__ __forceinline__ void xs_item_win(const DevJob& J, int jb, int local, int phase,
+                                            const double* __restrict__ sqt, int2* __restrict__ list,
+                                            int* __restrict__ count, int wv, int SW, double* red) {
+  const int lane = threadIdx.x & 63;
+  const int N = J.N, P = J.P;
+  const int ngroup = (N + kXsT - 1) / kXsT;
+  const int chunk = local / ngroup, group = local - chunk * ngroup;   // chunk-major
+  const int t0 = group * kXsT;
+  const int tb1 = min(t0 + kXsT - 1, N - 1);   // the item's last target
+  const int e = chunk * 64 + lane;
+  const bool valid = e < N;
+  const int ee = valid ? e : 0;
+  const_dptr sq = (const_dptr)sqt;
+  const int chunkS = ((N + 16 * SW - 1) / (16 * SW)) * 16;
+  const int rlo = min(N, wv * chunkS), rhi = min(N, rlo + chunkS);
+  const int NB = rhi - (rhi - rlo) % 16;   // sources in whole pairs of blocks of 8 end here
+  // phase 1: rounded minima of t0 and tb1 over this wave's sources, with the
+  // first source attaining the one and the last attaining the other
+  double b0 = INFINITY, b1 = INFINITY;
+  int lo = 0x7fffffff, hi = -1;
+  constexpr int EB = FIRST ? 4 : 8;
+  const void* base = FIRST ? (const void*)(phase == 0 ? J.fhat : J.g) : (const void*)J.xs_v;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, EB * P, 0x00020000);
+  const int lob = ee * EB;
+  const int st8 = N * EB, last_off = (N - 1) * st8;
+  int soff = rlo * st8;
+  typedef typename std::conditional<FIRST, float, double>::type HT;
+  auto next = [&]() {
+    HT x;
+    if constexpr (FIRST) {
+      x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lob, soff, 0));
+    } else {
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lob, soff, 0);
+      __builtin_memcpy(&x, &w, 8);
+    }
+    soff = min(soff + st8, last_off);
+    __asm__ volatile("" : "+s"(soff));
+    return x;
+  };
+  // a block's minima update the running ones: lo is the first block start
+  // and hi the last block end at which they are attained (bounds on the
+  // first and last sources attaining them, at most seven sources wider)
+  auto take = [&](double m0, double m1, int first, int last) {
+    lo = m0 < b0 ? first : lo;
+    hi = m1 <= b1 ? last : hi;
+    b0 = vmin_f64(b0, m0);
+    b1 = vmin_f64(b1, m1);
+  };
+  // a ring of sixteen loads, eight ahead: a step does a few instructions
+  // per load, so the loads in flight, not the arithmetic, hide the latency
+  HT hb[16];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) hb[u] = next();
+  for (int r0 = rlo; r0 < NB; r0 += 16) {
+#pragma unroll
+    for (int bk = 0; bk < 2; ++bk) {
+      const int rb = r0 + 8 * bk;
+      const_dptr q0 = sq + (rb - t0 + kXsOff), q1 = sq + (rb - tb1 + kXsOff);
+      double m0 = INFINITY, m1 = INFINITY;
+      // in two halves, each with its own eight squares in scalar registers
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        double s0[4], s1[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { s0[j] = q0[4 * hf + j]; s1[j] = q1[4 * hf + j]; }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int j = 8 * bk + 4 * hf + jj;
+          hb[(j + 8) & 15] = next();   // source r0 + j + 8
+          const double h = FIRST ? -(double)hb[j] : (double)hb[j];
+          m0 = vmin_f64(m0, h + s0[jj]);
+          m1 = vmin_f64(m1, h + s1[jj]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      take(m0, m1, rb, rb + 7);
+    }
+  }
+  for (int r = NB; r < rhi; ++r) {
+    const double h = FIRST ? -(double)(phase == 0 ? J.fhat : J.g)[(size_t)r * N + ee]
+                           : J.xs_v[(size_t)r * N + ee];
+    take(h + sq[r - t0 + kXsOff], h + sq[r - tb1 + kXsOff], r, r);
+  }
+  // the waves' partials, combined in wave order by every wave
+  double* rb = red;                                        // SW x 64 x (b0, b1)
+  int* ri = reinterpret_cast<int*>(red + 2 * 64 * SW);     // SW x 64 x (lo, hi)
+  rb[(wv * 64 + lane) * 2] = b0;
+  rb[(wv * 64 + lane) * 2 + 1] = b1;
+  ri[(wv * 64 + lane) * 2] = lo;
+  ri[(wv * 64 + lane) * 2 + 1] = hi;
+  __syncthreads();
+  b0 = INFINITY; b1 = INFINITY; lo = 0x7fffffff; hi = -1;
+  for (int w = 0; w < SW; ++w) {
+    const double c0 = rb[(w * 64 + lane) * 2], c1 = rb[(w * 64 + lane) * 2 + 1];
+    const int l0 = ri[(w * 64 + lane) * 2], h1 = ri[(w * 64 + lane) * 2 + 1];
+    lo = c0 < b0 ? l0 : (c0 == b0 ? min(lo, l0) : lo);
+    hi = c1 < b1 ? h1 : (c1 == b1 ? max(hi, h1) : hi);
+    b0 = vmin_f64(b0, c0);
+    b1 = vmin_f64(b1, c1);
+  }
+  // the window over the wave's lines
+  if (!valid) { lo = 0x7fffffff; hi = -1; }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o, 64));
+    hi = max(hi, __shfl_xor(hi, o, 64));
+  }
+  const int wlo = __builtin_amdgcn_readfirstlane(max(lo, 0));
+  const int whi = __builtin_amdgcn_readfirstlane(min(hi, N - 1));
+  // phase 2: this wave's targets
+  const int tpw = kXsT / SW;
+  const int tw0 = t0 + wv * tpw;
+  if (tw0 >= N) return;
+  // (four targets per pass at most, which keeps one pass within the
+  // stage's registers; more passes re-read the window from the caches)
+  if (tpw == 2) {
+    xs_win_scan<FIRST, 2>(J, jb, phase, sq, list, count, e, valid, tw0, wlo, whi, rs, lob, st8);
+  } else {
+    for (int c = 0; c < tpw; c += 4)
+      xs_win_scan<FIRST, 4>(J, jb, phase, sq, list, count, e, valid, tw0 + c, wlo, whi, rs, lob, st8);
+  }
+}
+
 // One instance per (stage kind, targets per lane T, arg-mins): each has its
 // own register budget.  T (16, 8, 4 or 2) is the plan's: fewer for small
 // plans, so that a launch still has enough waves (16 only without arg-mins,
 // where a target holds one running minimum).  A work-group of SW = blockDim / 64
 // waves takes one item, its waves splitting the sources.
-template <bool FIRST, int T, bool ARG, bool XT>
-__attribute__((amdgpu_waves_per_eu((ARG || (FIRST && !XT)) ? 4 : 8)))
-__global__ __launch_bounds__(256) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
+template <bool FIRST, int T, bool ARG, int XT>
+__attribute__((amdgpu_waves_per_eu((ARG || (FIRST && XT == 0)) ? 4 : 8)))
+__global__ __launch_bounds__(XT == 2 ? 512 : 256) void k_xs_stage(const DevJob* __restrict__ jobs, int njobs,
                                                   const int* __restrict__ off, int total, int phase, int k,
                                                   const double* __restrict__ sqt, int2* __restrict__ list,
                                                   int* __restrict__ count) {
   // dynamic LDS, sized by the launcher (xs_lds_bytes): the first stage's
   // per-wave tiles (64 x 17 floats, with arg-mins only), then SW / 2 x 64 x T
-  // doubles for the waves' minima on their way to wave 0
+  // doubles for the waves' minima on their way to wave 0 (argmin windows:
+  // SW x 64 x (two minima, two source bounds) for the waves' partials)
   extern __shared__ double xs_lds[];
   const int SW = blockDim.x >> 6;
   // the wave index, known wave-uniform: source ranges and load addresses
@@ -1232,15 +1457,25 @@ __global__ __launch_bounds__(256) void k_xs_stage(const DevJob* __restrict__ job
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* tiles = reinterpret_cast<float*>(xs_lds);
   double* red = xs_lds + (FIRST && ARG ? (SW * 64 * 17 + 1) / 2 : 0);
-  if constexpr (XT) {
+  if constexpr (XT > 0) {
     // one item per work-group (the launcher's grid is the item count): with
     // the source loop not nested in an item loop, the wait before each block
-    // is for the load four sources back, not for every load in flight
-    const int it = blockIdx.x;
+    // is for the load four sources back, not for every load in flight.  XT 2:
+    // argmin windows (xs_item_win), XT 1: every source (xs_item_xt), each in
+    // its own instance with its own registers
+    int it = blockIdx.x;
     if (it >= total) return;
+    // argmin windows: work-groups go to the eight XCDs in turn, so XCD x
+    // takes the x-th eighth of the items, whole line chunks (chunk-major
+    // items), each chunk's sources read into one L2
+    if (XT == 2 && (total & 7) == 0) it = (it & 7) * (total >> 3) + (it >> 3);
     const int jb = find_job(off, njobs, it);
     const DevJob& J = jobs[jb];
-    if (J.xs && k < J.d && J.xs_xt) xs_item_xt<FIRST, T>(J, jb, it - off[jb], phase, sqt, list, count, wv, SW, red);
+    if (!J.xs || k >= J.d || J.xs_xt != XT) return;
+    if constexpr (XT == 2)
+      xs_item_win<FIRST, T>(J, jb, it - off[jb], phase, sqt, list, count, wv, SW, red);
+    else
+      xs_item_xt<FIRST, T>(J, jb, it - off[jb], phase, sqt, list, count, wv, SW, red);
   } else {
     for (int it = blockIdx.x; it < total; it += gridDim.x) {
       const int jb = find_job(off, njobs, it);
@@ -1252,9 +1487,10 @@ __global__ __launch_bounds__(256) void k_xs_stage(const DevJob* __restrict__ job
 }
 
 // LDS bytes of one k_xs_stage work-group (matches the kernel's carving).
-static size_t xs_lds_bytes(bool first, int T, bool arg, int waves) {
+static size_t xs_lds_bytes(bool first, int T, bool arg, int waves, bool xt) {
   const size_t tiles = first && arg ? 8 * (size_t)((waves * 64 * 17 + 1) / 2) : 0;
-  const size_t red = arg ? 0 : 8 * (size_t)(waves / 2) * 64 * T;
+  // the waves' minima on their way to wave 0, or the windows' partials
+  const size_t red = xt ? (size_t)waves * 64 * (16 + 8) : arg ? 0 : 8 * (size_t)(waves / 2) * 64 * T;
   return std::max<size_t>(8, tiles + red);
 }
 
@@ -3528,24 +3764,28 @@ int launch_xs_squares(double* t, void* stream) {
   return QBW_OK;
 }
 template <bool FIRST>
-static void launch_xs_kind(int T, bool arg, bool xt, int waves, const DevJob* jobs, int njobs, const int* off,
+static void launch_xs_kind(int T, bool arg, int xt, int waves, const DevJob* jobs, int njobs, const int* off,
                            int total, int phase, int k, const double* sqt, int2* list, int* count, hipStream_t st) {
   const dim3 g(xt ? total : grid_for(total)), b(64 * waves);
-  const size_t lds = xs_lds_bytes(FIRST && !xt, T, arg, waves);
+  const size_t lds = xs_lds_bytes(FIRST && !xt, T, arg, waves, xt == 2);
 #define QBW_XS(TT, AA, XX) hipLaunchKernelGGL((k_xs_stage<FIRST, TT, AA, XX>), g, b, lds, st, jobs, njobs, off, total, \
                                               phase, k, sqt, list, count)
-  if (xt) {
-    if (T == 16) QBW_XS(16, false, true);
-    else QBW_XS(8, false, true);
+  if (xt == 2) {
+    if (T == 32) QBW_XS(32, false, 2);
+    else if (T == 16) QBW_XS(16, false, 2);
+    else QBW_XS(8, false, 2);
+  } else if (xt == 1) {
+    if (T == 16) QBW_XS(16, false, 1);
+    else QBW_XS(8, false, 1);
   } else if (arg) {
-    if (T == 2) QBW_XS(2, true, false);
-    else if (T == 4) QBW_XS(4, true, false);
-    else QBW_XS(8, true, false);
+    if (T == 2) QBW_XS(2, true, 0);
+    else if (T == 4) QBW_XS(4, true, 0);
+    else QBW_XS(8, true, 0);
   } else {
-    if (T == 2) QBW_XS(2, false, false);
-    else if (T == 4) QBW_XS(4, false, false);
-    else if (T == 16) QBW_XS(16, false, false);
-    else QBW_XS(8, false, false);
+    if (T == 2) QBW_XS(2, false, 0);
+    else if (T == 4) QBW_XS(4, false, 0);
+    else if (T == 16) QBW_XS(16, false, 0);
+    else QBW_XS(8, false, 0);
   }
 #undef QBW_XS
 }
@@ -3555,13 +3795,14 @@ int launch_xs_stage(const DevJob* jobs, int njobs, const int* off, int total, in
   hipStream_t st = (hipStream_t)stream;
   int2* l2 = reinterpret_cast<int2*>(list);
   if (argmin) waves = 1;
-  if (xt && (argmin || T < 8)) return QBW_E_INVAL;
+  if (xt < 0 || xt > 2 || (xt && (argmin || T < 8)) || (xt != 2 && T > 16) || waves > (xt == 2 ? 8 : 4))
+    return QBW_E_INVAL;
   if (xt && total > (1 << 23)) {   // one work-group per item: the grid's threads must stay below 2^32
     set_error("launch_xs_stage: %d items exceed one work-group per item", total);
     return QBW_E_INVAL;
   }
-  if (k == 0) launch_xs_kind<true>(T, argmin != 0, xt != 0, waves, jobs, njobs, off, total, phase, 0, sqt, l2, count, st);
-  else launch_xs_kind<false>(T, argmin != 0, xt != 0, waves, jobs, njobs, off, total, phase, k, sqt, l2, count, st);
+  if (k == 0) launch_xs_kind<true>(T, argmin != 0, xt, waves, jobs, njobs, off, total, phase, 0, sqt, l2, count, st);
+  else launch_xs_kind<false>(T, argmin != 0, xt, waves, jobs, njobs, off, total, phase, k, sqt, l2, count, st);
   HIP_TRY(hipGetLastError());
   return QBW_OK;
 }

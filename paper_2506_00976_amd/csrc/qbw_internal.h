@@ -125,7 +125,8 @@ struct DevJob {
   const float* sqrt_tab;    // p = 1 c-transform table fill: RN32(sqrt(n)) for n < kSqrtTab, or null
   int xs;                   // p = 2 c-transforms by exact separable minima (certified, re-evaluated where not)
   int xs_T;                 // targets per lane of its stages (8, 4 or 2)
-  int xs_xt;                // 2D, no arg-mins, 8 or 16 targets per lane: axis 0 first (xs_item_xt)
+  int xs_xt;                // 2D, no arg-mins, 8 or 16 targets per lane: axis 0 first (1: xs_item_xt,
+                            // every source; 2: xs_item_win, argmin windows)
   double* xs_v;             // 2 x (2 P): per stage buffer, best value then runner-up value
   int* xs_i;                // 2 x P: per stage buffer, flat source index of the best value
   int* sep_arg;             // d x P or null
@@ -213,9 +214,12 @@ int launch_sqrt_table(float* t, int n, void* stream);
 // pixel count) and `count` their number (zero before stage 0).
 constexpr int kXsSquares = 2 * 2904 + 1;
 int launch_xs_squares(double* t, void* stream);
-// T: the plan's targets per lane (every job's xs_T); argmin: the plan wants
-// arg-mins; waves: waves per work-group splitting an item's sources (1, 2, 4;
-// 1 with arg-mins).
+// T: the plan's targets per lane (every job's xs_T; for xt 2 the item's
+// targets, xs_T times the group factor); argmin: the plan wants arg-mins;
+// waves: waves per work-group splitting an item's sources (1, 2, 4; 1 with
+// arg-mins; up to 8 for xt 2).
+// xt: 0 axis d-1 first (xs_item), 1 two-dimensional axis 0 first over every
+// source (xs_item_xt), 2 the same by argmin windows (xs_item_win)
 int launch_xs_stage(const DevJob* jobs, int njobs, const int* off, int total, int phase, int k, const double* sqt,
                     int* list, int* count, int T, int argmin, int waves, int xt, void* stream);
 int launch_xs_fallback(const DevJob* jobs, const int* list, const int* count, int phase, int grid, void* stream);

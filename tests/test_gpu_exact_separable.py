@@ -155,6 +155,38 @@ def test_ctransform_exact_values_16_targets_per_lane(N, d, kind, monkeypatch):
     assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32))
 
 
+# Two-dimensional value-only stages scan, per item, only the sources between
+# the first minimiser of its first target and the last minimiser of its last
+# target (the per-axis candidates form a Monge matrix).  Every split of an
+# item over 1, 2 or 4 waves (the second phase then takes 16 or 8, 8 or 4, 4 or
+# 2 targets per wave), partial target groups and line chunks, and potentials
+# of -inf (sources that never attain a minimum; a whole line of them has no
+# finite candidate), against the oracle bit for bit.  An item spans one or
+# two target groups (QBW_XS_WG, on as many times the waves); QBW_XS_WIN=0
+# scans every source.
+@pytest.mark.parametrize("mode", ["wg2", "wg1", "full"])
+@pytest.mark.parametrize("W", ["1", "2", "4"])
+@pytest.mark.parametrize("T", ["8", "16"])
+@pytest.mark.parametrize("kind", ["normal", "smooth", "ties", "near_ties", "nonfinite"])
+@pytest.mark.parametrize("N", [15, 64, 100])
+def test_ctransform_exact_windows(N, kind, T, W, mode, monkeypatch):
+    monkeypatch.setenv("QBW_XS_T", T)
+    monkeypatch.setenv("QBW_XS_W", W)
+    monkeypatch.setenv("QBW_XS_W0", W)
+    monkeypatch.setenv("QBW_XS_WIN", "0" if mode == "full" else "1")
+    monkeypatch.setenv("QBW_XS_WG", "1" if mode == "wg1" else "2")
+    seed = 12800 + N + int(T) + int(W)
+    phi = potential("smooth" if kind == "nonfinite" else kind, N, 2, seed)
+    if kind == "nonfinite":
+        r = si.rng(seed + 1)
+        phi = phi.copy()
+        phi[r.choice(N * N, N, replace=False)] = -np.inf
+        phi.reshape(N, N)[:, int(r.integers(0, N))] = -np.inf   # a line of the first stage
+    out = qbw.ctransform_exact(dev(phi), N, 2)
+    ref, _ = lower.ctransform_o32(phi, N, 2, 2)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+
+
 # full-size grids on sampled targets (the oracle evaluates them one by one)
 @pytest.mark.parametrize("kind", ["normal", "smooth"])
 @pytest.mark.parametrize("N,d", [(256, 2), (32, 3), (128, 2)])
