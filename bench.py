@@ -39,6 +39,11 @@ PEAK_PAIRS = PEAK_LANE_OPS / INSTR_PER_PAIR
 # stage needs at least a v_add_f64 and a v_min_f64 (the best value); with arg-mins also
 # v_cmp_lt_f64 + v_cndmask_b32 (the index) and v_max_f64 + v_min_f64 (the runner-up).  The
 # timed batch asks for no arg-mins (the gradients in a and b are f and g themselves).
+# The value-only two-dimensional stages scan argmin windows (the per-axis candidates
+# are Monge): per item, its two boundary targets over every source, its other targets
+# over the window between their minimisers.  The candidate count stays the separable
+# evaluation's (P N per stage, every source for every target), so against this peak
+# the fraction is the rate relative to evaluating all of them at full issue rate.
 PEAK_F64_LANE_OPS = 256 * 64 * 2.4e9
 XS_INSTR_PER_CAND = 2
 XS_INSTR_PER_CAND_ARGMIN = 6
@@ -423,6 +428,8 @@ def main():
         if sep_mode == "exact":
             return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_XS / 1e12, "unit": "Tcand/s",
                     "frac": ach / PEAK_XS, "traffic": read_traffic("xs_stage"), "kernel": "k_xs_stage",
+                    "work": "separable candidates, P N per stage launch; the kernel itself evaluates the two "
+                            "boundary targets of each item over every source and the rest over argmin windows",
                     "mean_launch_ms": mean, "candidates_per_launch": evals}
         return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_PAIRS / 1e12, "unit": "Tpair/s",
                 "frac": ach / PEAK_PAIRS, "traffic": read_traffic("ctransform"), "kernel": "k_ctransform",
