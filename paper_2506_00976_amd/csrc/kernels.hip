@@ -713,6 +713,7 @@ __global__ __launch_bounds__(256) void k_argmin(const DevJob* __restrict__ jobs,
 // test (near ties, exact ties, non-finite potentials) are queued and
 // evaluated by brute force exactly as the all-pairs kernel does.
 constexpr int kXsOff = 2904;   // squares table: xs_sq[i] = (i - kXsOff)^2, 0 <= i <= 2 kXsOff (any valid N)
+constexpr int kXsWinCap = 72;  // argmin windows staged in LDS up to this many sources (64 lines each)
 
 __global__ __launch_bounds__(256) void k_xs_squares(double* __restrict__ t) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i <= 2 * kXsOff; i += gridDim.x * 256) {
@@ -1211,6 +1212,39 @@ __device__ __forceinline__ void xs_item_xt(const DevJob& J, int jb, int local, i
   }
 }
 
+// The window minima of a wave's TPW targets: the first stage stores them, the
+// second certifies them (as in xs_item_xt).
+template <bool FIRST, int TPW>
+__device__ __forceinline__ void xs_win_store(const DevJob& J, int jb, int phase, int2* __restrict__ list,
+                                             int* __restrict__ count, int e, bool valid, int tw0,
+                                             const double (&m)[TPW]) {
+  const int N = J.N;
+  if (!valid) return;
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int j = 0; j < TPW; ++j)
+      if (tw0 + j < N) J.xs_v[(size_t)e * N + tw0 + j] = m[j];
+  } else {
+    float* dst = phase == 0 ? J.g : J.f;
+    const double dk = 2.0 * 4.440892098500626e-16;    // d 2^-51, d = 2
+    const double c0 = 4.0 * (double)(N - 1) * (N - 1) + 1.0;
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      if (tw0 + j >= N) break;
+      const int o = e * N + tw0 + j;   // target (y_0 = e, y_1 = tw0 + j)
+      const double w1 = m[j];
+      const double del1 = dk * (fabs(w1) + c0);
+      const float lo = (float)(w1 - del1), hi = (float)(w1 + del1);
+      if (lo == hi) {   // false for NaN and infinite values
+        dst[o] = lo;
+      } else {
+        const int slot = atomicAdd(count, 1);
+        list[slot] = make_int2(jb, o);
+      }
+    }
+  }
+}
+
 // The same stage by windows (the default for these jobs).  Along one axis the
 // candidate matrix a[r] + (r - t)^2 is Monge, so the first exact minimiser of
 // a target never lies left of the first one of a smaller target, nor the last
@@ -1228,7 +1262,9 @@ __device__ __forceinline__ void xs_item_xt(const DevJob& J, int jb, int local, i
 // waves' partials meet through LDS.
 // Phase 2: each wave scans the window (the union over its 64 lines, so that
 // loads stay coalesced and the squares wave-uniform) for T / SW of the
-// item's targets, and certifies and stores them as above.
+// item's targets, and certifies and stores them as above; a window of up to
+// kXsWinCap sources is first staged in LDS by the work-group, so that its
+// waves read it from the L2 once between them.
 template <bool FIRST, int TPW>
 __device__ __forceinline__ void xs_win_scan(const DevJob& J, int jb, int phase, const_dptr sq,
                                             int2* __restrict__ list, int* __restrict__ count, int e,
@@ -1284,30 +1320,38 @@ __device__ __forceinline__ void xs_win_scan(const DevJob& J, int jb, int phase, 
     for (; r0 + 15 <= whi; r0 += 16) block(r0, std::false_type());
     if (r0 <= whi) block(r0, std::true_type());
   }
-  if (!valid) return;
-  if constexpr (FIRST) {
+  xs_win_store<FIRST, TPW>(J, jb, phase, list, count, e, valid, tw0, m);
+}
+
+// Phase 2 from a window staged in LDS by the work-group, wb[(r - wlo) 64 +
+// lane] the source r of the lane's line, in blocks of eight (the last one
+// masked past the window).
+template <bool FIRST, int TPW>
+__device__ __forceinline__ void xs_win_scan_lds(const DevJob& J, int jb, int phase, const_dptr sq,
+                                                int2* __restrict__ list, int* __restrict__ count, int e,
+                                                bool valid, int tw0, int wlo, int whi,
+                                                const typename std::conditional<FIRST, float, double>::type* wb) {
+  const int lane = threadIdx.x & 63;
+  double m[TPW];
 #pragma unroll
-    for (int j = 0; j < TPW; ++j)
-      if (tw0 + j < N) J.xs_v[(size_t)e * N + tw0 + j] = m[j];
-  } else {
-    float* dst = phase == 0 ? J.g : J.f;
-    const double dk = 2.0 * 4.440892098500626e-16;    // d 2^-51, d = 2
-    const double c0 = 4.0 * (double)(N - 1) * (N - 1) + 1.0;
+  for (int j = 0; j < TPW; ++j) m[j] = INFINITY;
+  const int last = whi - wlo;
+  auto block = [&](int r0, auto partial) {
+    // sb[j + TPW - 1 - t] = (r0 + j - tw0 - t)^2
+    const_dptr sb = sq + (r0 - tw0 + kXsOff - (TPW - 1));
 #pragma unroll
-    for (int j = 0; j < TPW; ++j) {
-      if (tw0 + j >= N) break;
-      const int o = e * N + tw0 + j;   // target (y_0 = e, y_1 = tw0 + j)
-      const double w1 = m[j];
-      const double del1 = dk * (fabs(w1) + c0);
-      const float lo = (float)(w1 - del1), hi = (float)(w1 + del1);
-      if (lo == hi) {   // false for NaN and infinite values
-        dst[o] = lo;
-      } else {
-        const int slot = atomicAdd(count, 1);
-        list[slot] = make_int2(jb, o);
-      }
+    for (int j = 0; j < 8; ++j) {
+      const int sidx = decltype(partial)::value ? min(r0 + j - wlo, last) : r0 + j - wlo;
+      double h = FIRST ? -(double)wb[sidx * 64 + lane] : (double)wb[sidx * 64 + lane];
+      if constexpr (decltype(partial)::value) h = r0 + j <= whi ? h : INFINITY;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) m[t] = vmin_f64(m[t], h + sb[j + TPW - 1 - t]);
     }
-  }
+  };
+  int r0 = wlo;
+  for (; r0 + 7 <= whi; r0 += 8) block(r0, std::false_type());
+  if (r0 <= whi) block(r0, std::true_type());
+  xs_win_store<FIRST, TPW>(J, jb, phase, list, count, e, valid, tw0, m);
 }
 
 template <bool FIRST, int kXsT>
@@ -1349,6 +1393,16 @@ __device__ __forceinline__ void xs_item_win(const DevJob& J, int jb, int local, 
     }
     soff = min(soff + st8, last_off);
     __asm__ volatile("" : "+s"(soff));
+    return x;
+  };
+  auto load_src = [&](int r) {   // source r of the lane's line (r a scalar)
+    HT x;
+    if constexpr (FIRST) {
+      x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lob, r * st8, 0));
+    } else {
+      const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lob, r * st8, 0);
+      __builtin_memcpy(&x, &w, 8);
+    }
     return x;
   };
   // a block's minima update the running ones: lo is the first block start
@@ -1424,6 +1478,23 @@ __device__ __forceinline__ void xs_item_win(const DevJob& J, int jb, int local, 
   // phase 2: this wave's targets
   const int tpw = kXsT / SW;
   const int tw0 = t0 + wv * tpw;
+  const int nw = whi - wlo + 1;   // the same in every wave of the work-group
+  if (nw > 0 && nw <= kXsWinCap) {
+    // the window staged once in LDS (over the partials, once every wave has
+    // read them), each wave loading every SW-th source of it
+    HT* wb = reinterpret_cast<HT*>(red);
+    __syncthreads();
+    for (int sidx = wv; sidx < nw; sidx += SW) wb[sidx * 64 + lane] = load_src(wlo + sidx);
+    __syncthreads();
+    if (tw0 >= N) return;
+    if (tpw == 2) {
+      xs_win_scan_lds<FIRST, 2>(J, jb, phase, sq, list, count, e, valid, tw0, wlo, whi, wb);
+    } else {
+      for (int c = 0; c < tpw; c += 4)
+        xs_win_scan_lds<FIRST, 4>(J, jb, phase, sq, list, count, e, valid, tw0 + c, wlo, whi, wb);
+    }
+    return;
+  }
   if (tw0 >= N) return;
   // (four targets per pass at most, which keeps one pass within the
   // stage's registers; more passes re-read the window from the caches)
@@ -1449,7 +1520,8 @@ __global__ __launch_bounds__(XT == 2 ? 512 : 256) void k_xs_stage(const DevJob* 
   // dynamic LDS, sized by the launcher (xs_lds_bytes): the first stage's
   // per-wave tiles (64 x 17 floats, with arg-mins only), then SW / 2 x 64 x T
   // doubles for the waves' minima on their way to wave 0 (argmin windows:
-  // SW x 64 x (two minima, two source bounds) for the waves' partials)
+  // SW x 64 x (two minima, two source bounds) for the waves' partials, then
+  // the window's sources, up to kXsWinCap x 64)
   extern __shared__ double xs_lds[];
   const int SW = blockDim.x >> 6;
   // the wave index, known wave-uniform: source ranges and load addresses
@@ -1487,10 +1559,12 @@ __global__ __launch_bounds__(XT == 2 ? 512 : 256) void k_xs_stage(const DevJob* 
 }
 
 // LDS bytes of one k_xs_stage work-group (matches the kernel's carving).
-static size_t xs_lds_bytes(bool first, int T, bool arg, int waves, bool xt) {
+static size_t xs_lds_bytes(bool first, int T, bool arg, int waves, bool xt, bool first_src32) {
   const size_t tiles = first && arg ? 8 * (size_t)((waves * 64 * 17 + 1) / 2) : 0;
-  // the waves' minima on their way to wave 0, or the windows' partials
-  const size_t red = xt ? (size_t)waves * 64 * (16 + 8) : arg ? 0 : 8 * (size_t)(waves / 2) * 64 * T;
+  // the waves' minima on their way to wave 0, or the windows' partials and
+  // then the staged window (float32 sources in the first stage, else float64)
+  const size_t red = xt ? std::max<size_t>((size_t)waves * 64 * (16 + 8), (size_t)kXsWinCap * 64 * (first_src32 ? 4 : 8))
+                        : arg ? 0 : 8 * (size_t)(waves / 2) * 64 * T;
   return std::max<size_t>(8, tiles + red);
 }
 
@@ -3767,7 +3841,7 @@ template <bool FIRST>
 static void launch_xs_kind(int T, bool arg, int xt, int waves, const DevJob* jobs, int njobs, const int* off,
                            int total, int phase, int k, const double* sqt, int2* list, int* count, hipStream_t st) {
   const dim3 g(xt ? total : grid_for(total)), b(64 * waves);
-  const size_t lds = xs_lds_bytes(FIRST && !xt, T, arg, waves, xt == 2);
+  const size_t lds = xs_lds_bytes(FIRST && !xt, T, arg, waves, xt == 2, FIRST);
 #define QBW_XS(TT, AA, XX) hipLaunchKernelGGL((k_xs_stage<FIRST, TT, AA, XX>), g, b, lds, st, jobs, njobs, off, total, \
                                               phase, k, sqt, list, count)
   if (xt == 2) {
