@@ -2577,13 +2577,31 @@ __device__ void finalize_job(const DevJob& J, double* sh) {
   const double kd = (double)kdi;
   const double cc = 1.0 / (kd * kd);
   double pc = 0, mm = 0;
-  // unrolled so that several entries' loads are in flight at once (the sums
-  // keep their order)
-#pragma unroll 8
-  for (int e = threadIdx.x; e < J.nnz; e += 256) {
-    const double ce = cc * J.e_val[e];
-    pc += ce * J.red_pc[e];
-    if (J.p == 2) mm += ce * J.red_pm[e];
+  // eight of a thread's entries at a time, all their loads issued before the
+  // first is used (the sums keep their order: entry e, e + 256, ...)
+  {
+    const int nnz = J.nnz;
+    const double* ev = J.e_val;
+    const double* rp = J.red_pc;
+    const double* rm = J.p == 2 ? J.red_pm : J.red_pc;
+    for (int e0 = threadIdx.x; e0 < nnz; e0 += 256 * 8) {
+      double a[8], b[8], c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = min(e0 + 256 * u, nnz - 1);
+        a[u] = ev[e];
+        b[u] = rp[e];
+        c[u] = rm[e];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (e0 + 256 * u < nnz) {
+          const double ce = cc * a[u];
+          pc += ce * b[u];
+          if (J.p == 2) mm += ce * c[u];
+        }
+      }
+    }
   }
   const double rmax = (double)J.row_max, cmax = (double)J.col_max;
   // all sums and maxima in one work-group reduction
