@@ -1639,18 +1639,47 @@ __global__ __launch_bounds__(64) void k_xs_fallback(const DevJob* __restrict__ j
       const int ci = oc >> 6;
       const double bo = ci == 0 ? obv[0] : ci == 1 ? obv[1] : ci == 2 ? obv[2] : ci == 3 ? obv[3] : 0.0;
       unsigned long long m = __ballot(o < N && !skip(ci < 4 ? bo : outer_bound(o)));
+      if (xt) {
+        // value only: the selected columns four at a time, the sources (r, ob)
+        // of each, r = 0 .. N-1, loaded 256 rows at a time before any is used
+        while (m) {
+          int cols[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            cols[c] = m ? oc + __ffsll((long long)m) - 1 : -1;
+            m &= m - 1;
+          }
+          for (int r0 = 0; r0 < N; r0 += 256) {
+            float v[4][4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const int r = r0 + lane + 64 * k;
+                v[c][k] = (cols[c] >= 0 && r < N) ? src[r * N + cols[c]] : 0.0f;
+              }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              if (cols[c] < 0) continue;
+              const int co = (cols[c] - oy) * (cols[c] - oy);
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const int r = r0 + lane + 64 * k;
+                if (r < N) {
+                  const int e = r - y1;
+                  xs_take((float)(co + e * e) - v[c][k], r * N + cols[c], best, bi);
+                }
+              }
+            }
+          }
+        }
+        continue;
+      }
       while (m) {
         const int ob = oc + __ffsll((long long)m) - 1;
         m &= m - 1;
         const int co = (ob - oy) * (ob - oy);
-        if (xt) {
-          // sources (r, ob) of the column, r = 0 .. N-1
-#pragma unroll 4
-          for (int r = lane; r < N; r += 64) {
-            const int e = r - y1;
-            xs_take((float)(co + e * e) - src[r * N + ob], r * N + ob, best, bi);
-          }
-        } else if (d == 2) {
+        if (d == 2) {
           scan_row(ob * N, co, y2);
         } else {
           // rows (ob, x_1) of the plane, bounded by stage 0
