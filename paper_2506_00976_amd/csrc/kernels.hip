@@ -1270,7 +1270,6 @@ __device__ __forceinline__ void xs_win_scan(const DevJob& J, int jb, int phase, 
                                             int2* __restrict__ list, int* __restrict__ count, int e,
                                             bool valid, int tw0, int wlo, int whi,
                                             __amdgpu_buffer_rsrc_t rs, int lob, int st8) {
-  const int N = J.N;
   double m[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) m[j] = INFINITY;
