@@ -129,6 +129,31 @@ def test_exact_separable_on_pipeline_potentials_256(fam, big_records):
 
 
 @pytest.mark.parametrize("fam", ["grf", "cauchy"])
+def test_exact_separable_windows_on_pipeline_potentials_256(fam, big_records, monkeypatch):
+    # values only at 16 targets per lane: the two-dimensional stages scan
+    # argmin windows (items of 64 lines x 32 targets on eight waves, the
+    # benchmark's configuration); whole vectors against the all-pairs kernel,
+    # sampled targets against the oracle
+    monkeypatch.setenv("QBW_XS_T", "16")
+    N, d, k, p = 256, 2, 8, 2
+    R = big_records
+    fh_ref = lower.upscale_potential(R[f"{fam}_f"], N, d, k).astype(np.float32)
+    fhat = dev(fh_ref)
+    print(f"exact separable windows 256^2 {fam}", flush=True)
+    g, nfb_g = qbw.ctransform_exact(fhat, N, d, return_fallback=True)
+    f, nfb_f = qbw.ctransform_exact(g, N, d, return_fallback=True)
+    assert nfb_g > 0 and nfb_f > 0
+    ga = qbw.ctransform(fhat, N, d, p)
+    fa = qbw.ctransform(g, N, d, p)
+    assert torch.equal(g, ga) and torch.equal(f, fa)
+    rng = si.rng(9310 + (fam == "cauchy"))
+    for src, val in ((fh_ref, g), (g.cpu().numpy(), f)):
+        tg = rng.choice(N * N, 400, replace=False)
+        ref, _ = lower.ctransform_o32(src, N, d, p, targets=tg)
+        assert np.array_equal(val.cpu().numpy()[tg].view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("fam", ["grf", "cauchy"])
 def test_upper_bound_256_against_oracle(fam, big_records):
     N, d, k, p = 256, 2, 8, 2
     R = big_records
