@@ -2079,8 +2079,12 @@ qbw_status qbw_batch_create(qbw_ctx* ctx, const qbw_job* jobs, int32_t njobs, co
   const char* cse = std::getenv("QBW_COARSE_STREAM");
   if (!(cse && std::strcmp(cse, "main") == 0)) {
     HIPCHK(hipStreamCreateWithFlags(&B->side.st, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&B->side.fork, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&B->side.join, hipEventDisableTiming));
+    // the fork and the join order work between two streams of this device
+    // only (the host never waits on them): no system-scope fence (QBW_EVENT_FENCE=1 keeps it)
+    const char* efe = std::getenv("QBW_EVENT_FENCE");
+    const unsigned ef = hipEventDisableTiming | ((efe && std::strcmp(efe, "1") == 0) ? 0u : hipEventDisableSystemFence);
+    HIPCHK(hipEventCreateWithFlags(&B->side.fork, ef));
+    HIPCHK(hipEventCreateWithFlags(&B->side.join, ef));
   }
   if (batch_flags & QBW_BATCH_GRAPH) {
     HIPCHK(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
