@@ -2873,6 +2873,33 @@ __global__ __launch_bounds__(256) void k_moments(const DevJob* __restrict__ jobs
         for (int c0 = 0; c0 < N; c0 += W) {
           const int x2 = c0 + col;
           if (rg >= RG || x2 >= N) continue;
+          if (J.interp == 0 && J.d == 2) {
+            // bilinear: a 2D strip's rows lie between the coarse rows b1 - 1
+            // and b1 + 1, so the three interpolations along x_2 are formed
+            // once (the same operations as upscale_value's), then each
+            // pixel's along x_1
+            const double* __restrict__ F = J.ftil;
+            int B0, B1;
+            double wb;
+            axis_weight(x2, k, n, B0, B1, wb);
+            const int a0 = max(b1 - 1, 0);
+            double rr[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              const int a = min(a0 + q, n - 1);
+              rr[q] = lerp_nc(F[a * n + B0], F[a * n + B1], wb);
+            }
+            for (int r = rg; r < nrows; r += RG) {
+              const int X1 = b1 * k + r;
+              int A0, A1;
+              double wa;
+              axis_weight(X1, k, n, A0, A1, wa);
+              const double v0 = A0 - a0 == 0 ? rr[0] : rr[1];
+              const double v1 = A1 - a0 == 1 ? rr[1] : (A1 - a0 == 2 ? rr[2] : rr[0]);
+              J.fhat[(size_t)X1 * N + x2] = (float)lerp_nc(v0, v1, wa);
+            }
+            continue;
+          }
           for (int r = rg; r < nrows; r += RG) {
             const int u0 = J.d == 2 ? 0 : r / k, u1 = J.d == 2 ? r : r - (r / k) * k;
             const int X0 = J.d == 2 ? 0 : b0 * k + u0, X1 = b1 * k + u1;
