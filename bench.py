@@ -621,7 +621,7 @@ def main():
                    "launch": "hipGraph replay per step" if use_graph else "kernels launched on the stream per step"},
         "launch_modes_ms_per_step": launch_modes,
         "roofline": roof,
-        "roofline_note": ("the c-transform roofline target is judged on the timed path's kernel, "
+        "roofline_note": ("the c-transform roofline is that of the timed path's kernel, "
                           + ("k_xs_stage (exact separable stages); the all-pairs k_ctransform is reported "
                              "beside it under all_pairs" if mode else "k_ctransform (all-pairs)")),
         ("all_pairs" if mode else "exact_separable"): {

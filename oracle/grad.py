@@ -1,7 +1,7 @@
 """Gradients of both bounds with respect to the input measures (oracle side).
 
 The paper does not differentiate its bounds; the contract used here (a
-reading, listed in the design doc) is:
+reading of ours, not the paper's) is:
 
 * the coarse solution (coupling pi~ and potential f~) is frozen;
 * lower bound: f^ = R(f~) does not depend on (mu, nu), so neither do the

@@ -1,6 +1,6 @@
 """The regular grid X = [N]^d and the ground cost (Section 2.1, Section 2.2).
 
-Conventions (readings of the paper, listed in the design doc):
+Conventions (readings of the paper where it leaves them open):
 
 * Pixels sit at integer coordinates 0..N-1 along every axis, spacing 1.  The
   paper uses [N] = {1..N}; the cost is translation invariant, so the shift

@@ -1,13 +1,14 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
-Tolerances (derivations in the design doc):
+Tolerances:
 * float32 values and arg-mins of the c-transform, the upscaled potential:
   bit-exact against the oracle's float32 reading;
 * float64 sums (lower bound, plan cost, pooled masses, C-bar): relative 1e-9
   or tighter;
 * upper bound: the plan-cost part to 1e-9 relative; the total-variation terms
   are square roots (p = 2) of rounding-level sums, so the emitted upper bound
-  must lie in [oracle, oracle + 1e-9 UB + 2 * 2^(1-1/p) (2^-39 <w, mu>)^(1/p)].
+  must lie in [oracle, oracle + the room `ub_tol` derives from the library's
+  rounding allowance].
 """
 from __future__ import annotations
 
