@@ -1371,7 +1371,8 @@ __device__ __forceinline__ void xs_item_win(const DevJob& J, int jb, int local, 
   const int rlo = min(N, wv * chunkS), rhi = min(N, rlo + chunkS);
   const int NB = rhi - (rhi - rlo) % 16;   // sources in whole pairs of blocks of 8 end here
   // phase 1: rounded minima of t0 and tb1 over this wave's sources, with the
-  // first source attaining the one and the last attaining the other
+  // start of the first block of eight attaining the one and the end of the
+  // last block attaining the other
   double b0 = INFINITY, b1 = INFINITY;
   int lo = 0x7fffffff, hi = -1;
   constexpr int EB = FIRST ? 4 : 8;
